@@ -1,0 +1,201 @@
+"""Seeded synthetic inputs: materials, phantoms, beams, physics settings.
+
+This module holds data and seeded generators only -- no transport or
+cross-section arithmetic -- so that the HIP path and the CPU oracle can be fed
+identical inputs without sharing any of the method's code.
+
+Workloads follow the paper's set-ups (Sec. II.D and Sec. III): monoenergetic
+parallel beams entering a voxelized phantom along +z, a 64^3 grid of 0.5 cm
+water voxels at 15 MeV (Table IV), slab heterogeneities of water, bone and lung
+(Sec. III.A), plus ellipsoid phantoms with several materials for beamlet
+batches and request streams.  No public dataset is involved; every array is
+generated from a numpy ``default_rng`` seed.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+PHOTON, ELECTRON = 0, 1
+MONO, TRIANGULAR = 0, 1
+
+
+@dataclass(frozen=True)
+class Material:
+    """Effective-element material: Z/A (mol/g), effective Z, mean excitation energy (eV)."""
+    name: str
+    z_over_a: float
+    z_eff: float
+    i_ev: float
+
+
+# Approximate standard tissue values; any self-consistent set works because both
+# sides read the same numbers.
+WATER = Material("water", 0.55509, 7.42, 75.0)
+LUNG = Material("lung", 0.55509, 7.42, 75.0)        # water composition, low density
+BONE = Material("bone", 0.5213, 13.8, 106.4)
+SOFT_TISSUE = Material("soft_tissue", 0.5512, 7.2, 72.3)
+DEFAULT_MATERIALS: Tuple[Material, ...] = (LUNG, WATER, SOFT_TISSUE, BONE)
+
+
+@dataclass
+class Phantom:
+    """Voxel densities (g/cm^3) and material indices, arrays [nz, ny, nx] (x fastest)."""
+    rho: np.ndarray
+    mat: np.ndarray
+    voxel: Tuple[float, float, float]   # (dx, dy, dz) cm
+
+    @property
+    def shape(self):
+        return self.rho.shape
+
+    @property
+    def extent(self):
+        nz, ny, nx = self.rho.shape
+        return (nx * self.voxel[0], ny * self.voxel[1], nz * self.voxel[2])
+
+
+@dataclass
+class Source:
+    """Parallel beam along +z entering at z = 0 over a rectangular field."""
+    particle: int = PHOTON
+    spectrum: int = MONO
+    e: float = 1.0
+    e_lo: float = 0.0
+    e_mode: float = 0.0
+    e_hi: float = 0.0
+    cx: float = 0.0
+    cy: float = 0.0
+    wx: float = 1.0
+    wy: float = 1.0
+    beam_id: int = 0
+
+
+@dataclass
+class Physics:
+    """Transport cutoffs (kinetic, MeV) and run options."""
+    ecut: float = 0.2
+    pcut: float = 0.01
+    kcut: float = 0.0          # <= 0: equal to ecut
+    kc: float = 0.0            # <= 0: equal to pcut
+    esmax_gcm2: float = 0.0    # <= 0: no user step bound
+    n_batches: int = 32
+    test_mode: int = 0         # 0 full, 1 photon first collision, 2 electron CSDA straight-ahead
+
+
+# ------------------------------------------------------------------ phantoms
+def homogeneous(n: Sequence[int], voxel: float, material_index: int = 0, density: float = 1.0) -> Phantom:
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else tuple(n)
+    rho = np.full((nz, ny, nx), density, np.float32)
+    mat = np.full((nz, ny, nx), material_index, np.uint8)
+    return Phantom(rho, mat, (float(voxel),) * 3)
+
+
+def z_slabs(n: Sequence[int], voxel: float, slabs: Sequence[Tuple[float, int, float]]) -> Phantom:
+    """Slabs along depth: ``slabs`` = [(z_end_cm, material_index, density), ...];
+    the last slab runs to the end of the phantom."""
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else tuple(n)
+    zc = (np.arange(nz) + 0.5) * voxel
+    rho = np.empty((nz, ny, nx), np.float32)
+    mat = np.empty((nz, ny, nx), np.uint8)
+    start = 0.0
+    for i, (zend, m, d) in enumerate(slabs):
+        sel = (zc >= start) & ((zc < zend) | (i == len(slabs) - 1))
+        rho[sel] = d
+        mat[sel] = m
+        start = zend
+    return Phantom(rho, mat, (float(voxel),) * 3)
+
+
+def material_from_density(rho: np.ndarray) -> np.ndarray:
+    """Index into DEFAULT_MATERIALS: < 0.6 lung, < 1.1 water, < 1.4 soft tissue, else bone."""
+    return np.select([rho < 0.6, rho < 1.1, rho < 1.4], [0, 1, 2], 3).astype(np.uint8)
+
+
+def ellipsoids(n: Sequence[int], voxel: float, seed: int, count: int = 12,
+               rho_range=(0.2, 1.9), axis_frac=(0.05, 0.35)) -> Phantom:
+    """Water box with ``count`` seeded axis-aligned ellipsoids (later ones
+    overwrite earlier ones); densities U(rho_range), materials from density."""
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else tuple(n)
+    rng = np.random.default_rng(seed)
+    ext = np.array([nx, ny, nz], np.float64) * voxel
+    rho = np.ones((nz, ny, nx), np.float32)
+    zc = ((np.arange(nz) + 0.5) * voxel)[:, None, None]
+    yc = ((np.arange(ny) + 0.5) * voxel)[None, :, None]
+    xc = ((np.arange(nx) + 0.5) * voxel)[None, None, :]
+    for _ in range(count):
+        c = rng.uniform(0, 1, 3) * ext
+        a = rng.uniform(axis_frac[0], axis_frac[1], 3) * ext
+        d = rng.uniform(*rho_range)
+        inside = ((xc - c[0]) / a[0]) ** 2 + ((yc - c[1]) / a[1]) ** 2 + ((zc - c[2]) / a[2]) ** 2 <= 1.0
+        rho[inside] = d
+    return Phantom(rho, material_from_density(rho), (float(voxel),) * 3)
+
+
+# ------------------------------------------------------------------ workloads
+@dataclass
+class Workload:
+    name: str
+    materials: Tuple[Material, ...]
+    phantom: Phantom
+    source: Source
+    physics: Physics
+    n_hist: int
+    seed: int = 1
+    extra: dict = field(default_factory=dict)
+
+
+def centred(ph: Phantom, src: Source) -> Source:
+    ex, ey, _ = ph.extent
+    return replace(src, cx=ex / 2.0, cy=ey / 2.0)
+
+
+def small_photon_water(n_hist: int = 100000) -> Workload:
+    """1 MeV photons, 0.5 x 0.5 cm beam on 32^3 water at 0.5 cm; ECUT 0.2, PCUT 0.01."""
+    ph = homogeneous(32, 0.5, 0)
+    src = centred(ph, Source(PHOTON, MONO, 1.0, wx=0.5, wy=0.5))
+    return Workload("photon_1MeV_water_32^3", (WATER,), ph, src, Physics(ecut=0.2, pcut=0.01), n_hist)
+
+
+def water_15mev(particle: int, n_hist: int = None) -> Workload:
+    """15 MeV parallel beam, 10 x 10 cm field, 64^3 water at 0.5 cm (Table IV set-up);
+    1e6 electrons or 4e6 photons; ECUT 0.7 (kinetic), PCUT 0.01."""
+    ph = homogeneous(64, 0.5, 0)
+    src = centred(ph, Source(particle, MONO, 15.0, wx=10.0, wy=10.0))
+    if n_hist is None:
+        n_hist = 1_000_000 if particle == ELECTRON else 4_000_000
+    name = "%s_15MeV_water_64^3" % ("electron" if particle == ELECTRON else "photon")
+    return Workload(name, (WATER,), ph, src, Physics(ecut=0.7, pcut=0.01), n_hist)
+
+
+def slab_6mev(n_hist: int = 40_000_000) -> Workload:
+    """6 MeV photons, 10 x 10 cm, 128^3 at 0.25 cm: water 0-3 cm, bone (1.85) 3-5,
+    lung (0.26) 5-12, water to the end."""
+    mats = (WATER, BONE, LUNG)
+    ph = z_slabs(128, 0.25, [(3.0, 0, 1.0), (5.0, 1, 1.85), (12.0, 2, 0.26), (32.0, 0, 1.0)])
+    src = centred(ph, Source(PHOTON, MONO, 6.0, wx=10.0, wy=10.0))
+    return Workload("photon_6MeV_slabs_128^3", mats, ph, src, Physics(ecut=0.7, pcut=0.01), n_hist)
+
+
+def beamlets(seed: int = 11, phantom_seed: int = 7, n_beamlets: int = 256, shape=(200, 200, 160),
+             voxel: float = 0.25) -> Tuple[Phantom, List[Source], np.ndarray]:
+    """Pencil beamlets 0.5 x 0.5 cm on a 16 x 16 grid at 1 cm pitch, centred on an
+    ellipsoid phantom; energies U(1, 20) MeV; photons:electrons 3:1 by seeded
+    permutation; history counts log-uniform on [1e4, 1e6]."""
+    ph = ellipsoids(shape, voxel, phantom_seed)
+    rng = np.random.default_rng(seed)
+    ex, ey, _ = ph.extent
+    side = int(round(np.sqrt(n_beamlets)))
+    kinds = np.array([PHOTON] * (n_beamlets * 3 // 4) + [ELECTRON] * (n_beamlets - n_beamlets * 3 // 4))
+    kinds = rng.permutation(kinds)
+    energies = rng.uniform(1.0, 20.0, n_beamlets)
+    counts = np.round(10.0 ** rng.uniform(4.0, 6.0, n_beamlets)).astype(np.uint64)
+    srcs = []
+    for i in range(n_beamlets):
+        gx, gy = i % side, i // side
+        cx = ex / 2.0 + (gx - (side - 1) / 2.0) * 1.0
+        cy = ey / 2.0 + (gy - (side - 1) / 2.0) * 1.0
+        srcs.append(Source(int(kinds[i]), MONO, float(energies[i]), cx=cx, cy=cy, wx=0.5, wy=0.5, beam_id=i))
+    return ph, srcs, counts

@@ -1,0 +1,240 @@
+"""Transport-level pins of the oracle (Sec. II.A and II.B.3).
+
+* Woodcock tracking (Eq. 3) reproduces narrow-beam first-collision
+  attenuation exp(-sum mu_i x_i), homogeneous and through slabs, and the
+  fictitious-event fraction 1 - mu/mu_hat.
+* In CSDA straight-ahead mode the electron track is deterministic; the energy
+  deposited up to depth z equals T0 - T(z) with dT/dz = -L(T) (Eq. 5 with the
+  restricted L of Eq. 6), integrated here by quad.
+* The energy ledger closes to 1e-9 (incident = deposited + escaped + pair sink).
+* Scaling density by 2 and lengths by 1/2 leaves every trajectory unchanged
+  (power-of-two scaling is exact in binary arithmetic), so the per-voxel
+  energy must be bit-identical.
+* Lateral mirror symmetry, batch vs history-by-history uncertainty (Eq. 13),
+  history-range splitting, and degenerate inputs.
+"""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+from scipy.integrate import quad
+from scipy.optimize import brentq
+
+from paper_1101_1245_amd.inputs import (BONE, ELECTRON, LUNG, PHOTON, WATER, Physics, Source, centred,
+                                        homogeneous, z_slabs)
+
+MC2 = 0.51099895
+
+
+def mu_tot(oracle, m, e):
+    return sum(oracle.xs(m, w, [e])[0] for w in ("mu_C", "mu_pe", "mu_pair"))
+
+
+def depth_profile(res):
+    return res.e1.sum(axis=(1, 2))
+
+
+def test_first_collision_homogeneous(oracle):
+    ph = homogeneous((4, 4, 40), 0.5)
+    src = centred(ph, Source(PHOTON, e=1.0, wx=0.5, wy=0.5))
+    n = 200000
+    res = oracle.run((WATER,), ph, src, Physics(test_mode=1, n_batches=4), seed=5, n_hist=n)
+    mu = mu_tot(oracle, WATER, 1.0)
+    z = np.arange(41) * 0.5
+    p = np.exp(-mu * z[:-1]) - np.exp(-mu * z[1:])
+    counts = depth_profile(res) / 1.0
+    sig = np.sqrt(n * p * (1 - p))
+    zs = (counts - n * p) / sig
+    assert np.max(np.abs(zs)) < 4.5
+    assert abs(np.mean(zs)) < 4.0 / np.sqrt(zs.size) * 1.5
+    # escapes = transmitted fraction
+    esc = res.stats["e_esc"]
+    pt = np.exp(-mu * 20.0)
+    assert abs(esc - n * pt) < 5 * np.sqrt(n * pt * (1 - pt))
+    assert res.stats["n_majorant_violations"] == 0
+
+
+def test_first_collision_slabs(oracle):
+    # water 0-3, bone 3-5 (1.85), lung 5-12 (0.26), water to 20 cm; 6 MeV
+    mats = (WATER, BONE, LUNG)
+    ph = z_slabs((4, 4, 80), 0.25, [(3.0, 0, 1.0), (5.0, 1, 1.85), (12.0, 2, 0.26), (20.0, 0, 1.0)])
+    src = centred(ph, Source(PHOTON, e=6.0, wx=0.25, wy=0.25))
+    n = 200000
+    res = oracle.run(mats, ph, src, Physics(test_mode=1, n_batches=4), seed=6, n_hist=n)
+    mw, mb = mu_tot(oracle, WATER, 6.0), mu_tot(oracle, BONE, 6.0) * 1.85
+    ml = mu_tot(oracle, LUNG, 6.0) * 0.26
+
+    def mu_of(z):
+        return mw if z < 3 else (mb if z < 5 else (ml if z < 12 else mw))
+
+    edges = np.arange(81) * 0.25
+    tau = np.concatenate([[0.0], np.cumsum([mu_of(0.5 * (a + b)) * (b - a) for a, b in zip(edges[:-1], edges[1:])])])
+    p = np.exp(-tau[:-1]) - np.exp(-tau[1:])
+    counts = depth_profile(res) / 6.0
+    zs = (counts - n * p) / np.sqrt(n * p * (1 - p))
+    assert np.max(np.abs(zs)) < 4.5
+    assert res.stats["n_majorant_violations"] == 0
+
+
+def test_fictitious_fraction(oracle):
+    # lung everywhere except one bone voxel far from the beam: the majorant is
+    # set by bone, so each event in lung is fictitious with 1 - mu/mu_hat
+    mats = (LUNG, BONE)
+    ph = homogeneous((8, 8, 40), 0.5, 0, 0.26)
+    ph.rho[0, 0, 0] = 1.85
+    ph.mat[0, 0, 0] = 1
+    src = centred(ph, Source(PHOTON, e=6.0, wx=0.5, wy=0.5))
+    phys = Physics(test_mode=1, n_batches=4)
+    mu_hat, _ = oracle.majorants(mats, ph, phys)
+    n = oracle.grid_size()
+    b = int(np.floor(np.log(6.0 / 1e-3) * (n - 1) / np.log(32e3)))
+    want = 1 - 0.26 * mu_tot(oracle, LUNG, 6.0) / mu_hat[b]
+    res = oracle.run(mats, ph, src, phys, seed=7, n_hist=50000)
+    st = res.stats
+    ev = st["n_photon_events"]
+    # events that escape are neither real nor fictitious; count decisions only
+    decided = ev - 50000 + (res.e1.sum() / 6.0)   # escapes = N - real
+    frac = st["n_fictitious"] / decided
+    assert abs(frac - want) < 5 * np.sqrt(want * (1 - want) / decided)
+    assert abs(want - 0.8627) < 2e-3   # value fixed by the cross sections at 6 MeV
+
+
+def test_csda_straight_ahead_depth_dose(oracle):
+    t0, ecut = 5.0, 0.2
+    ph = homogeneous((4, 4, 64), 0.25)
+    src = centred(ph, Source(ELECTRON, e=t0, wx=0.1, wy=0.1))
+    phys = Physics(ecut=ecut, pcut=0.01, esmax_gcm2=0.01, test_mode=2, n_batches=2)
+    n = 20
+    res = oracle.run((WATER,), ph, src, phys, seed=8, n_hist=n)
+    dep = depth_profile(res) / n
+    assert dep.sum() == pytest.approx(t0, rel=1e-12)
+    L = lambda t: oracle.xs(WATER, "L", [t], kcut=ecut, kc=0.01)[0]
+    depth_of = lambda t: quad(lambda x: 1.0 / L(x), t, t0, epsrel=1e-11)[0]
+    r_stop = depth_of(ecut)
+    cum = np.cumsum(dep)
+    for j in range(64):
+        zb = (j + 1) * 0.25
+        if zb < r_stop - 0.02:
+            t_z = brentq(lambda t: depth_of(t) - zb, ecut, t0, xtol=1e-13)
+            assert cum[j] == pytest.approx(t0 - t_z, abs=2e-4 * t0)
+        elif zb > r_stop + 0.02:
+            assert cum[j] == pytest.approx(t0, rel=1e-12)
+    assert res.stats["n_hard"] == 0
+
+
+@pytest.mark.parametrize("particle,energy", [(ELECTRON, 15.0), (PHOTON, 15.0), (PHOTON, 6.0)])
+def test_energy_ledger(oracle, particle, energy):
+    mats = (WATER, BONE, LUNG)
+    ph = z_slabs((24, 24, 48), 0.5, [(3.0, 0, 1.0), (5.0, 1, 1.85), (12.0, 2, 0.26), (24.0, 0, 1.0)])
+    src = centred(ph, Source(particle, e=energy, wx=6.0, wy=6.0))
+    n = 600 if particle == ELECTRON else 3000
+    res = oracle.run(mats, ph, src, Physics(ecut=0.2, pcut=0.01, n_batches=4), seed=9, n_hist=n)
+    st = res.stats
+    assert st["e_in"] == pytest.approx(n * energy, rel=1e-14)
+    resid = st["e_in"] - st["e_dep"] - st["e_esc"] - st["e_sink"]
+    assert abs(resid) <= 1e-9 * st["e_in"]
+    assert res.e1.sum() == pytest.approx(st["e_dep"], rel=1e-12)
+    npair = st["e_sink"] / (2 * MC2)
+    assert abs(npair - round(npair)) < 1e-6
+    if energy > 2 * MC2 * 2:
+        assert npair > 0
+    assert st["n_majorant_violations"] == 0
+    assert st["n_secondaries"] > 0
+
+
+@pytest.mark.parametrize("particle", [ELECTRON, PHOTON])
+def test_density_scaling_is_exact(oracle, particle):
+    mats = (WATER, BONE)
+    a = z_slabs((12, 12, 24), 0.5, [(4.0, 0, 1.0), (6.0, 1, 1.85), (12.0, 0, 1.0)])
+    b = replace(a, rho=(a.rho * 2).astype(np.float32), voxel=(0.25, 0.25, 0.25))
+    sa = centred(a, Source(particle, e=8.0, wx=2.0, wy=2.0))
+    sb = centred(b, Source(particle, e=8.0, wx=1.0, wy=1.0))
+    phys = Physics(ecut=0.2, pcut=0.01, esmax_gcm2=0.3, n_batches=2)
+    ra = oracle.run(mats, a, sa, phys, seed=10, n_hist=300)
+    rb = oracle.run(mats, b, sb, phys, seed=10, n_hist=300)
+    assert np.array_equal(ra.e1, rb.e1)
+    for k in ("n_e_steps", "n_photon_events", "n_hard", "n_secondaries"):
+        assert ra.stats[k] == rb.stats[k]
+
+
+def test_lateral_mirror_symmetry(oracle):
+    ph = homogeneous((16, 16, 16), 0.5)
+    src = centred(ph, Source(ELECTRON, e=6.0, wx=3.0, wy=3.0))
+    n = 4000
+    res = oracle.run((WATER,), ph, src, Physics(ecut=0.2, pcut=0.01, n_batches=4), seed=11, n_hist=n)
+    prof = res.e1.sum(axis=(0, 1))            # energy vs x
+    prof2 = res.e2.sum(axis=(0, 1))
+    left, right = prof, prof[::-1]
+    var = (prof2 - prof ** 2 / n)             # per-column variance of the sum over histories
+    var = np.maximum(var, 1e-30)
+    z = (left - right) / np.sqrt(var + var[::-1])
+    sel = prof > 0.01 * prof.max()
+    assert np.max(np.abs(z[sel])) < 4.0
+
+
+def test_batch_and_history_uncertainties_agree(oracle):
+    ph = homogeneous((8, 8, 16), 0.5)
+    src = centred(ph, Source(PHOTON, e=2.0, wx=4.0, wy=4.0))
+    n = 40000
+    phys = Physics(ecut=0.2, pcut=0.01, n_batches=32)
+    res = oracle.run((WATER,), ph, src, phys, seed=12, n_hist=n)
+    d, dd = oracle.dose(res, ph)
+    sb = oracle.batch_sigma(res, ph, n)
+    sel = d > 0.3 * d.max()
+    ratio = sb[sel] / dd[sel]
+    # K = 32 batches: the batch estimate scatters by about 1/sqrt(2(K-1)) = 13%
+    assert abs(np.mean(ratio) - 1.0) < 0.05
+    assert np.array_equal(res.eb.sum(axis=0) > 0, res.e1 > 0)
+    assert np.allclose(res.eb.sum(axis=0), res.e1, rtol=1e-12, atol=0)
+
+
+def test_history_ranges_add_up(oracle):
+    ph = homogeneous((8, 8, 8), 0.5)
+    src = centred(ph, Source(PHOTON, e=3.0, wx=2.0, wy=2.0))
+    phys = Physics(ecut=0.2, pcut=0.01, n_batches=4)
+    full = oracle.run((WATER,), ph, src, phys, seed=13, n_hist=3000)
+    a = oracle.run((WATER,), ph, src, phys, seed=13, n_hist=3000, h_begin=0, h_end=1234)
+    b = oracle.run((WATER,), ph, src, phys, seed=13, n_hist=3000, h_begin=1234, h_end=3000)
+    assert np.allclose(a.e1 + b.e1, full.e1, rtol=1e-12, atol=1e-15)
+    assert np.allclose(a.eb + b.eb, full.eb, rtol=1e-12, atol=1e-15)
+    again = oracle.run((WATER,), ph, src, phys, seed=13, n_hist=3000)
+    assert np.array_equal(again.e1, full.e1)
+    other = oracle.run((WATER,), ph, src, phys, seed=14, n_hist=3000)
+    assert not np.array_equal(other.e1, full.e1)
+
+
+def test_degenerate_inputs(oracle):
+    ph = homogeneous((4, 4, 4), 0.5)
+    phys = Physics(ecut=0.2, pcut=0.01, n_batches=2)
+    # no histories
+    r = oracle.run((WATER,), ph, centred(ph, Source(PHOTON, e=1.0)), phys, seed=1, n_hist=0)
+    assert r.e1.sum() == 0 and r.stats["e_in"] == 0
+    # beam entirely outside the phantom: everything escapes
+    r = oracle.run((WATER,), ph, Source(PHOTON, e=1.0, cx=-5, cy=1, wx=1, wy=1), phys, seed=1, n_hist=100)
+    assert r.e1.sum() == 0 and r.stats["e_esc"] == pytest.approx(100.0)
+    # sub-cutoff primaries deposit where they enter (z = 0 layer)
+    r = oracle.run((WATER,), ph, centred(ph, Source(ELECTRON, e=0.1)), phys, seed=1, n_hist=50)
+    assert r.e1[0].sum() == pytest.approx(5.0) and r.e1[1:].sum() == 0
+    # vacuum: no interactions at all
+    vac = homogeneous((4, 4, 4), 0.5, density=0.0)
+    r = oracle.run((WATER,), vac, centred(vac, Source(PHOTON, e=1.0)), phys, seed=1, n_hist=100)
+    assert r.e1.sum() == 0 and r.stats["e_esc"] == pytest.approx(100.0)
+    r = oracle.run((WATER,), vac, centred(vac, Source(ELECTRON, e=1.0)), phys, seed=1, n_hist=100)
+    assert r.e1.sum() == 0 and r.stats["e_esc"] == pytest.approx(100.0)
+    # invalid inputs are rejected
+    with pytest.raises(ValueError):
+        oracle.run((WATER,), ph, centred(ph, Source(PHOTON, e=40.0)), phys, seed=1, n_hist=10)
+    bad = homogeneous((4, 4, 4), 0.5, material_index=3)
+    with pytest.raises(ValueError):
+        oracle.run((WATER,), bad, centred(bad, Source(PHOTON, e=1.0)), phys, seed=1, n_hist=10)
+
+
+def test_first_events_follow_exponential(oracle):
+    ph = homogeneous((4, 4, 400), 0.5)
+    src = centred(ph, Source(PHOTON, e=1.0, wx=0.5, wy=0.5))
+    xyz, nu = oracle.first_events((WATER,), ph, src, Physics(test_mode=1), seed=3, h_begin=0, h_end=50000)
+    z = xyz[:, 2]
+    assert np.all(np.isfinite(z))          # 200 cm of water: escape probability 7e-7
+    mu = mu_tot(oracle, WATER, 1.0)
+    assert np.mean(z) == pytest.approx(1 / mu, rel=4 / np.sqrt(50000))
+    assert np.all(nu >= 6) and np.all(nu % 2 == 0)   # 4 source words + 2 per event
