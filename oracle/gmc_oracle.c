@@ -113,6 +113,10 @@ static void stream_init(stream_t* s, const uint32_t key[2], uint32_t hist, uint6
   s->hist = hist; s->path = path; s->n = n; s->have = 0;
 }
 
+/* Every photon event and every electron step starts at the next block
+ * boundary of the particle's stream. */
+static void stream_align(stream_t* s) { s->n = (s->n + 3u) & ~3u; }
+
 static uint32_t stream_word(stream_t* s) {
   uint32_t id = s->n >> 2;
   if (!s->have || s->blk_id != id) {
@@ -640,6 +644,7 @@ static void move(part_t* p, double s) {
 static void photon_run(ctx_t* c, part_t* p) {
   stream_t s; stream_init(&s, c->key, c->hist, p->path, p->n);
   for (;;) {
+    stream_align(&s);
     double e = p->e;
     double muh = c->mu_hat[ebin(e)];
     if (!(muh > 0.0)) { escape(c, e); return; }
@@ -719,6 +724,7 @@ static void photon_run(ctx_t* c, part_t* p) {
 static void electron_run(ctx_t* c, part_t* p) {
   stream_t s; stream_init(&s, c->key, c->hist, p->path, p->n);
   for (;;) {
+    stream_align(&s);
     double t = p->e;
     if (!inside(c, p->x)) { escape(c, t); return; }
     int ix, iy, iz;
