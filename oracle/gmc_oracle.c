@@ -546,7 +546,7 @@ typedef struct {
   double ecut, pcut, kcut, kc, esmax;
   int mode;
   double mu_hat[NE], sig_hat[NE];
-  double lx, ly, lz, dvox_min;
+  double lx, ly, lz, skin;
   uint32_t key[2];
   uint32_t hist;
   double* tmp;
@@ -578,6 +578,32 @@ static size_t voxel_of(const ctx_t* c, const double* x, int* ix, int* iy, int* i
   if (k >= p->nz) k = p->nz - 1;
   if (ix) { *ix = i; *iy = j; *iz = k; }
   return ((size_t)k * p->ny + j) * p->nx + i;
+}
+
+/* [reading] Voxel of an electron: each coordinate is first advanced by a skin
+ * of 1e-4 voxel widths in the direction of travel, so a point that a hinge
+ * leaves a hair short of a face it is moving towards already belongs to the
+ * voxel beyond it.  Forward-peaked deflections pile such shortfalls up near
+ * zero; without the skin the step count would depend on how finely the
+ * arithmetic resolves them.  Returns 0 when the advanced point is outside the
+ * phantom (the electron escapes). */
+static int electron_voxel(const ctx_t* c, const double* x, const double* d, int* ix, int* iy, int* iz, size_t* v) {
+  const orc_phantom* p = c->ph;
+  double ext[3] = { c->lx, c->ly, c->lz };
+  double del[3] = { p->dx, p->dy, p->dz };
+  int n[3] = { p->nx, p->ny, p->nz };
+  int idx[3];
+  for (int a = 0; a < 3; ++a) {
+    double q = x[a] + (d[a] > 0.0 ? c->skin : (d[a] < 0.0 ? -c->skin : 0.0));
+    if (!(q >= 0.0 && q < ext[a])) return 0;
+    int i = (int)floor(q / del[a]);
+    if (i < 0) i = 0;
+    if (i >= n[a]) i = n[a] - 1;
+    idx[a] = i;
+  }
+  *ix = idx[0]; *iy = idx[1]; *iz = idx[2];
+  *v = ((size_t)idx[2] * p->ny + idx[1]) * p->nx + idx[0];
+  return 1;
 }
 
 /* d_vox of Eq. 4: distance along d to the boundary of voxel (i, j, k). */
@@ -726,9 +752,9 @@ static void electron_run(ctx_t* c, part_t* p) {
   for (;;) {
     stream_align(&s);
     double t = p->e;
-    if (!inside(c, p->x)) { escape(c, t); return; }
     int ix, iy, iz;
-    size_t v0 = voxel_of(c, p->x, &ix, &iy, &iz);
+    size_t v0;
+    if (!electron_voxel(c, p->x, p->d, &ix, &iy, &iz, &v0)) { escape(c, t); return; }
     if (t < c->ecut) { deposit(c, v0, t); return; }
     double rho0 = c->ph->rho[v0];
     const mat_t* m0 = &c->mats[c->ph->mat[v0]];
@@ -737,7 +763,7 @@ static void electron_run(ctx_t* c, part_t* p) {
     double uh = next_u(&s);
     double ehard = (c->mode == 2 || !(sh > 0.0)) ? INFINITY : -log(uh) / sh;
     double dv = dist_boundary(c, p->x, p->d, ix, iy, iz);
-    if (dv < c->dvox_min) dv = c->dvox_min;
+    if (dv < c->skin) dv = c->skin;
     double emax = (c->esmax > 0.0 && rho0 > 0.0) ? c->esmax / rho0 : INFINITY;
     double es = dv;
     int hard = 0;
@@ -763,10 +789,11 @@ static void electron_run(ctx_t* c, part_t* p) {
     deposit(c, v0, de);
     p->e = t1;
     move(p, (1.0 - zeta) * es);
-    if (!inside(c, p->x)) { escape(c, t1); return; }
+    int jx, jy, jz;
+    size_t v1;
+    if (!electron_voxel(c, p->x, p->d, &jx, &jy, &jz, &v1)) { escape(c, t1); return; }
     if (!hard) continue;
     double ur = next_u(&s);
-    size_t v1 = voxel_of(c, p->x, 0, 0, 0);
     double rho1 = c->ph->rho[v1];
     const mat_t* m1 = &c->mats[c->ph->mat[v1]];
     double sm = rho1 * sig_moller(m1, t1, c->kcut);
@@ -821,7 +848,7 @@ static int ctx_setup(ctx_t* c, const orc_material* mats, int n_mat, const orc_ph
   c->lx = ph->nx * ph->dx; c->ly = ph->ny * ph->dy; c->lz = ph->nz * ph->dz;
   double dmin = ph->dx < ph->dy ? ph->dx : ph->dy;
   if (ph->dz < dmin) dmin = ph->dz;
-  c->dvox_min = 1e-4 * dmin;
+  c->skin = 1e-4 * dmin;
   make_key(seed, beam, c->key);
   if (build_majorants(c->mats, n_mat, ph, c->kcut, c->kc, c->mu_hat, c->sig_hat)) return -2;
   c->tmp = (double*)calloc(nv, sizeof(double));
