@@ -1,0 +1,166 @@
+/*
+ * gpumcd.h -- C ABI of the MI355X (gfx950) coupled photon-electron Monte Carlo
+ * dose engine.  The transport follows Hissoiny et al., "GPUMCD: a new
+ * GPU-oriented Monte Carlo dose calculation platform": analogue photon
+ * transport with Woodcock tracking (Sec. II.A, Eqs. 1-3), class II
+ * condensed-history electrons with CSDA loss, random-hinge multiple
+ * scattering and hard Moller / bremsstrahlung events (Sec. II.B, Eqs. 4-8),
+ * particle arrays per type processed in alternating passes (Sec. II.C.2-3),
+ * and the dose / uncertainty estimators of Sec. II.D (Eqs. 11-13).
+ *
+ * Conventions
+ *  - Units: cm, g/cm^3, MeV.  Dose is Gy per history; sigma is the absolute
+ *    one-standard-deviation uncertainty of that mean, same unit.
+ *  - Volumes are [nz][ny][nx] with x fastest.  Beams enter at z = 0 along +z.
+ *  - Every function returns GMC_OK (0) or a negative GMC_E* code; on error
+ *    gmc_last_error() describes it.  No exception crosses the ABI.
+ *  - A context is not thread safe.  All work runs on the context's HIP
+ *    stream; gmc_run_* return after their results are complete.
+ *  - Inputs are copied: the caller may free them when the call returns.
+ *    Outputs go to caller-owned buffers, host or device memory according to
+ *    the *_ptr_kind argument.
+ *  - Determinism: the same (phantom, tables, source incl. beam_id, n, seed)
+ *    gives bit-identical dose and sigma on every run and for every tuning,
+ *    because every particle draws from its own counter-based stream and the
+ *    tallies are integer sums.
+ */
+#ifndef GPUMCD_H
+#define GPUMCD_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GMC_OK = 0,
+  GMC_EINVAL = -1,     /* invalid argument: sizes, ids, energies, cutoffs */
+  GMC_ENOMEM = -2,     /* device allocation failed */
+  GMC_EDEVICE = -3,    /* HIP runtime error */
+  GMC_ENOTFOUND = -4,  /* unknown tables / phantom id */
+  GMC_EBUSY = -5,
+  GMC_EOVERFLOW = -6,  /* an integer tally could overflow, or a queue overflowed */
+  GMC_EINTERNAL = -7   /* broken invariant (energy ledger, queue accounting) */
+};
+
+enum { GMC_HOST = 0, GMC_DEVICE = 1 };          /* pointer kinds */
+enum { GMC_PHOTON = 0, GMC_ELECTRON = 1 };
+enum { GMC_MONO = 0, GMC_TRIANGULAR = 1 };
+
+typedef struct gmc_context gmc_context;
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * run on (e.g. torch.cuda.current_stream().cuda_stream) or NULL for a stream
+ * owned by the context.  *out receives the context. */
+int gmc_create(int device, void* hip_stream, gmc_context** out);
+/* Free every device allocation of the context.  NULL is accepted. */
+void gmc_destroy(gmc_context* ctx);
+/* Text of the last error on this context; valid until the next call. */
+const char* gmc_last_error(const gmc_context* ctx);
+
+/* Effective-element material (Sec. II.A Eq. 2 uses N_A/A; the electron
+ * coefficients use Z/A, Z and the mean excitation energy I). */
+typedef struct { double z_over_a, z_eff, i_ev; } gmc_material;
+
+/* Physics settings.  Cutoffs are kinetic energies (MeV): electrons below
+ * ecut_mev and photons below pcut_mev deposit locally (P_cut of Sec. II.A).
+ * kcut_mev (Moller, K_cut of Eq. 6) and kc_mev (bremsstrahlung) default to
+ * ecut and pcut when <= 0.  esmax_gcm2 is the user step bound e_s-max of
+ * Eq. 4 in g/cm^2 (<= 0: none).  n_batches is K of the batch uncertainty
+ * estimate (default 32 when <= 0).  test_mode: 0 full transport; 1 photons
+ * deposit their energy at their first real interaction; 2 electrons move in
+ * straight lines with CSDA loss only (no hard events, no deflection). */
+typedef struct {
+  double ecut_mev, pcut_mev, kcut_mev, kc_mev, esmax_gcm2;
+  int n_batches;
+  int test_mode;
+} gmc_physics;
+
+/* Build the FP32 log-energy tables (cross sections, restricted stopping
+ * power, transport mean free path, screening inversion) for `n_mat`
+ * materials (1..8) in double precision and upload them.  *tables_id
+ * receives a handle. */
+int gmc_load_tables(gmc_context* ctx, const gmc_material* mats, int n_mat, const gmc_physics* phys,
+                    int32_t* tables_id);
+
+/* Upload a voxel phantom: densities (g/cm^3, >= 0, finite) and material
+ * indices (< n_mat of the tables used with it), both nx*ny*nz, x fastest,
+ * in host or device memory per ptr_kind (Sec. II.C.2: composition and
+ * density arrays).  *phantom_id receives a handle. */
+int gmc_load_phantom(gmc_context* ctx, int nx, int ny, int nz, double dx_cm, double dy_cm, double dz_cm,
+                     const float* density_gcc, const uint8_t* material_id, int ptr_kind, int32_t* phantom_id);
+
+/* Release a tables or phantom handle. */
+int gmc_release(gmc_context* ctx, int32_t id);
+
+/* Parallel beam along +z entering at z = 0 (Sec. II.C.2, initParticle):
+ * position uniform over the field of full widths (wx, wy) centred at
+ * (cx, cy); energy monoenergetic (e_mev) or triangular on
+ * [e_lo, e_hi] with mode e_mode (inverse CDF).  beam_id enters the random
+ * stream key, so beamlets with different ids draw independent streams. */
+typedef struct {
+  int particle;
+  int spectrum;
+  double e_mev, e_lo, e_mode, e_hi;
+  double cx_cm, cy_cm, wx_cm, wy_cm;
+  uint32_t beam_id;
+} gmc_source;
+
+/* Per-run statistics.  Energies in MeV; the integer ledger residual (in units
+ * of 2^-27 MeV) is incident - deposited - escaped - pair rest energy and is
+ * zero by construction.  t_photon_pass_s / t_electron_pass_s are the summed
+ * durations of the pass kernels, timed with HIP events on the context stream,
+ * over n_photon_launches / n_electron_launches launches. */
+typedef struct {
+  double t_total_s, t_device_s;
+  double e_in_mev, e_dep_mev, e_esc_mev, e_sink_mev;
+  uint64_t n_hist, n_photon_events, n_fictitious, n_e_steps, n_hard, n_secondaries,
+           n_majorant_violations, n_passes;
+  int64_t ledger_residual_lsb;
+  double t_photon_pass_s, t_electron_pass_s;
+  uint64_t n_photon_launches, n_electron_launches;
+} gmc_run_stats;
+
+/* Optional tuning of the pass kernels; NULL selects the defaults.
+ *   events_per_visit: events a particle may take per kernel visit before it
+ *     is requeued (the N of the stream-compaction scheme, Sec. II.C.3);
+ *   secondaries_per_visit: secondaries a particle may create per visit;
+ *   chunk: primaries admitted per admission step;
+ *   wg_size: threads per workgroup (64..256, multiple of 64). */
+typedef struct { int events_per_visit, secondaries_per_visit, chunk, wg_size; } gmc_tuning;
+
+/* Transport n_histories histories of one beam (the plain form: one beam per
+ * sequence of alternating electron and photon passes until both particle
+ * arrays are empty, Sec. II.C.2) and write the dose per history and its
+ * batch uncertainty per voxel.  seed keys the random streams.  Outputs are
+ * nx*ny*nz doubles in host or device memory per out_ptr_kind; sigma and
+ * stats may be NULL.  n_histories must be < 2^32 and at least n_batches. */
+int gmc_run_beam(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const gmc_source* src,
+                 uint64_t n_histories, uint64_t seed, double* dose_gy_per_hist, double* sigma_gy_per_hist,
+                 int out_ptr_kind, const gmc_tuning* tuning, gmc_run_stats* stats);
+
+/* ---------------------------------------------------------------- checks */
+/* Words n0 .. n0+count-1 of the stream (seed, beam, hist, path), computed
+ * on the device; out_words is host memory. */
+int gmc_rng_words(gmc_context* ctx, uint64_t seed, uint32_t beam, uint32_t hist, uint64_t path, uint32_t n0,
+                  int count, uint32_t* out_words);
+
+/* Evaluate the device-resident tables by their device interpolation at n
+ * energies (host arrays).  which: 0 mu_C, 1 mu_C+mu_pe, 2 mu_total (per unit
+ * density, cm^2/g), 3 restricted stopping power L, 4 Sigma_Moller,
+ * 5 Sigma_brems, 6 1/lambda_1 (cm^2/g or MeV cm^2/g), 7 Wentzel screening A
+ * for G1 = energies[i]. */
+int gmc_table_eval(gmc_context* ctx, int32_t tables_id, int which, int mat, const double* energies, int n,
+                   double* out);
+
+/* Per-history first real photon interaction of histories [h_begin, h_end)
+ * of a photon beam, on the device: xyz (3 floats per history, NaN if the
+ * photon escaped first) and the number of stream words used up to it. */
+int gmc_first_events(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const gmc_source* src,
+                     uint64_t seed, uint32_t h_begin, uint32_t h_end, float* out_xyz, uint32_t* out_nused);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,139 @@
+// gmc_internal.hpp -- device-visible data layout shared by the host runtime and
+// the gfx950 kernels of the transport engine.
+//
+// Memory layout in HBM (all linear, no textures):
+//  * phantom: one uint2 per voxel {float bits of density, material index},
+//    [nz][ny][nx], so a voxel costs one 8-byte gather (Sec. II.C.2 keeps
+//    composition and density in two 3D textures);
+//  * tables: FP32 nodes on a log-energy grid, one float4 per (material, node),
+//    staged into LDS by each workgroup;
+//  * particles: structure-of-arrays queues, 48 bytes per particle;
+//  * tallies: uint64 fixed-point energy (2^-27 MeV) per (batch, voxel).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gmc {
+
+constexpr int kNE = 1024;               // log-energy nodes on [kEmin, kEmax]
+constexpr double kEmin = 1.0e-3;        // MeV
+constexpr double kEmax = 32.0;          // MeV (the fixed-point energy range)
+constexpr int kNms = 512;               // nodes of the multiple-scattering screening table
+constexpr int kMaxMat = 8;
+constexpr int kMaxBatches = 1024;
+constexpr double kLsbMeV = 1.0 / 134217728.0;   // 2^-27 MeV per energy unit
+
+struct DevPhantom {
+  const uint2* vox;
+  int nx, ny, nz;
+  float dx, dy, dz;
+  float idx, idy, idz;
+  float lx, ly, lz;
+  float skin;         // 1e-4 of the smallest voxel width
+};
+
+struct DevTables {
+  const float4* ph;     // [n_mat][kNE] {mu_C, mu_C + mu_pe, mu_total, 0} per unit density, cm^2/g
+  const float4* el;     // [n_mat][kNE] {L, Sigma_M, Sigma_B, 1/lambda_1} per unit density
+  const float* ms;      // [kNms] ln A at evenly spaced logit(G1)
+  const float* maj_g;   // [kNE] photon majorant per grid bin, cm^-1
+  const float* maj_e;   // [kNE] electron hard-event majorant per grid bin, cm^-1
+  int n_mat;
+  float lg2_emin;       // log2(kEmin)
+  float inv_h2;         // grid nodes per unit of log2 E
+  float ms_y0;          // logit(G1) of the first screening node
+  float ms_inv_dy;      // nodes per unit of logit(G1)
+};
+
+struct DevCuts {
+  uint32_t ecut_lsb, pcut_lsb;   // transport cutoffs in energy units
+  uint32_t kcut2_lsb, kc_lsb;    // Moller needs T > 2 K_cut; brems needs T > k_c
+  uint32_t two_mc2_lsb;          // pair threshold and rest-energy sink
+  float kcut, kc;                // MeV
+  float esmax_gcm2;              // <= 0: none
+  float emin;                    // lowest table energy, MeV
+  int mode;                      // 0 full, 1 photon first collision, 2 electron CSDA straight-ahead
+};
+
+// Structure-of-arrays particle queue.
+struct DevQueue {
+  float *x, *y, *z, *u, *v, *w;
+  uint32_t *e;       // kinetic energy, units of 2^-27 MeV
+  uint32_t *hist;    // history index
+  uint32_t *plo, *phi;  // stream path
+  uint32_t *n;       // stream word counter
+  uint32_t *beam;    // index into the beam table
+  uint32_t cap;
+};
+
+struct DevBeam {
+  uint32_t key0, key1;          // Philox key (seed lo, seed hi ^ beam id)
+  uint32_t nhist;               // histories of the beam (batch assignment)
+  uint32_t nbatch;              // K
+  unsigned long long* tally;    // [K][nvox]
+};
+
+enum CounterIndex {
+  C_E_IN = 0, C_E_ESC, C_E_SINK, C_PH_EVENTS, C_FICT, C_VIOL, C_E_STEPS, C_HARD, C_SEC, C_OVERFLOW, C_COUNT
+};
+
+struct PassArgs {
+  DevPhantom ph;
+  DevTables tab;
+  DevCuts cut;
+  DevQueue work;
+  uint32_t n_work;
+  DevQueue same;          // survivors and same-type secondaries
+  uint32_t* same_count;
+  DevQueue other;         // other-type secondaries
+  uint32_t* other_count;
+  const DevBeam* beams;
+  unsigned long long* ctr;   // [C_COUNT]
+  int max_events;
+  int max_secondaries;
+};
+
+struct SourceArgs {
+  DevPhantom ph;
+  DevCuts cut;
+  DevQueue out;
+  uint32_t* out_count;
+  const DevBeam* beams;
+  unsigned long long* ctr;
+  uint32_t beam;
+  uint32_t h0, count;
+  int spectrum;
+  uint32_t e_lsb;               // monoenergetic energy
+  float e_lo, e_mode, e_hi;     // triangular spectrum
+  float cx, cy, wx, wy;
+  int particle;
+};
+
+struct FinalizeArgs {
+  const unsigned long long* tally;  // [K][nvox]
+  const uint2* vox;
+  const double* nk;                 // histories per batch
+  uint32_t nvox, K;
+  double n_total, conv;             // conv = LSB * J/MeV / (V * 1e-3 kg/g)
+  double* dose;
+  double* sigma;                    // may be null
+  unsigned long long* dep_total;
+};
+
+// Launchers (gmc_kernels.hip).
+size_t photon_lds_bytes(int n_mat);
+size_t electron_lds_bytes(int n_mat);
+hipError_t launch_source(const SourceArgs& a, hipStream_t s);
+hipError_t launch_photon_pass(const PassArgs& a, int grid, int block, hipStream_t s);
+hipError_t launch_electron_pass(const PassArgs& a, int grid, int block, hipStream_t s);
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
+hipError_t launch_rng_words(uint32_t key0, uint32_t key1, uint32_t hist, uint32_t plo, uint32_t phi, uint32_t n0,
+                            int count, uint32_t* out, hipStream_t s);
+hipError_t launch_table_eval(const DevTables& t, int which, int mat, const float* e, int n, float* out,
+                             hipStream_t s);
+hipError_t launch_first_events(const PassArgs& a, const SourceArgs& src, float* xyz, uint32_t* nused,
+                               hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
+int max_resident_blocks(int kernel, int block, size_t lds);
+
+}  // namespace gmc

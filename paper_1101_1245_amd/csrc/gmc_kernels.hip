@@ -1,0 +1,679 @@
+// gmc_kernels.hip -- gfx950 kernels of the coupled photon-electron transport.
+//
+// A pass kernel transports the particles of ONE type (Sec. II.C.2: photons and
+// electrons are never simulated together, which removes the divergence of
+// the photon-electron coupling).  Each lane takes a particle, runs events
+// until it dies, reaches the per-visit event cap (the N of Sec. II.C.3) or its
+// per-visit secondary budget, then takes the next particle of its stride
+// (lane-level refill, the "pool" idea of Sec. II.C.3 inside one launch).
+// Secondaries and survivors are appended to structure-of-arrays queues with
+// one atomic per wavefront; deposits are uint64 fixed-point atomics, so the
+// dose is an exact integer sum independent of thread order.  Cross-section
+// and stopping-power tables are staged in LDS by every workgroup.
+#include "gmc_device.hpp"
+
+namespace gmc {
+using namespace dev;
+
+// ------------------------------------------------------------------ source
+// Primary of history h (Sec. II.C.2, initParticle): parallel beam along +z at
+// z = 0, position uniform over the field, energy monoenergetic or triangular.
+// Uses the first block (words 0-3) of the history's root stream.
+struct Primary { float x, y; uint32_t e; };
+
+__device__ __forceinline__ Primary sample_primary(const SourceArgs& a, const DevBeam& b, uint32_t h) {
+  const Block blk = philox(0u, 0u, 0u, h, b.key0, b.key1);
+  const float u0 = to_uniform(blk.w0), u1 = to_uniform(blk.w1), u2 = to_uniform(blk.w2);
+  Primary p;
+  p.x = a.cx + (u0 - 0.5f) * a.wx;
+  p.y = a.cy + (u1 - 0.5f) * a.wy;
+  if (a.spectrum == 1) {
+    const float lo = a.e_lo, md = a.e_mode, hi = a.e_hi;
+    const float fc = (md - lo) / (hi - lo);
+    const float e = (u2 < fc) ? lo + sqrtf(u2 * (hi - lo) * (md - lo)) : hi - sqrtf((1.0f - u2) * (hi - lo) * (hi - md));
+    p.e = to_lsb(e);
+  } else {
+    p.e = a.e_lsb;
+  }
+  return p;
+}
+
+__global__ void __launch_bounds__(256) k_source(SourceArgs a) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < a.count;
+  const DevBeam b = a.beams[a.beam];
+  const uint32_t h = a.h0 + i;
+  Primary p{0.0f, 0.0f, 0u};
+  if (valid) p = sample_primary(a, b, h);
+  const bool in = valid && inside(a.ph, p.x, p.y, 0.0f);
+  const uint32_t cut = a.particle == 0 ? a.cut.pcut_lsb : a.cut.ecut_lsb;
+  const bool push = in && p.e >= cut;
+  unsigned long long esc = (valid && !in) ? p.e : 0ull;
+  if (in && !push) {
+    // a sub-cutoff primary deposits where it enters
+    int ix, iy, iz;
+    const int v = voxel(a.ph, p.x, p.y, 0.0f, ix, iy, iz);
+    const uint32_t kb = (uint32_t)(((uint64_t)h * b.nbatch) / b.nhist);
+    atomicAdd(b.tally + (size_t)kb * (size_t)(a.ph.nx * a.ph.ny * a.ph.nz) + v, (unsigned long long)p.e);
+  }
+  const Slots sl = wave_reserve(a.out_count, push, false);
+  if (push) {
+    if (sl.s0 < a.out.cap) put(a.out, sl.s0, p.x, p.y, 0.0f, 0.0f, 0.0f, 1.0f, p.e, h, 0u, 0u, 4u, a.beam);
+    else atomicAdd(&a.ctr[C_OVERFLOW], 1ull);
+  }
+  const unsigned long long ein = wave_sum(valid ? (unsigned long long)p.e : 0ull);
+  const unsigned long long es = wave_sum(esc);
+  if (lane_id() == 0) {
+    if (ein) atomicAdd(&a.ctr[C_E_IN], ein);
+    if (es) atomicAdd(&a.ctr[C_E_ESC], es);
+  }
+}
+
+// ------------------------------------------------------------ lane state
+struct Lane {
+  float x, y, z, u, v, w;
+  uint32_t e, beam;
+  Stream s;
+  unsigned long long* tally;   // this history's batch slice of its beam's tally
+};
+
+__device__ __forceinline__ void load_lane(Lane& L, const DevQueue& q, uint32_t i, const DevBeam* beams,
+                                          uint32_t nvox) {
+  L.x = q.x[i]; L.y = q.y[i]; L.z = q.z[i];
+  L.u = q.u[i]; L.v = q.v[i]; L.w = q.w[i];
+  L.e = q.e[i];
+  L.beam = q.beam[i];
+  L.s.hist = q.hist[i]; L.s.plo = q.plo[i]; L.s.phi = q.phi[i]; L.s.n = q.n[i];
+  const DevBeam b = beams[L.beam];
+  L.s.k0 = b.key0; L.s.k1 = b.key1;
+  const uint32_t kb = (uint32_t)(((uint64_t)L.s.hist * b.nbatch) / b.nhist);
+  L.tally = b.tally + (size_t)kb * nvox;
+}
+
+__device__ __forceinline__ void store_lane(const Lane& L, const DevQueue& q, uint32_t slot) {
+  put(q, slot, L.x, L.y, L.z, L.u, L.v, L.w, L.e, L.s.hist, L.s.plo, L.s.phi, L.s.n, L.beam);
+}
+
+struct Child { float u, v, w; uint32_t e, plo, phi; };
+
+__device__ __forceinline__ void deposit(unsigned long long* tally, int v, uint32_t e) {
+  if (e) atomicAdd(tally + v, (unsigned long long)e);
+}
+
+// One photon flight and interaction decision (Sec. II.A, Eqs. 1-3): free path
+// with the majorant, then one uniform against the cumulative Compton,
+// photoelectric, pair partials of the voxel; fictitious otherwise.
+enum { PH_ESCAPE = 0, PH_FICT = 1, PH_COMPTON = 2, PH_PHOTO = 3, PH_PAIR = 4 };
+
+__device__ __forceinline__ int photon_flight(Lane& L, const PassArgs& a, const float4* tab, const float* majg,
+                                             int& v0, uint32_t& viol) {
+  L.s.align();
+  const float ef = (float)L.e * kLsbF;
+  const TPos p = tpos(a.tab, ef);
+  const float muh = majg[p.i];
+  if (!(muh > 0.0f)) return PH_ESCAPE;
+  const float d = -__logf(L.s.uniform()) / muh;
+  L.x = fmaf(d, L.u, L.x);
+  L.y = fmaf(d, L.v, L.y);
+  L.z = fmaf(d, L.w, L.z);
+  if (!inside(a.ph, L.x, L.y, L.z)) return PH_ESCAPE;
+  int ix, iy, iz;
+  v0 = voxel(a.ph, L.x, L.y, L.z, ix, iy, iz);
+  const uint2 vx = a.ph.vox[v0];
+  const float rho = __uint_as_float(vx.x);
+  const float4 c = lerp4(tab, (int)vx.y * kNE, p);
+  const float mc = rho * c.x, mcp = rho * c.y;
+  const float mt = (L.e > a.cut.two_mc2_lsb) ? rho * c.z : mcp;
+  if (mt > muh) ++viol;
+  const float r = L.s.uniform() * muh;
+  if (r >= mt) return PH_FICT;
+  if (r < mc) return PH_COMPTON;
+  if (r < mcp) return PH_PHOTO;
+  return PH_PAIR;
+}
+
+// ------------------------------------------------------------ photon pass
+__global__ void __launch_bounds__(256) k_photon_pass(PassArgs a) {
+  extern __shared__ float4 smem[];
+  const int nt = a.tab.n_mat * kNE;
+  for (int i = threadIdx.x; i < nt; i += blockDim.x) smem[i] = a.tab.ph[i];
+  float* majg = reinterpret_cast<float*>(smem + nt);
+  for (int i = threadIdx.x; i < kNE; i += blockDim.x) majg[i] = a.tab.maj_g[i];
+  __syncthreads();
+
+  const uint32_t nvox = (uint32_t)(a.ph.nx * a.ph.ny * a.ph.nz);
+  const uint32_t stride = gridDim.x * blockDim.x;
+  uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
+  Lane L;
+  bool have = item < a.n_work;
+  if (have) load_lane(L, a.work, item, a.beams, nvox);
+  int events = 0, pushes = 0;
+  unsigned long long acc_esc = 0, acc_sink = 0;
+  uint32_t c_ev = 0, c_fict = 0, c_viol = 0, c_sec = 0;
+
+  while (__any(have)) {
+    int nchild = 0;
+    Child c0, c1;
+    bool surv = false;
+    if (have) {
+      int v0 = 0;
+      const int kind = photon_flight(L, a, smem, majg, v0, c_viol);
+      ++c_ev;
+      if (kind == PH_ESCAPE) {
+        acc_esc += L.e;
+        have = false;
+      } else if (kind == PH_FICT) {
+        ++c_fict;
+      } else if (a.cut.mode == 1) {
+        deposit(L.tally, v0, L.e);
+        have = false;
+      } else if (kind == PH_COMPTON) {
+        // scattered photon plus recoil electron (momentum conservation)
+        const float ef = (float)L.e * kLsbF;
+        float eps, cost;
+        sample_kn(ef / kMc2, L.s, eps, cost);
+        const float phi = kTwoPi * L.s.uniform();
+        float nu = L.u, nv = L.v, nw = L.w;
+        rotate(nu, nv, nw, cost, phi);
+        const uint32_t e1 = min(to_lsb(eps * ef), L.e);
+        const uint32_t te = L.e - e1;
+        if (te >= a.cut.ecut_lsb) {
+          const float e1f = (float)e1 * kLsbF;
+          float pu = ef * L.u - e1f * nu, pv = ef * L.v - e1f * nv, pw = ef * L.w - e1f * nw;
+          const float inv = rsqrtf(pu * pu + pv * pv + pw * pw);
+          c0.u = pu * inv; c0.v = pv * inv; c0.w = pw * inv;
+          c0.e = te;
+          child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
+          nchild = 1;
+        } else {
+          deposit(L.tally, v0, te);
+        }
+        L.u = nu; L.v = nv; L.w = nw;
+        L.e = e1;
+        if (e1 < a.cut.pcut_lsb) {
+          deposit(L.tally, v0, e1);
+          have = false;
+        }
+      } else if (kind == PH_PHOTO) {
+        // one electron with the whole photon energy, Sauter direction
+        const float ef = (float)L.e * kLsbF;
+        const float cost = sample_sauter(ef, L.s);
+        const float phi = kTwoPi * L.s.uniform();
+        c0.u = L.u; c0.v = L.v; c0.w = L.w;
+        rotate(c0.u, c0.v, c0.w, cost, phi);
+        if (L.e >= a.cut.ecut_lsb) {
+          c0.e = L.e;
+          child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
+          nchild = 1;
+        } else {
+          deposit(L.tally, v0, L.e);
+        }
+        have = false;
+      } else {
+        // pair: two electrons, uniform split, opposite azimuths; 2 mc^2 to the sink
+        const uint32_t avail = L.e - a.cut.two_mc2_lsb;
+        const uint32_t t1 = min((uint32_t)fminf(L.s.uniform() * (float)avail, kMaxLsbF), avail);
+        const uint32_t t2 = avail - t1;
+        const float cs1 = pair_cos((float)t1 * kLsbF, L.s.uniform());
+        const float cs2 = pair_cos((float)t2 * kLsbF, L.s.uniform());
+        const float phi = kTwoPi * L.s.uniform();
+        acc_sink += a.cut.two_mc2_lsb;
+        c0.u = L.u; c0.v = L.v; c0.w = L.w;
+        rotate(c0.u, c0.v, c0.w, cs1, phi);
+        c1.u = L.u; c1.v = L.v; c1.w = L.w;
+        rotate(c1.u, c1.v, c1.w, cs2, phi + kPi);
+        if (t1 >= a.cut.ecut_lsb) {
+          c0.e = t1;
+          child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
+          nchild = 1;
+        } else {
+          deposit(L.tally, v0, t1);
+        }
+        if (t2 >= a.cut.ecut_lsb) {
+          c1.e = t2;
+          child_path(L.s.plo, L.s.phi, L.s.n, 1u, c1.plo, c1.phi);
+          if (nchild == 0) c0 = c1;   // keep the pushed children contiguous
+          ++nchild;
+        } else {
+          deposit(L.tally, v0, t2);
+        }
+        have = false;
+      }
+      pushes += nchild;
+      c_sec += nchild;
+      if (have) {
+        ++events;
+        if (events >= a.max_events || pushes + 2 > a.max_secondaries) {
+          surv = true;
+          have = false;
+        }
+      }
+    }
+    // secondary electrons to the electron queue, survivors back to the photon queue
+    {
+      const Slots sl = wave_reserve(a.other_count, nchild >= 1, nchild >= 2);
+      if (sl.any) {
+        const uint32_t hist = L.s.hist;
+        if (nchild >= 1) {
+          if (sl.s0 < a.other.cap) put(a.other, sl.s0, L.x, L.y, L.z, c0.u, c0.v, c0.w, c0.e, hist, c0.plo, c0.phi, 0u, L.beam);
+          else atomicAdd(&a.ctr[C_OVERFLOW], 1ull);
+        }
+        if (nchild >= 2) {
+          if (sl.s1 < a.other.cap) put(a.other, sl.s1, L.x, L.y, L.z, c1.u, c1.v, c1.w, c1.e, hist, c1.plo, c1.phi, 0u, L.beam);
+          else atomicAdd(&a.ctr[C_OVERFLOW], 1ull);
+        }
+      }
+      const Slots ss = wave_reserve(a.same_count, surv, false);
+      if (surv) {
+        if (ss.s0 < a.same.cap) store_lane(L, a.same, ss.s0);
+        else atomicAdd(&a.ctr[C_OVERFLOW], 1ull);
+      }
+    }
+    if (!have && item < a.n_work) {
+      item += stride;
+      if (item < a.n_work) {
+        load_lane(L, a.work, item, a.beams, nvox);
+        have = true;
+        events = 0;
+        pushes = 0;
+      }
+    }
+  }
+  const unsigned long long s_esc = wave_sum(acc_esc), s_sink = wave_sum(acc_sink);
+  const unsigned long long s_ev = wave_sum(c_ev), s_fict = wave_sum(c_fict), s_viol = wave_sum(c_viol),
+                           s_sec = wave_sum(c_sec);
+  if (lane_id() == 0) {
+    if (s_esc) atomicAdd(&a.ctr[C_E_ESC], s_esc);
+    if (s_sink) atomicAdd(&a.ctr[C_E_SINK], s_sink);
+    if (s_ev) atomicAdd(&a.ctr[C_PH_EVENTS], s_ev);
+    if (s_fict) atomicAdd(&a.ctr[C_FICT], s_fict);
+    if (s_viol) atomicAdd(&a.ctr[C_VIOL], s_viol);
+    if (s_sec) atomicAdd(&a.ctr[C_SEC], s_sec);
+  }
+}
+
+// ---------------------------------------------------------- electron pass
+// One condensed step per iteration (Sec. II.B.3): e_s = min{d_vox, e_s-max,
+// e_hard} (Eq. 4) with e_hard from the majorant at the step-start energy;
+// energy loss of Eq. 8 read with the factor s; random hinge at zeta e_s with
+// the deflection energy taken before or after the loss at random; the loss is
+// deposited in the step-start voxel; after the second leg a hard-event
+// candidate is accepted with Sigma(end)/Sigma_hat and split into Moller or
+// bremsstrahlung.
+__global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
+  extern __shared__ float4 smem[];
+  const int nt = a.tab.n_mat * kNE;
+  for (int i = threadIdx.x; i < nt; i += blockDim.x) smem[i] = a.tab.el[i];
+  float* maje = reinterpret_cast<float*>(smem + nt);
+  float* ms = maje + kNE;
+  for (int i = threadIdx.x; i < kNE; i += blockDim.x) maje[i] = a.tab.maj_e[i];
+  for (int i = threadIdx.x; i < kNms; i += blockDim.x) ms[i] = a.tab.ms[i];
+  __syncthreads();
+
+  const uint32_t nvox = (uint32_t)(a.ph.nx * a.ph.ny * a.ph.nz);
+  const uint32_t stride = gridDim.x * blockDim.x;
+  uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
+  Lane L;
+  bool have = item < a.n_work;
+  if (have) load_lane(L, a.work, item, a.beams, nvox);
+  int events = 0, pushes = 0;
+  unsigned long long acc_esc = 0;
+  uint32_t c_steps = 0, c_hard = 0, c_viol = 0, c_sec = 0;
+  const float emin = a.cut.emin;
+
+  while (__any(have)) {
+    int ctype = -1;   // 0 photon child, 1 electron child
+    Child c0;
+    bool surv = false;
+    if (have) {
+      L.s.align();
+      int ix, iy, iz, v0;
+      if (!electron_voxel(a.ph, L.x, L.y, L.z, L.u, L.v, L.w, ix, iy, iz, v0)) {
+        acc_esc += L.e;
+        have = false;
+      } else {
+        const uint2 vx = a.ph.vox[v0];
+        const float rho0 = __uint_as_float(vx.x);
+        const int base0 = (int)vx.y * kNE;
+        if (L.e < a.cut.ecut_lsb) {
+          deposit(L.tally, v0, L.e);
+          have = false;
+        } else {
+          ++c_steps;
+          const float tf = (float)L.e * kLsbF;
+          const TPos p0 = tpos(a.tab, tf);
+          const float sh = maje[p0.i];
+          const float uh = L.s.uniform();
+          const float ehard = (a.cut.mode == 2 || !(sh > 0.0f)) ? kInf : -__logf(uh) / sh;
+          const float dv = fmaxf(dist_boundary(a.ph, L.x, L.y, L.z, L.u, L.v, L.w, ix, iy, iz), a.ph.skin);
+          const float emax = (a.cut.esmax_gcm2 > 0.0f && rho0 > 0.0f) ? a.cut.esmax_gcm2 / rho0 : kInf;
+          float es = dv;
+          bool hard = false;
+          if (emax < es) es = emax;
+          if (ehard < es) { es = ehard; hard = true; }
+          const float4 t0 = lerp4(smem, base0, p0);
+          const float l0 = rho0 * t0.x;
+          const float tm = fmaxf(tf - 0.5f * es * l0, emin);
+          const float de = es * rho0 * lerp_x(smem, base0, tpos(a.tab, tm));
+          const float zeta = L.s.uniform();
+          const float s1 = zeta * es;
+          L.x = fmaf(s1, L.u, L.x);
+          L.y = fmaf(s1, L.v, L.y);
+          L.z = fmaf(s1, L.w, L.z);
+          const uint32_t dl = to_lsb(de);
+          if (dl >= L.e || L.e - dl < a.cut.ecut_lsb) {
+            deposit(L.tally, v0, L.e);
+            have = false;
+          } else {
+            const uint32_t e1 = L.e - dl;
+            const float t1f = (float)e1 * kLsbF;
+            const float coin = L.s.uniform();
+            const float ua = L.s.uniform(), uphi = L.s.uniform();
+            if (a.cut.mode != 2) {
+              const float il = coin < 0.5f ? t0.w : lerp_w(smem, base0, tpos(a.tab, t1f));
+              const float xx = es * rho0 * il;
+              const float g1 = -expm1f(-xx);
+              const float cost = wentzel_cos(a.tab, ms, g1, ua);
+              rotate(L.u, L.v, L.w, cost, kTwoPi * uphi);
+            }
+            deposit(L.tally, v0, dl);
+            L.e = e1;
+            const float s2 = (1.0f - zeta) * es;
+            L.x = fmaf(s2, L.u, L.x);
+            L.y = fmaf(s2, L.v, L.y);
+            L.z = fmaf(s2, L.w, L.z);
+            int jx, jy, jz, v1;
+            if (!electron_voxel(a.ph, L.x, L.y, L.z, L.u, L.v, L.w, jx, jy, jz, v1)) {
+              acc_esc += L.e;
+              have = false;
+            } else if (hard) {
+              const float ur = L.s.uniform();
+              const uint2 vy = a.ph.vox[v1];
+              const float rho1 = __uint_as_float(vy.x);
+              const float4 t1 = lerp4(smem, (int)vy.y * kNE, tpos(a.tab, t1f));
+              const float sm = (L.e > a.cut.kcut2_lsb) ? rho1 * t1.y : 0.0f;
+              const float sb = (L.e > a.cut.kc_lsb) ? rho1 * t1.z : 0.0f;
+              if (sm + sb > sh) ++c_viol;
+              const float r = ur * sh;
+              if (r < sm) {
+                // Moller: binary collision with a free electron at rest
+                ++c_hard;
+                const float eps = sample_moller(t1f, a.cut.kcut, L.s);
+                const uint32_t wl = min(to_lsb(eps * t1f), L.e);
+                const uint32_t tp = L.e - wl;
+                const float wf = (float)wl * kLsbF, tpf = (float)tp * kLsbF;
+                const float cd = sqrtf(wf * (t1f + 2.0f * kMc2) / (t1f * (wf + 2.0f * kMc2)));
+                const float cpp = sqrtf(tpf * (t1f + 2.0f * kMc2) / (t1f * (tpf + 2.0f * kMc2)));
+                const float phi = kTwoPi * L.s.uniform();
+                c0.u = L.u; c0.v = L.v; c0.w = L.w;
+                rotate(c0.u, c0.v, c0.w, cd, phi);
+                rotate(L.u, L.v, L.w, cpp, phi + kPi);
+                if (wl >= a.cut.ecut_lsb) {
+                  c0.e = wl;
+                  child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
+                  ctype = 1;
+                } else {
+                  deposit(L.tally, v1, wl);
+                }
+                L.e = tp;
+                if (tp < a.cut.ecut_lsb) {
+                  deposit(L.tally, v1, tp);
+                  have = false;
+                }
+              } else if (r < sm + sb) {
+                // bremsstrahlung: electron direction unchanged, photon at mc^2/E
+                ++c_hard;
+                const float k = sample_brems(t1f, a.cut.kc, L.s);
+                const float phi = kTwoPi * L.s.uniform();
+                const uint32_t kl = min(to_lsb(k), L.e);
+                c0.u = L.u; c0.v = L.v; c0.w = L.w;
+                rotate(c0.u, c0.v, c0.w, __cosf(kMc2 / (t1f + kMc2)), phi);
+                if (kl >= a.cut.pcut_lsb) {
+                  c0.e = kl;
+                  child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
+                  ctype = 0;
+                } else {
+                  deposit(L.tally, v1, kl);
+                }
+                L.e -= kl;
+                if (L.e < a.cut.ecut_lsb) {
+                  deposit(L.tally, v1, L.e);
+                  have = false;
+                }
+              }
+            }
+          }
+        }
+      }
+      if (ctype >= 0) { ++pushes; ++c_sec; }
+      if (have) {
+        ++events;
+        if (events >= a.max_events || pushes + 1 > a.max_secondaries) {
+          surv = true;
+          have = false;
+        }
+      }
+    }
+    {
+      // delta rays and survivors to the electron queue, photons to the photon queue
+      const Slots se = wave_reserve(a.same_count, ctype == 1, surv);
+      if (se.any) {
+        if (ctype == 1) {
+          if (se.s0 < a.same.cap) put(a.same, se.s0, L.x, L.y, L.z, c0.u, c0.v, c0.w, c0.e, L.s.hist, c0.plo, c0.phi, 0u, L.beam);
+          else atomicAdd(&a.ctr[C_OVERFLOW], 1ull);
+        }
+        if (surv) {
+          if (se.s1 < a.same.cap) store_lane(L, a.same, se.s1);
+          else atomicAdd(&a.ctr[C_OVERFLOW], 1ull);
+        }
+      }
+      const Slots sg = wave_reserve(a.other_count, ctype == 0, false);
+      if (ctype == 0) {
+        if (sg.s0 < a.other.cap) put(a.other, sg.s0, L.x, L.y, L.z, c0.u, c0.v, c0.w, c0.e, L.s.hist, c0.plo, c0.phi, 0u, L.beam);
+        else atomicAdd(&a.ctr[C_OVERFLOW], 1ull);
+      }
+    }
+    if (!have && item < a.n_work) {
+      item += stride;
+      if (item < a.n_work) {
+        load_lane(L, a.work, item, a.beams, nvox);
+        have = true;
+        events = 0;
+        pushes = 0;
+      }
+    }
+  }
+  const unsigned long long s_esc = wave_sum(acc_esc);
+  const unsigned long long s_steps = wave_sum(c_steps), s_hard = wave_sum(c_hard), s_viol = wave_sum(c_viol),
+                           s_sec = wave_sum(c_sec);
+  if (lane_id() == 0) {
+    if (s_esc) atomicAdd(&a.ctr[C_E_ESC], s_esc);
+    if (s_steps) atomicAdd(&a.ctr[C_E_STEPS], s_steps);
+    if (s_hard) atomicAdd(&a.ctr[C_HARD], s_hard);
+    if (s_viol) atomicAdd(&a.ctr[C_VIOL], s_viol);
+    if (s_sec) atomicAdd(&a.ctr[C_SEC], s_sec);
+  }
+}
+
+// ---------------------------------------------------------------- finalize
+// Dose per history and batch uncertainty in double precision (Sec. II.D):
+// D = sum_k T_k / N converted to Gy; sigma^2 = sum_k n_k^2 (m_k - m)^2 /
+// (N^2 (K-1)/K) with m_k the batch means.  Also sums the deposited energy for
+// the integer ledger.
+__global__ void __launch_bounds__(256) k_finalize(FinalizeArgs a) {
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long s1 = 0;
+  if (v < a.nvox) {
+    for (uint32_t k = 0; k < a.K; ++k) s1 += a.tally[(size_t)k * a.nvox + v];
+    const double rho = (double)__uint_as_float(a.vox[v].x);
+    const double conv = rho > 0.0 ? a.conv / rho : 0.0;
+    const double m = (double)s1 / a.n_total;
+    a.dose[v] = m * conv;
+    if (a.sigma) {
+      double acc = 0.0;
+      for (uint32_t k = 0; k < a.K; ++k) {
+        const double nk = a.nk[k];
+        const double d = (double)a.tally[(size_t)k * a.nvox + v] / nk - m;
+        acc += nk * nk * d * d;
+      }
+      const double var = a.K > 1 ? acc / (a.n_total * a.n_total * (double)(a.K - 1) / (double)a.K) : 0.0;
+      a.sigma[v] = sqrt(var) * conv;
+    }
+  }
+  const unsigned long long t = wave_sum(s1);
+  if (lane_id() == 0 && t) atomicAdd(a.dep_total, t);
+}
+
+// ------------------------------------------------------------------ checks
+__global__ void k_rng_words(uint32_t key0, uint32_t key1, uint32_t hist, uint32_t plo, uint32_t phi, uint32_t n0,
+                            int count, uint32_t* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint32_t n = n0 + (uint32_t)i;
+  const Block b = philox(n >> 2, plo, phi, hist, key0, key1);
+  const uint32_t j = n & 3u;
+  out[i] = j == 0 ? b.w0 : (j == 1 ? b.w1 : (j == 2 ? b.w2 : b.w3));
+}
+
+__global__ void k_table_eval(DevTables t, int which, int mat, const float* e, int n, float* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (which == 7) {
+    const float g1 = e[i];
+    out[i] = screening_A(t, t.ms, g1);
+    return;
+  }
+  const TPos p = tpos(t, e[i]);
+  if (which <= 2) {
+    const float4 c = lerp4(t.ph, mat * kNE, p);
+    out[i] = which == 0 ? c.x : (which == 1 ? c.y : c.z);
+  } else {
+    const float4 c = lerp4(t.el, mat * kNE, p);
+    out[i] = which == 3 ? c.x : (which == 4 ? c.y : (which == 5 ? c.z : c.w));
+  }
+}
+
+// First real photon interaction of each history (checks the stream use, the
+// majorant and the table lookups against the oracle history by history).
+__global__ void __launch_bounds__(256) k_first_events(PassArgs a, SourceArgs sa, float* xyz, uint32_t* nused) {
+  extern __shared__ float4 smem[];
+  const int nt = a.tab.n_mat * kNE;
+  for (int i = threadIdx.x; i < nt; i += blockDim.x) smem[i] = a.tab.ph[i];
+  float* majg = reinterpret_cast<float*>(smem + nt);
+  for (int i = threadIdx.x; i < kNE; i += blockDim.x) majg[i] = a.tab.maj_g[i];
+  __syncthreads();
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= sa.count) return;
+  const uint32_t h = sa.h0 + i;
+  const DevBeam b = a.beams[sa.beam];
+  const Primary pr = sample_primary(sa, b, h);
+  const float nan = __builtin_nanf("");
+  xyz[3 * i] = nan; xyz[3 * i + 1] = nan; xyz[3 * i + 2] = nan;
+  nused[i] = 0;
+  if (!inside(a.ph, pr.x, pr.y, 0.0f) || pr.e < a.cut.pcut_lsb) return;
+  Lane L;
+  L.x = pr.x; L.y = pr.y; L.z = 0.0f; L.u = 0.0f; L.v = 0.0f; L.w = 1.0f; L.e = pr.e; L.beam = sa.beam;
+  L.s.k0 = b.key0; L.s.k1 = b.key1; L.s.hist = h; L.s.plo = 0; L.s.phi = 0; L.s.n = 4;
+  L.tally = nullptr;
+  uint32_t viol = 0;
+  for (int guard = 0; guard < (1 << 20); ++guard) {
+    int v0 = 0;
+    const int kind = photon_flight(L, a, smem, majg, v0, viol);
+    if (kind == PH_ESCAPE) return;
+    if (kind != PH_FICT) {
+      xyz[3 * i] = L.x; xyz[3 * i + 1] = L.y; xyz[3 * i + 2] = L.z;
+      nused[i] = L.s.n;
+      return;
+    }
+  }
+}
+
+__global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// ---------------------------------------------------------------- launchers
+size_t photon_lds_bytes(int n_mat) { return (size_t)n_mat * kNE * sizeof(float4) + kNE * sizeof(float); }
+size_t electron_lds_bytes(int n_mat) {
+  return (size_t)n_mat * kNE * sizeof(float4) + kNE * sizeof(float) + kNms * sizeof(float);
+}
+
+static hipError_t set_lds(const void* fn, size_t bytes) {
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_source(const SourceArgs& a, hipStream_t s) {
+  if (a.count == 0) return hipSuccess;
+  const int grid = (int)((a.count + 255) / 256);
+  hipLaunchKernelGGL(k_source, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_photon_pass(const PassArgs& a, int grid, int block, hipStream_t s) {
+  const size_t lds = photon_lds_bytes(a.tab.n_mat);
+  hipError_t e = set_lds((const void*)k_photon_pass, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_photon_pass, dim3(grid), dim3(block), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_electron_pass(const PassArgs& a, int grid, int block, hipStream_t s) {
+  const size_t lds = electron_lds_bytes(a.tab.n_mat);
+  hipError_t e = set_lds((const void*)k_electron_pass, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_electron_pass, dim3(grid), dim3(block), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s) {
+  const int grid = (int)((a.nvox + 255) / 256);
+  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rng_words(uint32_t key0, uint32_t key1, uint32_t hist, uint32_t plo, uint32_t phi, uint32_t n0,
+                            int count, uint32_t* out, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rng_words, dim3((count + 255) / 256), dim3(256), 0, s, key0, key1, hist, plo, phi, n0, count,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_table_eval(const DevTables& t, int which, int mat, const float* e, int n, float* out,
+                             hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_table_eval, dim3((n + 255) / 256), dim3(256), 0, s, t, which, mat, e, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_first_events(const PassArgs& a, const SourceArgs& src, float* xyz, uint32_t* nused,
+                               hipStream_t s) {
+  if (src.count == 0) return hipSuccess;
+  const size_t lds = photon_lds_bytes(a.tab.n_mat);
+  hipError_t e = set_lds((const void*)k_first_events, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_first_events, dim3((src.count + 255) / 256), dim3(256), lds, s, a, src, xyz, nused);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+int max_resident_blocks(int kernel, int block, size_t lds) {
+  int per_cu = 0;
+  const void* fn = kernel == 0 ? (const void*)k_photon_pass : (const void*)k_electron_pass;
+  (void)set_lds(fn, lds);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess || per_cu <= 0) per_cu = 1;
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (cus <= 0) cus = 256;
+  return per_cu * cus;
+}
+
+}  // namespace gmc

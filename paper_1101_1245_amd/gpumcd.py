@@ -1,0 +1,263 @@
+"""Thin ctypes binding of the C ABI in ``include/gpumcd.h``.
+
+Argument marshalling only: every step of the transport runs in the gfx950
+kernels of ``libgpumcd.so``.  There is no CPU fallback -- if the library is not
+built, or no GPU is present, these functions raise.
+
+PyTorch is used, when asked for, only to own device output buffers and to hand
+the library the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_build", "libgpumcd.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "gpumcd.h")
+
+GMC_OK, GMC_EINVAL, GMC_ENOMEM, GMC_EDEVICE, GMC_ENOTFOUND, GMC_EBUSY, GMC_EOVERFLOW, GMC_EINTERNAL = \
+    0, -1, -2, -3, -4, -5, -6, -7
+GMC_HOST, GMC_DEVICE = 0, 1
+_CODES = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTFOUND", -5: "EBUSY", -6: "EOVERFLOW",
+          -7: "EINTERNAL"}
+
+
+class GpumcdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("gpumcd %s (%d): %s" % (_CODES.get(code, "?"), code, msg))
+        self.code = code
+
+
+class gmc_material(C.Structure):
+    _fields_ = [("z_over_a", C.c_double), ("z_eff", C.c_double), ("i_ev", C.c_double)]
+
+
+class gmc_physics(C.Structure):
+    _fields_ = [("ecut_mev", C.c_double), ("pcut_mev", C.c_double), ("kcut_mev", C.c_double),
+                ("kc_mev", C.c_double), ("esmax_gcm2", C.c_double), ("n_batches", C.c_int),
+                ("test_mode", C.c_int)]
+
+
+class gmc_source(C.Structure):
+    _fields_ = [("particle", C.c_int), ("spectrum", C.c_int), ("e_mev", C.c_double), ("e_lo", C.c_double),
+                ("e_mode", C.c_double), ("e_hi", C.c_double), ("cx_cm", C.c_double), ("cy_cm", C.c_double),
+                ("wx_cm", C.c_double), ("wy_cm", C.c_double), ("beam_id", C.c_uint32)]
+
+
+class gmc_run_stats(C.Structure):
+    _fields_ = [("t_total_s", C.c_double), ("t_device_s", C.c_double), ("e_in_mev", C.c_double),
+                ("e_dep_mev", C.c_double), ("e_esc_mev", C.c_double), ("e_sink_mev", C.c_double),
+                ("n_hist", C.c_uint64), ("n_photon_events", C.c_uint64), ("n_fictitious", C.c_uint64),
+                ("n_e_steps", C.c_uint64), ("n_hard", C.c_uint64), ("n_secondaries", C.c_uint64),
+                ("n_majorant_violations", C.c_uint64), ("n_passes", C.c_uint64),
+                ("ledger_residual_lsb", C.c_int64), ("t_photon_pass_s", C.c_double),
+                ("t_electron_pass_s", C.c_double), ("n_photon_launches", C.c_uint64),
+                ("n_electron_launches", C.c_uint64)]
+
+
+class gmc_tuning(C.Structure):
+    _fields_ = [("events_per_visit", C.c_int), ("secondaries_per_visit", C.c_int), ("chunk", C.c_int),
+                ("wg_size", C.c_int)]
+
+
+_lib = None
+
+
+def header_symbols():
+    """Names of the functions declared in include/gpumcd.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gmc_[a-z_0-9]+)\s*\(", text)))
+
+
+def lib():
+    """Load libgpumcd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libgpumcd.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    try:
+        # torch bundles its own HIP runtime under the same soname; loading it
+        # first makes the library bind to that copy, so the process has a
+        # single HIP runtime and torch tensors/streams stay usable beside it.
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    dp = C.POINTER(C.c_double)
+    L.gmc_create.argtypes = [C.c_int, vp, C.POINTER(vp)]
+    L.gmc_destroy.argtypes = [vp]
+    L.gmc_destroy.restype = None
+    L.gmc_last_error.argtypes = [vp]
+    L.gmc_last_error.restype = C.c_char_p
+    L.gmc_load_tables.argtypes = [vp, C.POINTER(gmc_material), C.c_int, C.POINTER(gmc_physics),
+                                  C.POINTER(C.c_int32)]
+    L.gmc_load_phantom.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, vp, vp,
+                                   C.c_int, C.POINTER(C.c_int32)]
+    L.gmc_release.argtypes = [vp, C.c_int32]
+    L.gmc_run_beam.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(gmc_source), C.c_uint64, C.c_uint64, vp, vp,
+                               C.c_int, C.POINTER(gmc_tuning), C.POINTER(gmc_run_stats)]
+    L.gmc_rng_words.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint32, C.c_int,
+                                C.POINTER(C.c_uint32)]
+    L.gmc_table_eval.argtypes = [vp, C.c_int32, C.c_int, C.c_int, dp, C.c_int, dp]
+    L.gmc_first_events.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(gmc_source), C.c_uint64, C.c_uint32,
+                                   C.c_uint32, C.POINTER(C.c_float), C.POINTER(C.c_uint32)]
+    _lib = L
+    return L
+
+
+def _src(s) -> gmc_source:
+    return gmc_source(int(s.particle), int(s.spectrum), float(s.e), float(s.e_lo), float(s.e_mode), float(s.e_hi),
+                      float(s.cx), float(s.cy), float(s.wx), float(s.wy), int(s.beam_id))
+
+
+def _phys(p) -> gmc_physics:
+    return gmc_physics(float(p.ecut), float(p.pcut), float(p.kcut), float(p.kc), float(p.esmax_gcm2),
+                       int(p.n_batches), int(p.test_mode))
+
+
+def _tuning(t) -> Optional[gmc_tuning]:
+    if t is None:
+        return None
+    if isinstance(t, gmc_tuning):
+        return t
+    return gmc_tuning(int(t.get("events_per_visit", 0)), int(t.get("secondaries_per_visit", 0)),
+                      int(t.get("chunk", 0)), int(t.get("wg_size", 0)))
+
+
+def stats_dict(st: gmc_run_stats) -> dict:
+    return {name: getattr(st, name) for name, _ in gmc_run_stats._fields_}
+
+
+class Context:
+    """One gmc_context on a HIP device (optionally on torch's current stream)."""
+
+    def __init__(self, device: int = 0, use_torch_stream: bool = False):
+        L = lib()
+        stream = None
+        if use_torch_stream:
+            import torch
+            stream = C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+        h = C.c_void_p()
+        rc = L.gmc_create(device, stream, C.byref(h))
+        if rc != GMC_OK:
+            raise GpumcdError(rc, "gmc_create failed (no HIP device %d?)" % device)
+        self._h = h
+        self._L = L
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.gmc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc):
+        if rc != GMC_OK:
+            msg = self._L.gmc_last_error(self._h)
+            raise GpumcdError(rc, msg.decode() if msg else "")
+
+    # ------------------------------------------------------------ handles
+    def load_tables(self, materials, physics) -> int:
+        arr = (gmc_material * len(materials))(*[gmc_material(m.z_over_a, m.z_eff, m.i_ev) for m in materials])
+        tid = C.c_int32()
+        ph = _phys(physics)
+        self._check(self._L.gmc_load_tables(self._h, arr, len(materials), C.byref(ph), C.byref(tid)))
+        return tid.value
+
+    def load_phantom(self, phantom) -> int:
+        rho = np.ascontiguousarray(phantom.rho, dtype=np.float32)
+        mat = np.ascontiguousarray(phantom.mat, dtype=np.uint8)
+        nz, ny, nx = rho.shape
+        dx, dy, dz = phantom.voxel
+        pid = C.c_int32()
+        self._check(self._L.gmc_load_phantom(self._h, nx, ny, nz, dx, dy, dz, rho.ctypes.data, mat.ctypes.data,
+                                             GMC_HOST, C.byref(pid)))
+        return pid.value
+
+    def release(self, handle: int):
+        self._check(self._L.gmc_release(self._h, handle))
+
+    # --------------------------------------------------------------- runs
+    def run_beam(self, phantom_id: int, tables_id: int, source, n_hist: int, seed: int, shape=None,
+                 tuning=None, sigma: bool = True, out: str = "numpy"):
+        """Dose (Gy/history) and sigma per voxel, plus run statistics.
+
+        out="numpy": host arrays; out="torch": float64 tensors on the context's
+        GPU written directly by the finalize kernel."""
+        st = gmc_run_stats()
+        src = _src(source)
+        tun = _tuning(tuning)
+        tun_p = C.byref(tun) if tun is not None else None
+        if shape is None:
+            raise ValueError("shape (nz, ny, nx) is required")
+        n = int(np.prod(shape))
+        if out == "torch":
+            import torch
+            d = torch.empty(n, dtype=torch.float64, device="cuda")
+            s = torch.empty(n, dtype=torch.float64, device="cuda") if sigma else None
+            rc = self._L.gmc_run_beam(self._h, phantom_id, tables_id, C.byref(src), n_hist, seed, d.data_ptr(),
+                                      s.data_ptr() if s is not None else None, GMC_DEVICE, tun_p, C.byref(st))
+            self._check(rc)
+            return d.view(*shape), (s.view(*shape) if s is not None else None), stats_dict(st)
+        d = np.empty(n, np.float64)
+        s = np.empty(n, np.float64) if sigma else None
+        rc = self._L.gmc_run_beam(self._h, phantom_id, tables_id, C.byref(src), n_hist, seed, d.ctypes.data,
+                                  s.ctypes.data if s is not None else None, GMC_HOST, tun_p, C.byref(st))
+        self._check(rc)
+        return d.reshape(shape), (s.reshape(shape) if s is not None else None), stats_dict(st)
+
+    # ------------------------------------------------------------- checks
+    def rng_words(self, seed: int, beam: int, hist: int, path: int, n0: int, count: int) -> np.ndarray:
+        out = np.zeros(count, np.uint32)
+        self._check(self._L.gmc_rng_words(self._h, seed, beam, hist, path, n0, count,
+                                          out.ctypes.data_as(C.POINTER(C.c_uint32))))
+        return out
+
+    def table_eval(self, tables_id: int, which: int, mat: int, energies) -> np.ndarray:
+        e = np.ascontiguousarray(energies, dtype=np.float64)
+        out = np.zeros_like(e)
+        self._check(self._L.gmc_table_eval(self._h, tables_id, which, mat, e.ctypes.data_as(C.POINTER(C.c_double)),
+                                           e.size, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def first_events(self, phantom_id: int, tables_id: int, source, seed: int, h_begin: int, h_end: int):
+        n = h_end - h_begin
+        xyz = np.zeros(3 * n, np.float32)
+        nu = np.zeros(n, np.uint32)
+        src = _src(source)
+        self._check(self._L.gmc_first_events(self._h, phantom_id, tables_id, C.byref(src), seed, h_begin, h_end,
+                                             xyz.ctypes.data_as(C.POINTER(C.c_float)),
+                                             nu.ctypes.data_as(C.POINTER(C.c_uint32))))
+        return xyz.reshape(n, 3), nu
+
+
+def run_workload(ctx: Context, w, n_hist: Optional[int] = None, seed: Optional[int] = None, tuning=None,
+                 out: str = "numpy"):
+    """Load a Workload's tables and phantom, run its beam, release the handles."""
+    tid = ctx.load_tables(w.materials, w.physics)
+    pid = ctx.load_phantom(w.phantom)
+    try:
+        return ctx.run_beam(pid, tid, w.source, n_hist or w.n_hist, w.seed if seed is None else seed,
+                            shape=w.phantom.rho.shape, tuning=tuning, out=out)
+    finally:
+        ctx.release(pid)
+        ctx.release(tid)
