@@ -272,29 +272,29 @@ __device__ __forceinline__ float wentzel_cos(const DevTables& T, const float* ms
 // ---------------------------------------------------------------- wave helpers
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
-// Reserve slots for the calling wavefront's lanes: each lane asks for c0
-// (0/1) slots in a first group and c1 (0/1) in a second; one atomic per
-// wavefront.  Returns the base; the lane's slots are base + rank.
-struct Slots { uint32_t s0, s1; bool any; };
-
-__device__ __forceinline__ Slots wave_reserve(uint32_t* counter, bool want0, bool want1) {
-  const unsigned long long m0 = __ballot(want0);
-  const unsigned long long m1 = __ballot(want1);
-  const uint32_t n0 = (uint32_t)__popcll(m0), n1 = (uint32_t)__popcll(m1);
-  Slots r{0u, 0u, false};
-  if (n0 + n1 == 0) return r;
-  const unsigned long long active = __ballot(1);
-  const int leader = __ffsll((unsigned long long)active) - 1;
+__device__ __forceinline__ unsigned long long lanes_below() {
   const uint32_t lane = lane_id();
-  uint32_t base = 0;
-  if ((int)lane == leader) base = atomicAdd(counter, n0 + n1);
-  base = __shfl(base, leader);
-  const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-  r.s0 = base + (uint32_t)__popcll(m0 & lt);
-  r.s1 = base + n0 + (uint32_t)__popcll(m1 & lt);
-  r.any = true;
-  return r;
+  return lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
 }
+
+// A wavefront's private output segment [base, base + cap) of a staging queue;
+// `used` is wave-uniform.  Each lane appends 0, 1 or 2 entries; the slots
+// follow lane order, so no atomic is needed.
+struct WaveSeg {
+  uint32_t base, cap, used;
+  struct Slots { uint32_t s0, s1; };
+  __device__ __forceinline__ Slots append(bool want0, bool want1) {
+    const unsigned long long m0 = __ballot(want0);
+    const unsigned long long m1 = __ballot(want1);
+    const unsigned long long lt = lanes_below();
+    const uint32_t n0 = (uint32_t)__popcll(m0);
+    Slots r;
+    r.s0 = used + (uint32_t)__popcll(m0 & lt);
+    r.s1 = used + n0 + (uint32_t)__popcll(m1 & lt);
+    used += n0 + (uint32_t)__popcll(m1);
+    return r;
+  }
+};
 
 __device__ __forceinline__ void put(const DevQueue& q, uint32_t slot, float x, float y, float z, float u, float v,
                                     float w, uint32_t e, uint32_t hist, uint32_t plo, uint32_t phi, uint32_t n,

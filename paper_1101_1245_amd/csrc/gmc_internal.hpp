@@ -77,27 +77,39 @@ enum CounterIndex {
   C_E_IN = 0, C_E_ESC, C_E_SINK, C_PH_EVENTS, C_FICT, C_VIOL, C_E_STEPS, C_HARD, C_SEC, C_OVERFLOW, C_COUNT
 };
 
+// A pass kernel's work: wave w of the grid owns items [w q, (w+1) q) of the
+// work queue (q = per_wave), refills its lanes from that range, and appends
+// survivors and secondaries to its own segments of two staging queues
+// (same type / other type) -- no atomics on shared counters.  At exit each
+// wave stores how many entries it wrote; a compaction then packs the
+// segments into the pending queues.
 struct PassArgs {
   DevPhantom ph;
   DevTables tab;
   DevCuts cut;
   DevQueue work;
   uint32_t n_work;
-  DevQueue same;          // survivors and same-type secondaries
-  uint32_t* same_count;
-  DevQueue other;         // other-type secondaries
-  uint32_t* other_count;
+  uint32_t per_wave;
+  DevQueue stg_same;       // survivors and same-type secondaries
+  DevQueue stg_other;      // other-type secondaries
+  uint32_t seg_same, seg_other;   // slots per wave segment
+  uint32_t* used_same;     // [waves]
+  uint32_t* used_other;    // [waves]
   const DevBeam* beams;
   unsigned long long* ctr;   // [C_COUNT]
   int max_events;
   int max_secondaries;
 };
 
+// Primaries h0 .. h0+count-1 go to out[base + i]; primaries that start outside
+// the phantom or below their cutoff are settled here and stored with zero
+// energy, which the pass kernels skip.
 struct SourceArgs {
   DevPhantom ph;
   DevCuts cut;
   DevQueue out;
-  uint32_t* out_count;
+  uint32_t out_base;
+  uint32_t* out_count;          // set to out_base + count
   const DevBeam* beams;
   unsigned long long* ctr;
   uint32_t beam;
@@ -107,6 +119,18 @@ struct SourceArgs {
   float e_lo, e_mode, e_hi;     // triangular spectrum
   float cx, cy, wx, wy;
   int particle;
+};
+
+// Packing of wave segments into a pending queue.
+struct CompactArgs {
+  DevQueue stg;
+  uint32_t seg;
+  const uint32_t* used;    // [waves]
+  uint32_t waves;
+  uint32_t* offsets;       // [waves] destination of each segment
+  DevQueue dst;
+  uint32_t* dst_count;     // pending count, advanced by the total
+  unsigned long long* ctr;
 };
 
 struct FinalizeArgs {
@@ -134,6 +158,7 @@ hipError_t launch_table_eval(const DevTables& t, int which, int mat, const float
 hipError_t launch_first_events(const PassArgs& a, const SourceArgs& src, float* xyz, uint32_t* nused,
                                hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_compact(const CompactArgs& a, hipStream_t s);
 int max_resident_blocks(int kernel, int block, size_t lds);
 
 }  // namespace gmc

@@ -2,14 +2,17 @@
 //
 // A pass kernel transports the particles of ONE type (Sec. II.C.2: photons and
 // electrons are never simulated together, which removes the divergence of
-// the photon-electron coupling).  Each lane takes a particle, runs events
-// until it dies, reaches the per-visit event cap (the N of Sec. II.C.3) or its
-// per-visit secondary budget, then takes the next particle of its stride
-// (lane-level refill, the "pool" idea of Sec. II.C.3 inside one launch).
-// Secondaries and survivors are appended to structure-of-arrays queues with
-// one atomic per wavefront; deposits are uint64 fixed-point atomics, so the
-// dose is an exact integer sum independent of thread order.  Cross-section
-// and stopping-power tables are staged in LDS by every workgroup.
+// the photon-electron coupling).  Each wavefront owns a contiguous range of
+// the work queue; a lane runs events on its particle until it dies, reaches
+// the per-visit event cap (the N of Sec. II.C.3) or its per-visit secondary
+// budget, and then takes the next particle of the range (lane-level refill,
+// the "pool" idea of Sec. II.C.3 inside one launch).  Survivors and
+// secondaries go to the wavefront's private segments of two staging queues,
+// so no lane ever waits on a shared counter; a compaction kernel then packs
+// the segments into the pending queues (the stream compaction of Sec. II.C.3).
+// Deposits are uint64 fixed-point atomics, so the dose is an exact integer
+// sum independent of thread order.  Cross-section and stopping-power tables
+// are staged in LDS by every workgroup.
 #include "gmc_device.hpp"
 
 namespace gmc {
@@ -47,18 +50,19 @@ __global__ void __launch_bounds__(256) k_source(SourceArgs a) {
   if (valid) p = sample_primary(a, b, h);
   const bool in = valid && inside(a.ph, p.x, p.y, 0.0f);
   const uint32_t cut = a.particle == 0 ? a.cut.pcut_lsb : a.cut.ecut_lsb;
-  const bool push = in && p.e >= cut;
-  unsigned long long esc = (valid && !in) ? p.e : 0ull;
-  if (in && !push) {
+  const bool keep = in && p.e >= cut;
+  const unsigned long long esc = (valid && !in) ? p.e : 0ull;
+  if (in && !keep) {
     // a sub-cutoff primary deposits where it enters
     int ix, iy, iz;
     const int v = voxel(a.ph, p.x, p.y, 0.0f, ix, iy, iz);
     const uint32_t kb = (uint32_t)(((uint64_t)h * b.nbatch) / b.nhist);
     atomicAdd(b.tally + (size_t)kb * (size_t)(a.ph.nx * a.ph.ny * a.ph.nz) + v, (unsigned long long)p.e);
   }
-  const Slots sl = wave_reserve(a.out_count, push, false);
-  if (push) {
-    if (sl.s0 < a.out.cap) put(a.out, sl.s0, p.x, p.y, 0.0f, 0.0f, 0.0f, 1.0f, p.e, h, 0u, 0u, 4u, a.beam);
+  if (i == 0) a.out_count[0] = a.out_base + a.count;
+  if (valid) {
+    const uint32_t slot = a.out_base + i;
+    if (slot < a.out.cap) put(a.out, slot, p.x, p.y, 0.0f, 0.0f, 0.0f, 1.0f, keep ? p.e : 0u, h, 0u, 0u, 4u, a.beam);
     else atomicAdd(&a.ctr[C_OVERFLOW], 1ull);
   }
   const unsigned long long ein = wave_sum(valid ? (unsigned long long)p.e : 0ull);
@@ -95,6 +99,44 @@ __device__ __forceinline__ void store_lane(const Lane& L, const DevQueue& q, uin
 }
 
 struct Child { float u, v, w; uint32_t e, plo, phi; };
+
+// Wave-uniform cursor over the wavefront's range [next, end) of the work queue.
+struct WaveRange { uint32_t next, end; };
+
+__device__ __forceinline__ WaveRange wave_range(const PassArgs& a, uint32_t wave) {
+  const uint64_t lo = (uint64_t)wave * a.per_wave;
+  WaveRange r;
+  r.next = (uint32_t)(lo < a.n_work ? lo : a.n_work);
+  r.end = (uint32_t)(lo + a.per_wave < a.n_work ? lo + a.per_wave : a.n_work);
+  return r;
+}
+
+// Lanes without a particle take the next items of the range, in lane order.
+// Entries with zero energy (primaries settled by the source) are skipped.
+__device__ __forceinline__ void refill(Lane& L, bool& have, int& events, int& pushes, WaveRange& r,
+                                       const PassArgs& a, uint32_t nvox) {
+  const unsigned long long need = __ballot(!have);
+  if (need == 0 || r.next >= r.end) return;
+  if (!have) {
+    const uint32_t it = r.next + (uint32_t)__popcll(need & lanes_below());
+    if (it < r.end) {
+      load_lane(L, a.work, it, a.beams, nvox);
+      have = L.e != 0;
+      events = 0;
+      pushes = 0;
+    }
+  }
+  const uint32_t nxt = r.next + (uint32_t)__popcll(need);
+  r.next = nxt < r.end ? nxt : r.end;
+}
+
+// Write one entry into a wave segment; a slot beyond the segment (never
+// expected: the per-visit budgets bound every segment) is counted, not written.
+__device__ __forceinline__ bool seg_ok(const WaveSeg& g, uint32_t slot, unsigned long long* ctr) {
+  if (slot < g.cap) return true;
+  atomicAdd(&ctr[C_OVERFLOW], 1ull);
+  return false;
+}
 
 __device__ __forceinline__ void deposit(unsigned long long* tally, int v, uint32_t e) {
   if (e) atomicAdd(tally + v, (unsigned long long)e);
@@ -142,16 +184,18 @@ __global__ void __launch_bounds__(256) k_photon_pass(PassArgs a) {
   __syncthreads();
 
   const uint32_t nvox = (uint32_t)(a.ph.nx * a.ph.ny * a.ph.nz);
-  const uint32_t stride = gridDim.x * blockDim.x;
-  uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  WaveRange range = wave_range(a, wave);
+  WaveSeg gsame{wave * a.seg_same, a.seg_same, 0u}, gother{wave * a.seg_other, a.seg_other, 0u};
   Lane L;
-  bool have = item < a.n_work;
-  if (have) load_lane(L, a.work, item, a.beams, nvox);
+  bool have = false;
   int events = 0, pushes = 0;
   unsigned long long acc_esc = 0, acc_sink = 0;
   uint32_t c_ev = 0, c_fict = 0, c_viol = 0, c_sec = 0;
 
-  while (__any(have)) {
+  for (;;) {
+    refill(L, have, events, pushes, range, a, nvox);
+    if (!__any(have)) break;
     int nchild = 0;
     Child c0, c1;
     bool surv = false;
@@ -249,35 +293,21 @@ __global__ void __launch_bounds__(256) k_photon_pass(PassArgs a) {
         }
       }
     }
-    // secondary electrons to the electron queue, survivors back to the photon queue
+    // secondary electrons to the electron staging segment, survivors to the photon one
     {
-      const Slots sl = wave_reserve(a.other_count, nchild >= 1, nchild >= 2);
-      if (sl.any) {
-        const uint32_t hist = L.s.hist;
-        if (nchild >= 1) {
-          if (sl.s0 < a.other.cap) put(a.other, sl.s0, L.x, L.y, L.z, c0.u, c0.v, c0.w, c0.e, hist, c0.plo, c0.phi, 0u, L.beam);
-          else atomicAdd(&a.ctr[C_OVERFLOW], 1ull);
-        }
-        if (nchild >= 2) {
-          if (sl.s1 < a.other.cap) put(a.other, sl.s1, L.x, L.y, L.z, c1.u, c1.v, c1.w, c1.e, hist, c1.plo, c1.phi, 0u, L.beam);
-          else atomicAdd(&a.ctr[C_OVERFLOW], 1ull);
-        }
-      }
-      const Slots ss = wave_reserve(a.same_count, surv, false);
-      if (surv) {
-        if (ss.s0 < a.same.cap) store_lane(L, a.same, ss.s0);
-        else atomicAdd(&a.ctr[C_OVERFLOW], 1ull);
-      }
+      const WaveSeg::Slots sl = gother.append(nchild >= 1, nchild >= 2);
+      const uint32_t hist = L.s.hist;
+      if (nchild >= 1 && seg_ok(gother, sl.s0, a.ctr))
+        put(a.stg_other, gother.base + sl.s0, L.x, L.y, L.z, c0.u, c0.v, c0.w, c0.e, hist, c0.plo, c0.phi, 0u, L.beam);
+      if (nchild >= 2 && seg_ok(gother, sl.s1, a.ctr))
+        put(a.stg_other, gother.base + sl.s1, L.x, L.y, L.z, c1.u, c1.v, c1.w, c1.e, hist, c1.plo, c1.phi, 0u, L.beam);
+      const WaveSeg::Slots ss = gsame.append(surv, false);
+      if (surv && seg_ok(gsame, ss.s0, a.ctr)) store_lane(L, a.stg_same, gsame.base + ss.s0);
     }
-    if (!have && item < a.n_work) {
-      item += stride;
-      if (item < a.n_work) {
-        load_lane(L, a.work, item, a.beams, nvox);
-        have = true;
-        events = 0;
-        pushes = 0;
-      }
-    }
+  }
+  if (lane_id() == 0) {
+    a.used_same[wave] = gsame.used;
+    a.used_other[wave] = gother.used;
   }
   const unsigned long long s_esc = wave_sum(acc_esc), s_sink = wave_sum(acc_sink);
   const unsigned long long s_ev = wave_sum(c_ev), s_fict = wave_sum(c_fict), s_viol = wave_sum(c_viol),
@@ -311,17 +341,19 @@ __global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
   __syncthreads();
 
   const uint32_t nvox = (uint32_t)(a.ph.nx * a.ph.ny * a.ph.nz);
-  const uint32_t stride = gridDim.x * blockDim.x;
-  uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  WaveRange range = wave_range(a, wave);
+  WaveSeg gsame{wave * a.seg_same, a.seg_same, 0u}, gother{wave * a.seg_other, a.seg_other, 0u};
   Lane L;
-  bool have = item < a.n_work;
-  if (have) load_lane(L, a.work, item, a.beams, nvox);
+  bool have = false;
   int events = 0, pushes = 0;
   unsigned long long acc_esc = 0;
   uint32_t c_steps = 0, c_hard = 0, c_viol = 0, c_sec = 0;
   const float emin = a.cut.emin;
 
-  while (__any(have)) {
+  for (;;) {
+    refill(L, have, events, pushes, range, a, nvox);
+    if (!__any(have)) break;
     int ctype = -1;   // 0 photon child, 1 electron child
     Child c0;
     bool surv = false;
@@ -455,33 +487,19 @@ __global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
       }
     }
     {
-      // delta rays and survivors to the electron queue, photons to the photon queue
-      const Slots se = wave_reserve(a.same_count, ctype == 1, surv);
-      if (se.any) {
-        if (ctype == 1) {
-          if (se.s0 < a.same.cap) put(a.same, se.s0, L.x, L.y, L.z, c0.u, c0.v, c0.w, c0.e, L.s.hist, c0.plo, c0.phi, 0u, L.beam);
-          else atomicAdd(&a.ctr[C_OVERFLOW], 1ull);
-        }
-        if (surv) {
-          if (se.s1 < a.same.cap) store_lane(L, a.same, se.s1);
-          else atomicAdd(&a.ctr[C_OVERFLOW], 1ull);
-        }
-      }
-      const Slots sg = wave_reserve(a.other_count, ctype == 0, false);
-      if (ctype == 0) {
-        if (sg.s0 < a.other.cap) put(a.other, sg.s0, L.x, L.y, L.z, c0.u, c0.v, c0.w, c0.e, L.s.hist, c0.plo, c0.phi, 0u, L.beam);
-        else atomicAdd(&a.ctr[C_OVERFLOW], 1ull);
-      }
+      // delta rays and survivors to the electron staging segment, photons to the photon one
+      const WaveSeg::Slots se = gsame.append(ctype == 1, surv);
+      if (ctype == 1 && seg_ok(gsame, se.s0, a.ctr))
+        put(a.stg_same, gsame.base + se.s0, L.x, L.y, L.z, c0.u, c0.v, c0.w, c0.e, L.s.hist, c0.plo, c0.phi, 0u, L.beam);
+      if (surv && seg_ok(gsame, se.s1, a.ctr)) store_lane(L, a.stg_same, gsame.base + se.s1);
+      const WaveSeg::Slots sg = gother.append(ctype == 0, false);
+      if (ctype == 0 && seg_ok(gother, sg.s0, a.ctr))
+        put(a.stg_other, gother.base + sg.s0, L.x, L.y, L.z, c0.u, c0.v, c0.w, c0.e, L.s.hist, c0.plo, c0.phi, 0u, L.beam);
     }
-    if (!have && item < a.n_work) {
-      item += stride;
-      if (item < a.n_work) {
-        load_lane(L, a.work, item, a.beams, nvox);
-        have = true;
-        events = 0;
-        pushes = 0;
-      }
-    }
+  }
+  if (lane_id() == 0) {
+    a.used_same[wave] = gsame.used;
+    a.used_other[wave] = gother.used;
   }
   const unsigned long long s_esc = wave_sum(acc_esc);
   const unsigned long long s_steps = wave_sum(c_steps), s_hard = wave_sum(c_hard), s_viol = wave_sum(c_viol),
@@ -592,6 +610,46 @@ __global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
+// -------------------------------------------------------------- compaction
+// Exclusive scan of the per-wave counts (one workgroup of 1024 lanes) giving
+// each segment's destination after the pending queue's current end.
+__global__ void __launch_bounds__(1024) k_compact_scan(CompactArgs a) {
+  __shared__ uint32_t part[1024];
+  const uint32_t t = threadIdx.x;
+  const uint32_t per = (a.waves + 1023u) / 1024u;
+  const uint32_t lo = min(t * per, a.waves), hi = min(lo + per, a.waves);
+  uint32_t sum = 0;
+  for (uint32_t w = lo; w < hi; ++w) sum += min(a.used[w], a.seg);
+  part[t] = sum;
+  const uint32_t base = *a.dst_count;
+  __syncthreads();
+  for (uint32_t off = 1; off < 1024u; off <<= 1) {
+    const uint32_t v = t >= off ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = base + (t ? part[t - 1] : 0u);
+  for (uint32_t w = lo; w < hi; ++w) {
+    a.offsets[w] = run;
+    run += min(a.used[w], a.seg);
+  }
+  if (t == 1023u) a.dst_count[0] = base + part[1023];
+}
+
+// One workgroup per wave segment copies its entries to their destination.
+__global__ void __launch_bounds__(256) k_compact_copy(CompactArgs a) {
+  const uint32_t w = blockIdx.x;
+  const uint32_t n = min(a.used[w], a.seg);
+  const uint32_t src0 = w * a.seg, dst0 = a.offsets[w];
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const uint32_t s = src0 + i, d = dst0 + i;
+    if (d >= a.dst.cap) { atomicAdd(&a.ctr[C_OVERFLOW], 1ull); continue; }
+    put(a.dst, d, a.stg.x[s], a.stg.y[s], a.stg.z[s], a.stg.u[s], a.stg.v[s], a.stg.w[s], a.stg.e[s], a.stg.hist[s],
+        a.stg.plo[s], a.stg.phi[s], a.stg.n[s], a.stg.beam[s]);
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 size_t photon_lds_bytes(int n_mat) { return (size_t)n_mat * kNE * sizeof(float4) + kNE * sizeof(float); }
 size_t electron_lds_bytes(int n_mat) {
@@ -661,6 +719,15 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v
   size_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const CompactArgs& a, hipStream_t s) {
+  if (a.waves == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_compact_copy, dim3(a.waves), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

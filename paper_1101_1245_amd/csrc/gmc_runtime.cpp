@@ -52,6 +52,7 @@ struct QueueBuf {
 };
 
 constexpr uint32_t kDefaultCap = 1u << 23;
+constexpr uint32_t kMaxWaves = 1u << 15;
 
 }  // namespace
 
@@ -78,6 +79,10 @@ struct gmc_context {
   double* d_dose = nullptr;
   double* d_sigma = nullptr;
   size_t out_elems = 0;
+  QueueBuf stg[2];                 // staging: [0] same type, [1] other type
+  uint32_t stg_cap = 0;
+  uint32_t* d_used = nullptr;      // [2][kMaxWaves]
+  uint32_t* d_offsets = nullptr;   // [2][kMaxWaves]
   int resident[2] = {0, 0};
   int resident_block[2] = {0, 0};
   int resident_nmat[2] = {0, 0};
@@ -138,6 +143,15 @@ int ensure_queues(gmc_context* c, uint32_t cap) {
   for (auto& t : c->qbuf)
     for (auto& b : t) HIP_TRY(c, alloc_queue(b, cap));
   c->cap = cap;
+  return GMC_OK;
+}
+
+int ensure_staging(gmc_context* c, uint32_t slots) {
+  if (c->stg_cap >= slots) return GMC_OK;
+  for (auto& b : c->stg) free_queue(b);
+  c->stg_cap = 0;
+  for (auto& b : c->stg) HIP_TRY(c, alloc_queue(b, slots));
+  c->stg_cap = slots;
   return GMC_OK;
 }
 
@@ -257,11 +271,11 @@ int read_counts(gmc_context* c, uint32_t h[2]) {
 }
 
 struct Tune {
-  int events, secondaries, chunk, block;
+  int events, secondaries, chunk, block, pass_items;
 };
 
 Tune resolve_tuning(const gmc_tuning* t) {
-  Tune r{64, 4, 1 << 20, 256};
+  Tune r{64, 4, 1 << 20, 256, 1 << 21};
   if (t) {
     if (t->events_per_visit > 0) r.events = t->events_per_visit;
     if (t->secondaries_per_visit >= 2) r.secondaries = t->secondaries_per_visit;
@@ -282,9 +296,11 @@ int resident_blocks(gmc_context* c, int kernel, int block, int n_mat) {
 }
 
 // Run one pass over all pending particles of `type`.  The work is cut into
-// sub-ranges whose worst-case output (survivor plus per-visit secondary
-// budget per particle) fits the free space of both output queues, so no
-// particle is ever dropped.
+// launches of at most tu.pass_items particles; in each launch wavefront w owns
+// a range of q particles and private staging segments sized for the
+// worst-case output of q particles (survivor plus per-visit secondary
+// budget), so no particle is ever dropped.  After each launch the segments
+// are compacted into the pending queues.
 int run_pass(gmc_context* c, int type, const PassArgs& proto, const Tune& tu, uint32_t counts[2],
              uint64_t* n_launch) {
   const int other = 1 - type;
@@ -295,33 +311,59 @@ int run_pass(gmc_context* c, int type, const PassArgs& proto, const Tune& tu, ui
   c->pend_idx[type] ^= 1;
   HIP_TRY(c, hipMemsetAsync(c->d_counts + type, 0, sizeof(uint32_t), c->stream));
   counts[type] = 0;
-  const uint32_t per_same = type == 0 ? 1u : (uint32_t)tu.secondaries + 1u;
-  const uint32_t per_other = (uint32_t)tu.secondaries;
+  const uint32_t bud_same = type == 0 ? 1u : (uint32_t)tu.secondaries + 1u;
+  const uint32_t bud_other = (uint32_t)tu.secondaries;
   const DevQueue work = c->qbuf[type][wi].q;
+  const int res = resident_blocks(c, type, tu.block, proto.tab.n_mat);
+  const uint32_t waves_full = std::min<uint32_t>((uint32_t)res * (uint32_t)(tu.block / 64), kMaxWaves);
   uint32_t off = 0;
   while (off < n) {
-    const uint32_t free_same = c->cap - counts[type];
-    const uint32_t free_other = c->cap - counts[other];
-    const uint32_t m = std::min(n - off, std::min(free_same / per_same, free_other / per_other));
+    uint32_t m = std::min<uint32_t>(n - off, (uint32_t)tu.pass_items);
+    m = std::min(m, (c->cap - counts[type]) / bud_same);
+    m = std::min(m, (c->cap - counts[other]) / bud_other);
     if (m == 0) return fail(c, GMC_EOVERFLOW, "particle queues are full; raise the capacity or lower the chunk");
+    uint32_t waves = std::max<uint32_t>(1u, std::min<uint32_t>(waves_full, (m + 63u) / 64u));
+    const uint32_t q = (m + waves - 1) / waves;
+    waves = (m + q - 1) / q;
+    const uint32_t wpb = (uint32_t)tu.block / 64u;
+    const uint32_t blocks = (waves + wpb - 1) / wpb;
+    const uint32_t grid_waves = blocks * wpb;
+    const uint32_t seg_same = q * bud_same, seg_other = q * bud_other;
+    int rc = ensure_staging(c, grid_waves * std::max(seg_same, seg_other));
+    if (rc) return rc;
     PassArgs a = proto;
     a.work = offset_queue(work, off);
     a.n_work = m;
-    a.same = c->qbuf[type][c->pend_idx[type]].q;
-    a.same_count = c->d_counts + type;
-    a.other = c->qbuf[other][c->pend_idx[other]].q;
-    a.other_count = c->d_counts + other;
+    a.per_wave = q;
+    a.stg_same = c->stg[0].q;
+    a.stg_other = c->stg[1].q;
+    a.seg_same = seg_same;
+    a.seg_other = seg_other;
+    a.used_same = c->d_used;
+    a.used_other = c->d_used + kMaxWaves;
     a.max_events = tu.events;
     a.max_secondaries = tu.secondaries;
-    const int res = resident_blocks(c, type, tu.block, a.tab.n_mat);
-    const int grid = (int)std::min<uint64_t>((m + tu.block - 1) / tu.block, (uint64_t)res);
     HIP_TRY(c, hipEventRecord(c->kev0, c->stream));
-    hipError_t e = type == 0 ? launch_photon_pass(a, grid, tu.block, c->stream)
-                             : launch_electron_pass(a, grid, tu.block, c->stream);
+    hipError_t e = type == 0 ? launch_photon_pass(a, (int)blocks, tu.block, c->stream)
+                             : launch_electron_pass(a, (int)blocks, tu.block, c->stream);
     if (e != hipSuccess) return fail(c, GMC_EDEVICE, std::string("pass launch: ") + hipGetErrorString(e));
     HIP_TRY(c, hipEventRecord(c->kev1, c->stream));
     ++*n_launch;
-    int rc = read_counts(c, counts);
+    for (int d = 0; d < 2; ++d) {
+      const int dt = d == 0 ? type : other;
+      CompactArgs ca;
+      ca.stg = c->stg[d].q;
+      ca.seg = d == 0 ? seg_same : seg_other;
+      ca.used = d == 0 ? a.used_same : a.used_other;
+      ca.waves = grid_waves;
+      ca.offsets = c->d_offsets + d * kMaxWaves;
+      ca.dst = c->qbuf[dt][c->pend_idx[dt]].q;
+      ca.dst_count = c->d_counts + dt;
+      ca.ctr = c->d_ctr;
+      e = launch_compact(ca, c->stream);
+      if (e != hipSuccess) return fail(c, GMC_EDEVICE, std::string("compaction launch: ") + hipGetErrorString(e));
+    }
+    rc = read_counts(c, counts);
     if (rc) return rc;
     float ms = 0.0f;
     HIP_TRY(c, hipEventElapsedTime(&ms, c->kev0, c->kev1));
@@ -361,6 +403,8 @@ int gmc_create(int device, void* hip_stream, gmc_context** out) {
   if (hipMalloc(&c->d_counts, 2 * sizeof(uint32_t)) != hipSuccess ||
       hipMalloc(&c->d_ctr, (C_COUNT + 1) * sizeof(unsigned long long)) != hipSuccess ||
       hipMalloc(&c->d_nk, kMaxBatches * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->d_used, 2 * kMaxWaves * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(&c->d_offsets, 2 * kMaxWaves * sizeof(uint32_t)) != hipSuccess ||
       hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
       hipEventCreate(&c->kev0) != hipSuccess || hipEventCreate(&c->kev1) != hipSuccess) {
     gmc_destroy(c);
@@ -381,6 +425,8 @@ void gmc_destroy(gmc_context* c) {
   for (auto& kv : c->majorants) { (void)hipFree(kv.second.d_g); (void)hipFree(kv.second.d_e); }
   for (auto& t : c->qbuf)
     for (auto& b : t) free_queue(b);
+  for (auto& b : c->stg) free_queue(b);
+  (void)hipFree(c->d_used); (void)hipFree(c->d_offsets);
   (void)hipFree(c->d_counts); (void)hipFree(c->d_ctr); (void)hipFree(c->d_tally); (void)hipFree(c->d_beams);
   (void)hipFree(c->d_nk); (void)hipFree(c->d_dose); (void)hipFree(c->d_sigma);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -592,13 +638,13 @@ int gmc_run_beam(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gm
       const uint32_t cnt = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(tu.chunk, n_hist - admitted), room);
       if (cnt == 0) return fail(c, GMC_EOVERFLOW, "no room to admit primaries");
       sa.out = c->qbuf[ptype][c->pend_idx[ptype]].q;
+      sa.out_base = counts[ptype];
       sa.out_count = c->d_counts + ptype;
       sa.h0 = (uint32_t)admitted;
       sa.count = cnt;
       HIP_TRY(c, launch_source(sa, c->stream));
       admitted += cnt;
-      rc = read_counts(c, counts);
-      if (rc) return rc;
+      counts[ptype] += cnt;
     }
     if (counts[1]) { rc = run_pass(c, 1, proto, tu, counts, &launches); if (rc) return rc; }
     if (counts[0]) { rc = run_pass(c, 0, proto, tu, counts, &launches); if (rc) return rc; }
