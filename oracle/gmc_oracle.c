@@ -744,7 +744,9 @@ static void photon_run(ctx_t* c, part_t* p) {
  * Sigma_hat at the step-start energy; energy loss of Eq. 8 (read with the
  * factor s); random hinge at zeta e_s where the multiple-scattering
  * deflection is applied, with the deflection energy taken before or after the
- * loss at random; the loss is deposited in the step-start voxel; after the
+ * loss at random (a fair coin from the hinge word's lowest bit, so a step
+ * without a hard event uses one 4-word block); the loss is deposited in the
+ * step-start voxel; after the
  * second leg (1 - zeta) e_s a hard-event candidate is accepted with
  * Sigma(end)/Sigma_hat and split into Moller or bremsstrahlung. */
 static void electron_run(ctx_t* c, part_t* p) {
@@ -773,12 +775,14 @@ static void electron_run(ctx_t* c, part_t* p) {
     double tm = t - 0.5 * es * l0;
     if (tm < EMIN) tm = EMIN;
     double de = es * rho0 * l_total(m0, tm, c->kcut, c->kc);
-    double zeta = next_u(&s);
+    /* one word gives the hinge fraction (its top 24 bits) and the fair coin of
+     * the deflection energy (its lowest bit, which the uniform does not use) */
+    uint32_t wz = stream_word(&s);
+    double zeta = word_to_u(wz);
     move(p, zeta * es);
     double t1 = t - de;
     if (t1 < c->ecut) { deposit(c, v0, t); return; }
-    double coin = next_u(&s);
-    double tms = coin < 0.5 ? t : t1;
+    double tms = (wz & 1u) ? t1 : t;
     double ua = next_u(&s), uphi = next_u(&s);
     if (c->mode != 2) {
       double g1 = -expm1(-es * rho0 * inv_lambda1(m0, tms));
