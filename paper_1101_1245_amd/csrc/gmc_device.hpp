@@ -30,11 +30,12 @@ __device__ __forceinline__ Block philox(uint32_t c0, uint32_t c1, uint32_t c2, u
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-    const uint32_t n0 = hi1 ^ c1 ^ k0;
-    const uint32_t n2 = hi0 ^ c3 ^ k1;
-    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    // one 32x32->64 multiply each (a single v_mad_u64_u32)
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
   }
   return Block{c0, c1, c2, c3};
 }
@@ -296,12 +297,21 @@ struct WaveSeg {
   }
 };
 
+__device__ __forceinline__ uint32_t& qf(const DevQueue& q, int f, uint32_t i) { return q.base[f * q.stride + i]; }
+
 __device__ __forceinline__ void put(const DevQueue& q, uint32_t slot, float x, float y, float z, float u, float v,
                                     float w, uint32_t e, uint32_t hist, uint32_t plo, uint32_t phi, uint32_t n,
                                     uint32_t beam) {
-  q.x[slot] = x; q.y[slot] = y; q.z[slot] = z;
-  q.u[slot] = u; q.v[slot] = v; q.w[slot] = w;
-  q.e[slot] = e; q.hist[slot] = hist; q.plo[slot] = plo; q.phi[slot] = phi; q.n[slot] = n; q.beam[slot] = beam;
+  qf(q, Q_X, slot) = __float_as_uint(x); qf(q, Q_Y, slot) = __float_as_uint(y); qf(q, Q_Z, slot) = __float_as_uint(z);
+  qf(q, Q_U, slot) = __float_as_uint(u); qf(q, Q_V, slot) = __float_as_uint(v); qf(q, Q_W, slot) = __float_as_uint(w);
+  qf(q, Q_E, slot) = e; qf(q, Q_HIST, slot) = hist; qf(q, Q_PLO, slot) = plo; qf(q, Q_PHI, slot) = phi;
+  qf(q, Q_N, slot) = n; qf(q, Q_BEAM, slot) = beam;
+}
+
+// Add to run counter `idx` in the slot of the calling wavefront.
+__device__ __forceinline__ void ctr_add(unsigned long long* ctr, int idx, unsigned long long v) {
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  atomicAdd(&ctr[idx * kCtrSlots + (wave & (kCtrSlots - 1))], v);
 }
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {

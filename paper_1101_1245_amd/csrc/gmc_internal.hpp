@@ -55,14 +55,15 @@ struct DevCuts {
   int mode;                      // 0 full, 1 photon first collision, 2 electron CSDA straight-ahead
 };
 
-// Structure-of-arrays particle queue.
+// Structure-of-arrays particle queue: field f of entry i is the 32-bit word
+// base[f * stride + i].  Fields: position x y z and direction u v w (float
+// bits), kinetic energy in 2^-27 MeV units, history index, stream path (two
+// words), stream word counter, beam index.  A view at an offset keeps the
+// stride and shrinks the capacity.
+enum QueueField { Q_X = 0, Q_Y, Q_Z, Q_U, Q_V, Q_W, Q_E, Q_HIST, Q_PLO, Q_PHI, Q_N, Q_BEAM, Q_FIELDS };
 struct DevQueue {
-  float *x, *y, *z, *u, *v, *w;
-  uint32_t *e;       // kinetic energy, units of 2^-27 MeV
-  uint32_t *hist;    // history index
-  uint32_t *plo, *phi;  // stream path
-  uint32_t *n;       // stream word counter
-  uint32_t *beam;    // index into the beam table
+  uint32_t* base;
+  uint32_t stride;
   uint32_t cap;
 };
 
@@ -73,9 +74,15 @@ struct DevBeam {
   unsigned long long* tally;    // [K][nvox]
 };
 
+// Run counters (energy ledger in 2^-27 MeV units, event counts).  Each counter
+// is spread over kCtrSlots words, picked by wavefront, so that the per-wave
+// additions at the end of every kernel do not all hit one address; the host
+// sums the slots.  C_E_DEP is the deposited total summed by the finalize.
 enum CounterIndex {
-  C_E_IN = 0, C_E_ESC, C_E_SINK, C_PH_EVENTS, C_FICT, C_VIOL, C_E_STEPS, C_HARD, C_SEC, C_OVERFLOW, C_COUNT
+  C_E_IN = 0, C_E_ESC, C_E_SINK, C_PH_EVENTS, C_FICT, C_VIOL, C_E_STEPS, C_HARD, C_SEC, C_OVERFLOW, C_E_DEP,
+  C_COUNT
 };
+constexpr int kCtrSlots = 256;
 
 // A pass kernel's work: wave w of the grid owns items [w q, (w+1) q) of the
 // work queue (q = per_wave), refills its lanes from that range, and appends
@@ -96,7 +103,7 @@ struct PassArgs {
   uint32_t* used_same;     // [waves]
   uint32_t* used_other;    // [waves]
   const DevBeam* beams;
-  unsigned long long* ctr;   // [C_COUNT]
+  unsigned long long* ctr;   // [C_COUNT][kCtrSlots]
   int max_events;
   int max_secondaries;
 };
@@ -141,7 +148,7 @@ struct FinalizeArgs {
   double n_total, conv;             // conv = LSB * J/MeV / (V * 1e-3 kg/g)
   double* dose;
   double* sigma;                    // may be null
-  unsigned long long* dep_total;
+  unsigned long long* ctr;          // [C_COUNT][kCtrSlots]
 };
 
 // Launchers (gmc_kernels.hip).

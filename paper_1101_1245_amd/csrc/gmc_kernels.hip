@@ -63,13 +63,13 @@ __global__ void __launch_bounds__(256) k_source(SourceArgs a) {
   if (valid) {
     const uint32_t slot = a.out_base + i;
     if (slot < a.out.cap) put(a.out, slot, p.x, p.y, 0.0f, 0.0f, 0.0f, 1.0f, keep ? p.e : 0u, h, 0u, 0u, 4u, a.beam);
-    else atomicAdd(&a.ctr[C_OVERFLOW], 1ull);
+    else ctr_add(a.ctr, C_OVERFLOW, 1ull);
   }
   const unsigned long long ein = wave_sum(valid ? (unsigned long long)p.e : 0ull);
   const unsigned long long es = wave_sum(esc);
   if (lane_id() == 0) {
-    if (ein) atomicAdd(&a.ctr[C_E_IN], ein);
-    if (es) atomicAdd(&a.ctr[C_E_ESC], es);
+    if (ein) ctr_add(a.ctr, C_E_IN, ein);
+    if (es) ctr_add(a.ctr, C_E_ESC, es);
   }
 }
 
@@ -83,11 +83,11 @@ struct Lane {
 
 __device__ __forceinline__ void load_lane(Lane& L, const DevQueue& q, uint32_t i, const DevBeam* beams,
                                           uint32_t nvox) {
-  L.x = q.x[i]; L.y = q.y[i]; L.z = q.z[i];
-  L.u = q.u[i]; L.v = q.v[i]; L.w = q.w[i];
-  L.e = q.e[i];
-  L.beam = q.beam[i];
-  L.s.hist = q.hist[i]; L.s.plo = q.plo[i]; L.s.phi = q.phi[i]; L.s.n = q.n[i];
+  L.x = __uint_as_float(qf(q, Q_X, i)); L.y = __uint_as_float(qf(q, Q_Y, i)); L.z = __uint_as_float(qf(q, Q_Z, i));
+  L.u = __uint_as_float(qf(q, Q_U, i)); L.v = __uint_as_float(qf(q, Q_V, i)); L.w = __uint_as_float(qf(q, Q_W, i));
+  L.e = qf(q, Q_E, i);
+  L.beam = qf(q, Q_BEAM, i);
+  L.s.hist = qf(q, Q_HIST, i); L.s.plo = qf(q, Q_PLO, i); L.s.phi = qf(q, Q_PHI, i); L.s.n = qf(q, Q_N, i);
   const DevBeam b = beams[L.beam];
   L.s.k0 = b.key0; L.s.k1 = b.key1;
   const uint32_t kb = (uint32_t)(((uint64_t)L.s.hist * b.nbatch) / b.nhist);
@@ -134,7 +134,7 @@ __device__ __forceinline__ void refill(Lane& L, bool& have, int& events, int& pu
 // expected: the per-visit budgets bound every segment) is counted, not written.
 __device__ __forceinline__ bool seg_ok(const WaveSeg& g, uint32_t slot, unsigned long long* ctr) {
   if (slot < g.cap) return true;
-  atomicAdd(&ctr[C_OVERFLOW], 1ull);
+  ctr_add(ctr, C_OVERFLOW, 1ull);
   return false;
 }
 
@@ -313,12 +313,12 @@ __global__ void __launch_bounds__(256) k_photon_pass(PassArgs a) {
   const unsigned long long s_ev = wave_sum(c_ev), s_fict = wave_sum(c_fict), s_viol = wave_sum(c_viol),
                            s_sec = wave_sum(c_sec);
   if (lane_id() == 0) {
-    if (s_esc) atomicAdd(&a.ctr[C_E_ESC], s_esc);
-    if (s_sink) atomicAdd(&a.ctr[C_E_SINK], s_sink);
-    if (s_ev) atomicAdd(&a.ctr[C_PH_EVENTS], s_ev);
-    if (s_fict) atomicAdd(&a.ctr[C_FICT], s_fict);
-    if (s_viol) atomicAdd(&a.ctr[C_VIOL], s_viol);
-    if (s_sec) atomicAdd(&a.ctr[C_SEC], s_sec);
+    if (s_esc) ctr_add(a.ctr, C_E_ESC, s_esc);
+    if (s_sink) ctr_add(a.ctr, C_E_SINK, s_sink);
+    if (s_ev) ctr_add(a.ctr, C_PH_EVENTS, s_ev);
+    if (s_fict) ctr_add(a.ctr, C_FICT, s_fict);
+    if (s_viol) ctr_add(a.ctr, C_VIOL, s_viol);
+    if (s_sec) ctr_add(a.ctr, C_SEC, s_sec);
   }
 }
 
@@ -387,7 +387,9 @@ __global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
           const float l0 = rho0 * t0.x;
           const float tm = fmaxf(tf - 0.5f * es * l0, emin);
           const float de = es * rho0 * lerp_x(smem, base0, tpos(a.tab, tm));
-          const float zeta = L.s.uniform();
+          // the hinge word: fraction zeta from its top bits, deflection-energy coin from bit 0
+          const uint32_t wz = L.s.word();
+          const float zeta = to_uniform(wz);
           const float s1 = zeta * es;
           L.x = fmaf(s1, L.u, L.x);
           L.y = fmaf(s1, L.v, L.y);
@@ -399,12 +401,12 @@ __global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
           } else {
             const uint32_t e1 = L.e - dl;
             const float t1f = (float)e1 * kLsbF;
-            const float coin = L.s.uniform();
             const float ua = L.s.uniform(), uphi = L.s.uniform();
             if (a.cut.mode != 2) {
-              const float il = coin < 0.5f ? t0.w : lerp_w(smem, base0, tpos(a.tab, t1f));
+              const float il = (wz & 1u) ? lerp_w(smem, base0, tpos(a.tab, t1f)) : t0.w;
               const float xx = es * rho0 * il;
-              const float g1 = -expm1f(-xx);
+              // G1 = 1 - exp(-x), by its series where the subtraction would cancel
+              const float g1 = xx < 1e-3f ? xx * (1.0f - 0.5f * xx * (1.0f - xx * (1.0f / 3.0f))) : 1.0f - __expf(-xx);
               const float cost = wentzel_cos(a.tab, ms, g1, ua);
               rotate(L.u, L.v, L.w, cost, kTwoPi * uphi);
             }
@@ -505,11 +507,11 @@ __global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
   const unsigned long long s_steps = wave_sum(c_steps), s_hard = wave_sum(c_hard), s_viol = wave_sum(c_viol),
                            s_sec = wave_sum(c_sec);
   if (lane_id() == 0) {
-    if (s_esc) atomicAdd(&a.ctr[C_E_ESC], s_esc);
-    if (s_steps) atomicAdd(&a.ctr[C_E_STEPS], s_steps);
-    if (s_hard) atomicAdd(&a.ctr[C_HARD], s_hard);
-    if (s_viol) atomicAdd(&a.ctr[C_VIOL], s_viol);
-    if (s_sec) atomicAdd(&a.ctr[C_SEC], s_sec);
+    if (s_esc) ctr_add(a.ctr, C_E_ESC, s_esc);
+    if (s_steps) ctr_add(a.ctr, C_E_STEPS, s_steps);
+    if (s_hard) ctr_add(a.ctr, C_HARD, s_hard);
+    if (s_viol) ctr_add(a.ctr, C_VIOL, s_viol);
+    if (s_sec) ctr_add(a.ctr, C_SEC, s_sec);
   }
 }
 
@@ -539,7 +541,7 @@ __global__ void __launch_bounds__(256) k_finalize(FinalizeArgs a) {
     }
   }
   const unsigned long long t = wave_sum(s1);
-  if (lane_id() == 0 && t) atomicAdd(a.dep_total, t);
+  if (lane_id() == 0 && t) ctr_add(a.ctr, C_E_DEP, t);
 }
 
 // ------------------------------------------------------------------ checks
@@ -644,9 +646,9 @@ __global__ void __launch_bounds__(256) k_compact_copy(CompactArgs a) {
   const uint32_t src0 = w * a.seg, dst0 = a.offsets[w];
   for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
     const uint32_t s = src0 + i, d = dst0 + i;
-    if (d >= a.dst.cap) { atomicAdd(&a.ctr[C_OVERFLOW], 1ull); continue; }
-    put(a.dst, d, a.stg.x[s], a.stg.y[s], a.stg.z[s], a.stg.u[s], a.stg.v[s], a.stg.w[s], a.stg.e[s], a.stg.hist[s],
-        a.stg.plo[s], a.stg.phi[s], a.stg.n[s], a.stg.beam[s]);
+    if (d >= a.dst.cap) { ctr_add(a.ctr, C_OVERFLOW, 1ull); continue; }
+#pragma unroll
+    for (int f = 0; f < Q_FIELDS; ++f) qf(a.dst, f, d) = qf(a.stg, f, s);
   }
 }
 

@@ -70,7 +70,7 @@ struct gmc_context {
   QueueBuf qbuf[2][2];           // [type: 0 photon, 1 electron][2 buffers]
   int pend_idx[2] = {0, 0};      // which buffer of each type accumulates
   uint32_t* d_counts = nullptr;  // [2] pending counts per type
-  unsigned long long* d_ctr = nullptr;  // [C_COUNT + 1], last = deposited total
+  unsigned long long* d_ctr = nullptr;  // [C_COUNT][kCtrSlots]
   unsigned long long* d_tally = nullptr;
   size_t tally_elems = 0;
   DevBeam* d_beams = nullptr;
@@ -113,25 +113,19 @@ void free_queue(QueueBuf& b) {
 }
 
 hipError_t alloc_queue(QueueBuf& b, uint32_t cap) {
-  const size_t n = cap;
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, 12 * n * sizeof(uint32_t));
+  hipError_t e = hipMalloc(&p, (size_t)Q_FIELDS * cap * sizeof(uint32_t));
   if (e != hipSuccess) return e;
   b.base = p;
-  float* f = static_cast<float*>(p);
-  uint32_t* u = static_cast<uint32_t*>(p);
-  b.q.x = f; b.q.y = f + n; b.q.z = f + 2 * n;
-  b.q.u = f + 3 * n; b.q.v = f + 4 * n; b.q.w = f + 5 * n;
-  b.q.e = u + 6 * n; b.q.hist = u + 7 * n; b.q.plo = u + 8 * n; b.q.phi = u + 9 * n;
-  b.q.n = u + 10 * n; b.q.beam = u + 11 * n;
+  b.q.base = static_cast<uint32_t*>(p);
+  b.q.stride = cap;
   b.q.cap = cap;
   return hipSuccess;
 }
 
 DevQueue offset_queue(const DevQueue& q, uint32_t off) {
   DevQueue r = q;
-  r.x += off; r.y += off; r.z += off; r.u += off; r.v += off; r.w += off;
-  r.e += off; r.hist += off; r.plo += off; r.phi += off; r.n += off; r.beam += off;
+  r.base += off;
   r.cap = q.cap - off;
   return r;
 }
@@ -148,6 +142,7 @@ int ensure_queues(gmc_context* c, uint32_t cap) {
 
 int ensure_staging(gmc_context* c, uint32_t slots) {
   if (c->stg_cap >= slots) return GMC_OK;
+  if ((uint64_t)slots * Q_FIELDS >= (1ull << 32)) return fail(c, GMC_EOVERFLOW, "staging queue too large");
   for (auto& b : c->stg) free_queue(b);
   c->stg_cap = 0;
   for (auto& b : c->stg) HIP_TRY(c, alloc_queue(b, slots));
@@ -401,7 +396,7 @@ int gmc_create(int device, void* hip_stream, gmc_context** out) {
     c->own_stream = true;
   }
   if (hipMalloc(&c->d_counts, 2 * sizeof(uint32_t)) != hipSuccess ||
-      hipMalloc(&c->d_ctr, (C_COUNT + 1) * sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&c->d_ctr, C_COUNT * kCtrSlots * sizeof(unsigned long long)) != hipSuccess ||
       hipMalloc(&c->d_nk, kMaxBatches * sizeof(double)) != hipSuccess ||
       hipMalloc(&c->d_used, 2 * kMaxWaves * sizeof(uint32_t)) != hipSuccess ||
       hipMalloc(&c->d_offsets, 2 * kMaxWaves * sizeof(uint32_t)) != hipSuccess ||
@@ -573,6 +568,7 @@ int gmc_run_beam(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gm
   rc = get_majorants(c, phantom_id, tables_id, P, T, &maj);
   if (rc) return rc;
   // worst-case per-visit output must fit a chunk; the queues hold the chunk many times over
+  // 12 fields of a queue stay addressable with 32-bit word indices below 2^32
   const uint32_t want_cap = std::max<uint32_t>(kDefaultCap, (uint32_t)std::min<uint64_t>(
       (uint64_t)tu.chunk * (tu.secondaries + 1) * 2, 1u << 26));
   rc = ensure_queues(c, want_cap);
@@ -603,7 +599,7 @@ int gmc_run_beam(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gm
   HIP_TRY(c, hipMemcpyAsync(c->d_beams, &beam, sizeof(beam), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->d_nk, nk.data(), K * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, launch_fill_u64(c->d_tally, (size_t)K * nvox, 0ull, c->stream));
-  HIP_TRY(c, hipMemsetAsync(c->d_ctr, 0, (C_COUNT + 1) * sizeof(unsigned long long), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_ctr, 0, C_COUNT * kCtrSlots * sizeof(unsigned long long), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_counts, 0, 2 * sizeof(uint32_t), c->stream));
 
   const DevPhantom dph = dev_phantom(P);
@@ -661,25 +657,29 @@ int gmc_run_beam(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gm
   fa.conv = kLsbMeV * 1.602176634e-13 / (P.dx * P.dy * P.dz * 1e-3);
   fa.dose = out_kind == GMC_DEVICE ? dose : c->d_dose;
   fa.sigma = sigma ? (out_kind == GMC_DEVICE ? sigma : c->d_sigma) : nullptr;
-  fa.dep_total = c->d_ctr + C_COUNT;
+  fa.ctr = c->d_ctr;
   HIP_TRY(c, launch_finalize(fa, c->stream));
   if (out_kind == GMC_HOST) {
     rc = copy_out(c, dose, c->d_dose, nvox, GMC_HOST);
     if (rc) return rc;
     if (sigma) { rc = copy_out(c, sigma, c->d_sigma, nvox, GMC_HOST); if (rc) return rc; }
   }
-  unsigned long long ctr[C_COUNT + 1];
-  HIP_TRY(c, hipMemcpyAsync(ctr, c->d_ctr, sizeof(ctr), hipMemcpyDeviceToHost, c->stream));
+  std::vector<unsigned long long> slots((size_t)C_COUNT * kCtrSlots);
+  HIP_TRY(c, hipMemcpyAsync(slots.data(), c->d_ctr, slots.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                            c->stream));
   HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   float dev_ms = 0.0f;
   (void)hipEventElapsedTime(&dev_ms, c->ev0, c->ev1);
-  const long long resid = (long long)(ctr[C_E_IN] - ctr[C_COUNT] - ctr[C_E_ESC] - ctr[C_E_SINK]);
+  unsigned long long ctr[C_COUNT] = {};
+  for (int k = 0; k < C_COUNT; ++k)
+    for (int j = 0; j < kCtrSlots; ++j) ctr[k] += slots[(size_t)k * kCtrSlots + j];
+  const long long resid = (long long)(ctr[C_E_IN] - ctr[C_E_DEP] - ctr[C_E_ESC] - ctr[C_E_SINK]);
   if (stats) {
     stats->t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     stats->t_device_s = dev_ms * 1e-3;
     stats->e_in_mev = ctr[C_E_IN] * kLsbMeV;
-    stats->e_dep_mev = ctr[C_COUNT] * kLsbMeV;
+    stats->e_dep_mev = ctr[C_E_DEP] * kLsbMeV;
     stats->e_esc_mev = ctr[C_E_ESC] * kLsbMeV;
     stats->e_sink_mev = ctr[C_E_SINK] * kLsbMeV;
     stats->n_hist = n_hist;
