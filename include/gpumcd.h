@@ -109,9 +109,11 @@ typedef struct {
 
 /* Per-run statistics.  Energies in MeV; the integer ledger residual (in units
  * of 2^-27 MeV) is incident - deposited - escaped - pair rest energy and is
- * zero by construction.  t_photon_pass_s / t_electron_pass_s are the summed
- * durations of the pass kernels, timed with HIP events on the context stream,
- * over n_photon_launches / n_electron_launches launches. */
+ * zero by construction.  n_passes counts rounds (admission, electron pass,
+ * photon pass).  t_photon_pass_s / t_electron_pass_s are the summed
+ * durations of the pass kernels, timed with HIP events on the context
+ * stream, over n_photon_launches / n_electron_launches launches (plain form
+ * only; the batched form leaves them 0). */
 typedef struct {
   double t_total_s, t_device_s;
   double e_in_mev, e_dep_mev, e_esc_mev, e_sink_mev;
@@ -122,13 +124,27 @@ typedef struct {
   uint64_t n_photon_launches, n_electron_launches;
 } gmc_run_stats;
 
-/* Optional tuning of the pass kernels; NULL selects the defaults.
+/* Optional tuning of the engine; NULL, or a field <= 0, selects the default.
  *   events_per_visit: events a particle may take per kernel visit before it
- *     is requeued (the N of the stream-compaction scheme, Sec. II.C.3);
- *   secondaries_per_visit: secondaries a particle may create per visit;
- *   chunk: primaries admitted per admission step;
- *   wg_size: threads per workgroup (64..256, multiple of 64). */
-typedef struct { int events_per_visit, secondaries_per_visit, chunk, wg_size; } gmc_tuning;
+ *     is requeued (the N of the stream-compaction scheme, Sec. II.C.3;
+ *     default 64);
+ *   secondaries_per_visit: secondaries a particle may create per visit
+ *     (2..64, default 4);
+ *   chunk: primaries admitted per admission step while a particle type's
+ *     array holds fewer (default 2^20, at most 2^24);
+ *   wg_size: threads per workgroup of the pass kernels (64..256, multiple of
+ *     64, default 256);
+ *   pass_items: most particles one pass launch transports (1024..2^23,
+ *     default 2^21); the rest is carried to the next pass;
+ *   wave_items: fewest particles a wavefront owns in a pass (64..2^16,
+ *     default 64);
+ *   rounds_per_check: batched form only, graph replays (two rounds each)
+ *     between reads of the particle counts (1..1024, default 4).
+ * No tuning changes any result: the dose is bit-identical for every choice. */
+typedef struct {
+  int events_per_visit, secondaries_per_visit, chunk, wg_size;
+  int pass_items, wave_items, rounds_per_check;
+} gmc_tuning;
 
 /* Transport n_histories histories of one beam (the plain form: one beam per
  * sequence of alternating electron and photon passes until both particle
@@ -139,6 +155,31 @@ typedef struct { int events_per_visit, secondaries_per_visit, chunk, wg_size; } 
 int gmc_run_beam(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const gmc_source* src,
                  uint64_t n_histories, uint64_t seed, double* dose_gy_per_hist, double* sigma_gy_per_hist,
                  int out_ptr_kind, const gmc_tuning* tuning, gmc_run_stats* stats);
+
+/* Transport several beams in one job (the batched form): primaries of every
+ * beam are admitted into the shared per-type particle arrays as space frees
+ * up, and the rounds of alternating electron and photon passes (Sec. II.C.2)
+ * run from a captured HIP graph, the host reading the particle counts only
+ * every rounds_per_check replays.  srcs[b] and n_hist[b] (b < n_beams,
+ * 1 <= n_beams <= 2^20, each n_hist[b] >= 1) describe beam b; beam b draws
+ * the same random streams as gmc_run_beam(srcs[b], n_hist[b], seed), so
+ * beams with distinct beam_id are independent.
+ *   dose_per_beam: NULL, or an array of n_beams pointers (host array), each
+ *     NULL or an nx*ny*nz output of beam b's dose per history of that beam
+ *     (bit-identical to gmc_run_beam's dose for the same beam and seed);
+ *     asking for it adds nx*ny*nz uint64 tallies per beam in device memory;
+ *   combined_dose / combined_sigma: dose per history summed over all beams'
+ *     histories (divided by their total), with its batch uncertainty over
+ *     n_batches batches of consecutive histories (beams in order);
+ *     combined_dose is required, combined_sigma may be NULL.
+ * Output pointers are host or device memory per out_ptr_kind.  The sum of
+ * n_hist must be < 2^32 and at least n_batches.  The work runs on a stream
+ * owned by the context, ordered after the context stream's earlier work,
+ * and the context stream waits for it before the call returns. */
+int gmc_run_beams(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const gmc_source* srcs,
+                  const uint64_t* n_hist, int n_beams, uint64_t seed, double* const* dose_per_beam,
+                  double* combined_dose, double* combined_sigma, int out_ptr_kind, const gmc_tuning* tuning,
+                  gmc_run_stats* stats);
 
 /* ---------------------------------------------------------------- checks */
 /* Words n0 .. n0+count-1 of the stream (seed, beam, hist, path), computed

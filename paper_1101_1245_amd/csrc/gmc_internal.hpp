@@ -7,8 +7,14 @@
 //    composition and density in two 3D textures);
 //  * tables: FP32 nodes on a log-energy grid, one float4 per (material, node),
 //    staged into LDS by each workgroup;
-//  * particles: structure-of-arrays queues, 48 bytes per particle;
+//  * particles: structure-of-arrays queues, 48 bytes per particle, two
+//    buffers per particle type (one being consumed, one accumulating);
 //  * tallies: uint64 fixed-point energy (2^-27 MeV) per (batch, voxel).
+//
+// Pass sizes live on the device: a one-lane planning kernel reads the queue
+// counts and writes a PassPlan that the pass and compaction kernels read, so
+// a sequence of passes can be enqueued (or captured in a graph) without the
+// host reading counts in between.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -58,8 +64,7 @@ struct DevCuts {
 // Structure-of-arrays particle queue: field f of entry i is the 32-bit word
 // base[f * stride + i].  Fields: position x y z and direction u v w (float
 // bits), kinetic energy in 2^-27 MeV units, history index, stream path (two
-// words), stream word counter, beam index.  A view at an offset keeps the
-// stride and shrinks the capacity.
+// words), stream word counter, beam index.
 enum QueueField { Q_X = 0, Q_Y, Q_Z, Q_U, Q_V, Q_W, Q_E, Q_HIST, Q_PLO, Q_PHI, Q_N, Q_BEAM, Q_FIELDS };
 struct DevQueue {
   uint32_t* base;
@@ -67,11 +72,27 @@ struct DevQueue {
   uint32_t cap;
 };
 
+// One tally target: history h of the beam deposits into
+// base + ((off + h) * K / n) * nvox (a batch slice); base null: no target.
+struct DevTally {
+  unsigned long long* base;
+  uint32_t n, K, off;
+};
+
+// A beam: its stream key and up to two tally targets (the plain form uses
+// target a with the beam's own K batches; the batched form uses a per-beam
+// tally and a combined tally batched over all beams' histories).
 struct DevBeam {
   uint32_t key0, key1;          // Philox key (seed lo, seed hi ^ beam id)
-  uint32_t nhist;               // histories of the beam (batch assignment)
-  uint32_t nbatch;              // K
-  unsigned long long* tally;    // [K][nvox]
+  DevTally a, b;
+};
+
+// A beam's source, on the device for the admission kernel.
+struct DevSource {
+  int particle, spectrum;
+  uint32_t e_lsb;               // monoenergetic energy
+  float e_lo, e_mode, e_hi;     // triangular spectrum
+  float cx, cy, wx, wy;
 };
 
 // Run counters (energy ledger in 2^-27 MeV units, event counts).  Each counter
@@ -84,22 +105,39 @@ enum CounterIndex {
 };
 constexpr int kCtrSlots = 256;
 
+// Sizes of one pass, written by k_plan_pass.  The work buffer holds n
+// particles; this pass transports the first m; wavefront w owns items
+// [w per_wave, (w+1) per_wave) and staging segments of seg_same / seg_other
+// slots.  Particles m..n-1 are carried over to the next buffer.
+struct PassPlan {
+  uint32_t n, m, per_wave, seg_same, seg_other;
+};
+
+struct PlanArgs {
+  const uint32_t* n_work;       // count of the work buffer
+  const uint32_t* n_other;      // count of the other type's accumulating buffer
+  PassPlan* plan;
+  uint32_t cap;                 // queue capacity
+  uint32_t max_items;           // most particles per pass
+  uint32_t waves;               // wavefronts in the pass grid
+  uint32_t min_per_wave;        // fewest particles per wavefront (64: one per lane)
+  uint32_t bud_same, bud_other; // per-visit output budgets per particle
+};
+
 // A pass kernel's work: wave w of the grid owns items [w q, (w+1) q) of the
 // work queue (q = per_wave), refills its lanes from that range, and appends
 // survivors and secondaries to its own segments of two staging queues
 // (same type / other type) -- no atomics on shared counters.  At exit each
 // wave stores how many entries it wrote; a compaction then packs the
-// segments into the pending queues.
+// segments into the accumulating queues.
 struct PassArgs {
   DevPhantom ph;
   DevTables tab;
   DevCuts cut;
   DevQueue work;
-  uint32_t n_work;
-  uint32_t per_wave;
+  const PassPlan* plan;
   DevQueue stg_same;       // survivors and same-type secondaries
   DevQueue stg_other;      // other-type secondaries
-  uint32_t seg_same, seg_other;   // slots per wave segment
   uint32_t* used_same;     // [waves]
   uint32_t* used_other;    // [waves]
   const DevBeam* beams;
@@ -108,36 +146,52 @@ struct PassArgs {
   int max_secondaries;
 };
 
-// Primaries h0 .. h0+count-1 go to out[base + i]; primaries that start outside
-// the phantom or below their cutoff are settled here and stored with zero
-// energy, which the pass kernels skip.
-struct SourceArgs {
+// Packing of wave segments into an accumulating queue.  For the same-type
+// destination the particles the pass did not transport (m..n-1 of the work
+// buffer) are copied first, and the work buffer's count is cleared.
+struct CompactArgs {
+  DevQueue stg;
+  const PassPlan* plan;
+  int same;                // 1: same-type destination
+  const uint32_t* used;    // [waves]
+  uint32_t waves;
+  uint32_t* offsets;       // [waves + 1] destination of each segment, then the carry-over
+  DevQueue dst;
+  uint32_t* dst_count;     // accumulating count, advanced by the total
+  DevQueue work;           // the pass's work buffer (same-type only)
+  uint32_t* work_count;    // cleared (same-type only)
+  unsigned long long* ctr;
+};
+
+// Admission of primaries of one particle type.  The histories of all beams of
+// that type are numbered consecutively (beam j of the type owns
+// [start[j], start[j+1])); each admission takes the next `count` of them,
+// stored from `base` on in the type's accumulating buffer.
+struct AdmitPlan {
+  uint32_t base, count, cursor;
+};
+
+struct AdmitPlanArgs {
+  uint32_t* cursor;             // next history to admit, per type [2]
+  const uint32_t* total;        // histories per type [2]
+  uint32_t* count0;             // accumulating photon count
+  uint32_t* count1;             // accumulating electron count
+  AdmitPlan* out;               // [2]
+  uint32_t cap, chunk;
+};
+
+struct AdmitArgs {
   DevPhantom ph;
   DevCuts cut;
   DevQueue out;
-  uint32_t out_base;
-  uint32_t* out_count;          // set to out_base + count
+  const AdmitPlan* plan;
+  const uint32_t* start;        // [nb + 1] first history of each beam of this type
+  const uint32_t* beam_of;      // [nb] beam index of each beam of this type
+  uint32_t nb;
   const DevBeam* beams;
+  const DevSource* sources;     // indexed by beam
   unsigned long long* ctr;
-  uint32_t beam;
-  uint32_t h0, count;
-  int spectrum;
-  uint32_t e_lsb;               // monoenergetic energy
-  float e_lo, e_mode, e_hi;     // triangular spectrum
-  float cx, cy, wx, wy;
-  int particle;
-};
-
-// Packing of wave segments into a pending queue.
-struct CompactArgs {
-  DevQueue stg;
-  uint32_t seg;
-  const uint32_t* used;    // [waves]
-  uint32_t waves;
-  uint32_t* offsets;       // [waves] destination of each segment
-  DevQueue dst;
-  uint32_t* dst_count;     // pending count, advanced by the total
-  unsigned long long* ctr;
+  uint32_t nvox;
 };
 
 struct FinalizeArgs {
@@ -148,24 +202,26 @@ struct FinalizeArgs {
   double n_total, conv;             // conv = LSB * J/MeV / (V * 1e-3 kg/g)
   double* dose;
   double* sigma;                    // may be null
-  unsigned long long* ctr;          // [C_COUNT][kCtrSlots]
+  unsigned long long* ctr;          // [C_COUNT][kCtrSlots], gets C_E_DEP (may be null)
 };
 
 // Launchers (gmc_kernels.hip).
 size_t photon_lds_bytes(int n_mat);
 size_t electron_lds_bytes(int n_mat);
-hipError_t launch_source(const SourceArgs& a, hipStream_t s);
+hipError_t launch_plan_pass(const PlanArgs& a, hipStream_t s);
 hipError_t launch_photon_pass(const PassArgs& a, int grid, int block, hipStream_t s);
 hipError_t launch_electron_pass(const PassArgs& a, int grid, int block, hipStream_t s);
+hipError_t launch_compact(const CompactArgs& a, hipStream_t s);
+hipError_t launch_admit_plan(const AdmitPlanArgs& a, hipStream_t s);
+hipError_t launch_admit(const AdmitArgs& a, uint32_t max_count, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
 hipError_t launch_rng_words(uint32_t key0, uint32_t key1, uint32_t hist, uint32_t plo, uint32_t phi, uint32_t n0,
                             int count, uint32_t* out, hipStream_t s);
 hipError_t launch_table_eval(const DevTables& t, int which, int mat, const float* e, int n, float* out,
                              hipStream_t s);
-hipError_t launch_first_events(const PassArgs& a, const SourceArgs& src, float* xyz, uint32_t* nused,
-                               hipStream_t s);
+hipError_t launch_first_events(const PassArgs& a, const DevSource& src, uint32_t h0, uint32_t count, float* xyz,
+                               uint32_t* nused, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
-hipError_t launch_compact(const CompactArgs& a, hipStream_t s);
 int max_resident_blocks(int kernel, int block, size_t lds);
 
 }  // namespace gmc

@@ -24,7 +24,7 @@ using namespace dev;
 // Uses the first block (words 0-3) of the history's root stream.
 struct Primary { float x, y; uint32_t e; };
 
-__device__ __forceinline__ Primary sample_primary(const SourceArgs& a, const DevBeam& b, uint32_t h) {
+__device__ __forceinline__ Primary sample_primary(const DevSource& a, const DevBeam& b, uint32_t h) {
   const Block blk = philox(0u, 0u, 0u, h, b.key0, b.key1);
   const float u0 = to_uniform(blk.w0), u1 = to_uniform(blk.w1), u2 = to_uniform(blk.w2);
   Primary p;
@@ -41,28 +41,76 @@ __device__ __forceinline__ Primary sample_primary(const SourceArgs& a, const Dev
   return p;
 }
 
-__global__ void __launch_bounds__(256) k_source(SourceArgs a) {
+// Batch slice of a tally target for history h.
+__device__ __forceinline__ unsigned long long* tally_slice(const DevTally& t, uint32_t h, uint32_t nvox) {
+  if (!t.base) return nullptr;
+  const uint32_t k = (uint32_t)(((uint64_t)(t.off + h) * t.K) / t.n);
+  return t.base + (size_t)k * nvox;
+}
+
+// Admission sizes for both particle types: take the next histories of each
+// type while its accumulating buffer holds fewer than `chunk` particles.
+__global__ void k_admit_plan(AdmitPlanArgs a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int t = 0; t < 2; ++t) {
+    uint32_t* cnt = t == 0 ? a.count0 : a.count1;
+    const uint32_t have = *cnt;
+    const uint32_t left = a.total[t] - a.cursor[t];
+    uint32_t take = 0;
+    if (have < a.chunk) {
+      take = min(left, a.chunk);
+      take = min(take, a.cap - have);
+    }
+    a.out[t].base = have;
+    a.out[t].count = take;
+    a.out[t].cursor = a.cursor[t];
+    a.cursor[t] += take;
+    *cnt = have + take;
+  }
+}
+
+// Primaries of one particle type, written by index.  Primaries that start
+// outside the phantom escape and sub-cutoff ones deposit where they enter;
+// both are stored with zero energy, which the pass kernels skip.
+__global__ void __launch_bounds__(256) k_admit(AdmitArgs a) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = i < a.count;
-  const DevBeam b = a.beams[a.beam];
-  const uint32_t h = a.h0 + i;
+  const AdmitPlan pl = *a.plan;
+  const bool valid = i < pl.count;
+  const uint32_t g = pl.cursor + i;
+  uint32_t j = 0;
+  if (valid) {   // the beam owning history g: last j with start[j] <= g
+    uint32_t lo = 0, hi = a.nb;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (a.start[mid] <= g) lo = mid; else hi = mid;
+    }
+    j = lo;
+  }
+  const uint32_t beam = valid ? a.beam_of[j] : 0u;
+  const uint32_t h = valid ? g - a.start[j] : 0u;
   Primary p{0.0f, 0.0f, 0u};
-  if (valid) p = sample_primary(a, b, h);
+  int particle = 0;
+  if (valid) {
+    const DevSource src = a.sources[beam];
+    particle = src.particle;
+    p = sample_primary(src, a.beams[beam], h);
+  }
   const bool in = valid && inside(a.ph, p.x, p.y, 0.0f);
-  const uint32_t cut = a.particle == 0 ? a.cut.pcut_lsb : a.cut.ecut_lsb;
+  const uint32_t cut = particle == 0 ? a.cut.pcut_lsb : a.cut.ecut_lsb;
   const bool keep = in && p.e >= cut;
   const unsigned long long esc = (valid && !in) ? p.e : 0ull;
   if (in && !keep) {
-    // a sub-cutoff primary deposits where it enters
     int ix, iy, iz;
     const int v = voxel(a.ph, p.x, p.y, 0.0f, ix, iy, iz);
-    const uint32_t kb = (uint32_t)(((uint64_t)h * b.nbatch) / b.nhist);
-    atomicAdd(b.tally + (size_t)kb * (size_t)(a.ph.nx * a.ph.ny * a.ph.nz) + v, (unsigned long long)p.e);
+    const DevBeam b = a.beams[beam];
+    unsigned long long* ta = tally_slice(b.a, h, a.nvox);
+    unsigned long long* tb = tally_slice(b.b, h, a.nvox);
+    if (ta && p.e) atomicAdd(ta + v, (unsigned long long)p.e);
+    if (tb && p.e) atomicAdd(tb + v, (unsigned long long)p.e);
   }
-  if (i == 0) a.out_count[0] = a.out_base + a.count;
   if (valid) {
-    const uint32_t slot = a.out_base + i;
-    if (slot < a.out.cap) put(a.out, slot, p.x, p.y, 0.0f, 0.0f, 0.0f, 1.0f, keep ? p.e : 0u, h, 0u, 0u, 4u, a.beam);
+    const uint32_t slot = pl.base + i;
+    if (slot < a.out.cap) put(a.out, slot, p.x, p.y, 0.0f, 0.0f, 0.0f, 1.0f, keep ? p.e : 0u, h, 0u, 0u, 4u, beam);
     else ctr_add(a.ctr, C_OVERFLOW, 1ull);
   }
   const unsigned long long ein = wave_sum(valid ? (unsigned long long)p.e : 0ull);
@@ -78,7 +126,8 @@ struct Lane {
   float x, y, z, u, v, w;
   uint32_t e, beam;
   Stream s;
-  unsigned long long* tally;   // this history's batch slice of its beam's tally
+  unsigned long long* ta;      // this history's batch slice of tally target a
+  unsigned long long* tb;      // of target b (null when the beam has none)
 };
 
 __device__ __forceinline__ void load_lane(Lane& L, const DevQueue& q, uint32_t i, const DevBeam* beams,
@@ -90,8 +139,8 @@ __device__ __forceinline__ void load_lane(Lane& L, const DevQueue& q, uint32_t i
   L.s.hist = qf(q, Q_HIST, i); L.s.plo = qf(q, Q_PLO, i); L.s.phi = qf(q, Q_PHI, i); L.s.n = qf(q, Q_N, i);
   const DevBeam b = beams[L.beam];
   L.s.k0 = b.key0; L.s.k1 = b.key1;
-  const uint32_t kb = (uint32_t)(((uint64_t)L.s.hist * b.nbatch) / b.nhist);
-  L.tally = b.tally + (size_t)kb * nvox;
+  L.ta = tally_slice(b.a, L.s.hist, nvox);
+  L.tb = tally_slice(b.b, L.s.hist, nvox);
 }
 
 __device__ __forceinline__ void store_lane(const Lane& L, const DevQueue& q, uint32_t slot) {
@@ -103,11 +152,11 @@ struct Child { float u, v, w; uint32_t e, plo, phi; };
 // Wave-uniform cursor over the wavefront's range [next, end) of the work queue.
 struct WaveRange { uint32_t next, end; };
 
-__device__ __forceinline__ WaveRange wave_range(const PassArgs& a, uint32_t wave) {
-  const uint64_t lo = (uint64_t)wave * a.per_wave;
+__device__ __forceinline__ WaveRange wave_range(const PassPlan& P, uint32_t wave) {
+  const uint64_t lo = (uint64_t)wave * P.per_wave;
   WaveRange r;
-  r.next = (uint32_t)(lo < a.n_work ? lo : a.n_work);
-  r.end = (uint32_t)(lo + a.per_wave < a.n_work ? lo + a.per_wave : a.n_work);
+  r.next = (uint32_t)(lo < P.m ? lo : P.m);
+  r.end = (uint32_t)(lo + P.per_wave < P.m ? lo + P.per_wave : P.m);
   return r;
 }
 
@@ -138,8 +187,10 @@ __device__ __forceinline__ bool seg_ok(const WaveSeg& g, uint32_t slot, unsigned
   return false;
 }
 
-__device__ __forceinline__ void deposit(unsigned long long* tally, int v, uint32_t e) {
-  if (e) atomicAdd(tally + v, (unsigned long long)e);
+__device__ __forceinline__ void deposit(const Lane& L, int v, uint32_t e) {
+  if (!e) return;
+  atomicAdd(L.ta + v, (unsigned long long)e);
+  if (L.tb) atomicAdd(L.tb + v, (unsigned long long)e);
 }
 
 // One photon flight and interaction decision (Sec. II.A, Eqs. 1-3): free path
@@ -185,8 +236,9 @@ __global__ void __launch_bounds__(256) k_photon_pass(PassArgs a) {
 
   const uint32_t nvox = (uint32_t)(a.ph.nx * a.ph.ny * a.ph.nz);
   const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  WaveRange range = wave_range(a, wave);
-  WaveSeg gsame{wave * a.seg_same, a.seg_same, 0u}, gother{wave * a.seg_other, a.seg_other, 0u};
+  const PassPlan P = *a.plan;
+  WaveRange range = wave_range(P, wave);
+  WaveSeg gsame{wave * P.seg_same, P.seg_same, 0u}, gother{wave * P.seg_other, P.seg_other, 0u};
   Lane L;
   bool have = false;
   int events = 0, pushes = 0;
@@ -209,7 +261,7 @@ __global__ void __launch_bounds__(256) k_photon_pass(PassArgs a) {
       } else if (kind == PH_FICT) {
         ++c_fict;
       } else if (a.cut.mode == 1) {
-        deposit(L.tally, v0, L.e);
+        deposit(L, v0, L.e);
         have = false;
       } else if (kind == PH_COMPTON) {
         // scattered photon plus recoil electron (momentum conservation)
@@ -230,12 +282,12 @@ __global__ void __launch_bounds__(256) k_photon_pass(PassArgs a) {
           child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
           nchild = 1;
         } else {
-          deposit(L.tally, v0, te);
+          deposit(L, v0, te);
         }
         L.u = nu; L.v = nv; L.w = nw;
         L.e = e1;
         if (e1 < a.cut.pcut_lsb) {
-          deposit(L.tally, v0, e1);
+          deposit(L, v0, e1);
           have = false;
         }
       } else if (kind == PH_PHOTO) {
@@ -250,7 +302,7 @@ __global__ void __launch_bounds__(256) k_photon_pass(PassArgs a) {
           child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
           nchild = 1;
         } else {
-          deposit(L.tally, v0, L.e);
+          deposit(L, v0, L.e);
         }
         have = false;
       } else {
@@ -271,7 +323,7 @@ __global__ void __launch_bounds__(256) k_photon_pass(PassArgs a) {
           child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
           nchild = 1;
         } else {
-          deposit(L.tally, v0, t1);
+          deposit(L, v0, t1);
         }
         if (t2 >= a.cut.ecut_lsb) {
           c1.e = t2;
@@ -279,7 +331,7 @@ __global__ void __launch_bounds__(256) k_photon_pass(PassArgs a) {
           if (nchild == 0) c0 = c1;   // keep the pushed children contiguous
           ++nchild;
         } else {
-          deposit(L.tally, v0, t2);
+          deposit(L, v0, t2);
         }
         have = false;
       }
@@ -342,8 +394,9 @@ __global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
 
   const uint32_t nvox = (uint32_t)(a.ph.nx * a.ph.ny * a.ph.nz);
   const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  WaveRange range = wave_range(a, wave);
-  WaveSeg gsame{wave * a.seg_same, a.seg_same, 0u}, gother{wave * a.seg_other, a.seg_other, 0u};
+  const PassPlan P = *a.plan;
+  WaveRange range = wave_range(P, wave);
+  WaveSeg gsame{wave * P.seg_same, P.seg_same, 0u}, gother{wave * P.seg_other, P.seg_other, 0u};
   Lane L;
   bool have = false;
   int events = 0, pushes = 0;
@@ -368,7 +421,7 @@ __global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
         const float rho0 = __uint_as_float(vx.x);
         const int base0 = (int)vx.y * kNE;
         if (L.e < a.cut.ecut_lsb) {
-          deposit(L.tally, v0, L.e);
+          deposit(L, v0, L.e);
           have = false;
         } else {
           ++c_steps;
@@ -396,7 +449,7 @@ __global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
           L.z = fmaf(s1, L.w, L.z);
           const uint32_t dl = to_lsb(de);
           if (dl >= L.e || L.e - dl < a.cut.ecut_lsb) {
-            deposit(L.tally, v0, L.e);
+            deposit(L, v0, L.e);
             have = false;
           } else {
             const uint32_t e1 = L.e - dl;
@@ -410,7 +463,7 @@ __global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
               const float cost = wentzel_cos(a.tab, ms, g1, ua);
               rotate(L.u, L.v, L.w, cost, kTwoPi * uphi);
             }
-            deposit(L.tally, v0, dl);
+            deposit(L, v0, dl);
             L.e = e1;
             const float s2 = (1.0f - zeta) * es;
             L.x = fmaf(s2, L.u, L.x);
@@ -447,11 +500,11 @@ __global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
                   child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
                   ctype = 1;
                 } else {
-                  deposit(L.tally, v1, wl);
+                  deposit(L, v1, wl);
                 }
                 L.e = tp;
                 if (tp < a.cut.ecut_lsb) {
-                  deposit(L.tally, v1, tp);
+                  deposit(L, v1, tp);
                   have = false;
                 }
               } else if (r < sm + sb) {
@@ -467,11 +520,11 @@ __global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
                   child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
                   ctype = 0;
                 } else {
-                  deposit(L.tally, v1, kl);
+                  deposit(L, v1, kl);
                 }
                 L.e -= kl;
                 if (L.e < a.cut.ecut_lsb) {
-                  deposit(L.tally, v1, L.e);
+                  deposit(L, v1, L.e);
                   have = false;
                 }
               }
@@ -541,7 +594,7 @@ __global__ void __launch_bounds__(256) k_finalize(FinalizeArgs a) {
     }
   }
   const unsigned long long t = wave_sum(s1);
-  if (lane_id() == 0 && t) ctr_add(a.ctr, C_E_DEP, t);
+  if (lane_id() == 0 && t && a.ctr) ctr_add(a.ctr, C_E_DEP, t);
 }
 
 // ------------------------------------------------------------------ checks
@@ -575,7 +628,8 @@ __global__ void k_table_eval(DevTables t, int which, int mat, const float* e, in
 
 // First real photon interaction of each history (checks the stream use, the
 // majorant and the table lookups against the oracle history by history).
-__global__ void __launch_bounds__(256) k_first_events(PassArgs a, SourceArgs sa, float* xyz, uint32_t* nused) {
+__global__ void __launch_bounds__(256) k_first_events(PassArgs a, DevSource src, uint32_t h0, uint32_t count,
+                                                      float* xyz, uint32_t* nused) {
   extern __shared__ float4 smem[];
   const int nt = a.tab.n_mat * kNE;
   for (int i = threadIdx.x; i < nt; i += blockDim.x) smem[i] = a.tab.ph[i];
@@ -583,18 +637,19 @@ __global__ void __launch_bounds__(256) k_first_events(PassArgs a, SourceArgs sa,
   for (int i = threadIdx.x; i < kNE; i += blockDim.x) majg[i] = a.tab.maj_g[i];
   __syncthreads();
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= sa.count) return;
-  const uint32_t h = sa.h0 + i;
-  const DevBeam b = a.beams[sa.beam];
-  const Primary pr = sample_primary(sa, b, h);
+  if (i >= count) return;
+  const uint32_t h = h0 + i;
+  const DevBeam b = a.beams[0];
+  const Primary pr = sample_primary(src, b, h);
   const float nan = __builtin_nanf("");
   xyz[3 * i] = nan; xyz[3 * i + 1] = nan; xyz[3 * i + 2] = nan;
   nused[i] = 0;
   if (!inside(a.ph, pr.x, pr.y, 0.0f) || pr.e < a.cut.pcut_lsb) return;
   Lane L;
-  L.x = pr.x; L.y = pr.y; L.z = 0.0f; L.u = 0.0f; L.v = 0.0f; L.w = 1.0f; L.e = pr.e; L.beam = sa.beam;
+  L.x = pr.x; L.y = pr.y; L.z = 0.0f; L.u = 0.0f; L.v = 0.0f; L.w = 1.0f; L.e = pr.e; L.beam = 0;
   L.s.k0 = b.key0; L.s.k1 = b.key1; L.s.hist = h; L.s.plo = 0; L.s.phi = 0; L.s.n = 4;
-  L.tally = nullptr;
+  L.ta = nullptr;
+  L.tb = nullptr;
   uint32_t viol = 0;
   for (int guard = 0; guard < (1 << 20); ++guard) {
     int v0 = 0;
@@ -612,16 +667,49 @@ __global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
+// -------------------------------------------------------------- planning
+// Sizes of the next pass from the device-resident counts: at most max_items
+// particles, and no more than the free space of both destination buffers
+// admits under the worst-case per-visit output (the particles left over are
+// carried to the next buffer, one slot each).
+__global__ void k_plan_pass(PlanArgs a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const uint32_t n = *a.n_work;
+  const uint32_t no = *a.n_other;
+  uint64_t m = n < a.max_items ? n : a.max_items;
+  if (a.bud_same > 1) {
+    const uint64_t lim = (uint64_t)(a.cap - n) / (a.bud_same - 1);
+    if (m > lim) m = lim;
+  }
+  if (a.bud_other > 0) {
+    const uint64_t lim = (uint64_t)(a.cap - no) / a.bud_other;
+    if (m > lim) m = lim;
+  }
+  uint32_t q = (uint32_t)((m + a.waves - 1) / a.waves);
+  if (q < a.min_per_wave) q = a.min_per_wave;
+  PassPlan P;
+  P.n = n;
+  P.m = (uint32_t)m;
+  P.per_wave = q;
+  P.seg_same = q * a.bud_same;
+  P.seg_other = q * a.bud_other;
+  *a.plan = P;
+}
+
 // -------------------------------------------------------------- compaction
 // Exclusive scan of the per-wave counts (one workgroup of 1024 lanes) giving
-// each segment's destination after the pending queue's current end.
+// each segment's destination after the accumulating queue's current end; for
+// the same-type destination the carried-over particles go first.
 __global__ void __launch_bounds__(1024) k_compact_scan(CompactArgs a) {
   __shared__ uint32_t part[1024];
+  const PassPlan P = *a.plan;
+  const uint32_t seg = a.same ? P.seg_same : P.seg_other;
+  const uint32_t carry = a.same ? P.n - P.m : 0u;
   const uint32_t t = threadIdx.x;
   const uint32_t per = (a.waves + 1023u) / 1024u;
   const uint32_t lo = min(t * per, a.waves), hi = min(lo + per, a.waves);
   uint32_t sum = 0;
-  for (uint32_t w = lo; w < hi; ++w) sum += min(a.used[w], a.seg);
+  for (uint32_t w = lo; w < hi; ++w) sum += min(a.used[w], seg);
   part[t] = sum;
   const uint32_t base = *a.dst_count;
   __syncthreads();
@@ -631,24 +719,40 @@ __global__ void __launch_bounds__(1024) k_compact_scan(CompactArgs a) {
     part[t] += v;
     __syncthreads();
   }
-  uint32_t run = base + (t ? part[t - 1] : 0u);
+  uint32_t run = base + carry + (t ? part[t - 1] : 0u);
   for (uint32_t w = lo; w < hi; ++w) {
     a.offsets[w] = run;
-    run += min(a.used[w], a.seg);
+    run += min(a.used[w], seg);
   }
-  if (t == 1023u) a.dst_count[0] = base + part[1023];
+  if (t == 1023u) {
+    a.offsets[a.waves] = base;   // destination of the carried-over particles
+    a.dst_count[0] = base + carry + part[1023];
+    if (a.same) a.work_count[0] = 0u;
+  }
 }
 
-// One workgroup per wave segment copies its entries to their destination.
+// One workgroup per wave segment copies its entries to their destination;
+// the carried-over particles are copied grid-stride by all workgroups.
 __global__ void __launch_bounds__(256) k_compact_copy(CompactArgs a) {
+  const PassPlan P = *a.plan;
+  const uint32_t seg = a.same ? P.seg_same : P.seg_other;
   const uint32_t w = blockIdx.x;
-  const uint32_t n = min(a.used[w], a.seg);
-  const uint32_t src0 = w * a.seg, dst0 = a.offsets[w];
+  const uint32_t n = min(a.used[w], seg);
+  const uint32_t src0 = w * seg, dst0 = a.offsets[w];
   for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
     const uint32_t s = src0 + i, d = dst0 + i;
     if (d >= a.dst.cap) { ctr_add(a.ctr, C_OVERFLOW, 1ull); continue; }
 #pragma unroll
     for (int f = 0; f < Q_FIELDS; ++f) qf(a.dst, f, d) = qf(a.stg, f, s);
+  }
+  if (a.same) {
+    const uint32_t carry = P.n - P.m, cbase = a.offsets[a.waves];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < carry; i += gridDim.x * blockDim.x) {
+      const uint32_t s = P.m + i, d = cbase + i;
+      if (d >= a.dst.cap) { ctr_add(a.ctr, C_OVERFLOW, 1ull); continue; }
+#pragma unroll
+      for (int f = 0; f < Q_FIELDS; ++f) qf(a.dst, f, d) = qf(a.work, f, s);
+    }
   }
 }
 
@@ -658,20 +762,41 @@ size_t electron_lds_bytes(int n_mat) {
   return (size_t)n_mat * kNE * sizeof(float4) + kNE * sizeof(float) + kNms * sizeof(float);
 }
 
-static hipError_t set_lds(const void* fn, size_t bytes) {
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+// The pass kernels' dynamic-LDS limit is raised once, to what the largest
+// table set needs (occupancy follows the size each launch asks for), so that
+// launches -- also those recorded into a graph -- set no attributes.
+static hipError_t lds_limits() {
+  static const hipError_t e = [] {
+    hipError_t r = hipFuncSetAttribute((const void*)k_photon_pass, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)photon_lds_bytes(kMaxMat));
+    if (r == hipSuccess)
+      r = hipFuncSetAttribute((const void*)k_electron_pass, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)electron_lds_bytes(kMaxMat));
+    return r;
+  }();
+  return e;
 }
 
-hipError_t launch_source(const SourceArgs& a, hipStream_t s) {
-  if (a.count == 0) return hipSuccess;
-  const int grid = (int)((a.count + 255) / 256);
-  hipLaunchKernelGGL(k_source, dim3(grid), dim3(256), 0, s, a);
+hipError_t launch_plan_pass(const PlanArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_plan_pass, dim3(1), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_admit_plan(const AdmitPlanArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_admit_plan, dim3(1), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_admit(const AdmitArgs& a, uint32_t max_count, hipStream_t s) {
+  if (max_count == 0 || a.nb == 0) return hipSuccess;
+  const uint32_t grid = (max_count + 255u) / 256u;
+  hipLaunchKernelGGL(k_admit, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_photon_pass(const PassArgs& a, int grid, int block, hipStream_t s) {
   const size_t lds = photon_lds_bytes(a.tab.n_mat);
-  hipError_t e = set_lds((const void*)k_photon_pass, lds);
+  const hipError_t e = lds_limits();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_photon_pass, dim3(grid), dim3(block), lds, s, a);
   return hipGetLastError();
@@ -679,7 +804,7 @@ hipError_t launch_photon_pass(const PassArgs& a, int grid, int block, hipStream_
 
 hipError_t launch_electron_pass(const PassArgs& a, int grid, int block, hipStream_t s) {
   const size_t lds = electron_lds_bytes(a.tab.n_mat);
-  hipError_t e = set_lds((const void*)k_electron_pass, lds);
+  const hipError_t e = lds_limits();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_electron_pass, dim3(grid), dim3(block), lds, s, a);
   return hipGetLastError();
@@ -706,13 +831,14 @@ hipError_t launch_table_eval(const DevTables& t, int which, int mat, const float
   return hipGetLastError();
 }
 
-hipError_t launch_first_events(const PassArgs& a, const SourceArgs& src, float* xyz, uint32_t* nused,
-                               hipStream_t s) {
-  if (src.count == 0) return hipSuccess;
+hipError_t launch_first_events(const PassArgs& a, const DevSource& src, uint32_t h0, uint32_t count, float* xyz,
+                               uint32_t* nused, hipStream_t s) {
+  if (count == 0) return hipSuccess;
   const size_t lds = photon_lds_bytes(a.tab.n_mat);
-  hipError_t e = set_lds((const void*)k_first_events, lds);
+  const hipError_t e = hipFuncSetAttribute((const void*)k_first_events, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)photon_lds_bytes(kMaxMat));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_first_events, dim3((src.count + 255) / 256), dim3(256), lds, s, a, src, xyz, nused);
+  hipLaunchKernelGGL(k_first_events, dim3((count + 255) / 256), dim3(256), lds, s, a, src, h0, count, xyz, nused);
   return hipGetLastError();
 }
 
@@ -736,7 +862,7 @@ hipError_t launch_compact(const CompactArgs& a, hipStream_t s) {
 int max_resident_blocks(int kernel, int block, size_t lds) {
   int per_cu = 0;
   const void* fn = kernel == 0 ? (const void*)k_photon_pass : (const void*)k_electron_pass;
-  (void)set_lds(fn, lds);
+  (void)lds_limits();
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess || per_cu <= 0) per_cu = 1;
   int dev = 0, cus = 0;
   (void)hipGetDevice(&dev);

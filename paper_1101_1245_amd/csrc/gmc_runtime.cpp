@@ -1,8 +1,15 @@
 // gmc_runtime.cpp -- host runtime behind the C ABI of include/gpumcd.h: device
-// buffers, table and phantom handles, and the plain transport loop that
-// alternates electron and photon passes until both particle arrays are empty
-// (Sec. II.C.2, with the leftover threshold fixed at zero so that no particle
-// is ever dropped).
+// buffers, table and phantom handles, and the transport engine.
+//
+// The engine runs rounds of [admit primaries -> electron pass -> compaction
+// -> photon pass -> compaction] until every history is admitted and both
+// particle arrays are empty (Sec. II.C.2: photons and electrons are simulated
+// in alternating passes; the leftover threshold is zero, so no particle is
+// ever dropped).  Pass sizes are planned on the device from device-resident
+// counts.  The plain form (gmc_run_beam) reads the counts after admission and
+// after the electron pass of every round and skips empty passes; the batched
+// form (gmc_run_beams) captures two rounds in a HIP graph and replays it,
+// reading the counts only every few replays.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -52,42 +59,52 @@ struct QueueBuf {
 };
 
 constexpr uint32_t kDefaultCap = 1u << 23;
+constexpr uint32_t kMaxCap = 1u << 26;
 constexpr uint32_t kMaxWaves = 1u << 15;
 
 }  // namespace
 
 struct gmc_context {
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;     // the caller's (or an owned) stream
   bool own_stream = false;
+  hipStream_t gstream = nullptr;    // owned stream the batched form captures on
+  hipEvent_t join = nullptr;
   std::string err;
   int32_t next_id = 1;
   std::map<int32_t, std::unique_ptr<TablesObj>> tables;
   std::map<int32_t, std::unique_ptr<PhantomObj>> phantoms;
   std::map<std::pair<int32_t, int32_t>, MajObj> majorants;
-  // work buffers
+  // particle queues [type: 0 photon, 1 electron][2 buffers]; buffer acc[t]
+  // of each type accumulates, the other one is consumed by the next pass
   uint32_t cap = 0;
-  QueueBuf qbuf[2][2];           // [type: 0 photon, 1 electron][2 buffers]
-  int pend_idx[2] = {0, 0};      // which buffer of each type accumulates
-  uint32_t* d_counts = nullptr;  // [2] pending counts per type
+  QueueBuf qbuf[2][2];
+  int acc[2] = {0, 0};
+  QueueBuf stg[2];                 // staging: [0] same type, [1] other type
+  uint32_t stg_cap = 0;
+  uint32_t* d_counts = nullptr;    // [type][buffer]
+  uint32_t* d_sched = nullptr;     // admission cursor per type [2], histories per type [2]
+  AdmitPlan* d_adm = nullptr;      // [2]
+  PassPlan* d_plan = nullptr;      // [2]
+  uint32_t* d_used = nullptr;      // [2][kMaxWaves]
+  uint32_t* d_offsets = nullptr;   // [2][kMaxWaves + 1]
   unsigned long long* d_ctr = nullptr;  // [C_COUNT][kCtrSlots]
   unsigned long long* d_tally = nullptr;
   size_t tally_elems = 0;
   DevBeam* d_beams = nullptr;
+  DevSource* d_sources = nullptr;
+  uint32_t* d_start = nullptr;     // [2][beams_cap + 1]
+  uint32_t* d_beam_of = nullptr;   // [2][beams_cap]
   size_t beams_cap = 0;
   double* d_nk = nullptr;
   double* d_dose = nullptr;
   double* d_sigma = nullptr;
   size_t out_elems = 0;
-  QueueBuf stg[2];                 // staging: [0] same type, [1] other type
-  uint32_t stg_cap = 0;
-  uint32_t* d_used = nullptr;      // [2][kMaxWaves]
-  uint32_t* d_offsets = nullptr;   // [2][kMaxWaves]
   int resident[2] = {0, 0};
   int resident_block[2] = {0, 0};
   int resident_nmat[2] = {0, 0};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  hipEvent_t kev0 = nullptr, kev1 = nullptr;   // around each pass launch
+  hipEvent_t kev0 = nullptr, kev1 = nullptr;   // around each pass launch (plain form)
   double t_pass[2] = {0.0, 0.0};               // summed pass durations, s
   uint64_t n_pass[2] = {0, 0};
 };
@@ -123,17 +140,11 @@ hipError_t alloc_queue(QueueBuf& b, uint32_t cap) {
   return hipSuccess;
 }
 
-DevQueue offset_queue(const DevQueue& q, uint32_t off) {
-  DevQueue r = q;
-  r.base += off;
-  r.cap = q.cap - off;
-  return r;
-}
-
 int ensure_queues(gmc_context* c, uint32_t cap) {
   if (c->cap >= cap) return GMC_OK;
   for (auto& t : c->qbuf)
     for (auto& b : t) free_queue(b);
+  c->cap = 0;
   for (auto& t : c->qbuf)
     for (auto& b : t) HIP_TRY(c, alloc_queue(b, cap));
   c->cap = cap;
@@ -174,10 +185,19 @@ int ensure_out(gmc_context* c, size_t elems) {
 
 int ensure_beams(gmc_context* c, size_t n) {
   if (c->beams_cap >= n) return GMC_OK;
-  if (c->d_beams) (void)hipFree(c->d_beams);
+  (void)hipFree(c->d_beams);
+  (void)hipFree(c->d_sources);
+  (void)hipFree(c->d_start);
+  (void)hipFree(c->d_beam_of);
   c->d_beams = nullptr;
+  c->d_sources = nullptr;
+  c->d_start = nullptr;
+  c->d_beam_of = nullptr;
   c->beams_cap = 0;
   HIP_TRY(c, hipMalloc(&c->d_beams, n * sizeof(DevBeam)));
+  HIP_TRY(c, hipMalloc(&c->d_sources, n * sizeof(DevSource)));
+  HIP_TRY(c, hipMalloc(&c->d_start, 2 * (n + 1) * sizeof(uint32_t)));
+  HIP_TRY(c, hipMalloc(&c->d_beam_of, 2 * n * sizeof(uint32_t)));
   c->beams_cap = n;
   return GMC_OK;
 }
@@ -208,6 +228,21 @@ DevCuts dev_cuts(const TablesObj& t) {
   c.emin = (float)kEmin;
   c.mode = t.phys.test_mode;
   return c;
+}
+
+DevSource dev_source(const gmc_source& s) {
+  DevSource d;
+  d.particle = s.particle;
+  d.spectrum = s.spectrum;
+  d.e_lsb = mev_to_lsb(s.e_mev);
+  d.e_lo = (float)s.e_lo;
+  d.e_mode = (float)s.e_mode;
+  d.e_hi = (float)s.e_hi;
+  d.cx = (float)s.cx_cm;
+  d.cy = (float)s.cy_cm;
+  d.wx = (float)s.wx_cm;
+  d.wy = (float)s.wy_cm;
+  return d;
 }
 
 int get_majorants(gmc_context* c, int32_t pid, int32_t tid, const PhantomObj& p, const TablesObj& t, MajObj* out) {
@@ -255,27 +290,20 @@ int check_source(gmc_context* c, const gmc_source* s) {
   return GMC_OK;
 }
 
-// Pending counts per type.  A count above the capacity means the device
-// skipped writes (it never writes past the capacity); it is reported before
-// any kernel could read the missing entries.
-int read_counts(gmc_context* c, uint32_t h[2]) {
-  HIP_TRY(c, hipMemcpyAsync(h, c->d_counts, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  if (h[0] > c->cap || h[1] > c->cap) return fail(c, GMC_EINTERNAL, "particle queue overflow on the device");
-  return GMC_OK;
-}
-
 struct Tune {
-  int events, secondaries, chunk, block, pass_items;
+  int events, secondaries, chunk, block, pass_items, wave_items, rounds;
 };
 
 Tune resolve_tuning(const gmc_tuning* t) {
-  Tune r{64, 4, 1 << 20, 256, 1 << 21};
+  Tune r{64, 4, 1 << 20, 256, 1 << 21, 64, 4};
   if (t) {
     if (t->events_per_visit > 0) r.events = t->events_per_visit;
-    if (t->secondaries_per_visit >= 2) r.secondaries = t->secondaries_per_visit;
-    if (t->chunk > 0) r.chunk = t->chunk;
+    if (t->secondaries_per_visit >= 2) r.secondaries = std::min(t->secondaries_per_visit, 64);
+    if (t->chunk > 0) r.chunk = std::min(t->chunk, 1 << 24);
     if (t->wg_size >= 64 && t->wg_size <= 256 && t->wg_size % 64 == 0) r.block = t->wg_size;
+    if (t->pass_items > 0) r.pass_items = std::min(std::max(t->pass_items, 1024), 1 << 23);
+    if (t->wave_items > 0) r.wave_items = std::min(std::max(t->wave_items, 64), 1 << 16);
+    if (t->rounds_per_check > 0) r.rounds = std::min(t->rounds_per_check, 1024);
   }
   return r;
 }
@@ -290,90 +318,496 @@ int resident_blocks(gmc_context* c, int kernel, int block, int n_mat) {
   return c->resident[kernel];
 }
 
-// Run one pass over all pending particles of `type`.  The work is cut into
-// launches of at most tu.pass_items particles; in each launch wavefront w owns
-// a range of q particles and private staging segments sized for the
-// worst-case output of q particles (survivor plus per-visit secondary
-// budget), so no particle is ever dropped.  After each launch the segments
-// are compacted into the pending queues.
-int run_pass(gmc_context* c, int type, const PassArgs& proto, const Tune& tu, uint32_t counts[2],
-             uint64_t* n_launch) {
-  const int other = 1 - type;
-  const uint32_t n = counts[type];
-  if (n == 0) return GMC_OK;
-  // the pending buffer becomes the work buffer; the other one collects
-  const int wi = c->pend_idx[type];
-  c->pend_idx[type] ^= 1;
-  HIP_TRY(c, hipMemsetAsync(c->d_counts + type, 0, sizeof(uint32_t), c->stream));
-  counts[type] = 0;
-  const uint32_t bud_same = type == 0 ? 1u : (uint32_t)tu.secondaries + 1u;
-  const uint32_t bud_other = (uint32_t)tu.secondaries;
-  const DevQueue work = c->qbuf[type][wi].q;
-  const int res = resident_blocks(c, type, tu.block, proto.tab.n_mat);
-  const uint32_t waves_full = std::min<uint32_t>((uint32_t)res * (uint32_t)(tu.block / 64), kMaxWaves);
-  uint32_t off = 0;
-  while (off < n) {
-    uint32_t m = std::min<uint32_t>(n - off, (uint32_t)tu.pass_items);
-    m = std::min(m, (c->cap - counts[type]) / bud_same);
-    m = std::min(m, (c->cap - counts[other]) / bud_other);
-    if (m == 0) return fail(c, GMC_EOVERFLOW, "particle queues are full; raise the capacity or lower the chunk");
-    uint32_t waves = std::max<uint32_t>(1u, std::min<uint32_t>(waves_full, (m + 63u) / 64u));
-    const uint32_t q = (m + waves - 1) / waves;
-    waves = (m + q - 1) / q;
-    const uint32_t wpb = (uint32_t)tu.block / 64u;
-    const uint32_t blocks = (waves + wpb - 1) / wpb;
-    const uint32_t grid_waves = blocks * wpb;
-    const uint32_t seg_same = q * bud_same, seg_other = q * bud_other;
-    int rc = ensure_staging(c, grid_waves * std::max(seg_same, seg_other));
-    if (rc) return rc;
-    PassArgs a = proto;
-    a.work = offset_queue(work, off);
-    a.n_work = m;
-    a.per_wave = q;
-    a.stg_same = c->stg[0].q;
-    a.stg_other = c->stg[1].q;
-    a.seg_same = seg_same;
-    a.seg_other = seg_other;
-    a.used_same = c->d_used;
-    a.used_other = c->d_used + kMaxWaves;
-    a.max_events = tu.events;
-    a.max_secondaries = tu.secondaries;
-    HIP_TRY(c, hipEventRecord(c->kev0, c->stream));
-    hipError_t e = type == 0 ? launch_photon_pass(a, (int)blocks, tu.block, c->stream)
-                             : launch_electron_pass(a, (int)blocks, tu.block, c->stream);
-    if (e != hipSuccess) return fail(c, GMC_EDEVICE, std::string("pass launch: ") + hipGetErrorString(e));
-    HIP_TRY(c, hipEventRecord(c->kev1, c->stream));
-    ++*n_launch;
-    for (int d = 0; d < 2; ++d) {
-      const int dt = d == 0 ? type : other;
-      CompactArgs ca;
-      ca.stg = c->stg[d].q;
-      ca.seg = d == 0 ? seg_same : seg_other;
-      ca.used = d == 0 ? a.used_same : a.used_other;
-      ca.waves = grid_waves;
-      ca.offsets = c->d_offsets + d * kMaxWaves;
-      ca.dst = c->qbuf[dt][c->pend_idx[dt]].q;
-      ca.dst_count = c->d_counts + dt;
-      ca.ctr = c->d_ctr;
-      e = launch_compact(ca, c->stream);
-      if (e != hipSuccess) return fail(c, GMC_EDEVICE, std::string("compaction launch: ") + hipGetErrorString(e));
-    }
-    rc = read_counts(c, counts);
-    if (rc) return rc;
-    float ms = 0.0f;
-    HIP_TRY(c, hipEventElapsedTime(&ms, c->kev0, c->kev1));
-    c->t_pass[type] += ms * 1e-3;
-    ++c->n_pass[type];
-    off += m;
-  }
-  return GMC_OK;
-}
-
 int copy_out(gmc_context* c, double* dst, const double* src, size_t n, int kind) {
   if (!dst) return GMC_OK;
   HIP_TRY(c, hipMemcpyAsync(dst, src, n * sizeof(double),
                             kind == GMC_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, c->stream));
   return GMC_OK;
+}
+
+// ------------------------------------------------------------------ engine
+// One transport job: its beams, their sources and tally targets.  Histories
+// of each particle type are numbered consecutively over the beams of that
+// type (start[t][j] is the first history of the j-th beam of type t).
+struct Job {
+  const PhantomObj* P = nullptr;
+  const TablesObj* T = nullptr;
+  MajObj maj;
+  std::vector<DevBeam> beams;
+  std::vector<DevSource> sources;
+  std::vector<uint32_t> start[2], beam_of[2];
+  uint32_t total[2] = {0, 0};
+};
+
+struct Engine {
+  gmc_context* c = nullptr;
+  Tune tu{};
+  PassArgs proto{};
+  AdmitArgs adm[2]{};
+  uint32_t total[2] = {0, 0};
+  uint32_t waves[2] = {0, 0};     // wavefronts of each pass grid
+  uint32_t blocks[2] = {0, 0};
+  uint32_t bud_same[2] = {0, 0}, bud_other[2] = {0, 0};
+};
+
+uint32_t* count_ptr(gmc_context* c, int type, int buf) { return c->d_counts + 2 * type + buf; }
+
+// Enqueue plan, pass and the two compactions of `type` over its accumulating
+// buffer, which becomes the work buffer; the other buffer accumulates from
+// then on.  With `timed` the pass kernel is bracketed by events.
+int enqueue_pass(Engine& E, int type, bool timed) {
+  gmc_context* c = E.c;
+  const int other = 1 - type;
+  const int wi = c->acc[type];
+  c->acc[type] ^= 1;
+  const int ni = c->acc[type];
+  PlanArgs pa;
+  pa.n_work = count_ptr(c, type, wi);
+  pa.n_other = count_ptr(c, other, c->acc[other]);
+  pa.plan = c->d_plan + type;
+  pa.cap = c->cap;
+  pa.max_items = (uint32_t)E.tu.pass_items;
+  pa.waves = E.waves[type];
+  pa.min_per_wave = (uint32_t)E.tu.wave_items;
+  pa.bud_same = E.bud_same[type];
+  pa.bud_other = E.bud_other[type];
+  HIP_TRY(c, launch_plan_pass(pa, c->stream));
+  PassArgs a = E.proto;
+  a.work = c->qbuf[type][wi].q;
+  a.plan = c->d_plan + type;
+  a.stg_same = c->stg[0].q;
+  a.stg_other = c->stg[1].q;
+  a.used_same = c->d_used;
+  a.used_other = c->d_used + kMaxWaves;
+  if (timed) HIP_TRY(c, hipEventRecord(c->kev0, c->stream));
+  hipError_t e = type == 0 ? launch_photon_pass(a, (int)E.blocks[0], E.tu.block, c->stream)
+                           : launch_electron_pass(a, (int)E.blocks[1], E.tu.block, c->stream);
+  if (e != hipSuccess) return fail(c, GMC_EDEVICE, std::string("pass launch: ") + hipGetErrorString(e));
+  if (timed) HIP_TRY(c, hipEventRecord(c->kev1, c->stream));
+  for (int d = 0; d < 2; ++d) {
+    const int dt = d == 0 ? type : other;
+    const int dbuf = d == 0 ? ni : c->acc[other];
+    CompactArgs ca;
+    ca.stg = c->stg[d].q;
+    ca.plan = c->d_plan + type;
+    ca.same = d == 0;
+    ca.used = d == 0 ? a.used_same : a.used_other;
+    ca.waves = E.waves[type];
+    ca.offsets = c->d_offsets + d * (kMaxWaves + 1);
+    ca.dst = c->qbuf[dt][dbuf].q;
+    ca.dst_count = count_ptr(c, dt, dbuf);
+    ca.work = c->qbuf[type][wi].q;
+    ca.work_count = count_ptr(c, type, wi);
+    ca.ctr = c->d_ctr;
+    e = launch_compact(ca, c->stream);
+    if (e != hipSuccess) return fail(c, GMC_EDEVICE, std::string("compaction launch: ") + hipGetErrorString(e));
+  }
+  return GMC_OK;
+}
+
+int enqueue_admission(Engine& E) {
+  gmc_context* c = E.c;
+  AdmitPlanArgs ap;
+  ap.cursor = c->d_sched;
+  ap.total = c->d_sched + 2;
+  ap.count0 = count_ptr(c, 0, c->acc[0]);
+  ap.count1 = count_ptr(c, 1, c->acc[1]);
+  ap.out = c->d_adm;
+  ap.cap = c->cap;
+  ap.chunk = (uint32_t)E.tu.chunk;
+  HIP_TRY(c, launch_admit_plan(ap, c->stream));
+  for (int t = 0; t < 2; ++t) {
+    AdmitArgs a = E.adm[t];
+    a.out = c->qbuf[t][c->acc[t]].q;
+    HIP_TRY(c, launch_admit(a, std::min<uint32_t>((uint32_t)E.tu.chunk, E.total[t]), c->stream));
+  }
+  return GMC_OK;
+}
+
+struct Status {
+  uint32_t counts[4];
+  uint32_t sched[4];            // cursor[2], total[2]
+  PassPlan plan[2];
+  AdmitPlan adm[2];
+  bool done() const {
+    return sched[0] == sched[2] && sched[1] == sched[3] && counts[0] == 0 && counts[1] == 0 && counts[2] == 0 &&
+           counts[3] == 0;
+  }
+};
+
+int read_status(gmc_context* c, Status* s) {
+  HIP_TRY(c, hipMemcpyAsync(s->counts, c->d_counts, sizeof(s->counts), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(s->sched, c->d_sched, sizeof(s->sched), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(s->plan, c->d_plan, sizeof(s->plan), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(s->adm, c->d_adm, sizeof(s->adm), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < 4; ++i)
+    if (s->counts[i] > c->cap) return fail(c, GMC_EINTERNAL, "particle queue overflow on the device");
+  return GMC_OK;
+}
+
+int stuck(gmc_context* c) {
+  return fail(c, GMC_EOVERFLOW,
+              "both particle queues are too full for any pass to proceed; lower the chunk or the secondaries "
+              "budget");
+}
+
+// Device state of a job: queues, staging, beam tables, counters.
+int engine_setup(gmc_context* c, Engine& E, const Job& J, const Tune& tu) {
+  E.c = c;
+  E.tu = tu;
+  E.total[0] = J.total[0];
+  E.total[1] = J.total[1];
+  const int n_mat = J.T->host.n_mat;
+  const uint64_t want = (uint64_t)tu.chunk * (uint64_t)(tu.secondaries + 1) * 2u;
+  const uint32_t cap = (uint32_t)std::max<uint64_t>(kDefaultCap, std::min<uint64_t>(want, kMaxCap));
+  int rc = ensure_queues(c, cap);
+  if (rc) return rc;
+  uint32_t stg = 0;
+  for (int t = 0; t < 2; ++t) {
+    E.bud_same[t] = t == 0 ? 1u : (uint32_t)tu.secondaries + 1u;
+    E.bud_other[t] = (uint32_t)tu.secondaries;
+    const uint32_t wpb = (uint32_t)tu.block / 64u;
+    const uint32_t res = (uint32_t)resident_blocks(c, t, tu.block, n_mat);
+    E.blocks[t] = std::max<uint32_t>(1u, std::min<uint32_t>(res, kMaxWaves / wpb));
+    E.waves[t] = E.blocks[t] * wpb;
+    const uint32_t qmax =
+        std::max<uint32_t>((uint32_t)tu.wave_items, ((uint32_t)tu.pass_items + E.waves[t] - 1) / E.waves[t]);
+    stg = std::max<uint32_t>(stg, E.waves[t] * qmax * std::max(E.bud_same[t], E.bud_other[t]));
+  }
+  rc = ensure_staging(c, stg);
+  if (rc) return rc;
+  const size_t nb = J.beams.size();
+  rc = ensure_beams(c, nb);
+  if (rc) return rc;
+  HIP_TRY(c, hipMemcpy(c->d_beams, J.beams.data(), nb * sizeof(DevBeam), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->d_sources, J.sources.data(), nb * sizeof(DevSource), hipMemcpyHostToDevice));
+  for (int t = 0; t < 2; ++t) {
+    HIP_TRY(c, hipMemcpy(c->d_start + t * (c->beams_cap + 1), J.start[t].data(), J.start[t].size() * sizeof(uint32_t),
+                         hipMemcpyHostToDevice));
+    if (!J.beam_of[t].empty())
+      HIP_TRY(c, hipMemcpy(c->d_beam_of + t * c->beams_cap, J.beam_of[t].data(),
+                           J.beam_of[t].size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+  }
+  const uint32_t sched[4] = {0u, 0u, J.total[0], J.total[1]};
+  HIP_TRY(c, hipMemcpy(c->d_sched, sched, sizeof(sched), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemsetAsync(c->d_counts, 0, 4 * sizeof(uint32_t), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_ctr, 0, C_COUNT * kCtrSlots * sizeof(unsigned long long), c->stream));
+  c->acc[0] = c->acc[1] = 0;
+  const DevPhantom dph = dev_phantom(*J.P);
+  const DevCuts cuts = dev_cuts(*J.T);
+  E.proto = PassArgs{};
+  E.proto.ph = dph;
+  E.proto.tab = dev_tables(*J.T, J.maj);
+  E.proto.cut = cuts;
+  E.proto.beams = c->d_beams;
+  E.proto.ctr = c->d_ctr;
+  E.proto.max_events = tu.events;
+  E.proto.max_secondaries = tu.secondaries;
+  for (int t = 0; t < 2; ++t) {
+    AdmitArgs& a = E.adm[t];
+    a = AdmitArgs{};
+    a.ph = dph;
+    a.cut = cuts;
+    a.plan = c->d_adm + t;
+    a.start = c->d_start + t * (c->beams_cap + 1);
+    a.beam_of = c->d_beam_of + t * c->beams_cap;
+    a.nb = (uint32_t)J.beam_of[t].size();
+    a.beams = c->d_beams;
+    a.sources = c->d_sources;
+    a.ctr = c->d_ctr;
+    a.nvox = (uint32_t)((size_t)J.P->nx * J.P->ny * J.P->nz);
+  }
+  c->t_pass[0] = c->t_pass[1] = 0.0;
+  c->n_pass[0] = c->n_pass[1] = 0;
+  return GMC_OK;
+}
+
+int add_pass_time(gmc_context* c, int type) {
+  float ms = 0.0f;
+  HIP_TRY(c, hipEventElapsedTime(&ms, c->kev0, c->kev1));
+  c->t_pass[type] += ms * 1e-3;
+  ++c->n_pass[type];
+  return GMC_OK;
+}
+
+// Plain form: counts read after admission and after the electron pass of
+// every round; passes with nothing to do are skipped.  A round in which no
+// primary was admitted and no pass transported anything leaves the state
+// unchanged, so the next one would too: that is reported, not looped on.
+int engine_run_plain(Engine& E, uint64_t* rounds) {
+  gmc_context* c = E.c;
+  Status st;
+  bool e_prog = true, g_ran = false;
+  for (;;) {
+    int rc = enqueue_admission(E);
+    if (rc) return rc;
+    rc = read_status(c, &st);
+    if (rc) return rc;
+    if (g_ran) rc = add_pass_time(c, 0);
+    if (rc) return rc;
+    if (st.done()) break;
+    const bool g_prog = g_ran && st.plan[0].m > 0;
+    if (*rounds > 0 && st.adm[0].count == 0 && st.adm[1].count == 0 && !e_prog && !g_prog) return stuck(c);
+    ++*rounds;
+    e_prog = false;
+    g_ran = false;
+    if (st.counts[2 + c->acc[1]] > 0) {
+      rc = enqueue_pass(E, 1, true);
+      if (rc) return rc;
+      rc = read_status(c, &st);
+      if (rc) return rc;
+      rc = add_pass_time(c, 1);
+      if (rc) return rc;
+      e_prog = st.plan[1].m > 0;
+    }
+    if (st.counts[c->acc[0]] > 0) {
+      rc = enqueue_pass(E, 0, true);
+      if (rc) return rc;
+      g_ran = true;
+    }
+  }
+  return GMC_OK;
+}
+
+// Batched form: two rounds captured in a graph (each type's buffers swap once
+// per round, so after two rounds the buffer roles are back where they
+// started) and replayed tu.rounds times between status reads.
+int engine_run_graph(Engine& E, uint64_t* rounds) {
+  gmc_context* c = E.c;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  int rc = GMC_OK;
+  for (int r = 0; r < 2 && rc == GMC_OK; ++r) {
+    rc = enqueue_admission(E);
+    if (rc == GMC_OK) rc = enqueue_pass(E, 1, false);
+    if (rc == GMC_OK) rc = enqueue_pass(E, 0, false);
+  }
+  const hipError_t ec = hipStreamEndCapture(c->stream, &graph);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (ec != hipSuccess) return fail(c, GMC_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(c, GMC_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  Status st;
+  for (;;) {
+    for (int i = 0; i < E.tu.rounds && e == hipSuccess; ++i) {
+      e = hipGraphLaunch(exec, c->stream);
+      if (e == hipSuccess) *rounds += 2;
+    }
+    if (e != hipSuccess) break;
+    rc = read_status(c, &st);
+    if (rc) break;
+    if (st.done()) break;
+    // the last round admitted nothing and both of its passes transported
+    // nothing: a fixed point
+    if (st.adm[0].count == 0 && st.adm[1].count == 0 && st.plan[0].m == 0 && st.plan[1].m == 0) {
+      rc = stuck(c);
+      break;
+    }
+  }
+  (void)hipGraphExecDestroy(exec);
+  if (e != hipSuccess) return fail(c, GMC_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+  return rc;
+}
+
+// Histories per batch, n_k = #{h < n : floor(h K / n) = k}.
+std::vector<double> batch_sizes(uint64_t n, uint32_t K) {
+  std::vector<double> nk(K);
+  for (uint32_t k = 0; k < K; ++k) {
+    const uint64_t lo = ((uint64_t)k * n + K - 1) / K, hi = ((uint64_t)(k + 1) * n + K - 1) / K;
+    nk[k] = (double)(hi - lo);
+  }
+  return nk;
+}
+
+// Dose and sigma of one tally ([K][nvox]) into device buffers (Eqs. 11-13).
+int finalize(gmc_context* c, const PhantomObj& P, const unsigned long long* tally, uint32_t K, uint64_t n,
+             double* d_dose, double* d_sigma, bool ledger) {
+  const std::vector<double> nk = batch_sizes(n, K);
+  HIP_TRY(c, hipMemcpyAsync(c->d_nk, nk.data(), K * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  FinalizeArgs fa;
+  fa.tally = tally;
+  fa.vox = P.d_vox;
+  fa.nk = c->d_nk;
+  fa.nvox = (uint32_t)((size_t)P.nx * P.ny * P.nz);
+  fa.K = K;
+  fa.n_total = (double)n;
+  fa.conv = kLsbMeV * 1.602176634e-13 / (P.dx * P.dy * P.dz * 1e-3);
+  fa.dose = d_dose;
+  fa.sigma = d_sigma;
+  fa.ctr = ledger ? c->d_ctr : nullptr;
+  HIP_TRY(c, launch_finalize(fa, c->stream));
+  // nk lives on the host stack: the copy must be done before it goes
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return GMC_OK;
+}
+
+int collect_stats(gmc_context* c, gmc_run_stats* stats, uint64_t n_hist, uint64_t rounds,
+                  std::chrono::steady_clock::time_point t_start) {
+  std::vector<unsigned long long> slots((size_t)C_COUNT * kCtrSlots);
+  HIP_TRY(c, hipMemcpyAsync(slots.data(), c->d_ctr, slots.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  float dev_ms = 0.0f;
+  HIP_TRY(c, hipEventElapsedTime(&dev_ms, c->ev0, c->ev1));
+  unsigned long long ctr[C_COUNT] = {};
+  for (int k = 0; k < C_COUNT; ++k)
+    for (int j = 0; j < kCtrSlots; ++j) ctr[k] += slots[(size_t)k * kCtrSlots + j];
+  const long long resid = (long long)(ctr[C_E_IN] - ctr[C_E_DEP] - ctr[C_E_ESC] - ctr[C_E_SINK]);
+  if (stats) {
+    stats->t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    stats->t_device_s = dev_ms * 1e-3;
+    stats->e_in_mev = ctr[C_E_IN] * kLsbMeV;
+    stats->e_dep_mev = ctr[C_E_DEP] * kLsbMeV;
+    stats->e_esc_mev = ctr[C_E_ESC] * kLsbMeV;
+    stats->e_sink_mev = ctr[C_E_SINK] * kLsbMeV;
+    stats->n_hist = n_hist;
+    stats->n_photon_events = ctr[C_PH_EVENTS];
+    stats->n_fictitious = ctr[C_FICT];
+    stats->n_e_steps = ctr[C_E_STEPS];
+    stats->n_hard = ctr[C_HARD];
+    stats->n_secondaries = ctr[C_SEC];
+    stats->n_majorant_violations = ctr[C_VIOL];
+    stats->n_passes = rounds;
+    stats->ledger_residual_lsb = resid;
+    stats->t_photon_pass_s = c->t_pass[0];
+    stats->t_electron_pass_s = c->t_pass[1];
+    stats->n_photon_launches = c->n_pass[0];
+    stats->n_electron_launches = c->n_pass[1];
+  }
+  if (ctr[C_OVERFLOW]) return fail(c, GMC_EINTERNAL, "queue overflow detected on the device");
+  if (resid != 0) return fail(c, GMC_EINTERNAL, "energy ledger does not close: residual " + std::to_string(resid));
+  return GMC_OK;
+}
+
+// The batched form works on the context's own capture stream, ordered after
+// the caller's stream on entry and before it on exit.
+struct StreamSwap {
+  gmc_context* c;
+  hipStream_t user;
+  bool on;
+  StreamSwap(gmc_context* ctx, bool enable) : c(ctx), user(ctx->stream), on(enable) {
+    if (!on) return;
+    (void)hipEventRecord(c->join, user);
+    (void)hipStreamWaitEvent(c->gstream, c->join, 0);
+    c->stream = c->gstream;
+  }
+  ~StreamSwap() {
+    if (!on) return;
+    (void)hipEventRecord(c->join, c->gstream);
+    (void)hipStreamWaitEvent(user, c->join, 0);
+    c->stream = user;
+  }
+};
+
+// Shared by the plain and batched forms.
+int run_job(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_source* srcs, const uint64_t* n_hist,
+            int n_beams, uint64_t seed, double* const* dose_per_beam, double* dose, double* sigma, int out_kind,
+            const gmc_tuning* tuning, gmc_run_stats* stats, bool batched) {
+  const auto t_start = std::chrono::steady_clock::now();
+  auto pi = c->phantoms.find(phantom_id);
+  auto ti = c->tables.find(tables_id);
+  if (pi == c->phantoms.end() || ti == c->tables.end()) return fail(c, GMC_ENOTFOUND, "unknown phantom or tables id");
+  const PhantomObj& P = *pi->second;
+  const TablesObj& T = *ti->second;
+  if (n_beams < 1 || n_beams > (1 << 20) || !srcs || !n_hist) return fail(c, GMC_EINVAL, "need 1 .. 2^20 beams");
+  if (!dose) return fail(c, GMC_EINVAL, "dose output is NULL");
+  if (out_kind != GMC_HOST && out_kind != GMC_DEVICE) return fail(c, GMC_EINVAL, "bad out_ptr_kind");
+  if (P.max_mat >= T.host.n_mat) return fail(c, GMC_EINVAL, "phantom uses a material index beyond the tables");
+  const uint32_t K = (uint32_t)T.phys.n_batches;
+  uint64_t n_total = 0, per_type[2] = {0, 0};
+  double e_sum = 0.0;
+  for (int b = 0; b < n_beams; ++b) {
+    const int rc = check_source(c, &srcs[b]);
+    if (rc) return rc;
+    if (n_hist[b] == 0) return fail(c, GMC_EINVAL, "every beam needs at least one history");
+    if (n_hist[b] >= (1ull << 32)) return fail(c, GMC_EINVAL, "histories must be < 2^32");
+    n_total += n_hist[b];
+    per_type[srcs[b].particle] += n_hist[b];
+    const double e_max = srcs[b].spectrum == GMC_MONO ? srcs[b].e_mev : srcs[b].e_hi;
+    e_sum += (double)n_hist[b] * (e_max * 134217728.0 + 1.0);
+  }
+  if (n_total < K) return fail(c, GMC_EINVAL, "need at least n_batches histories");
+  if (n_total >= (1ull << 32)) return fail(c, GMC_EINVAL, "total histories must be < 2^32");
+  if (e_sum >= 9.2e18) return fail(c, GMC_EOVERFLOW, "histories x energy would overflow the 64-bit tallies");
+  (void)hipSetDevice(c->device);
+  const Tune tu = resolve_tuning(tuning);
+  const size_t nvox = (size_t)P.nx * P.ny * P.nz;
+  const bool per_beam = batched && dose_per_beam != nullptr;
+  const size_t tally_elems = nvox * ((size_t)K + (per_beam ? (size_t)n_beams : 0u));
+  int rc = ensure_tally(c, tally_elems);
+  if (rc) return rc;
+  rc = ensure_out(c, nvox);
+  if (rc) return rc;
+
+  Job J;
+  J.P = &P;
+  J.T = &T;
+  rc = get_majorants(c, phantom_id, tables_id, P, T, &J.maj);
+  if (rc) return rc;
+  for (int t = 0; t < 2; ++t) J.start[t].push_back(0u);
+  uint32_t off = 0;
+  for (int b = 0; b < n_beams; ++b) {
+    DevBeam db{};
+    db.key0 = (uint32_t)seed;
+    db.key1 = (uint32_t)(seed >> 32) ^ srcs[b].beam_id;
+    const DevTally comb{c->d_tally, (uint32_t)n_total, K, off};
+    if (per_beam) {
+      db.a = DevTally{c->d_tally + nvox * ((size_t)K + (size_t)b), (uint32_t)n_hist[b], 1u, 0u};
+      db.b = comb;
+    } else {
+      db.a = comb;
+      db.b = DevTally{nullptr, 1u, 1u, 0u};
+    }
+    J.beams.push_back(db);
+    J.sources.push_back(dev_source(srcs[b]));
+    const int t = srcs[b].particle;
+    J.beam_of[t].push_back((uint32_t)b);
+    J.start[t].push_back(J.start[t].back() + (uint32_t)n_hist[b]);
+    off += (uint32_t)n_hist[b];
+  }
+  J.total[0] = (uint32_t)per_type[0];
+  J.total[1] = (uint32_t)per_type[1];
+
+  StreamSwap swap(c, batched);
+  HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+  HIP_TRY(c, launch_fill_u64(c->d_tally, tally_elems, 0ull, c->stream));
+  Engine E;
+  rc = engine_setup(c, E, J, tu);
+  if (rc) return rc;
+  uint64_t rounds = 0;
+  rc = batched ? engine_run_graph(E, &rounds) : engine_run_plain(E, &rounds);
+  if (rc) return rc;
+
+  double* d_out = out_kind == GMC_DEVICE ? dose : c->d_dose;
+  double* s_out = sigma ? (out_kind == GMC_DEVICE ? sigma : c->d_sigma) : nullptr;
+  rc = finalize(c, P, c->d_tally, K, n_total, d_out, s_out, true);
+  if (rc) return rc;
+  if (out_kind == GMC_HOST) {
+    rc = copy_out(c, dose, c->d_dose, nvox, GMC_HOST);
+    if (rc) return rc;
+    if (sigma) rc = copy_out(c, sigma, c->d_sigma, nvox, GMC_HOST);
+    if (rc) return rc;
+  }
+  if (per_beam) {
+    for (int b = 0; b < n_beams; ++b) {
+      if (!dose_per_beam[b]) continue;
+      double* dst = out_kind == GMC_DEVICE ? dose_per_beam[b] : c->d_dose;
+      rc = finalize(c, P, c->d_tally + nvox * ((size_t)K + (size_t)b), 1u, n_hist[b], dst, nullptr, false);
+      if (rc) return rc;
+      if (out_kind == GMC_HOST) {
+        rc = copy_out(c, dose_per_beam[b], c->d_dose, nvox, GMC_HOST);
+        if (rc) return rc;
+      }
+    }
+  }
+  return collect_stats(c, stats, n_total, rounds, t_start);
 }
 
 }  // namespace
@@ -395,11 +829,16 @@ int gmc_create(int device, void* hip_stream, gmc_context** out) {
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) { delete c; return GMC_EDEVICE; }
     c->own_stream = true;
   }
-  if (hipMalloc(&c->d_counts, 2 * sizeof(uint32_t)) != hipSuccess ||
+  if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->join, hipEventDisableTiming) != hipSuccess ||
+      hipMalloc(&c->d_counts, 4 * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(&c->d_sched, 4 * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(&c->d_adm, 2 * sizeof(AdmitPlan)) != hipSuccess ||
+      hipMalloc(&c->d_plan, 2 * sizeof(PassPlan)) != hipSuccess ||
       hipMalloc(&c->d_ctr, C_COUNT * kCtrSlots * sizeof(unsigned long long)) != hipSuccess ||
       hipMalloc(&c->d_nk, kMaxBatches * sizeof(double)) != hipSuccess ||
       hipMalloc(&c->d_used, 2 * kMaxWaves * sizeof(uint32_t)) != hipSuccess ||
-      hipMalloc(&c->d_offsets, 2 * kMaxWaves * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(&c->d_offsets, 2 * (kMaxWaves + 1) * sizeof(uint32_t)) != hipSuccess ||
       hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
       hipEventCreate(&c->kev0) != hipSuccess || hipEventCreate(&c->kev1) != hipSuccess) {
     gmc_destroy(c);
@@ -413,21 +852,27 @@ void gmc_destroy(gmc_context* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->gstream) (void)hipStreamSynchronize(c->gstream);
   for (auto& kv : c->tables) {
-    (void)hipFree(kv.second->d_ph); (void)hipFree(kv.second->d_el); (void)hipFree(kv.second->d_ms);
+    (void)hipFree(kv.second->d_ph);
+    (void)hipFree(kv.second->d_el);
+    (void)hipFree(kv.second->d_ms);
   }
   for (auto& kv : c->phantoms) (void)hipFree(kv.second->d_vox);
-  for (auto& kv : c->majorants) { (void)hipFree(kv.second.d_g); (void)hipFree(kv.second.d_e); }
+  for (auto& kv : c->majorants) {
+    (void)hipFree(kv.second.d_g);
+    (void)hipFree(kv.second.d_e);
+  }
   for (auto& t : c->qbuf)
     for (auto& b : t) free_queue(b);
   for (auto& b : c->stg) free_queue(b);
-  (void)hipFree(c->d_used); (void)hipFree(c->d_offsets);
-  (void)hipFree(c->d_counts); (void)hipFree(c->d_ctr); (void)hipFree(c->d_tally); (void)hipFree(c->d_beams);
-  (void)hipFree(c->d_nk); (void)hipFree(c->d_dose); (void)hipFree(c->d_sigma);
-  if (c->ev0) (void)hipEventDestroy(c->ev0);
-  if (c->ev1) (void)hipEventDestroy(c->ev1);
-  if (c->kev0) (void)hipEventDestroy(c->kev0);
-  if (c->kev1) (void)hipEventDestroy(c->kev1);
+  for (void* p : {(void*)c->d_used, (void*)c->d_offsets, (void*)c->d_sched, (void*)c->d_adm, (void*)c->d_plan,
+                  (void*)c->d_counts, (void*)c->d_ctr, (void*)c->d_tally, (void*)c->d_beams, (void*)c->d_sources,
+                  (void*)c->d_start, (void*)c->d_beam_of, (void*)c->d_nk, (void*)c->d_dose, (void*)c->d_sigma})
+    if (p) (void)hipFree(p);
+  for (hipEvent_t e : {c->ev0, c->ev1, c->kev0, c->kev1, c->join})
+    if (e) (void)hipEventDestroy(e);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -516,7 +961,8 @@ int gmc_release(gmc_context* c, int32_t id) {
   auto drop_maj = [&](bool by_phantom) {
     for (auto it = c->majorants.begin(); it != c->majorants.end();) {
       if ((by_phantom ? it->first.first : it->first.second) == id) {
-        (void)hipFree(it->second.d_g); (void)hipFree(it->second.d_e);
+        (void)hipFree(it->second.d_g);
+        (void)hipFree(it->second.d_e);
         it = c->majorants.erase(it);
       } else {
         ++it;
@@ -525,7 +971,9 @@ int gmc_release(gmc_context* c, int32_t id) {
   };
   auto t = c->tables.find(id);
   if (t != c->tables.end()) {
-    (void)hipFree(t->second->d_ph); (void)hipFree(t->second->d_el); (void)hipFree(t->second->d_ms);
+    (void)hipFree(t->second->d_ph);
+    (void)hipFree(t->second->d_el);
+    (void)hipFree(t->second->d_ms);
     c->tables.erase(t);
     drop_maj(false);
     return GMC_OK;
@@ -540,169 +988,26 @@ int gmc_release(gmc_context* c, int32_t id) {
   return fail(c, GMC_ENOTFOUND, "unknown id " + std::to_string(id));
 }
 
-int gmc_run_beam(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_source* src,
-                 uint64_t n_hist, uint64_t seed, double* dose, double* sigma, int out_kind,
-                 const gmc_tuning* tuning, gmc_run_stats* stats) {
+int gmc_run_beam(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_source* src, uint64_t n_hist,
+                 uint64_t seed, double* dose, double* sigma, int out_kind, const gmc_tuning* tuning,
+                 gmc_run_stats* stats) {
   if (!c) return GMC_EINVAL;
-  const auto t_start = std::chrono::steady_clock::now();
-  auto pi = c->phantoms.find(phantom_id);
-  auto ti = c->tables.find(tables_id);
-  if (pi == c->phantoms.end() || ti == c->tables.end()) return fail(c, GMC_ENOTFOUND, "unknown phantom or tables id");
-  const PhantomObj& P = *pi->second;
-  const TablesObj& T = *ti->second;
-  int rc = check_source(c, src);
-  if (rc) return rc;
-  if (!dose) return fail(c, GMC_EINVAL, "dose output is NULL");
-  if (out_kind != GMC_HOST && out_kind != GMC_DEVICE) return fail(c, GMC_EINVAL, "bad out_ptr_kind");
-  if (P.max_mat >= T.host.n_mat) return fail(c, GMC_EINVAL, "phantom uses a material index beyond the tables");
-  const uint32_t K = (uint32_t)T.phys.n_batches;
-  if (n_hist < K || n_hist >= (1ull << 32)) return fail(c, GMC_EINVAL, "n_histories must be in [n_batches, 2^32)");
-  const double emax = src->spectrum == GMC_MONO ? src->e_mev : src->e_hi;
-  if ((double)n_hist * (emax * 134217728.0 + 1.0) >= 9.2e18)
-    return fail(c, GMC_EOVERFLOW, "n_histories * energy would overflow the 64-bit tallies");
-  (void)hipSetDevice(c->device);
-  const Tune tu = resolve_tuning(tuning);
-  const size_t nvox = (size_t)P.nx * P.ny * P.nz;
-
-  MajObj maj;
-  rc = get_majorants(c, phantom_id, tables_id, P, T, &maj);
-  if (rc) return rc;
-  // worst-case per-visit output must fit a chunk; the queues hold the chunk many times over
-  // 12 fields of a queue stay addressable with 32-bit word indices below 2^32
-  const uint32_t want_cap = std::max<uint32_t>(kDefaultCap, (uint32_t)std::min<uint64_t>(
-      (uint64_t)tu.chunk * (tu.secondaries + 1) * 2, 1u << 26));
-  rc = ensure_queues(c, want_cap);
-  if (rc) return rc;
-  rc = ensure_tally(c, (size_t)K * nvox);
-  if (rc) return rc;
-  rc = ensure_beams(c, 1);
-  if (rc) return rc;
-  if (out_kind == GMC_HOST || !sigma) {
-    rc = ensure_out(c, nvox);
-    if (rc) return rc;
-  }
-
-  // batch sizes n_k = #{h : floor(h K / N) = k}
-  std::vector<double> nk(K, 0.0);
-  for (uint32_t k = 0; k < K; ++k) {
-    const uint64_t lo = (k * n_hist + K - 1) / K, hi = ((k + 1) * n_hist + K - 1) / K;
-    nk[k] = (double)(hi - lo);
-  }
-  DevBeam beam;
-  beam.key0 = (uint32_t)seed;
-  beam.key1 = (uint32_t)(seed >> 32) ^ src->beam_id;
-  beam.nhist = (uint32_t)n_hist;
-  beam.nbatch = K;
-  beam.tally = c->d_tally;
-
-  HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(c->d_beams, &beam, sizeof(beam), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(c->d_nk, nk.data(), K * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, launch_fill_u64(c->d_tally, (size_t)K * nvox, 0ull, c->stream));
-  HIP_TRY(c, hipMemsetAsync(c->d_ctr, 0, C_COUNT * kCtrSlots * sizeof(unsigned long long), c->stream));
-  HIP_TRY(c, hipMemsetAsync(c->d_counts, 0, 2 * sizeof(uint32_t), c->stream));
-
-  const DevPhantom dph = dev_phantom(P);
-  const DevCuts cuts = dev_cuts(T);
-  PassArgs proto{};
-  proto.ph = dph;
-  proto.tab = dev_tables(T, maj);
-  proto.cut = cuts;
-  proto.beams = c->d_beams;
-  proto.ctr = c->d_ctr;
-
-  SourceArgs sa{};
-  sa.ph = dph;
-  sa.cut = cuts;
-  sa.beams = c->d_beams;
-  sa.ctr = c->d_ctr;
-  sa.beam = 0;
-  sa.spectrum = src->spectrum;
-  sa.e_lsb = mev_to_lsb(src->e_mev);
-  sa.e_lo = (float)src->e_lo; sa.e_mode = (float)src->e_mode; sa.e_hi = (float)src->e_hi;
-  sa.cx = (float)src->cx_cm; sa.cy = (float)src->cy_cm; sa.wx = (float)src->wx_cm; sa.wy = (float)src->wy_cm;
-  sa.particle = src->particle;
-
-  c->t_pass[0] = c->t_pass[1] = 0.0;
-  c->n_pass[0] = c->n_pass[1] = 0;
-  const int ptype = src->particle == GMC_PHOTON ? 0 : 1;
-  uint32_t counts[2] = {0, 0};
-  uint64_t admitted = 0, launches = 0;
-  for (;;) {
-    if (admitted < n_hist && counts[0] + counts[1] < (uint32_t)tu.chunk) {
-      const uint32_t room = c->cap - counts[ptype];
-      const uint32_t cnt = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(tu.chunk, n_hist - admitted), room);
-      if (cnt == 0) return fail(c, GMC_EOVERFLOW, "no room to admit primaries");
-      sa.out = c->qbuf[ptype][c->pend_idx[ptype]].q;
-      sa.out_base = counts[ptype];
-      sa.out_count = c->d_counts + ptype;
-      sa.h0 = (uint32_t)admitted;
-      sa.count = cnt;
-      HIP_TRY(c, launch_source(sa, c->stream));
-      admitted += cnt;
-      counts[ptype] += cnt;
-    }
-    if (counts[1]) { rc = run_pass(c, 1, proto, tu, counts, &launches); if (rc) return rc; }
-    if (counts[0]) { rc = run_pass(c, 0, proto, tu, counts, &launches); if (rc) return rc; }
-    if (admitted == n_hist && counts[0] == 0 && counts[1] == 0) break;
-  }
-
-  FinalizeArgs fa;
-  fa.tally = c->d_tally;
-  fa.vox = P.d_vox;
-  fa.nk = c->d_nk;
-  fa.nvox = (uint32_t)nvox;
-  fa.K = K;
-  fa.n_total = (double)n_hist;
-  fa.conv = kLsbMeV * 1.602176634e-13 / (P.dx * P.dy * P.dz * 1e-3);
-  fa.dose = out_kind == GMC_DEVICE ? dose : c->d_dose;
-  fa.sigma = sigma ? (out_kind == GMC_DEVICE ? sigma : c->d_sigma) : nullptr;
-  fa.ctr = c->d_ctr;
-  HIP_TRY(c, launch_finalize(fa, c->stream));
-  if (out_kind == GMC_HOST) {
-    rc = copy_out(c, dose, c->d_dose, nvox, GMC_HOST);
-    if (rc) return rc;
-    if (sigma) { rc = copy_out(c, sigma, c->d_sigma, nvox, GMC_HOST); if (rc) return rc; }
-  }
-  std::vector<unsigned long long> slots((size_t)C_COUNT * kCtrSlots);
-  HIP_TRY(c, hipMemcpyAsync(slots.data(), c->d_ctr, slots.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                            c->stream));
-  HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  float dev_ms = 0.0f;
-  (void)hipEventElapsedTime(&dev_ms, c->ev0, c->ev1);
-  unsigned long long ctr[C_COUNT] = {};
-  for (int k = 0; k < C_COUNT; ++k)
-    for (int j = 0; j < kCtrSlots; ++j) ctr[k] += slots[(size_t)k * kCtrSlots + j];
-  const long long resid = (long long)(ctr[C_E_IN] - ctr[C_E_DEP] - ctr[C_E_ESC] - ctr[C_E_SINK]);
-  if (stats) {
-    stats->t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-    stats->t_device_s = dev_ms * 1e-3;
-    stats->e_in_mev = ctr[C_E_IN] * kLsbMeV;
-    stats->e_dep_mev = ctr[C_E_DEP] * kLsbMeV;
-    stats->e_esc_mev = ctr[C_E_ESC] * kLsbMeV;
-    stats->e_sink_mev = ctr[C_E_SINK] * kLsbMeV;
-    stats->n_hist = n_hist;
-    stats->n_photon_events = ctr[C_PH_EVENTS];
-    stats->n_fictitious = ctr[C_FICT];
-    stats->n_e_steps = ctr[C_E_STEPS];
-    stats->n_hard = ctr[C_HARD];
-    stats->n_secondaries = ctr[C_SEC];
-    stats->n_majorant_violations = ctr[C_VIOL];
-    stats->n_passes = launches;
-    stats->ledger_residual_lsb = resid;
-    stats->t_photon_pass_s = c->t_pass[0];
-    stats->t_electron_pass_s = c->t_pass[1];
-    stats->n_photon_launches = c->n_pass[0];
-    stats->n_electron_launches = c->n_pass[1];
-  }
-  if (ctr[C_OVERFLOW]) return fail(c, GMC_EINTERNAL, "queue overflow detected on the device");
-  if (resid != 0) return fail(c, GMC_EINTERNAL, "energy ledger does not close: residual " + std::to_string(resid));
-  return GMC_OK;
+  if (!src) return fail(c, GMC_EINVAL, "source is NULL");
+  return run_job(c, phantom_id, tables_id, src, &n_hist, 1, seed, nullptr, dose, sigma, out_kind, tuning, stats,
+                 false);
 }
 
-int gmc_rng_words(gmc_context* c, uint64_t seed, uint32_t beam, uint32_t hist, uint64_t path, uint32_t n0,
-                  int count, uint32_t* out) {
+int gmc_run_beams(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_source* srcs,
+                  const uint64_t* n_hist, int n_beams, uint64_t seed, double* const* dose_per_beam,
+                  double* combined_dose, double* combined_sigma, int out_kind, const gmc_tuning* tuning,
+                  gmc_run_stats* stats) {
+  if (!c) return GMC_EINVAL;
+  return run_job(c, phantom_id, tables_id, srcs, n_hist, n_beams, seed, dose_per_beam, combined_dose, combined_sigma,
+                 out_kind, tuning, stats, true);
+}
+
+int gmc_rng_words(gmc_context* c, uint64_t seed, uint32_t beam, uint32_t hist, uint64_t path, uint32_t n0, int count,
+                  uint32_t* out) {
   if (!c) return GMC_EINVAL;
   if (!out || count < 0) return fail(c, GMC_EINVAL, "bad output");
   if (count == 0) return GMC_OK;
@@ -732,8 +1037,8 @@ int gmc_table_eval(gmc_context* c, int32_t tables_id, int which, int mat, const 
   float *de = nullptr, *dout = nullptr;
   HIP_TRY(c, hipMalloc(&de, n * sizeof(float)));
   HIP_TRY(c, hipMalloc(&dout, n * sizeof(float)));
-  MajObj none;
-  DevTables t = dev_tables(*ti->second, none);
+  const MajObj none;
+  const DevTables t = dev_tables(*ti->second, none);
   hipError_t e = hipMemcpyAsync(de, ef.data(), n * sizeof(float), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = launch_table_eval(t, which, mat, de, n, dout, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(of.data(), dout, n * sizeof(float), hipMemcpyDeviceToHost, c->stream);
@@ -769,36 +1074,26 @@ int gmc_first_events(gmc_context* c, int32_t phantom_id, int32_t tables_id, cons
   DevBeam beam{};
   beam.key0 = (uint32_t)seed;
   beam.key1 = (uint32_t)(seed >> 32) ^ src->beam_id;
-  beam.nhist = 1;
-  beam.nbatch = 1;
-  beam.tally = nullptr;
+  beam.a = DevTally{nullptr, 1u, 1u, 0u};
+  beam.b = DevTally{nullptr, 1u, 1u, 0u};
   PassArgs a{};
   a.ph = dev_phantom(P);
   a.tab = dev_tables(T, maj);
   a.cut = dev_cuts(T);
   a.beams = c->d_beams;
-  SourceArgs sa{};
-  sa.ph = a.ph;
-  sa.cut = a.cut;
-  sa.beam = 0;
-  sa.h0 = h_begin;
-  sa.count = n;
-  sa.spectrum = src->spectrum;
-  sa.e_lsb = mev_to_lsb(src->e_mev);
-  sa.e_lo = (float)src->e_lo; sa.e_mode = (float)src->e_mode; sa.e_hi = (float)src->e_hi;
-  sa.cx = (float)src->cx_cm; sa.cy = (float)src->cy_cm; sa.wx = (float)src->wx_cm; sa.wy = (float)src->wy_cm;
-  sa.particle = 0;
+  const DevSource ds = dev_source(*src);
   float* dx = nullptr;
   uint32_t* dn = nullptr;
+  HIP_TRY(c, hipMemcpy(c->d_beams, &beam, sizeof(beam), hipMemcpyHostToDevice));
   HIP_TRY(c, hipMalloc(&dx, (size_t)n * 3 * sizeof(float)));
-  HIP_TRY(c, hipMalloc(&dn, (size_t)n * sizeof(uint32_t)));
-  hipError_t e = hipMemcpyAsync(c->d_beams, &beam, sizeof(beam), hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = launch_first_events(a, sa, dx, dn, c->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(out_xyz, dx, (size_t)n * 3 * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+  hipError_t e = hipMalloc(&dn, (size_t)n * sizeof(uint32_t));
+  if (e == hipSuccess) e = launch_first_events(a, ds, h_begin, n, dx, dn, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out_xyz, dx, (size_t)n * 3 * sizeof(float), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(out_nused, dn, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   (void)hipFree(dx);
-  (void)hipFree(dn);
+  if (dn) (void)hipFree(dn);
   if (e != hipSuccess) return fail(c, GMC_EDEVICE, hipGetErrorString(e));
   return GMC_OK;
 }

@@ -62,7 +62,8 @@ class gmc_run_stats(C.Structure):
 
 class gmc_tuning(C.Structure):
     _fields_ = [("events_per_visit", C.c_int), ("secondaries_per_visit", C.c_int), ("chunk", C.c_int),
-                ("wg_size", C.c_int)]
+                ("wg_size", C.c_int), ("pass_items", C.c_int), ("wave_items", C.c_int),
+                ("rounds_per_check", C.c_int)]
 
 
 _lib = None
@@ -105,6 +106,9 @@ def lib():
     L.gmc_release.argtypes = [vp, C.c_int32]
     L.gmc_run_beam.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(gmc_source), C.c_uint64, C.c_uint64, vp, vp,
                                C.c_int, C.POINTER(gmc_tuning), C.POINTER(gmc_run_stats)]
+    L.gmc_run_beams.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(gmc_source), C.POINTER(C.c_uint64), C.c_int,
+                                C.c_uint64, C.POINTER(vp), vp, vp, C.c_int, C.POINTER(gmc_tuning),
+                                C.POINTER(gmc_run_stats)]
     L.gmc_rng_words.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint32, C.c_int,
                                 C.POINTER(C.c_uint32)]
     L.gmc_table_eval.argtypes = [vp, C.c_int32, C.c_int, C.c_int, dp, C.c_int, dp]
@@ -129,8 +133,10 @@ def _tuning(t) -> Optional[gmc_tuning]:
         return None
     if isinstance(t, gmc_tuning):
         return t
-    return gmc_tuning(int(t.get("events_per_visit", 0)), int(t.get("secondaries_per_visit", 0)),
-                      int(t.get("chunk", 0)), int(t.get("wg_size", 0)))
+    unknown = set(t) - {f for f, _ in gmc_tuning._fields_}
+    if unknown:
+        raise ValueError("unknown tuning keys: %s" % sorted(unknown))
+    return gmc_tuning(*[int(t.get(f, 0)) for f, _ in gmc_tuning._fields_])
 
 
 def stats_dict(st: gmc_run_stats) -> dict:
@@ -224,6 +230,44 @@ class Context:
                                   s.ctypes.data if s is not None else None, GMC_HOST, tun_p, C.byref(st))
         self._check(rc)
         return d.reshape(shape), (s.reshape(shape) if s is not None else None), stats_dict(st)
+
+    def run_beams(self, phantom_id: int, tables_id: int, sources, n_hist, seed: int, shape=None, tuning=None,
+                  per_beam: bool = False, sigma: bool = True, out: str = "numpy"):
+        """Batched form: several beams in one job.  Returns (per_beam_dose or
+        None, combined_dose, combined_sigma or None, stats); per_beam_dose has
+        shape (n_beams, nz, ny, nx)."""
+        if shape is None:
+            raise ValueError("shape (nz, ny, nx) is required")
+        nb = len(sources)
+        if nb != len(n_hist):
+            raise ValueError("one history count per source")
+        st = gmc_run_stats()
+        srcs = (gmc_source * nb)(*[_src(s) for s in sources])
+        counts = (C.c_uint64 * nb)(*[int(n) for n in n_hist])
+        tun = _tuning(tuning)
+        tun_p = C.byref(tun) if tun is not None else None
+        n = int(np.prod(shape))
+        if out == "torch":
+            import torch
+            mk = lambda *sz: torch.empty(*sz, dtype=torch.float64, device="cuda")  # noqa: E731
+            ptr = lambda a: a.data_ptr()  # noqa: E731
+            kind = GMC_DEVICE
+        else:
+            mk = lambda *sz: np.empty(sz, np.float64)  # noqa: E731
+            ptr = lambda a: a.ctypes.data  # noqa: E731
+            kind = GMC_HOST
+        d = mk(n)
+        s = mk(n) if sigma else None
+        pb = mk(nb, n) if per_beam else None
+        pb_ptrs = None
+        if pb is not None:
+            row = n * 8
+            pb_ptrs = (C.c_void_p * nb)(*[ptr(pb) + b * row for b in range(nb)])
+        rc = self._L.gmc_run_beams(self._h, phantom_id, tables_id, srcs, counts, nb, seed, pb_ptrs, ptr(d),
+                                   ptr(s) if s is not None else None, kind, tun_p, C.byref(st))
+        self._check(rc)
+        rs = lambda a, sh: a.reshape(*sh) if a is not None else None  # noqa: E731
+        return rs(pb, (nb,) + tuple(shape)), rs(d, tuple(shape)), rs(s, tuple(shape)), stats_dict(st)
 
     # ------------------------------------------------------------- checks
     def rng_words(self, seed: int, beam: int, hist: int, path: int, n0: int, count: int) -> np.ndarray:

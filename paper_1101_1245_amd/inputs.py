@@ -199,3 +199,29 @@ def beamlets(seed: int = 11, phantom_seed: int = 7, n_beamlets: int = 256, shape
         cy = ey / 2.0 + (gy - (side - 1) / 2.0) * 1.0
         srcs.append(Source(int(kinds[i]), MONO, float(energies[i]), cx=cx, cy=cy, wx=0.5, wy=0.5, beam_id=i))
     return ph, srcs, counts
+
+
+@dataclass
+class BeamJob:
+    """Several beams on one phantom, run as one job (the batched form)."""
+    name: str
+    materials: Tuple[Material, ...]
+    phantom: Phantom
+    sources: List[Source]
+    counts: np.ndarray           # histories per beam, uint64
+    physics: Physics
+    seed: int = 1
+
+
+def beamlet_job(n_beamlets: int = 256, shape=(200, 200, 160), voxel: float = 0.25, count_scale: float = 1.0,
+                min_count: int = 1, seed: int = 11, phantom_seed: int = 7) -> BeamJob:
+    """The pencil-beamlet batch on the ellipsoid phantom (four materials:
+    lung, water, soft tissue, bone), ECUT 0.7 (kinetic) and PCUT 0.01 MeV as
+    in the 15 MeV and slab set-ups.  ``count_scale`` shrinks every history
+    count (for oracle-sized cases), never below ``min_count``."""
+    ph, srcs, counts = beamlets(seed, phantom_seed, n_beamlets, shape, voxel)
+    if count_scale != 1.0:
+        counts = np.maximum(np.round(counts * count_scale), min_count).astype(np.uint64)
+    name = "beamlets_%d_%dx%dx%d" % (n_beamlets, shape[0], shape[1], shape[2])
+    return BeamJob(name, DEFAULT_MATERIALS, ph, srcs, counts, Physics(ecut=0.7, pcut=0.01))
+
