@@ -919,8 +919,9 @@ int orc_run(const orc_material* mats, int n_mat, const orc_phantom* ph,
       part_t q = c.stack[--c.sp];
       if (q.type == 0) photon_run(&c, &q); else electron_run(&c, &q);
     }
-    /* History-by-history tallies for Eq. 13 and batch sums. */
-    size_t k = (size_t)((h * (uint64_t)nb) / n_total);
+    /* History-by-history tallies for Eq. 13 and batch sums; history h
+     * belongs to batch h mod K (batches interleaved over the histories). */
+    size_t k = (size_t)(h % (uint64_t)nb);
     for (size_t i = 0; i < c.n_touched; ++i) {
       size_t w = c.touched[i];
       double t = c.tmp[w];

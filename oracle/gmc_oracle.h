@@ -81,7 +81,8 @@ int orc_majorants(const orc_material* mats, int n_mat, const orc_phantom* ph,
 
 /* Run histories [h_begin, h_end) of a beam of n_total histories.
  * e1[v] += sum_h E_vh, e2[v] += sum_h E_vh^2 (history by history, Eq. 13),
- * eb[k*nvox + v] += batch sums (nullable).  Accumulates into the outputs.
+ * eb[k*nvox + v] += batch sums, history h in batch k = h mod K (nullable).
+ * Accumulates into the outputs.
  * Returns 0, or a negative code for invalid input. */
 int orc_run(const orc_material* mats, int n_mat, const orc_phantom* ph,
             const orc_source* src, const orc_physics* phys, uint64_t seed,

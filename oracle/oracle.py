@@ -324,12 +324,12 @@ def dose(result: OracleResult, phantom, n_total: Optional[int] = None):
 
 def batch_sigma(result: OracleResult, phantom, n_total: int):
     """Batch estimate of the uncertainty of the mean dose, K batches of
-    histories h with k = floor(h K / N): sigma^2 = sum_k n_k^2 (m_k - m)^2 /
+    histories h with k = h mod K: sigma^2 = sum_k n_k^2 (m_k - m)^2 /
     (N^2 (K-1)/K), m_k the per-history mean of batch k (equal-size batches
     give the textbook sum_k (m_k - m)^2 / (K (K-1)))."""
     K = result.eb.shape[0]
     h = np.arange(n_total, dtype=np.int64)
-    nk = np.bincount((h * K) // n_total, minlength=K).astype(np.float64)
+    nk = np.bincount(h % K, minlength=K).astype(np.float64)
     rho = np.asarray(phantom.rho, dtype=np.float64)
     vol = float(np.prod(phantom.voxel))
     with np.errstate(divide="ignore", invalid="ignore"):
