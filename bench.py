@@ -1,17 +1,29 @@
 #!/usr/bin/env python3
-"""Throughput benchmark: histories/s at 1% statistical uncertainty.
+"""Throughput benchmark: histories/s at 1% statistical uncertainty, plain vs batched.
 
-Workload (the paper's Table IV set-up): 15 MeV monoenergetic parallel beams,
-10 x 10 cm field, on a 64^3 water phantom of 0.5 cm voxels, ECUT 0.7 MeV
-(kinetic), PCUT 0.01 MeV: one electron beam and one photon beam.  A pilot run
-at the paper's counts (1e6 electrons, 4e6 photons) measures the uncertainty s
-of Eq. 12; each beam is then run with the histories N_1% that bring s to 1%.
-One step = both beams at N_1% through the plain form (alternating electron and
-photon passes), inputs resident in HBM, outputs left in device memory.
+Default workload (the paper's Table IV set-up): 15 MeV monoenergetic parallel
+beams, 10 x 10 cm field, on a 64^3 water phantom of 0.5 cm voxels, ECUT 0.7
+MeV (kinetic), PCUT 0.01 MeV: one electron beam and one photon beam.  A pilot
+run at the paper's counts (1e6 electrons, 4e6 photons) measures the
+uncertainty s of Eq. 12 for each beam; each beam is then run with the
+histories N_1% that bring s to 1%.  One step = both beams at N_1%:
+
+* plain leg: two gmc_run_beam calls (one beam per sequence of passes);
+* batched leg: one gmc_run_beams call holding both beams (graph-replayed
+  rounds), with each beam's own dose as well as the combined one.
+
+`value` is the batched leg's rate; the plain leg's is reported beside it.
+Inputs are resident in HBM and outputs stay in device memory.
+
+``--workload beamlets``: 256 pencil beamlets (0.5 x 0.5 cm, 1-20 MeV,
+photons:electrons 3:1, 1e4-1e6 histories each) on a 200x200x160 ellipsoid
+phantom at 0.25 cm; plain = 256 gmc_run_beam calls, batched = one
+gmc_run_beams call with per-beamlet doses.
 
 Prints one JSON line with the throughput, the roofline of the dominant kernel
-(live HIP-event durations of the pass launches) and the oracle's CPU rate on
-a bounded sample.
+(average launch duration from the HIP event pairs around every pass launch in
+the timed region) and, for the default workload, the oracle's CPU rate on a
+bounded sample.
 """
 import argparse
 import json
@@ -25,14 +37,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # Algorithmic work per unit (lane operations): one condensed electron step and
-# one photon flight + interaction decision; see the design doc for the derivation.
+# one photon flight + interaction decision (derivation in the design notes).
 OPS_PER_E_STEP = 400.0
 OPS_PER_PH_EVENT = 175.0
 # 32-bit VALU lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (no packed FP32).
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
 
-def cpu_baseline(seconds_target=15.0):
+def cpu_baseline():
     """The FP64 oracle, single-threaded, on a bounded sample of the same beams."""
     from oracle import oracle as O
     from paper_1101_1245_amd import inputs as I
@@ -49,24 +61,59 @@ def cpu_baseline(seconds_target=15.0):
                       (ne, t1 - t0, ng, t2 - t1, platform.processor() or platform.machine())}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--target", type=float, default=0.01, help="statistical uncertainty s of Eq. 12")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the per-GPU transport is the product; "
-              "sharding across GPUs is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
+class Acc:
+    """Sums of pass-kernel times and work units over runs."""
 
+    def __init__(self):
+        self.t = [0.0, 0.0]      # photon, electron pass seconds
+        self.n = [0, 0]          # launches
+        self.steps = 0
+        self.events = 0
+        self.resid = 0
+        self.hist = 0
+
+    def add(self, st):
+        self.t[0] += st["t_photon_pass_s"]
+        self.t[1] += st["t_electron_pass_s"]
+        self.n[0] += st["n_photon_launches"]
+        self.n[1] += st["n_electron_launches"]
+        self.steps += st["n_e_steps"]
+        self.events += st["n_photon_events"]
+        self.resid |= st["ledger_residual_lsb"]
+        self.hist += st["n_hist"]
+
+    def merge(self, o):
+        for i in range(2):
+            self.t[i] += o.t[i]
+            self.n[i] += o.n[i]
+        self.steps += o.steps
+        self.events += o.events
+        self.resid |= o.resid
+        self.hist += o.hist
+
+
+def roofline(acc):
+    """Dominant pass kernel (most device time), its average launch duration and
+    algorithmic lane-ops per launch against the VALU lane-op peak."""
+    if acc.t[1] >= acc.t[0]:
+        name, t, n, ops = "k_electron_pass", acc.t[1], acc.n[1], acc.steps * OPS_PER_E_STEP
+    else:
+        name, t, n, ops = "k_photon_pass", acc.t[0], acc.n[0], acc.events * OPS_PER_PH_EVENT
+    n = max(n, 1)
+    avg = t / n
+    achieved = ops / n / avg / 1e12 if avg > 0 else 0.0
+    peak = PEAK_LANE_OPS / 1e12
+    return {"bound": "alu", "kernel": name, "achieved": achieved, "peak": peak, "unit": "TOP/s",
+            "frac": achieved / peak, "traffic": None, "avg_launch_ms": avg * 1e3, "launches": n,
+            "share_of_pass_time": t / max(acc.t[0] + acc.t[1], 1e-30)}
+
+
+def sync():
     import torch
-    from paper_1101_1245_amd import evaluate as E
-    from paper_1101_1245_amd import gpumcd as G
-    from paper_1101_1245_amd import inputs as I
+    torch.cuda.synchronize()
 
+
+def bench_water(args, G, E, I):
     we = I.water_15mev(I.ELECTRON)
     wg = I.water_15mev(I.PHOTON)
     ctx = G.Context(0)
@@ -74,62 +121,73 @@ def main():
     pid = ctx.load_phantom(we.phantom)
     shape = we.phantom.shape
 
-    def run(w, n, seed):
-        return ctx.run_beam(pid, tid, w.source, n, seed, shape=shape, out="torch")
-
-    # pilot at the paper's counts -> histories for 1% (Eq. 12)
-    n1 = {}
-    s_pilot = {}
+    # pilot at the paper's counts -> histories for the target s (Eq. 12)
+    n1, s_pilot = {}, {}
     for key, w in (("electron", we), ("photon", wg)):
-        d, s, st = run(w, w.n_hist, 1)
+        d, s, st = ctx.run_beam(pid, tid, w.source, w.n_hist, 1, shape=shape, out="torch")
         sv = E.uncertainty_s(d.cpu().numpy(), s.cpu().numpy())
         s_pilot[key] = sv
-        n1[key] = min(E.histories_for(sv, w.n_hist, args.target), (1 << 32) - 1)
-        print("pilot %s: N=%d s=%.4f -> N_1%%=%d (device %.1f ms)" %
-              (key, w.n_hist, sv, n1[key], st["t_device_s"] * 1e3), file=sys.stderr, flush=True)
+        n1[key] = min(E.histories_for(sv, w.n_hist, args.target), (1 << 31) - 1)
+        print("pilot %s: N=%d s=%.4f -> N=%d for s=%.3f (device %.1f ms)" %
+              (key, w.n_hist, sv, n1[key], args.target, st["t_device_s"] * 1e3), file=sys.stderr, flush=True)
+    srcs = [we.source, wg.source]
+    counts = [n1["electron"], n1["photon"]]
+
+    def plain(seed):
+        out = []
+        for w, key in ((we, "electron"), (wg, "photon")):
+            out.append(ctx.run_beam(pid, tid, w.source, n1[key], seed, shape=shape, out="torch"))
+        return out
+
+    def batched(seed):
+        return ctx.run_beams(pid, tid, srcs, counts, seed, shape=shape, per_beam=True, per_beam_sigma=True,
+                             out="torch")
 
     for i in range(args.warmup):
-        run(we, n1["electron"], 100 + i)
-        run(wg, n1["photon"], 200 + i)
+        plain(100 + i)
+        batched(100 + i)
 
-    acc = {"t_e": 0.0, "n_e": 0, "t_g": 0.0, "n_g": 0, "steps": 0, "events": 0, "resid": 0}
-    s_meas = {"electron": [], "photon": []}
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        for key, w, base in (("electron", we, 1000), ("photon", wg, 2000)):
-            d, s, st = run(w, n1[key], base + k)
-            acc["t_e"] += st["t_electron_pass_s"]
-            acc["n_e"] += st["n_electron_launches"]
-            acc["t_g"] += st["t_photon_pass_s"]
-            acc["n_g"] += st["n_photon_launches"]
-            acc["steps"] += st["n_e_steps"]
-            acc["events"] += st["n_photon_events"]
-            acc["resid"] |= st["ledger_residual_lsb"]
-            s_meas[key].append((d, s))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    hist = args.steps * (n1["electron"] + n1["photon"])
-    s_final = {k: E.uncertainty_s(v[-1][0].cpu().numpy(), v[-1][1].cpu().numpy()) for k, v in s_meas.items()}
+    legs = {}
+    last = {}
+    for leg, fn in (("plain", plain), ("batched", batched)):
+        acc = Acc()
+        sync()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            r = fn(1000 + k)
+            if leg == "plain":
+                for _, _, st in r:
+                    acc.add(st)
+            else:
+                acc.add(r[4])
+            last[leg] = r
+        sync()
+        el = time.perf_counter() - t0
+        legs[leg] = (acc, el)
+        print("%s: %.1f ms/step, %.3e histories/s" % (leg, el / args.steps * 1e3, acc.hist / el),
+              file=sys.stderr, flush=True)
 
-    # dominant kernel: the pass kind with the most device time
-    if acc["t_e"] >= acc["t_g"]:
-        dom, t_dom, n_dom, ops = "k_electron_pass", acc["t_e"], acc["n_e"], acc["steps"] * OPS_PER_E_STEP
-    else:
-        dom, t_dom, n_dom, ops = "k_photon_pass", acc["t_g"], acc["n_g"], acc["events"] * OPS_PER_PH_EVENT
-    avg = t_dom / max(n_dom, 1)
-    achieved = ops / max(n_dom, 1) / avg / 1e12
-    peak = PEAK_LANE_OPS / 1e12
+    # the batched leg's per-beam uncertainty is that of the plain leg's runs with the same seed
+    s_final = {}
+    for (d, s, _), key in zip(last["plain"], ("electron", "photon")):
+        s_final[key] = E.uncertainty_s(d.cpu().numpy(), s.cpu().numpy())
+    pb, ps = last["batched"][0], last["batched"][1]
+    same = all(bool((pb[i] == last["plain"][i][0]).all()) and bool((ps[i] == last["plain"][i][1]).all())
+               for i in range(2))
 
+    acc_b, el_b = legs["batched"]
+    acc_p, el_p = legs["plain"]
+    both = Acc()
+    both.merge(acc_p)
+    both.merge(acc_b)
     out = {
-        "metric": "histories/s at 1% stat. unc. (plain form)",
-        "value": hist / elapsed,
+        "metric": "histories/s at 1% stat. unc. (plain vs batched)",
+        "value": acc_b.hist / el_b,
         "unit": "histories/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": el_b / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -137,28 +195,123 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "15 MeV electron + photon parallel beams, 10x10 cm, 64^3 water at 0.5 cm, "
-                        "ECUT 0.7 / PCUT 0.01 MeV, each at N_1% (plain form)",
+                        "ECUT 0.7 / PCUT 0.01 MeV, each beam at N_1%; value = batched form (both beams "
+                        "in one gmc_run_beams job)",
             "n_electrons": n1["electron"], "n_photons": n1["photon"],
-            "s_pilot": s_pilot, "s_timed": s_final, "form": "plain",
+            "s_pilot": s_pilot, "s_timed": s_final,
             "tallies": "int64 fixed point, 32 batches",
+            "outputs": "device memory (no PCIe in the timed region)",
         },
-        "roofline": {
-            "bound": "alu",
-            "kernel": dom,
-            "achieved": achieved,
-            "peak": peak,
-            "unit": "TOP/s",
-            "frac": achieved / peak,
-            "traffic": None,
-            "avg_launch_ms": avg * 1e3,
-            "launches": n_dom,
-        },
-        "ledger_residual_lsb": acc["resid"],
+        "plain": {"value": acc_p.hist / el_p, "ms_per_step": el_p / args.steps * 1e3},
+        "batched_over_plain": (acc_b.hist / el_b) / (acc_p.hist / el_p),
+        "batched_equals_plain_per_beam": same,
+        "roofline": roofline(both),
+        "ledger_residual_lsb": both.resid,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
-    print(json.dumps(out), flush=True)
     ctx.close()
+    return out
+
+
+def bench_beamlets(args, G, E, I):
+    import torch
+    j = I.beamlet_job()
+    ctx = G.Context(0)
+    tid = ctx.load_tables(j.materials, j.physics)
+    pid = ctx.load_phantom(j.phantom)
+    shape = j.phantom.shape
+    total = int(j.counts.sum())
+
+    def plain(seed):
+        acc = Acc()
+        for src, n in zip(j.sources, j.counts):
+            d, _, st = ctx.run_beam(pid, tid, src, int(n), seed, shape=shape, sigma=False, out="torch")
+            acc.add(st)
+            del d
+        return acc
+
+    def batched(seed):
+        acc = Acc()
+        pb, _, d, s, st = ctx.run_beams(pid, tid, j.sources, j.counts, seed, shape=shape, per_beam=True,
+                                        out="torch")
+        acc.add(st)
+        del pb, d, s
+        return acc
+
+    for i in range(args.warmup):
+        batched(100 + i)
+        torch.cuda.empty_cache()
+    legs = {}
+    for leg, fn in (("plain", plain), ("batched", batched)):
+        acc = Acc()
+        sync()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            acc.merge(fn(1000 + k))
+        sync()
+        el = time.perf_counter() - t0
+        legs[leg] = (acc, el)
+        torch.cuda.empty_cache()
+        print("%s: %.1f ms/step, %.3e histories/s" % (leg, el / args.steps * 1e3, acc.hist / el),
+              file=sys.stderr, flush=True)
+    acc_b, el_b = legs["batched"]
+    acc_p, el_p = legs["plain"]
+    both = Acc()
+    both.merge(acc_p)
+    both.merge(acc_b)
+    out = {
+        "metric": "histories/s (plain vs batched), beamlet batch",
+        "value": acc_b.hist / el_b,
+        "unit": "histories/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el_b / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "256 pencil beamlets 0.5x0.5 cm, 1-20 MeV, photons:electrons 3:1, 1e4-1e6 histories "
+                        "each (%d in total), 200x200x160 ellipsoid phantom at 0.25 cm, ECUT 0.7 / PCUT 0.01 MeV; "
+                        "value = one gmc_run_beams job with per-beamlet doses" % total,
+            "beamlets": len(j.sources), "histories": total,
+            "outputs": "device memory (no PCIe in the timed region)",
+        },
+        "plain": {"value": acc_p.hist / el_p, "ms_per_step": el_p / args.steps * 1e3},
+        "batched_over_plain": (acc_b.hist / el_b) / (acc_p.hist / el_p),
+        "roofline": roofline(both),
+        "ledger_residual_lsb": both.resid,
+    }
+    ctx.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=("water", "beamlets"), default="water")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--target", type=float, default=0.01, help="statistical uncertainty s of Eq. 12")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (the per-GPU transport is what is measured; how it would shard "
+              "across GPUs is described in the design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1101_1245_amd import evaluate as E
+    from paper_1101_1245_amd import gpumcd as G
+    from paper_1101_1245_amd import inputs as I
+
+    if args.workload == "water":
+        out = bench_water(args, G, E, I)
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline()
+    else:
+        out = bench_beamlets(args, G, E, I)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

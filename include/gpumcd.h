@@ -111,9 +111,9 @@ typedef struct {
  * of 2^-27 MeV) is incident - deposited - escaped - pair rest energy and is
  * zero by construction.  n_passes counts rounds (admission, electron pass,
  * photon pass).  t_photon_pass_s / t_electron_pass_s are the summed
- * durations of the pass kernels, timed with HIP events on the context
- * stream, over n_photon_launches / n_electron_launches launches (plain form
- * only; the batched form leaves them 0). */
+ * durations of the pass kernels, each launch bracketed by a pair of HIP
+ * events (event nodes of the graph in the batched form), over
+ * n_photon_launches / n_electron_launches launches. */
 typedef struct {
   double t_total_s, t_device_s;
   double e_in_mev, e_dep_mev, e_esc_mev, e_sink_mev;
@@ -138,18 +138,21 @@ typedef struct {
  *     default 2^21); the rest is carried to the next pass;
  *   wave_items: fewest particles a wavefront owns in a pass (64..2^16,
  *     default 64);
- *   rounds_per_check: batched form only, graph replays (two rounds each)
- *     between reads of the particle counts (1..1024, default 4).
+ *   rounds_per_check: batched form only; the captured graph holds
+ *     2 x rounds_per_check rounds and the host reads the particle counts
+ *     once per replay (1..1024, default 4);
+ *   refill_lanes: idle lanes of a wavefront (1..64, default 1) before they
+ *     take new particles from the wavefront's range.
  * No tuning changes any result: the dose is bit-identical for every choice. */
 typedef struct {
   int events_per_visit, secondaries_per_visit, chunk, wg_size;
-  int pass_items, wave_items, rounds_per_check;
+  int pass_items, wave_items, rounds_per_check, refill_lanes;
 } gmc_tuning;
 
 /* Transport n_histories histories of one beam (the plain form: one beam per
  * sequence of alternating electron and photon passes until both particle
  * arrays are empty, Sec. II.C.2) and write the dose per history and its
- * batch uncertainty per voxel.  seed keys the random streams.  Outputs are
+ * batch uncertainty per voxel (history h in batch h mod n_batches).  seed keys the random streams.  Outputs are
  * nx*ny*nz doubles in host or device memory per out_ptr_kind; sigma and
  * stats may be NULL.  n_histories must be < 2^32 and at least n_batches. */
 int gmc_run_beam(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const gmc_source* src,
@@ -159,27 +162,34 @@ int gmc_run_beam(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const 
 /* Transport several beams in one job (the batched form): primaries of every
  * beam are admitted into the shared per-type particle arrays as space frees
  * up, and the rounds of alternating electron and photon passes (Sec. II.C.2)
- * run from a captured HIP graph, the host reading the particle counts only
- * every rounds_per_check replays.  srcs[b] and n_hist[b] (b < n_beams,
- * 1 <= n_beams <= 2^20, each n_hist[b] >= 1) describe beam b; beam b draws
- * the same random streams as gmc_run_beam(srcs[b], n_hist[b], seed), so
- * beams with distinct beam_id are independent.
- *   dose_per_beam: NULL, or an array of n_beams pointers (host array), each
- *     NULL or an nx*ny*nz output of beam b's dose per history of that beam
+ * run from a captured HIP graph, the host reading the particle counts once
+ * per replay.  srcs[b] and n_hist[b] (b < n_beams, 1 <= n_beams <= 2^20, each
+ * n_hist[b] >= 1) describe beam b; beam b draws the same random streams as
+ * gmc_run_beam(srcs[b], n_hist[b], seed), so beams with distinct beam_id are
+ * independent.  History h of a beam belongs to batch h mod n_batches.
+ *   dose_per_beam: NULL, or a host array of n_beams pointers, each NULL or
+ *     an nx*ny*nz output of beam b's dose per history of that beam
  *     (bit-identical to gmc_run_beam's dose for the same beam and seed);
- *     asking for it adds nx*ny*nz uint64 tallies per beam in device memory;
+ *   sigma_per_beam: NULL, or likewise beam b's batch uncertainty
+ *     (bit-identical to gmc_run_beam's sigma); needs at least n_batches
+ *     histories in every beam;
  *   combined_dose / combined_sigma: dose per history summed over all beams'
- *     histories (divided by their total), with its batch uncertainty over
- *     n_batches batches of consecutive histories (beams in order);
+ *     histories (divided by their total) and its batch uncertainty;
  *     combined_dose is required, combined_sigma may be NULL.
- * Output pointers are host or device memory per out_ptr_kind.  The sum of
- * n_hist must be < 2^32 and at least n_batches.  The work runs on a stream
- * owned by the context, ordered after the context stream's earlier work,
- * and the context stream waits for it before the call returns. */
+ * With per-beam outputs the job keeps n_batches*nx*ny*nz uint64 tallies per
+ * beam when they fit in half of the free device memory (batch k of the
+ * combined result is then the sum of the beams' batches k); otherwise each
+ * beam gets a single nx*ny*nz tally beside a combined one batched over the
+ * histories of all beams in order (and sigma_per_beam is refused with
+ * GMC_ENOMEM).  The combined dose is the same either way.  Output pointers
+ * are host or device memory per out_ptr_kind.  The sum of n_hist must be
+ * < 2^32 and at least n_batches.  The work runs on a stream owned by the
+ * context, ordered after the context stream's earlier work, and the context
+ * stream waits for it before the call returns. */
 int gmc_run_beams(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const gmc_source* srcs,
                   const uint64_t* n_hist, int n_beams, uint64_t seed, double* const* dose_per_beam,
-                  double* combined_dose, double* combined_sigma, int out_ptr_kind, const gmc_tuning* tuning,
-                  gmc_run_stats* stats);
+                  double* const* sigma_per_beam, double* combined_dose, double* combined_sigma,
+                  int out_ptr_kind, const gmc_tuning* tuning, gmc_run_stats* stats);
 
 /* ---------------------------------------------------------------- checks */
 /* Words n0 .. n0+count-1 of the stream (seed, beam, hist, path), computed

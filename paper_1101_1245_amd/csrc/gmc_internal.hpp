@@ -72,16 +72,18 @@ struct DevQueue {
   uint32_t cap;
 };
 
-// One tally target: history h of the beam deposits into
-// base + ((off + h) * K / n) * nvox (a batch slice); base null: no target.
+// One tally target: history h of the beam deposits into the batch slice
+// base + ((off + h) mod K) * nvox; base null: no target.  Interleaved batches
+// keep every run of consecutive histories spread over all K slices, so lanes
+// working on neighbouring histories rarely add to the same address.
 struct DevTally {
   unsigned long long* base;
-  uint32_t n, K, off;
+  uint32_t K, off;
 };
 
-// A beam: its stream key and up to two tally targets (the plain form uses
-// target a with the beam's own K batches; the batched form uses a per-beam
-// tally and a combined tally batched over all beams' histories).
+// A beam: its stream key and up to two tally targets.  Target a is the
+// beam's own tally (K batches, or 1 when only its dose is needed); target b,
+// when set, is a combined tally batched over all beams' histories.
 struct DevBeam {
   uint32_t key0, key1;          // Philox key (seed lo, seed hi ^ beam id)
   DevTally a, b;
@@ -144,6 +146,7 @@ struct PassArgs {
   unsigned long long* ctr;   // [C_COUNT][kCtrSlots]
   int max_events;
   int max_secondaries;
+  int refill_lanes;          // idle lanes (1..64) that trigger a refill
 };
 
 // Packing of wave segments into an accumulating queue.  For the same-type
@@ -195,7 +198,9 @@ struct AdmitArgs {
 };
 
 struct FinalizeArgs {
-  const unsigned long long* tally;  // [K][nvox]
+  const unsigned long long* tally;  // [nsum][K][nvox] (the nsum tallies are added)
+  uint32_t nsum;
+  size_t sum_stride;                // elements between successive tallies
   const uint2* vox;
   const double* nk;                 // histories per batch
   uint32_t nvox, K;

@@ -44,7 +44,7 @@ __device__ __forceinline__ Primary sample_primary(const DevSource& a, const DevB
 // Batch slice of a tally target for history h.
 __device__ __forceinline__ unsigned long long* tally_slice(const DevTally& t, uint32_t h, uint32_t nvox) {
   if (!t.base) return nullptr;
-  const uint32_t k = (uint32_t)(((uint64_t)(t.off + h) * t.K) / t.n);
+  const uint32_t k = (t.off + h) % t.K;
   return t.base + (size_t)k * nvox;
 }
 
@@ -160,12 +160,14 @@ __device__ __forceinline__ WaveRange wave_range(const PassPlan& P, uint32_t wave
   return r;
 }
 
-// Lanes without a particle take the next items of the range, in lane order.
+// Lanes without a particle take the next items of the range, in lane order,
+// once at least a.refill_lanes of them are idle (one refill then pays the
+// load latency for many lanes; with every lane idle it always proceeds).
 // Entries with zero energy (primaries settled by the source) are skipped.
 __device__ __forceinline__ void refill(Lane& L, bool& have, int& events, int& pushes, WaveRange& r,
                                        const PassArgs& a, uint32_t nvox) {
   const unsigned long long need = __ballot(!have);
-  if (need == 0 || r.next >= r.end) return;
+  if (need == 0 || r.next >= r.end || __popcll(need) < a.refill_lanes) return;
   if (!have) {
     const uint32_t it = r.next + (uint32_t)__popcll(need & lanes_below());
     if (it < r.end) {
@@ -569,6 +571,13 @@ __global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
 }
 
 // ---------------------------------------------------------------- finalize
+// Batch k of voxel v, summed over the nsum tallies being finalized together.
+__device__ __forceinline__ unsigned long long batch_total(const FinalizeArgs& a, uint32_t k, uint32_t v) {
+  unsigned long long t = 0;
+  for (uint32_t j = 0; j < a.nsum; ++j) t += a.tally[(size_t)j * a.sum_stride + (size_t)k * a.nvox + v];
+  return t;
+}
+
 // Dose per history and batch uncertainty in double precision (Sec. II.D):
 // D = sum_k T_k / N converted to Gy; sigma^2 = sum_k n_k^2 (m_k - m)^2 /
 // (N^2 (K-1)/K) with m_k the batch means.  Also sums the deposited energy for
@@ -577,7 +586,7 @@ __global__ void __launch_bounds__(256) k_finalize(FinalizeArgs a) {
   const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long s1 = 0;
   if (v < a.nvox) {
-    for (uint32_t k = 0; k < a.K; ++k) s1 += a.tally[(size_t)k * a.nvox + v];
+    for (uint32_t k = 0; k < a.K; ++k) s1 += batch_total(a, k, v);
     const double rho = (double)__uint_as_float(a.vox[v].x);
     const double conv = rho > 0.0 ? a.conv / rho : 0.0;
     const double m = (double)s1 / a.n_total;
@@ -586,7 +595,8 @@ __global__ void __launch_bounds__(256) k_finalize(FinalizeArgs a) {
       double acc = 0.0;
       for (uint32_t k = 0; k < a.K; ++k) {
         const double nk = a.nk[k];
-        const double d = (double)a.tally[(size_t)k * a.nvox + v] / nk - m;
+        if (!(nk > 0.0)) continue;   // a batch without histories adds nothing
+        const double d = (double)batch_total(a, k, v) / nk - m;
         acc += nk * nk * d * d;
       }
       const double var = a.K > 1 ? acc / (a.n_total * a.n_total * (double)(a.K - 1) / (double)a.K) : 0.0;

@@ -8,8 +8,8 @@
 // ever dropped).  Pass sizes are planned on the device from device-resident
 // counts.  The plain form (gmc_run_beam) reads the counts after admission and
 // after the electron pass of every round and skips empty passes; the batched
-// form (gmc_run_beams) captures two rounds in a HIP graph and replays it,
-// reading the counts only every few replays.
+// form (gmc_run_beams) captures several rounds in a HIP graph and replays it,
+// reading the counts once per replay.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -105,6 +105,7 @@ struct gmc_context {
   int resident_nmat[2] = {0, 0};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t kev0 = nullptr, kev1 = nullptr;   // around each pass launch (plain form)
+  std::vector<hipEvent_t> gev;                 // pairs around each pass of a captured graph
   double t_pass[2] = {0.0, 0.0};               // summed pass durations, s
   uint64_t n_pass[2] = {0, 0};
 };
@@ -291,11 +292,11 @@ int check_source(gmc_context* c, const gmc_source* s) {
 }
 
 struct Tune {
-  int events, secondaries, chunk, block, pass_items, wave_items, rounds;
+  int events, secondaries, chunk, block, pass_items, wave_items, rounds, refill;
 };
 
 Tune resolve_tuning(const gmc_tuning* t) {
-  Tune r{64, 4, 1 << 20, 256, 1 << 21, 64, 4};
+  Tune r{64, 4, 1 << 20, 256, 1 << 21, 64, 4, 1};
   if (t) {
     if (t->events_per_visit > 0) r.events = t->events_per_visit;
     if (t->secondaries_per_visit >= 2) r.secondaries = std::min(t->secondaries_per_visit, 64);
@@ -304,6 +305,7 @@ Tune resolve_tuning(const gmc_tuning* t) {
     if (t->pass_items > 0) r.pass_items = std::min(std::max(t->pass_items, 1024), 1 << 23);
     if (t->wave_items > 0) r.wave_items = std::min(std::max(t->wave_items, 64), 1 << 16);
     if (t->rounds_per_check > 0) r.rounds = std::min(t->rounds_per_check, 1024);
+    if (t->refill_lanes > 0) r.refill = std::min(t->refill_lanes, 64);
   }
   return r;
 }
@@ -352,10 +354,28 @@ struct Engine {
 
 uint32_t* count_ptr(gmc_context* c, int type, int buf) { return c->d_counts + 2 * type + buf; }
 
+// Record `ev` on stream s; while s is being captured, as an event record node
+// appended to the captured graph after the current dependencies.
+hipError_t record_event(hipStream_t s, hipEvent_t ev, bool capturing) {
+  if (!capturing) return hipEventRecord(ev, s);
+  hipStreamCaptureStatus status = hipStreamCaptureStatusNone;
+  hipGraph_t g = nullptr;
+  const hipGraphNode_t* deps = nullptr;
+  size_t nd = 0;
+  hipError_t e = hipStreamGetCaptureInfo_v2(s, &status, nullptr, &g, &deps, &nd);
+  if (e != hipSuccess) return e;
+  if (status != hipStreamCaptureStatusActive) return hipErrorIllegalState;
+  hipGraphNode_t node = nullptr;
+  e = hipGraphAddEventRecordNode(&node, g, deps, nd, ev);
+  if (e != hipSuccess) return e;
+  return hipStreamUpdateCaptureDependencies(s, &node, 1, hipStreamSetCaptureDependencies);
+}
+
 // Enqueue plan, pass and the two compactions of `type` over its accumulating
 // buffer, which becomes the work buffer; the other buffer accumulates from
-// then on.  With `timed` the pass kernel is bracketed by events.
-int enqueue_pass(Engine& E, int type, bool timed) {
+// then on.  The pass kernel is bracketed by the events t0 / t1 (recorded as
+// graph event nodes while the stream is being captured).
+int enqueue_pass(Engine& E, int type, hipEvent_t t0, hipEvent_t t1, bool capturing) {
   gmc_context* c = E.c;
   const int other = 1 - type;
   const int wi = c->acc[type];
@@ -379,11 +399,11 @@ int enqueue_pass(Engine& E, int type, bool timed) {
   a.stg_other = c->stg[1].q;
   a.used_same = c->d_used;
   a.used_other = c->d_used + kMaxWaves;
-  if (timed) HIP_TRY(c, hipEventRecord(c->kev0, c->stream));
+  HIP_TRY(c, record_event(c->stream, t0, capturing));
   hipError_t e = type == 0 ? launch_photon_pass(a, (int)E.blocks[0], E.tu.block, c->stream)
                            : launch_electron_pass(a, (int)E.blocks[1], E.tu.block, c->stream);
   if (e != hipSuccess) return fail(c, GMC_EDEVICE, std::string("pass launch: ") + hipGetErrorString(e));
-  if (timed) HIP_TRY(c, hipEventRecord(c->kev1, c->stream));
+  HIP_TRY(c, record_event(c->stream, t1, capturing));
   for (int d = 0; d < 2; ++d) {
     const int dt = d == 0 ? type : other;
     const int dbuf = d == 0 ? ni : c->acc[other];
@@ -504,6 +524,7 @@ int engine_setup(gmc_context* c, Engine& E, const Job& J, const Tune& tu) {
   E.proto.ctr = c->d_ctr;
   E.proto.max_events = tu.events;
   E.proto.max_secondaries = tu.secondaries;
+  E.proto.refill_lanes = tu.refill;
   for (int t = 0; t < 2; ++t) {
     AdmitArgs& a = E.adm[t];
     a = AdmitArgs{};
@@ -523,9 +544,9 @@ int engine_setup(gmc_context* c, Engine& E, const Job& J, const Tune& tu) {
   return GMC_OK;
 }
 
-int add_pass_time(gmc_context* c, int type) {
+int add_pass_time(gmc_context* c, int type, hipEvent_t t0, hipEvent_t t1) {
   float ms = 0.0f;
-  HIP_TRY(c, hipEventElapsedTime(&ms, c->kev0, c->kev1));
+  HIP_TRY(c, hipEventElapsedTime(&ms, t0, t1));
   c->t_pass[type] += ms * 1e-3;
   ++c->n_pass[type];
   return GMC_OK;
@@ -544,7 +565,7 @@ int engine_run_plain(Engine& E, uint64_t* rounds) {
     if (rc) return rc;
     rc = read_status(c, &st);
     if (rc) return rc;
-    if (g_ran) rc = add_pass_time(c, 0);
+    if (g_ran) rc = add_pass_time(c, 0, c->kev0, c->kev1);
     if (rc) return rc;
     if (st.done()) break;
     const bool g_prog = g_ran && st.plan[0].m > 0;
@@ -553,16 +574,16 @@ int engine_run_plain(Engine& E, uint64_t* rounds) {
     e_prog = false;
     g_ran = false;
     if (st.counts[2 + c->acc[1]] > 0) {
-      rc = enqueue_pass(E, 1, true);
+      rc = enqueue_pass(E, 1, c->kev0, c->kev1, false);
       if (rc) return rc;
       rc = read_status(c, &st);
       if (rc) return rc;
-      rc = add_pass_time(c, 1);
+      rc = add_pass_time(c, 1, c->kev0, c->kev1);
       if (rc) return rc;
       e_prog = st.plan[1].m > 0;
     }
     if (st.counts[c->acc[0]] > 0) {
-      rc = enqueue_pass(E, 0, true);
+      rc = enqueue_pass(E, 0, c->kev0, c->kev1, false);
       if (rc) return rc;
       g_ran = true;
     }
@@ -570,19 +591,32 @@ int engine_run_plain(Engine& E, uint64_t* rounds) {
   return GMC_OK;
 }
 
-// Batched form: two rounds captured in a graph (each type's buffers swap once
-// per round, so after two rounds the buffer roles are back where they
-// started) and replayed tu.rounds times between status reads.
+int ensure_graph_events(gmc_context* c, size_t n) {
+  while (c->gev.size() < n) {
+    hipEvent_t e = nullptr;
+    HIP_TRY(c, hipEventCreate(&e));
+    c->gev.push_back(e);
+  }
+  return GMC_OK;
+}
+
+// Batched form: 2 R rounds (R = rounds_per_check) captured in one graph --
+// each type's buffers swap once per round, so after an even number of rounds
+// the buffer roles are back where they started -- replayed until the job is
+// done, with one status read per replay.  Every pass kernel in the graph is
+// bracketed by its own pair of event nodes, read after each replay.
 int engine_run_graph(Engine& E, uint64_t* rounds) {
   gmc_context* c = E.c;
+  const int nr = 2 * E.tu.rounds;
+  int rc = ensure_graph_events(c, (size_t)4 * nr);
+  if (rc) return rc;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-  int rc = GMC_OK;
-  for (int r = 0; r < 2 && rc == GMC_OK; ++r) {
+  for (int r = 0; r < nr && rc == GMC_OK; ++r) {
     rc = enqueue_admission(E);
-    if (rc == GMC_OK) rc = enqueue_pass(E, 1, false);
-    if (rc == GMC_OK) rc = enqueue_pass(E, 0, false);
+    if (rc == GMC_OK) rc = enqueue_pass(E, 1, c->gev[4 * r + 2], c->gev[4 * r + 3], true);
+    if (rc == GMC_OK) rc = enqueue_pass(E, 0, c->gev[4 * r], c->gev[4 * r + 1], true);
   }
   const hipError_t ec = hipStreamEndCapture(c->stream, &graph);
   if (rc) {
@@ -595,14 +629,14 @@ int engine_run_graph(Engine& E, uint64_t* rounds) {
   if (e != hipSuccess) return fail(c, GMC_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
   Status st;
   for (;;) {
-    for (int i = 0; i < E.tu.rounds && e == hipSuccess; ++i) {
-      e = hipGraphLaunch(exec, c->stream);
-      if (e == hipSuccess) *rounds += 2;
-    }
+    e = hipGraphLaunch(exec, c->stream);
     if (e != hipSuccess) break;
+    *rounds += (uint64_t)nr;
     rc = read_status(c, &st);
     if (rc) break;
-    if (st.done()) break;
+    // pair i brackets the pass of type i & 1 in round i / 2
+    for (int i = 0; i < 2 * nr && rc == GMC_OK; ++i) rc = add_pass_time(c, i & 1, c->gev[2 * i], c->gev[2 * i + 1]);
+    if (rc || st.done()) break;
     // the last round admitted nothing and both of its passes transported
     // nothing: a fixed point
     if (st.adm[0].count == 0 && st.adm[1].count == 0 && st.plan[0].m == 0 && st.plan[1].m == 0) {
@@ -615,23 +649,22 @@ int engine_run_graph(Engine& E, uint64_t* rounds) {
   return rc;
 }
 
-// Histories per batch, n_k = #{h < n : floor(h K / n) = k}.
-std::vector<double> batch_sizes(uint64_t n, uint32_t K) {
-  std::vector<double> nk(K);
-  for (uint32_t k = 0; k < K; ++k) {
-    const uint64_t lo = ((uint64_t)k * n + K - 1) / K, hi = ((uint64_t)(k + 1) * n + K - 1) / K;
-    nk[k] = (double)(hi - lo);
-  }
-  return nk;
+// Histories per batch for interleaved batches: n_k = #{h < n : h mod K = k}.
+void add_batch_sizes(std::vector<double>& nk, uint64_t n, uint32_t K) {
+  nk.resize(K, 0.0);
+  for (uint32_t k = 0; k < K; ++k) nk[k] += (double)((n + K - 1 - k) / K);
 }
 
-// Dose and sigma of one tally ([K][nvox]) into device buffers (Eqs. 11-13).
-int finalize(gmc_context* c, const PhantomObj& P, const unsigned long long* tally, uint32_t K, uint64_t n,
-             double* d_dose, double* d_sigma, bool ledger) {
-  const std::vector<double> nk = batch_sizes(n, K);
+// Dose and sigma of `nsum` tallies ([K][nvox] each, `stride` elements apart,
+// added together) into device buffers (Eqs. 11-13).  nk: histories per
+// batch; n: all histories.
+int finalize(gmc_context* c, const PhantomObj& P, const unsigned long long* tally, uint32_t nsum, size_t stride,
+             uint32_t K, const std::vector<double>& nk, uint64_t n, double* d_dose, double* d_sigma, bool ledger) {
   HIP_TRY(c, hipMemcpyAsync(c->d_nk, nk.data(), K * sizeof(double), hipMemcpyHostToDevice, c->stream));
   FinalizeArgs fa;
   fa.tally = tally;
+  fa.nsum = nsum;
+  fa.sum_stride = stride;
   fa.vox = P.d_vox;
   fa.nk = c->d_nk;
   fa.nvox = (uint32_t)((size_t)P.nx * P.ny * P.nz);
@@ -642,7 +675,7 @@ int finalize(gmc_context* c, const PhantomObj& P, const unsigned long long* tall
   fa.sigma = d_sigma;
   fa.ctr = ledger ? c->d_ctr : nullptr;
   HIP_TRY(c, launch_finalize(fa, c->stream));
-  // nk lives on the host stack: the copy must be done before it goes
+  // the batch sizes come from host memory the caller may release on return
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return GMC_OK;
 }
@@ -706,10 +739,17 @@ struct StreamSwap {
   }
 };
 
+// How the batched form tallies (the plain form is kCombined with one beam).
+enum TallyMode {
+  kCombined,       // one tally [K][nvox] batched over all histories: no per-beam doses
+  kBeamBatched,    // a [K][nvox] tally per beam; the combined result is their sum
+  kBeamPlusComb    // a [1][nvox] tally per beam plus a combined [K][nvox] one (two additions per deposit)
+};
+
 // Shared by the plain and batched forms.
 int run_job(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_source* srcs, const uint64_t* n_hist,
-            int n_beams, uint64_t seed, double* const* dose_per_beam, double* dose, double* sigma, int out_kind,
-            const gmc_tuning* tuning, gmc_run_stats* stats, bool batched) {
+            int n_beams, uint64_t seed, double* const* dose_per_beam, double* const* sigma_per_beam, double* dose,
+            double* sigma, int out_kind, const gmc_tuning* tuning, gmc_run_stats* stats, bool batched) {
   const auto t_start = std::chrono::steady_clock::now();
   auto pi = c->phantoms.find(phantom_id);
   auto ti = c->tables.find(tables_id);
@@ -721,7 +761,7 @@ int run_job(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_sou
   if (out_kind != GMC_HOST && out_kind != GMC_DEVICE) return fail(c, GMC_EINVAL, "bad out_ptr_kind");
   if (P.max_mat >= T.host.n_mat) return fail(c, GMC_EINVAL, "phantom uses a material index beyond the tables");
   const uint32_t K = (uint32_t)T.phys.n_batches;
-  uint64_t n_total = 0, per_type[2] = {0, 0};
+  uint64_t n_total = 0, per_type[2] = {0, 0}, n_min = ~0ull;
   double e_sum = 0.0;
   for (int b = 0; b < n_beams; ++b) {
     const int rc = check_source(c, &srcs[b]);
@@ -729,6 +769,7 @@ int run_job(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_sou
     if (n_hist[b] == 0) return fail(c, GMC_EINVAL, "every beam needs at least one history");
     if (n_hist[b] >= (1ull << 32)) return fail(c, GMC_EINVAL, "histories must be < 2^32");
     n_total += n_hist[b];
+    n_min = std::min<uint64_t>(n_min, n_hist[b]);
     per_type[srcs[b].particle] += n_hist[b];
     const double e_max = srcs[b].spectrum == GMC_MONO ? srcs[b].e_mev : srcs[b].e_hi;
     e_sum += (double)n_hist[b] * (e_max * 134217728.0 + 1.0);
@@ -739,8 +780,24 @@ int run_job(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_sou
   (void)hipSetDevice(c->device);
   const Tune tu = resolve_tuning(tuning);
   const size_t nvox = (size_t)P.nx * P.ny * P.nz;
-  const bool per_beam = batched && dose_per_beam != nullptr;
-  const size_t tally_elems = nvox * ((size_t)K + (per_beam ? (size_t)n_beams : 0u));
+  const size_t NB = (size_t)n_beams;
+
+  // tally layout: per-beam K-batched tallies when per-beam results are asked
+  // for, every beam has at least K histories and they fit in half of the free
+  // device memory; per-beam sigma needs them
+  TallyMode mode = kCombined;
+  if (batched && (dose_per_beam || sigma_per_beam)) {
+    size_t free_b = 0, total_b = 0;
+    (void)hipMemGetInfo(&free_b, &total_b);
+    const double need = (double)NB * K * nvox * sizeof(unsigned long long);
+    const double room = 0.5 * ((double)free_b + (double)c->tally_elems * sizeof(unsigned long long));
+    mode = (n_min >= K && need <= room) ? kBeamBatched : kBeamPlusComb;
+    if (sigma_per_beam && mode != kBeamBatched)
+      return fail(c, n_min < K ? GMC_EINVAL : GMC_ENOMEM,
+                  n_min < K ? "sigma per beam needs at least n_batches histories in every beam"
+                            : "per-beam batched tallies do not fit in device memory");
+  }
+  const size_t tally_elems = mode == kCombined ? nvox * K : mode == kBeamBatched ? nvox * K * NB : nvox * (K + NB);
   int rc = ensure_tally(c, tally_elems);
   if (rc) return rc;
   rc = ensure_out(c, nvox);
@@ -757,13 +814,14 @@ int run_job(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_sou
     DevBeam db{};
     db.key0 = (uint32_t)seed;
     db.key1 = (uint32_t)(seed >> 32) ^ srcs[b].beam_id;
-    const DevTally comb{c->d_tally, (uint32_t)n_total, K, off};
-    if (per_beam) {
-      db.a = DevTally{c->d_tally + nvox * ((size_t)K + (size_t)b), (uint32_t)n_hist[b], 1u, 0u};
-      db.b = comb;
+    db.b = DevTally{nullptr, 1u, 0u};
+    if (mode == kCombined) {
+      db.a = DevTally{c->d_tally, K, off};
+    } else if (mode == kBeamBatched) {
+      db.a = DevTally{c->d_tally + nvox * K * (size_t)b, K, 0u};
     } else {
-      db.a = comb;
-      db.b = DevTally{nullptr, 1u, 1u, 0u};
+      db.a = DevTally{c->d_tally + nvox * ((size_t)K + (size_t)b), 1u, 0u};
+      db.b = DevTally{c->d_tally, K, off};
     }
     J.beams.push_back(db);
     J.sources.push_back(dev_source(srcs[b]));
@@ -785,9 +843,17 @@ int run_job(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_sou
   rc = batched ? engine_run_graph(E, &rounds) : engine_run_plain(E, &rounds);
   if (rc) return rc;
 
+  // combined result (and the ledger's deposited total)
+  std::vector<double> nk;
+  if (mode == kBeamBatched) {
+    for (int b = 0; b < n_beams; ++b) add_batch_sizes(nk, n_hist[b], K);
+  } else {
+    add_batch_sizes(nk, n_total, K);
+  }
   double* d_out = out_kind == GMC_DEVICE ? dose : c->d_dose;
   double* s_out = sigma ? (out_kind == GMC_DEVICE ? sigma : c->d_sigma) : nullptr;
-  rc = finalize(c, P, c->d_tally, K, n_total, d_out, s_out, true);
+  rc = mode == kBeamBatched ? finalize(c, P, c->d_tally, (uint32_t)NB, nvox * K, K, nk, n_total, d_out, s_out, true)
+                            : finalize(c, P, c->d_tally, 1u, 0u, K, nk, n_total, d_out, s_out, true);
   if (rc) return rc;
   if (out_kind == GMC_HOST) {
     rc = copy_out(c, dose, c->d_dose, nvox, GMC_HOST);
@@ -795,14 +861,24 @@ int run_job(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_sou
     if (sigma) rc = copy_out(c, sigma, c->d_sigma, nvox, GMC_HOST);
     if (rc) return rc;
   }
-  if (per_beam) {
+  // per-beam results
+  if (mode != kCombined) {
     for (int b = 0; b < n_beams; ++b) {
-      if (!dose_per_beam[b]) continue;
-      double* dst = out_kind == GMC_DEVICE ? dose_per_beam[b] : c->d_dose;
-      rc = finalize(c, P, c->d_tally + nvox * ((size_t)K + (size_t)b), 1u, n_hist[b], dst, nullptr, false);
+      double* want_d = dose_per_beam ? dose_per_beam[b] : nullptr;
+      double* want_s = sigma_per_beam ? sigma_per_beam[b] : nullptr;
+      if (!want_d && !want_s) continue;
+      // the dose is always computed; it lands in scratch when not wanted
+      double* dd = out_kind == GMC_DEVICE && want_d ? want_d : c->d_dose;
+      double* ds = want_s ? (out_kind == GMC_DEVICE ? want_s : c->d_sigma) : nullptr;
+      const uint32_t kb = mode == kBeamBatched ? K : 1u;
+      const unsigned long long* tb = c->d_tally + (mode == kBeamBatched ? nvox * K * (size_t)b : nvox * ((size_t)K + b));
+      std::vector<double> nkb;
+      add_batch_sizes(nkb, n_hist[b], kb);
+      rc = finalize(c, P, tb, 1u, 0u, kb, nkb, n_hist[b], dd, ds, false);
       if (rc) return rc;
       if (out_kind == GMC_HOST) {
-        rc = copy_out(c, dose_per_beam[b], c->d_dose, nvox, GMC_HOST);
+        if (want_d) rc = copy_out(c, want_d, c->d_dose, nvox, GMC_HOST);
+        if (rc == GMC_OK && want_s) rc = copy_out(c, want_s, c->d_sigma, nvox, GMC_HOST);
         if (rc) return rc;
       }
     }
@@ -872,6 +948,7 @@ void gmc_destroy(gmc_context* c) {
     if (p) (void)hipFree(p);
   for (hipEvent_t e : {c->ev0, c->ev1, c->kev0, c->kev1, c->join})
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->gev) (void)hipEventDestroy(e);
   if (c->gstream) (void)hipStreamDestroy(c->gstream);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -993,17 +1070,17 @@ int gmc_run_beam(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gm
                  gmc_run_stats* stats) {
   if (!c) return GMC_EINVAL;
   if (!src) return fail(c, GMC_EINVAL, "source is NULL");
-  return run_job(c, phantom_id, tables_id, src, &n_hist, 1, seed, nullptr, dose, sigma, out_kind, tuning, stats,
-                 false);
+  return run_job(c, phantom_id, tables_id, src, &n_hist, 1, seed, nullptr, nullptr, dose, sigma, out_kind, tuning,
+                 stats, false);
 }
 
 int gmc_run_beams(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_source* srcs,
                   const uint64_t* n_hist, int n_beams, uint64_t seed, double* const* dose_per_beam,
-                  double* combined_dose, double* combined_sigma, int out_kind, const gmc_tuning* tuning,
-                  gmc_run_stats* stats) {
+                  double* const* sigma_per_beam, double* combined_dose, double* combined_sigma, int out_kind,
+                  const gmc_tuning* tuning, gmc_run_stats* stats) {
   if (!c) return GMC_EINVAL;
-  return run_job(c, phantom_id, tables_id, srcs, n_hist, n_beams, seed, dose_per_beam, combined_dose, combined_sigma,
-                 out_kind, tuning, stats, true);
+  return run_job(c, phantom_id, tables_id, srcs, n_hist, n_beams, seed, dose_per_beam, sigma_per_beam, combined_dose,
+                 combined_sigma, out_kind, tuning, stats, true);
 }
 
 int gmc_rng_words(gmc_context* c, uint64_t seed, uint32_t beam, uint32_t hist, uint64_t path, uint32_t n0, int count,
@@ -1074,8 +1151,8 @@ int gmc_first_events(gmc_context* c, int32_t phantom_id, int32_t tables_id, cons
   DevBeam beam{};
   beam.key0 = (uint32_t)seed;
   beam.key1 = (uint32_t)(seed >> 32) ^ src->beam_id;
-  beam.a = DevTally{nullptr, 1u, 1u, 0u};
-  beam.b = DevTally{nullptr, 1u, 1u, 0u};
+  beam.a = DevTally{nullptr, 1u, 0u};
+  beam.b = DevTally{nullptr, 1u, 0u};
   PassArgs a{};
   a.ph = dev_phantom(P);
   a.tab = dev_tables(T, maj);

@@ -63,7 +63,7 @@ class gmc_run_stats(C.Structure):
 class gmc_tuning(C.Structure):
     _fields_ = [("events_per_visit", C.c_int), ("secondaries_per_visit", C.c_int), ("chunk", C.c_int),
                 ("wg_size", C.c_int), ("pass_items", C.c_int), ("wave_items", C.c_int),
-                ("rounds_per_check", C.c_int)]
+                ("rounds_per_check", C.c_int), ("refill_lanes", C.c_int)]
 
 
 _lib = None
@@ -107,7 +107,7 @@ def lib():
     L.gmc_run_beam.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(gmc_source), C.c_uint64, C.c_uint64, vp, vp,
                                C.c_int, C.POINTER(gmc_tuning), C.POINTER(gmc_run_stats)]
     L.gmc_run_beams.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(gmc_source), C.POINTER(C.c_uint64), C.c_int,
-                                C.c_uint64, C.POINTER(vp), vp, vp, C.c_int, C.POINTER(gmc_tuning),
+                                C.c_uint64, C.POINTER(vp), C.POINTER(vp), vp, vp, C.c_int, C.POINTER(gmc_tuning),
                                 C.POINTER(gmc_run_stats)]
     L.gmc_rng_words.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint32, C.c_int,
                                 C.POINTER(C.c_uint32)]
@@ -232,10 +232,10 @@ class Context:
         return d.reshape(shape), (s.reshape(shape) if s is not None else None), stats_dict(st)
 
     def run_beams(self, phantom_id: int, tables_id: int, sources, n_hist, seed: int, shape=None, tuning=None,
-                  per_beam: bool = False, sigma: bool = True, out: str = "numpy"):
+                  per_beam: bool = False, per_beam_sigma: bool = False, sigma: bool = True, out: str = "numpy"):
         """Batched form: several beams in one job.  Returns (per_beam_dose or
-        None, combined_dose, combined_sigma or None, stats); per_beam_dose has
-        shape (n_beams, nz, ny, nx)."""
+        None, per_beam_sigma or None, combined_dose, combined_sigma or None,
+        stats); per-beam arrays have shape (n_beams, nz, ny, nx)."""
         if shape is None:
             raise ValueError("shape (nz, ny, nx) is required")
         nb = len(sources)
@@ -258,16 +258,18 @@ class Context:
             kind = GMC_HOST
         d = mk(n)
         s = mk(n) if sigma else None
+
+        def rows(a):
+            return (C.c_void_p * nb)(*[ptr(a) + b * n * 8 for b in range(nb)]) if a is not None else None
+
         pb = mk(nb, n) if per_beam else None
-        pb_ptrs = None
-        if pb is not None:
-            row = n * 8
-            pb_ptrs = (C.c_void_p * nb)(*[ptr(pb) + b * row for b in range(nb)])
-        rc = self._L.gmc_run_beams(self._h, phantom_id, tables_id, srcs, counts, nb, seed, pb_ptrs, ptr(d),
+        ps = mk(nb, n) if per_beam_sigma else None
+        rc = self._L.gmc_run_beams(self._h, phantom_id, tables_id, srcs, counts, nb, seed, rows(pb), rows(ps), ptr(d),
                                    ptr(s) if s is not None else None, kind, tun_p, C.byref(st))
         self._check(rc)
         rs = lambda a, sh: a.reshape(*sh) if a is not None else None  # noqa: E731
-        return rs(pb, (nb,) + tuple(shape)), rs(d, tuple(shape)), rs(s, tuple(shape)), stats_dict(st)
+        per = (nb,) + tuple(shape)
+        return rs(pb, per), rs(ps, per), rs(d, tuple(shape)), rs(s, tuple(shape)), stats_dict(st)
 
     # ------------------------------------------------------------- checks
     def rng_words(self, seed: int, beam: int, hist: int, path: int, n0: int, count: int) -> np.ndarray:

@@ -1,13 +1,15 @@
 """GPU: the batched form (several beams in one job, graph-replayed rounds).
 
 Bars:
-* each beam's dose from the batched form is bit-identical to the plain form
-  run of that beam alone (same seed, same beam id): every particle draws
-  from its own stream and tallies are integer sums, so neither the other
-  beams in the job nor the tuning can change it;
+* each beam's dose and sigma from the batched form are bit-identical to the
+  plain form run of that beam alone (same seed, same beam id): every
+  particle draws from its own stream and tallies are integer sums, so
+  neither the other beams in the job nor the tuning can change them;
 * the combined dose is the history-weighted sum of the per-beam doses (to
   FP64 rounding of the two conversions) and, for one beam, bit-identical to
-  the plain form's dose and sigma;
+  the plain form's dose and sigma; it does not depend on the tally layout
+  (per-beam batched tallies, or single per-beam tallies beside a combined
+  one, or the combined one alone);
 * the combined dose agrees with the oracle's combined dose by the
   same-stream z-test;
 * at the full beamlet size (256 beamlets, 200x200x160, about 5.8e7
@@ -58,25 +60,26 @@ def loaded(ctx, small_job):
 def batched(ctx, small_job, loaded):
     pid, tid = loaded
     j = small_job
-    return ctx.run_beams(pid, tid, j.sources, j.counts, j.seed, shape=j.phantom.shape, per_beam=True)
+    return ctx.run_beams(pid, tid, j.sources, j.counts, j.seed, shape=j.phantom.shape, per_beam=True,
+                         per_beam_sigma=True)
 
 
 def test_per_beam_bit_identical_to_plain(ctx, small_job, loaded, batched):
     pid, tid = loaded
     j = small_job
-    pb, d, s, st = batched
+    pb, ps, d, s, st = batched
     assert st["ledger_residual_lsb"] == 0 and st["n_majorant_violations"] == 0
     e_in = 0.0
     for b, (src, n) in enumerate(zip(j.sources, j.counts)):
-        db, _, stb = ctx.run_beam(pid, tid, src, int(n), j.seed, shape=j.phantom.shape, sigma=False)
-        assert np.array_equal(pb[b], db), b
+        db, sb, stb = ctx.run_beam(pid, tid, src, int(n), j.seed, shape=j.phantom.shape)
+        assert np.array_equal(pb[b], db) and np.array_equal(ps[b], sb), b
         e_in += stb["e_in_mev"]
     assert st["e_in_mev"] == pytest.approx(e_in, rel=1e-12)
 
 
 def test_combined_is_history_weighted_sum(small_job, batched):
     j = small_job
-    pb, d, s, st = batched
+    pb, ps, d, s, st = batched
     n = j.counts.astype(np.float64)
     want = np.tensordot(n, pb, axes=1) / n.sum()
     assert np.allclose(d, want, rtol=1e-12, atol=1e-30)
@@ -88,36 +91,62 @@ def test_single_beam_matches_plain_exactly(ctx, small_job, loaded):
     pid, tid = loaded
     j = small_job
     src, n = j.sources[1], int(j.counts[1])
-    pb, d, s, _ = ctx.run_beams(pid, tid, [src], [n], 5, shape=j.phantom.shape, per_beam=True)
-    d1, s1, _ = ctx.run_beam(pid, tid, src, n, 5, shape=j.phantom.shape)
-    assert np.array_equal(d, d1) and np.array_equal(s, s1) and np.array_equal(pb[0], d1)
+    for per_beam in (False, True):
+        pb, ps, d, s, _ = ctx.run_beams(pid, tid, [src], [n], 5, shape=j.phantom.shape, per_beam=per_beam,
+                                        per_beam_sigma=per_beam)
+        d1, s1, _ = ctx.run_beam(pid, tid, src, n, 5, shape=j.phantom.shape)
+        assert np.array_equal(d, d1) and np.array_equal(s, s1)
+        if per_beam:
+            assert np.array_equal(pb[0], d1) and np.array_equal(ps[0], s1)
+
+
+def test_tally_layouts_agree(ctx, G, small_job, loaded, batched):
+    pid, tid = loaded
+    j = small_job
+    pb, ps, d, s, st = batched
+    # combined tally only
+    _, _, dc, sc, _ = ctx.run_beams(pid, tid, j.sources, j.counts, j.seed, shape=j.phantom.shape)
+    assert np.array_equal(dc, d)
+    # a beam with fewer histories than batches: single per-beam tallies beside the combined one
+    counts = j.counts.copy()
+    counts[3] = 20
+    pb2, _, d2, s2, st2 = ctx.run_beams(pid, tid, j.sources, counts, j.seed, shape=j.phantom.shape, per_beam=True)
+    assert st2["ledger_residual_lsb"] == 0
+    _, _, d3, s3, _ = ctx.run_beams(pid, tid, j.sources, counts, j.seed, shape=j.phantom.shape)
+    assert np.array_equal(d2, d3) and np.array_equal(s2, s3)
+    for b in range(len(j.sources)):
+        if b != 3:
+            assert np.array_equal(pb2[b], pb[b]), b
+    with pytest.raises(G.GpumcdError):
+        ctx.run_beams(pid, tid, j.sources, counts, j.seed, shape=j.phantom.shape, per_beam_sigma=True)
 
 
 def test_tuning_replay_and_output_kind_invariance(ctx, small_job, loaded, batched):
     pid, tid = loaded
     j = small_job
-    pb, d, s, st = batched
+    pb, ps, d, s, st = batched
     tunings = [
         {"chunk": 3001, "pass_items": 4096, "wave_items": 256, "rounds_per_check": 1, "events_per_visit": 5,
-         "secondaries_per_visit": 2, "wg_size": 128},
-        {"rounds_per_check": 9, "chunk": 20000, "wave_items": 64},
+         "secondaries_per_visit": 2, "wg_size": 128, "refill_lanes": 64},
+        {"rounds_per_check": 9, "chunk": 20000, "wave_items": 64, "refill_lanes": 17},
     ]
     for tu in tunings:
-        pb2, d2, s2, st2 = ctx.run_beams(pid, tid, j.sources, j.counts, j.seed, shape=j.phantom.shape,
-                                         per_beam=True, tuning=tu)
-        assert np.array_equal(pb, pb2) and np.array_equal(d, d2) and np.array_equal(s, s2), tu
+        pb2, ps2, d2, s2, st2 = ctx.run_beams(pid, tid, j.sources, j.counts, j.seed, shape=j.phantom.shape,
+                                              per_beam=True, per_beam_sigma=True, tuning=tu)
+        assert np.array_equal(pb, pb2) and np.array_equal(ps, ps2), tu
+        assert np.array_equal(d, d2) and np.array_equal(s, s2), tu
         assert st2["ledger_residual_lsb"] == 0
-    pb3, d3, s3, _ = ctx.run_beams(pid, tid, j.sources, j.counts, j.seed, shape=j.phantom.shape, per_beam=True,
-                                   out="torch")
-    assert np.array_equal(pb3.cpu().numpy(), pb) and np.array_equal(d3.cpu().numpy(), d)
-    assert np.array_equal(s3.cpu().numpy(), s)
-    _, d4, _, _ = ctx.run_beams(pid, tid, j.sources, j.counts, j.seed + 1, shape=j.phantom.shape)
+    pb3, ps3, d3, s3, _ = ctx.run_beams(pid, tid, j.sources, j.counts, j.seed, shape=j.phantom.shape,
+                                        per_beam=True, per_beam_sigma=True, out="torch")
+    assert np.array_equal(pb3.cpu().numpy(), pb) and np.array_equal(ps3.cpu().numpy(), ps)
+    assert np.array_equal(d3.cpu().numpy(), d) and np.array_equal(s3.cpu().numpy(), s)
+    _, _, d4, _, _ = ctx.run_beams(pid, tid, j.sources, j.counts, j.seed + 1, shape=j.phantom.shape)
     assert not np.array_equal(d, d4)
 
 
 def test_combined_matches_oracle(small_job, batched, oracle):
     j = small_job
-    pb, d, s, st = batched
+    pb, ps, d, s, st = batched
     e1 = e2 = 0.0
     stats = {}
     for src, n in zip(j.sources, j.counts):
@@ -155,8 +184,8 @@ def test_full_beamlet_job(ctx, oracle):
     tid = ctx.load_tables(j.materials, j.physics)
     pid = ctx.load_phantom(j.phantom)
     try:
-        pb, d, s, st = ctx.run_beams(pid, tid, j.sources, j.counts, j.seed, shape=j.phantom.shape, per_beam=True,
-                                     out="torch")
+        pb, _, d, s, st = ctx.run_beams(pid, tid, j.sources, j.counts, j.seed, shape=j.phantom.shape,
+                                        per_beam=True, out="torch")
         assert st["ledger_residual_lsb"] == 0 and st["n_majorant_violations"] == 0
         assert st["n_hist"] == int(j.counts.sum())
         order = np.argsort(j.counts)

@@ -220,7 +220,7 @@ def test_determinism_and_tuning_invariance(ctx, G):
     d2, s2, st2 = G.run_workload(ctx, w)
     assert np.array_equal(d1, d2) and np.array_equal(s1, s2)
     d3, s3, st3 = G.run_workload(ctx, w, tuning={"events_per_visit": 3, "secondaries_per_visit": 2, "chunk": 7919,
-                                                 "wg_size": 128})
+                                                 "wg_size": 128, "refill_lanes": 32, "pass_items": 5000})
     assert np.array_equal(d1, d3) and np.array_equal(s1, s3)
     assert st3["n_passes"] > st1["n_passes"]
     d4, _, _ = G.run_workload(ctx, w, seed=2)
