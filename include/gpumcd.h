@@ -124,7 +124,9 @@ typedef struct {
   uint64_t n_photon_launches, n_electron_launches;
 } gmc_run_stats;
 
-/* Optional tuning of the engine; NULL, or a field <= 0, selects the default.
+/* Optional tuning of the engine.  A field <= 0 selects its default; a NULL
+ * tuning selects all defaults in gmc_run_beam and the autotuner's cached
+ * choice in gmc_run_beams.
  *   events_per_visit: events a particle may take per kernel visit before it
  *     is requeued (the N of the stream-compaction scheme, Sec. II.C.3;
  *     default 64);
@@ -190,6 +192,31 @@ int gmc_run_beams(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const
                   const uint64_t* n_hist, int n_beams, uint64_t seed, double* const* dose_per_beam,
                   double* const* sigma_per_beam, double* combined_dose, double* combined_sigma,
                   int out_ptr_kind, const gmc_tuning* tuning, gmc_run_stats* stats);
+
+/* Autotuner of the batched form.  Picks the admission chunk, the pass size,
+ * the events per visit, the workgroup size, the particles per wavefront,
+ * the refill threshold and the rounds per status check by coordinate
+ * descent: each candidate runs a sample of the job (the first histories of
+ * every beam, in proportion: about 5% of the job and at least 2^20
+ * histories) and is timed on the device; a change is kept when it saves at
+ * least 2%.  Choices are cached in the context per job class (grid size,
+ * mean energy, electron fraction, field area, history count and material
+ * count on coarse logarithmic scales); a cached class returns at once.
+ * budget_s bounds the search's wall time (<= 0: 3 s).  gmc_run_beams with
+ * tuning NULL calls this first.  *out receives the choice; report may be
+ * NULL. */
+typedef struct {
+  int trials;                 /* sample jobs run */
+  int from_cache;             /* 1: the class was tuned before, nothing run */
+  int complete;               /* 0: the budget ran out before every knob was tried */
+  uint64_t sample_histories;
+  double t_default_s;         /* sample's device time with the default tuning */
+  double t_best_s;            /* with the chosen tuning */
+} gmc_autotune_report;
+
+int gmc_autotune(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const gmc_source* srcs,
+                 const uint64_t* n_hist, int n_beams, double budget_s, gmc_tuning* out,
+                 gmc_autotune_report* report);
 
 /* ---------------------------------------------------------------- checks */
 /* Words n0 .. n0+count-1 of the stream (seed, beam, hist, path), computed

@@ -61,6 +61,7 @@ struct QueueBuf {
 constexpr uint32_t kDefaultCap = 1u << 23;
 constexpr uint32_t kMaxCap = 1u << 26;
 constexpr uint32_t kMaxWaves = 1u << 15;
+constexpr double kAutotuneBudgetS = 3.0;   // default wall-clock budget of one tuning
 
 }  // namespace
 
@@ -75,6 +76,7 @@ struct gmc_context {
   std::map<int32_t, std::unique_ptr<TablesObj>> tables;
   std::map<int32_t, std::unique_ptr<PhantomObj>> phantoms;
   std::map<std::pair<int32_t, int32_t>, MajObj> majorants;
+  std::map<std::vector<int>, gmc_tuning> tuned;   // autotuner choices per job class
   // particle queues [type: 0 photon, 1 electron][2 buffers]; buffer acc[t]
   // of each type accumulates, the other one is consumed by the next pass
   uint32_t cap = 0;
@@ -886,6 +888,132 @@ int run_job(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_sou
   return collect_stats(c, stats, n_total, rounds, t_start);
 }
 
+// ---------------------------------------------------------------- autotuner
+// Job class for the autotuner's cache: grid size, beam energy, particle mix,
+// field area and material count, each on a coarse (mostly logarithmic) scale.
+std::vector<int> job_class(const PhantomObj& P, const TablesObj& T, const gmc_source* srcs, const uint64_t* n_hist,
+                           int n_beams) {
+  double n = 0, e = 0, fe = 0, area = 0;
+  for (int b = 0; b < n_beams; ++b) {
+    const double w = (double)n_hist[b];
+    n += w;
+    e += w * (srcs[b].spectrum == GMC_MONO ? srcs[b].e_mev : srcs[b].e_mode);
+    fe += srcs[b].particle == GMC_ELECTRON ? w : 0.0;
+    area += w * srcs[b].wx_cm * srcs[b].wy_cm;
+  }
+  const double nvox = (double)P.nx * P.ny * P.nz;
+  return {(int)std::lround(std::log2(nvox)), (int)std::lround(2.0 * std::log2(e / n)), (int)std::lround(4.0 * fe / n),
+          (int)std::lround(std::log2(area / n + 0.01)), (int)std::lround(std::log2(n)), T.host.n_mat};
+}
+
+gmc_tuning default_tuning() {
+  const Tune d = resolve_tuning(nullptr);
+  gmc_tuning t;
+  t.events_per_visit = d.events;
+  t.secondaries_per_visit = d.secondaries;
+  t.chunk = d.chunk;
+  t.wg_size = d.block;
+  t.pass_items = d.pass_items;
+  t.wave_items = d.wave_items;
+  t.rounds_per_check = d.rounds;
+  t.refill_lanes = d.refill;
+  return t;
+}
+
+// Coordinate descent over the engine's knobs on a sample of the job (the
+// first histories of every beam, in proportion, about 5% of the job and at
+// least 2^20 histories), each candidate timed on the device from the
+// admission to the finalize; a change is kept when it saves at least 2%.
+int autotune(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_source* srcs, const uint64_t* n_hist,
+             int n_beams, double budget_s, gmc_tuning* out, gmc_autotune_report* rep) {
+  auto pi = c->phantoms.find(phantom_id);
+  auto ti = c->tables.find(tables_id);
+  if (pi == c->phantoms.end() || ti == c->tables.end()) return fail(c, GMC_ENOTFOUND, "unknown phantom or tables id");
+  if (n_beams < 1 || !srcs || !n_hist || !out) return fail(c, GMC_EINVAL, "bad autotune arguments");
+  const PhantomObj& P = *pi->second;
+  const TablesObj& T = *ti->second;
+  uint64_t n_total = 0;
+  for (int b = 0; b < n_beams; ++b) {
+    if (n_hist[b] == 0) return fail(c, GMC_EINVAL, "every beam needs at least one history");
+    n_total += n_hist[b];
+  }
+  if (n_total >= (1ull << 32)) return fail(c, GMC_EINVAL, "total histories must be < 2^32");
+  const std::vector<int> key = job_class(P, T, srcs, n_hist, n_beams);
+  gmc_autotune_report r{};
+  auto hit = c->tuned.find(key);
+  if (hit != c->tuned.end()) {
+    *out = hit->second;
+    r.from_cache = 1;
+    if (rep) *rep = r;
+    return GMC_OK;
+  }
+  const uint64_t want = std::min<uint64_t>(n_total, std::max<uint64_t>(1ull << 20, n_total / 20));
+  const double f = (double)want / (double)n_total;
+  std::vector<uint64_t> ns(n_beams);
+  uint64_t n_sample = 0;
+  for (int b = 0; b < n_beams; ++b) {
+    ns[b] = std::max<uint64_t>(1, (uint64_t)std::llround(f * (double)n_hist[b]));
+    n_sample += ns[b];
+  }
+  if (n_sample < (uint64_t)T.phys.n_batches || n_sample >= (1ull << 32))
+    return fail(c, GMC_EINVAL, "job too small or too large to tune");
+  int rc = ensure_out(c, (size_t)P.nx * P.ny * P.nz);
+  if (rc) return rc;
+  const auto t0 = std::chrono::steady_clock::now();
+  auto trial = [&](const gmc_tuning& t, double* sec) -> int {
+    gmc_run_stats st{};
+    const int e = run_job(c, phantom_id, tables_id, srcs, ns.data(), n_beams, 0x5eedull, nullptr, nullptr, c->d_dose,
+                          nullptr, GMC_DEVICE, &t, &st, true);
+    ++r.trials;
+    *sec = st.t_device_s;
+    return e;
+  };
+  gmc_tuning best = default_tuning();
+  double t_best = 0.0;
+  rc = trial(best, &t_best);   // first run warms the buffers; time again
+  if (rc == GMC_OK) rc = trial(best, &t_best);
+  if (rc) return rc;
+  r.t_default_s = t_best;
+  struct Dim { int gmc_tuning::*field; std::vector<int> values; };
+  const std::vector<Dim> dims = {
+      {&gmc_tuning::chunk, {1 << 18, 1 << 19, 1 << 20, 1 << 21, 1 << 22}},
+      {&gmc_tuning::pass_items, {1 << 20, 1 << 21, 1 << 22}},
+      {&gmc_tuning::events_per_visit, {16, 32, 64, 128}},
+      {&gmc_tuning::wg_size, {128, 256}},
+      {&gmc_tuning::wave_items, {64, 128, 256}},
+      {&gmc_tuning::refill_lanes, {1, 4, 8}},
+      {&gmc_tuning::rounds_per_check, {2, 4, 8}},
+  };
+  bool out_of_time = false;
+  for (const Dim& d : dims) {
+    const int cur = best.*(d.field);
+    for (int v : d.values) {
+      if (v == cur) continue;
+      if (std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > budget_s) {
+        out_of_time = true;
+        break;
+      }
+      gmc_tuning cand = best;
+      cand.*(d.field) = v;
+      double t = 0.0;
+      rc = trial(cand, &t);
+      if (rc) return rc;
+      if (t < 0.98 * t_best) {
+        t_best = t;
+        best = cand;
+      }
+    }
+    if (out_of_time) break;
+  }
+  r.t_best_s = t_best;
+  r.sample_histories = n_sample;
+  r.complete = out_of_time ? 0 : 1;
+  c->tuned[key] = best;
+  *out = best;
+  if (rep) *rep = r;
+  return GMC_OK;
+}
+
 }  // namespace
 
 // ======================================================================= ABI
@@ -1079,8 +1207,25 @@ int gmc_run_beams(gmc_context* c, int32_t phantom_id, int32_t tables_id, const g
                   double* const* sigma_per_beam, double* combined_dose, double* combined_sigma, int out_kind,
                   const gmc_tuning* tuning, gmc_run_stats* stats) {
   if (!c) return GMC_EINVAL;
+  gmc_tuning tuned;
+  if (!tuning && srcs && n_hist && n_beams >= 1) {
+    const int rc = autotune(c, phantom_id, tables_id, srcs, n_hist, n_beams, kAutotuneBudgetS, &tuned, nullptr);
+    if (rc) return rc;
+    tuning = &tuned;
+  }
   return run_job(c, phantom_id, tables_id, srcs, n_hist, n_beams, seed, dose_per_beam, sigma_per_beam, combined_dose,
                  combined_sigma, out_kind, tuning, stats, true);
+}
+
+int gmc_autotune(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_source* srcs,
+                 const uint64_t* n_hist, int n_beams, double budget_s, gmc_tuning* out, gmc_autotune_report* report) {
+  if (!c) return GMC_EINVAL;
+  for (int b = 0; srcs && b < n_beams; ++b) {
+    const int rc = check_source(c, &srcs[b]);
+    if (rc) return rc;
+  }
+  return autotune(c, phantom_id, tables_id, srcs, n_hist, n_beams, budget_s > 0 ? budget_s : kAutotuneBudgetS, out,
+                  report);
 }
 
 int gmc_rng_words(gmc_context* c, uint64_t seed, uint32_t beam, uint32_t hist, uint64_t path, uint32_t n0, int count,

@@ -66,6 +66,11 @@ class gmc_tuning(C.Structure):
                 ("rounds_per_check", C.c_int), ("refill_lanes", C.c_int)]
 
 
+class gmc_autotune_report(C.Structure):
+    _fields_ = [("trials", C.c_int), ("from_cache", C.c_int), ("complete", C.c_int),
+                ("sample_histories", C.c_uint64), ("t_default_s", C.c_double), ("t_best_s", C.c_double)]
+
+
 _lib = None
 
 
@@ -109,6 +114,8 @@ def lib():
     L.gmc_run_beams.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(gmc_source), C.POINTER(C.c_uint64), C.c_int,
                                 C.c_uint64, C.POINTER(vp), C.POINTER(vp), vp, vp, C.c_int, C.POINTER(gmc_tuning),
                                 C.POINTER(gmc_run_stats)]
+    L.gmc_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(gmc_source), C.POINTER(C.c_uint64), C.c_int,
+                               C.c_double, C.POINTER(gmc_tuning), C.POINTER(gmc_autotune_report)]
     L.gmc_rng_words.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint32, C.c_int,
                                 C.POINTER(C.c_uint32)]
     L.gmc_table_eval.argtypes = [vp, C.c_int32, C.c_int, C.c_int, dp, C.c_int, dp]
@@ -270,6 +277,18 @@ class Context:
         rs = lambda a, sh: a.reshape(*sh) if a is not None else None  # noqa: E731
         per = (nb,) + tuple(shape)
         return rs(pb, per), rs(ps, per), rs(d, tuple(shape)), rs(s, tuple(shape)), stats_dict(st)
+
+    def autotune(self, phantom_id: int, tables_id: int, sources, n_hist, budget_s: float = 0.0):
+        """The autotuner's choice for this job (cached per job class): (tuning dict, report dict)."""
+        nb = len(sources)
+        srcs = (gmc_source * nb)(*[_src(s) for s in sources])
+        counts = (C.c_uint64 * nb)(*[int(n) for n in n_hist])
+        tun = gmc_tuning()
+        rep = gmc_autotune_report()
+        self._check(self._L.gmc_autotune(self._h, phantom_id, tables_id, srcs, counts, nb, budget_s, C.byref(tun),
+                                         C.byref(rep)))
+        return ({f: getattr(tun, f) for f, _ in gmc_tuning._fields_},
+                {f: getattr(rep, f) for f, _ in gmc_autotune_report._fields_})
 
     # ------------------------------------------------------------- checks
     def rng_words(self, seed: int, beam: int, hist: int, path: int, n0: int, count: int) -> np.ndarray:

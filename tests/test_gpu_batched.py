@@ -209,3 +209,21 @@ def test_full_beamlet_job(ctx, oracle):
     finally:
         ctx.release(pid)
         ctx.release(tid)
+
+
+def test_autotuner_choice_is_cached_and_result_invariant(ctx, G, small_job, loaded):
+    pid, tid = loaded
+    j = small_job
+    counts = j.counts * 2            # another job class than the fixture's (tuned when it ran)
+    tun, rep = ctx.autotune(pid, tid, j.sources, counts, budget_s=20.0)
+    assert rep["from_cache"] == 0 and rep["trials"] >= 3 and rep["complete"] == 1
+    assert rep["t_best_s"] <= rep["t_default_s"]
+    assert tun["wg_size"] in (128, 256) and 1 <= tun["refill_lanes"] <= 64 and tun["chunk"] > 0
+    tun2, rep2 = ctx.autotune(pid, tid, j.sources, counts)
+    assert rep2["from_cache"] == 1 and rep2["trials"] == 0 and tun2 == tun
+    # tuning=None runs with the cached choice; the result does not depend on it
+    pb, ps, d, s, _ = ctx.run_beams(pid, tid, j.sources, counts, j.seed, shape=j.phantom.shape, per_beam=True,
+                                    per_beam_sigma=True, tuning=None)
+    pb2, ps2, d2, s2, _ = ctx.run_beams(pid, tid, j.sources, counts, j.seed, shape=j.phantom.shape, per_beam=True,
+                                        per_beam_sigma=True, tuning={"chunk": 4099, "refill_lanes": 3})
+    assert np.array_equal(pb, pb2) and np.array_equal(ps, ps2) and np.array_equal(d, d2) and np.array_equal(s, s2)
