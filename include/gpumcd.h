@@ -14,8 +14,9 @@
  *  - Volumes are [nz][ny][nx] with x fastest.  Beams enter at z = 0 along +z.
  *  - Every function returns GMC_OK (0) or a negative GMC_E* code; on error
  *    gmc_last_error() describes it.  No exception crosses the ABI.
- *  - A context is not thread safe.  All work runs on the context's HIP
- *    stream; gmc_run_* return after their results are complete.
+ *  - A context is not thread safe, except that the served form's server
+ *    thread works beside the caller's calls.  Blocking work runs on the
+ *    context's HIP stream; gmc_run_* return after their results are complete.
  *  - Inputs are copied: the caller may free them when the call returns.
  *    Outputs go to caller-owned buffers, host or device memory according to
  *    the *_ptr_kind argument.
@@ -217,6 +218,56 @@ typedef struct {
 int gmc_autotune(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const gmc_source* srcs,
                  const uint64_t* n_hist, int n_beams, double budget_s, gmc_tuning* out,
                  gmc_autotune_report* report);
+
+/* ----------------------------------------------------------- served form
+ * Continuous batching of dose requests.  gmc_server_start starts a server
+ * thread on the context; each request is one beam on a loaded phantom and
+ * tables (which stay resident: a request only references them, and they
+ * cannot be released while a request holds them).  Requests wait in
+ * submission order for one of max_slots slots; a request starts as soon as
+ * a slot is free and its device footprint fits beside the other slots'
+ * within hbm_budget_bytes, so requests that arrive while others run are
+ * admitted at once and their kernels overlap on the device.  Footprint of a
+ * request: its slot's particle queues and staging plus n_batches*nx*ny*nz
+ * uint64 tallies and the nx*ny*nz dose and sigma.  Each request runs the
+ * batched form's engine on one beam with the autotuner's cached choice for
+ * its class (defaults when none), so its dose and sigma are bit-identical
+ * to gmc_run_beam's for the same phantom, tables, source, histories and
+ * seed, whatever else runs beside it.  Results stay in host memory until
+ * polled. */
+typedef struct {
+  size_t hbm_budget_bytes;    /* device memory the slots may hold; 0: 3/4 of the free memory */
+  int max_slots;              /* requests on the device at once, 1..16 (0: 4) */
+} gmc_server_config;
+
+typedef struct {
+  double t_queue_s;           /* submission to start on a slot */
+  double t_run_s;             /* start to result ready */
+  double t_latency_s;         /* submission to result ready */
+  gmc_run_stats run;
+} gmc_request_stats;
+
+typedef struct {
+  int running, pending, in_flight, finished_unpolled;
+  size_t budget_bytes;
+} gmc_server_status_t;
+
+/* Start the server (cfg may be NULL).  GMC_EBUSY if one is running. */
+int gmc_server_start(gmc_context* ctx, const gmc_server_config* cfg);
+/* Queue a request; *ticket identifies it.  n_histories in [n_batches, 2^32).
+ * GMC_EBUSY if its footprint can never fit in the budget. */
+int gmc_submit(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const gmc_source* src,
+               uint64_t n_histories, uint64_t seed, uint64_t* ticket);
+/* *done = 1 once the request has finished (waiting for it when wait != 0);
+ * then its dose and sigma (nx*ny*nz doubles, either may be NULL) are written
+ * to host or device memory per out_ptr_kind, stats (may be NULL) filled, the
+ * ticket retired, and the request's own error code returned if it failed. */
+int gmc_poll(gmc_context* ctx, uint64_t ticket, int wait, int* done, double* dose, double* sigma,
+             int out_ptr_kind, gmc_request_stats* stats);
+/* Finish every queued and running request, then stop the thread and free
+ * the slots; finished tickets stay pollable. */
+int gmc_server_stop(gmc_context* ctx);
+int gmc_server_status(gmc_context* ctx, gmc_server_status_t* status);
 
 /* ---------------------------------------------------------------- checks */
 /* Words n0 .. n0+count-1 of the stream (seed, beam, hist, path), computed

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libgpumcd.so")
-SOURCES = ["gmc_kernels.hip", "gmc_runtime.cpp", "gmc_tables.cpp"]
+SOURCES = ["gmc_kernels.hip", "gmc_engine.cpp", "gmc_server.cpp", "gmc_runtime.cpp", "gmc_tables.cpp"]
 ARCH = os.environ.get("GPUMCD_ARCH", "gfx950")
 
 FLAGS = [

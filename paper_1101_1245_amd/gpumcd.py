@@ -71,6 +71,20 @@ class gmc_autotune_report(C.Structure):
                 ("sample_histories", C.c_uint64), ("t_default_s", C.c_double), ("t_best_s", C.c_double)]
 
 
+class gmc_server_config(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int)]
+
+
+class gmc_request_stats(C.Structure):
+    _fields_ = [("t_queue_s", C.c_double), ("t_run_s", C.c_double), ("t_latency_s", C.c_double),
+                ("run", gmc_run_stats)]
+
+
+class gmc_server_status_t(C.Structure):
+    _fields_ = [("running", C.c_int), ("pending", C.c_int), ("in_flight", C.c_int),
+                ("finished_unpolled", C.c_int), ("budget_bytes", C.c_size_t)]
+
+
 _lib = None
 
 
@@ -116,6 +130,13 @@ def lib():
                                 C.POINTER(gmc_run_stats)]
     L.gmc_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(gmc_source), C.POINTER(C.c_uint64), C.c_int,
                                C.c_double, C.POINTER(gmc_tuning), C.POINTER(gmc_autotune_report)]
+    L.gmc_server_start.argtypes = [vp, C.POINTER(gmc_server_config)]
+    L.gmc_server_stop.argtypes = [vp]
+    L.gmc_submit.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(gmc_source), C.c_uint64, C.c_uint64,
+                             C.POINTER(C.c_uint64)]
+    L.gmc_poll.argtypes = [vp, C.c_uint64, C.c_int, C.POINTER(C.c_int), vp, vp, C.c_int,
+                           C.POINTER(gmc_request_stats)]
+    L.gmc_server_status.argtypes = [vp, C.POINTER(gmc_server_status_t)]
     L.gmc_rng_words.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint32, C.c_int,
                                 C.POINTER(C.c_uint32)]
     L.gmc_table_eval.argtypes = [vp, C.c_int32, C.c_int, C.c_int, dp, C.c_int, dp]
@@ -289,6 +310,49 @@ class Context:
                                          C.byref(rep)))
         return ({f: getattr(tun, f) for f, _ in gmc_tuning._fields_},
                 {f: getattr(rep, f) for f, _ in gmc_autotune_report._fields_})
+
+    # --------------------------------------------------------- served form
+    def server_start(self, hbm_budget_bytes: int = 0, max_slots: int = 0):
+        cfg = gmc_server_config(int(hbm_budget_bytes), int(max_slots))
+        self._check(self._L.gmc_server_start(self._h, C.byref(cfg)))
+
+    def server_stop(self):
+        self._check(self._L.gmc_server_stop(self._h))
+
+    def server_status(self) -> dict:
+        st = gmc_server_status_t()
+        self._check(self._L.gmc_server_status(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in gmc_server_status_t._fields_}
+
+    def submit(self, phantom_id: int, tables_id: int, source, n_hist: int, seed: int) -> int:
+        src = _src(source)
+        t = C.c_uint64()
+        self._check(self._L.gmc_submit(self._h, phantom_id, tables_id, C.byref(src), int(n_hist), int(seed),
+                                       C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, shape, wait: bool = True, sigma: bool = True, out: str = "numpy"):
+        """(done, dose, sigma, stats); dose/sigma None while not done.  A
+        finished ticket is retired by the call that returns it."""
+        n = int(np.prod(shape))
+        if out == "torch":
+            import torch
+            d = torch.empty(n, dtype=torch.float64, device="cuda")
+            s = torch.empty(n, dtype=torch.float64, device="cuda") if sigma else None
+            dp, sp, kind = d.data_ptr(), (s.data_ptr() if s is not None else None), GMC_DEVICE
+        else:
+            d = np.empty(n, np.float64)
+            s = np.empty(n, np.float64) if sigma else None
+            dp, sp, kind = d.ctypes.data, (s.ctypes.data if s is not None else None), GMC_HOST
+        done = C.c_int()
+        st = gmc_request_stats()
+        self._check(self._L.gmc_poll(self._h, int(ticket), 1 if wait else 0, C.byref(done), dp, sp, kind,
+                                     C.byref(st)))
+        if not done.value:
+            return False, None, None, None
+        stats = {"t_queue_s": st.t_queue_s, "t_run_s": st.t_run_s, "t_latency_s": st.t_latency_s}
+        stats.update(stats_dict(st.run))
+        return True, d.reshape(*shape), (s.reshape(*shape) if s is not None else None), stats
 
     # ------------------------------------------------------------- checks
     def rng_words(self, seed: int, beam: int, hist: int, path: int, n0: int, count: int) -> np.ndarray:

@@ -125,12 +125,19 @@ def ellipsoids(n: Sequence[int], voxel: float, seed: int, count: int = 12,
     zc = ((np.arange(nz) + 0.5) * voxel)[:, None, None]
     yc = ((np.arange(ny) + 0.5) * voxel)[None, :, None]
     xc = ((np.arange(nx) + 0.5) * voxel)[None, None, :]
+    def span(cen, axis, ncell):   # voxel centres within the ellipsoid's bounding box on one axis
+        lo = max(int(np.floor((cen - axis) / voxel - 0.5)), 0)
+        hi = min(int(np.ceil((cen + axis) / voxel + 0.5)) + 1, ncell)
+        return slice(lo, max(lo, hi))
+
     for _ in range(count):
         c = rng.uniform(0, 1, 3) * ext
         a = rng.uniform(axis_frac[0], axis_frac[1], 3) * ext
         d = rng.uniform(*rho_range)
-        inside = ((xc - c[0]) / a[0]) ** 2 + ((yc - c[1]) / a[1]) ** 2 + ((zc - c[2]) / a[2]) ** 2 <= 1.0
-        rho[inside] = d
+        sx, sy, sz = span(c[0], a[0], nx), span(c[1], a[1], ny), span(c[2], a[2], nz)
+        inside = (((xc[:, :, sx] - c[0]) / a[0]) ** 2 + ((yc[:, sy, :] - c[1]) / a[1]) ** 2
+                  + ((zc[sz, :, :] - c[2]) / a[2]) ** 2 <= 1.0)
+        rho[sz, sy, sx][inside] = d
     return Phantom(rho, material_from_density(rho), (float(voxel),) * 3)
 
 
@@ -225,3 +232,51 @@ def beamlet_job(n_beamlets: int = 256, shape=(200, 200, 160), voxel: float = 0.2
     name = "beamlets_%d_%dx%dx%d" % (n_beamlets, shape[0], shape[1], shape[2])
     return BeamJob(name, DEFAULT_MATERIALS, ph, srcs, counts, Physics(ecut=0.7, pcut=0.01))
 
+
+
+@dataclass
+class DoseRequest:
+    """One request of the served form: a beam on one phantom of the pool."""
+    phantom: int                 # index into the request stream's phantom pool
+    source: Source
+    n_hist: int
+    seed: int
+
+
+def request_stream(seed: int = 13, n_requests: int = 200, n_phantoms: int = 16, grid=(32, 256),
+                   voxel=(0.25, 0.5), log10_hist=(5.0, 8.0)) -> Tuple[List[Phantom], List[DoseRequest]]:
+    """Seeded dose requests: a pool of ellipsoid phantoms (cubic grids of
+    U{grid} voxels of U(voxel) cm) that requests draw from, photons or
+    electrons at 3:1, energy monoenergetic U(1, 20) MeV or triangular on
+    [2, 18] MeV with mode 10 (even odds), square field U(1, 10) cm centred on
+    the entry face, 10^U(log10_hist) histories.  ECUT/PCUT as in
+    ``serving_physics``."""
+    rng = np.random.default_rng(seed)
+    pool = []
+    for i in range(n_phantoms):
+        n = int(rng.integers(grid[0], grid[1] + 1))
+        pool.append(ellipsoids(n, float(rng.uniform(*voxel)), seed=10_000 + 97 * seed + i))
+    reqs = []
+    for j in range(n_requests):
+        k = int(rng.integers(n_phantoms))
+        particle = ELECTRON if rng.random() < 0.25 else PHOTON
+        side = float(rng.uniform(1.0, 10.0))
+        if rng.random() < 0.5:
+            src = Source(particle, MONO, float(rng.uniform(1.0, 20.0)), wx=side, wy=side, beam_id=j)
+        else:
+            src = Source(particle, TRIANGULAR, 10.0, e_lo=2.0, e_mode=10.0, e_hi=18.0, wx=side, wy=side, beam_id=j)
+        reqs.append(DoseRequest(k, centred(pool[k], src), int(round(10.0 ** rng.uniform(*log10_hist))), 1 + j))
+    return pool, reqs
+
+
+def serving_physics() -> Physics:
+    """Cutoffs of the served requests (as in the 15 MeV and slab set-ups)."""
+    return Physics(ecut=0.7, pcut=0.01)
+
+
+def poisson_arrivals(rate: float, n: int, seed: int = 17) -> np.ndarray:
+    """Arrival times (s from the first) of a Poisson stream of n requests at ``rate`` per second."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, n)
+    gaps[0] = 0.0
+    return np.cumsum(gaps)

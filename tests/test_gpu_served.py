@@ -1,0 +1,116 @@
+"""GPU: the served form (continuous batching of dose requests).
+
+Bars:
+* every request's dose and sigma are bit-identical to running the same
+  request alone through the plain form (same phantom, tables, source,
+  histories and seed), whatever ran beside it;
+* requests submitted together overlap: with several slots, later requests
+  start before earlier ones finish; with a budget that fits one slot, they
+  run one after another;
+* a request whose footprint can never fit is refused (GMC_EBUSY), ids held by
+  queued requests cannot be released, and bad requests are rejected at
+  submission.
+"""
+import numpy as np
+import pytest
+
+from paper_1101_1245_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_1101_1245_amd import gpumcd
+    return gpumcd
+
+
+@pytest.fixture(scope="module")
+def ctx(G):
+    c = G.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def stream(ctx):
+    pool, reqs = I.request_stream(seed=5, n_requests=10, n_phantoms=3, grid=(24, 48), log10_hist=(4.0, 5.3))
+    tid = ctx.load_tables(I.DEFAULT_MATERIALS, I.serving_physics())
+    pids = [ctx.load_phantom(p) for p in pool]
+    yield pool, reqs, tid, pids
+    for p in pids:
+        ctx.release(p)
+    ctx.release(tid)
+
+
+def run_all(ctx, pool, reqs, tid, pids):
+    tickets = [ctx.submit(pids[r.phantom], tid, r.source, r.n_hist, r.seed) for r in reqs]
+    out = []
+    for t, r in zip(tickets, reqs):
+        done, d, s, st = ctx.poll(t, pool[r.phantom].shape, wait=True)
+        assert done
+        out.append((d, s, st))
+    return out
+
+
+def test_results_equal_alone(ctx, stream):
+    pool, reqs, tid, pids = stream
+    ctx.server_start(max_slots=4)
+    try:
+        res = run_all(ctx, pool, reqs, tid, pids)
+    finally:
+        ctx.server_stop()
+    for (d, s, st), r in zip(res, reqs):
+        assert st["ledger_residual_lsb"] == 0 and st["n_majorant_violations"] == 0
+        da, sa, _ = ctx.run_beam(pids[r.phantom], tid, r.source, r.n_hist, r.seed, shape=pool[r.phantom].shape)
+        assert np.array_equal(d, da) and np.array_equal(s, sa), r
+    # overlap: some request started before an earlier one finished
+    starts = [st["t_queue_s"] for _, _, st in res]
+    ends = [st["t_latency_s"] for _, _, st in res]
+    assert any(starts[j] < ends[i] for i in range(len(res)) for j in range(i + 1, len(res)))
+
+
+def test_one_slot_budget_serialises(ctx, G, stream):
+    pool, reqs, tid, pids = stream
+    sub = reqs[:4]
+    ctx.server_start(max_slots=1)
+    try:
+        tickets = [ctx.submit(pids[r.phantom], tid, r.source, r.n_hist, r.seed) for r in sub]
+        # the last request waits behind the others on the single slot: its phantom is held
+        with pytest.raises(G.GpumcdError) as e:
+            ctx.release(pids[sub[-1].phantom])
+        assert e.value.code == G.GMC_EBUSY
+        res = [ctx.poll(t, pool[r.phantom].shape, wait=True)[1:] for t, r in zip(tickets, sub)]
+    finally:
+        ctx.server_stop()
+    for i in range(1, len(res)):
+        assert res[i][2]["t_queue_s"] >= res[i - 1][2]["t_latency_s"] - 1e-4
+    ctx.server_start(max_slots=2, hbm_budget_bytes=1 << 20)
+    try:
+        with pytest.raises(G.GpumcdError) as e:
+            ctx.submit(pids[0], tid, reqs[0].source, reqs[0].n_hist, 1)
+        assert e.value.code == G.GMC_EBUSY
+    finally:
+        ctx.server_stop()
+
+
+def test_bad_requests_and_device_output(ctx, G, stream):
+    pool, reqs, tid, pids = stream
+    ctx.server_start()
+    try:
+        with pytest.raises(G.GpumcdError):
+            ctx.submit(pids[0], tid, reqs[0].source, 5, 1)                 # fewer histories than batches
+        with pytest.raises(G.GpumcdError):
+            ctx.submit(9999, tid, reqs[0].source, 1000, 1)                 # unknown phantom
+        with pytest.raises(G.GpumcdError):
+            ctx.submit(pids[0], tid, I.Source(I.PHOTON, e=45.0), 1000, 1)  # energy out of range
+        r = reqs[1]
+        t = ctx.submit(pids[r.phantom], tid, r.source, r.n_hist, r.seed)
+        done, d, s, st = ctx.poll(t, pool[r.phantom].shape, wait=True, out="torch")
+        assert done
+        with pytest.raises(G.GpumcdError):
+            ctx.poll(t, pool[r.phantom].shape)                             # retired
+    finally:
+        ctx.server_stop()
+    da, sa, _ = ctx.run_beam(pids[r.phantom], tid, r.source, r.n_hist, r.seed, shape=pool[r.phantom].shape)
+    assert np.array_equal(d.cpu().numpy(), da) and np.array_equal(s.cpu().numpy(), sa)
