@@ -15,6 +15,12 @@ histories N_1% that bring s to 1%.  One step = both beams at N_1%:
 `value` is the batched leg's rate; the plain leg's is reported beside it.
 Inputs are resident in HBM and outputs stay in device memory.
 
+Served leg (``served``): a seeded Poisson stream of 200 dose requests
+(ellipsoid phantoms of 32^3-256^3 voxels from a resident pool, mixed beams,
+1e5-1e8 histories) at 0.7 x the capacity measured by a closed-loop pilot,
+through the continuous-batching server; p50/p99 latency from submission to
+result and the aggregate histories/s.
+
 ``--workload beamlets``: 256 pencil beamlets (0.5 x 0.5 cm, 1-20 MeV,
 photons:electrons 3:1, 1e4-1e6 histories each) on a 200x200x160 ellipsoid
 phantom at 0.25 cm; plain = 256 gmc_run_beam calls, batched = one
@@ -22,8 +28,8 @@ gmc_run_beams call with per-beamlet doses.
 
 Prints one JSON line with the throughput, the roofline of the dominant kernel
 (average launch duration from the HIP event pairs around every pass launch in
-the timed region) and, for the default workload, the oracle's CPU rate on a
-bounded sample.
+the timed regions of all legs) and, for the default workload, the oracle's CPU
+rate on a bounded sample.
 """
 import argparse
 import json
@@ -181,7 +187,7 @@ def bench_water(args, G, E, I):
     both.merge(acc_p)
     both.merge(acc_b)
     out = {
-        "metric": "histories/s at 1% stat. unc. (plain vs batched)",
+        "metric": "histories/s at 1% stat. unc. (plain vs batched); served dose p50/p99 latency",
         "value": acc_b.hist / el_b,
         "unit": "histories/s",
         "n_gpus": 1,
@@ -205,11 +211,9 @@ def bench_water(args, G, E, I):
         "plain": {"value": acc_p.hist / el_p, "ms_per_step": el_p / args.steps * 1e3},
         "batched_over_plain": (acc_b.hist / el_b) / (acc_p.hist / el_p),
         "batched_equals_plain_per_beam": same,
-        "roofline": roofline(both),
-        "ledger_residual_lsb": both.resid,
     }
     ctx.close()
-    return out
+    return out, both
 
 
 def bench_beamlets(args, G, E, I):
@@ -287,6 +291,79 @@ def bench_beamlets(args, G, E, I):
     return out
 
 
+def bench_serve(args, G, I):
+    """Served form: a Poisson stream of dose requests at 0.7 x the capacity of
+    a closed-loop pilot; latency from submission to result."""
+    import threading
+    import numpy as np
+    pool, reqs = I.request_stream(seed=13, n_requests=args.serve_requests)
+    ctx = G.Context(0)
+    tid = ctx.load_tables(I.DEFAULT_MATERIALS, I.serving_physics())
+    pids = [ctx.load_phantom(p) for p in pool]
+    acc = Acc()
+
+    def drain(tickets, sub):
+        out = []
+        for t, r in zip(tickets, sub):
+            _, _, _, st = ctx.poll(t, pool[r.phantom].shape, wait=True, sigma=True)
+            acc.add(st)
+            out.append(st)
+        return out
+
+    ctx.server_start(max_slots=args.serve_slots)
+    try:
+        # closed-loop pilot: a batch of requests submitted at once
+        pilot = reqs[:min(len(reqs), 40)]
+        t0 = time.perf_counter()
+        drain([ctx.submit(pids[r.phantom], tid, r.source, r.n_hist, 10_000 + r.seed) for r in pilot], pilot)
+        capacity = len(pilot) / (time.perf_counter() - t0)
+        rate = 0.7 * capacity
+        arrivals = I.poisson_arrivals(rate, len(reqs), seed=17)
+        acc = Acc()
+        tickets = [None] * len(reqs)
+        ready = [threading.Event() for _ in reqs]
+
+        def submitter():
+            start = time.perf_counter()
+            for i, r in enumerate(reqs):
+                delay = start + arrivals[i] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                tickets[i] = ctx.submit(pids[r.phantom], tid, r.source, r.n_hist, r.seed)
+                ready[i].set()
+
+        th = threading.Thread(target=submitter)
+        t0 = time.perf_counter()
+        th.start()
+        stats = []
+        for i, r in enumerate(reqs):
+            ready[i].wait()
+            stats.extend(drain([tickets[i]], [r]))
+        el = time.perf_counter() - t0
+        th.join()
+    finally:
+        ctx.server_stop()
+    lat = np.array([st["t_latency_s"] for st in stats])
+    queue = np.array([st["t_queue_s"] for st in stats])
+    hist = sum(r.n_hist for r in reqs)
+    for p in pids:
+        ctx.release(p)
+    ctx.close()
+    out = {
+        "requests": len(reqs), "slots": args.serve_slots, "phantom_pool": len(pool),
+        "capacity_req_per_s": capacity, "rate_req_per_s": rate,
+        "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+        "mean_latency_s": float(lat.mean()), "p99_queue_s": float(np.percentile(queue, 99)),
+        "histories_per_s": hist / el, "histories": hist, "elapsed_s": el,
+        "workload": "Poisson stream of %d requests (seed 13) at 0.7 x closed-loop capacity: cubic ellipsoid "
+                    "phantoms 32^3-256^3 at 0.25-0.5 cm (pool of %d), photons:electrons 3:1, 1-20 MeV mono or "
+                    "2-10-18 MeV triangular, 1-10 cm fields, 1e5-1e8 histories" % (len(reqs), len(pool)),
+    }
+    print("served: p50 %.3f s p99 %.3f s, %.3e histories/s at %.2f req/s" %
+          (out["p50_latency_s"], out["p99_latency_s"], out["histories_per_s"], rate), file=sys.stderr, flush=True)
+    return out, acc
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,6 +371,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=("water", "beamlets"), default="water")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-form leg")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--target", type=float, default=0.01, help="statistical uncertainty s of Eq. 12")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -306,7 +386,12 @@ def main():
     from paper_1101_1245_amd import inputs as I
 
     if args.workload == "water":
-        out = bench_water(args, G, E, I)
+        out, acc = bench_water(args, G, E, I)
+        if not args.no_serve:
+            out["served"], acc_s = bench_serve(args, G, I)
+            acc.merge(acc_s)
+        out["roofline"] = roofline(acc)
+        out["ledger_residual_lsb"] = acc.resid
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline()
     else:

@@ -228,13 +228,17 @@ gmc_tuning default_tuning() {
   return t;
 }
 
-// Queue capacity: room for two admission chunks of primaries with their
-// per-visit secondaries, at least 2^23 and at most 2^26 particles.  Staging:
-// every wavefront of the pass grid gets segments for its largest share of a
-// pass times the per-visit output budget.
-void queue_sizes(Workspace* w, const Tune& tu, int n_mat, uint32_t* cap, uint32_t* stg) {
-  const uint64_t want = (uint64_t)tu.chunk * (uint64_t)(tu.secondaries + 1) * 2u;
-  *cap = (uint32_t)std::max<uint64_t>(kDefaultCap, std::min<uint64_t>(want, kMaxCap));
+// Queue capacity.  Soft: what admission and the outputs of the other type
+// may fill -- four admission chunks, at least 2^22 and at most 2^25
+// particles.  Allocated: the soft capacity plus a full pass of this type's
+// own per-visit outputs, so a pass is never shrunk by its own backlog (a
+// type whose pass could only take a sliver of its queue would fall behind
+// the other type feeding it).  Staging: every wavefront of the pass grid
+// gets segments for its largest share of a pass times the per-visit budget.
+void queue_sizes(Workspace* w, const Tune& tu, int n_mat, uint32_t* cap, uint32_t* cap_soft, uint32_t* stg) {
+  const uint64_t soft = std::max<uint64_t>(kMinSoftCap, std::min<uint64_t>(4ull * (uint64_t)tu.chunk, kMaxSoftCap));
+  *cap_soft = (uint32_t)soft;
+  *cap = (uint32_t)(soft + (uint64_t)tu.secondaries * (uint64_t)tu.pass_items);
   uint32_t s = 0;
   for (int t = 0; t < 2; ++t) {
     const uint32_t bud = t == 0 ? (uint32_t)tu.secondaries : (uint32_t)tu.secondaries + 1u;
@@ -427,6 +431,7 @@ int enqueue_pass(Engine& E, int type, hipEvent_t t0, hipEvent_t t1, bool capturi
   pa.n_other = count_ptr(w, other, w->acc[other]);
   pa.plan = w->d_ctl->plan + type;
   pa.cap = w->cap;
+  pa.cap_other = w->cap_soft;
   pa.max_items = (uint32_t)E.tu.pass_items;
   pa.waves = E.waves[type];
   pa.min_per_wave = (uint32_t)E.tu.wave_items;
@@ -474,7 +479,7 @@ int enqueue_admission(Engine& E) {
   ap.count0 = count_ptr(w, 0, w->acc[0]);
   ap.count1 = count_ptr(w, 1, w->acc[1]);
   ap.out = w->d_ctl->adm;
-  ap.cap = w->cap;
+  ap.cap = w->cap_soft;
   ap.chunk = (uint32_t)E.tu.chunk;
   WS_TRY(w, launch_admit_plan(ap, w->stream));
   for (int t = 0; t < 2; ++t) {
@@ -499,9 +504,12 @@ int read_control(Workspace* w) {
 }
 
 int stuck(Workspace* w) {
+  const Control& st = *w->h_ctl;
   return wfail(w, GMC_EOVERFLOW,
-               "both particle queues are too full for any pass to proceed; lower the chunk or the secondaries "
-               "budget");
+               "both particle queues are too full for any pass to proceed (photons " +
+                   std::to_string(st.counts[0] + st.counts[1]) + ", electrons " +
+                   std::to_string(st.counts[2] + st.counts[3]) + ", capacity " + std::to_string(w->cap_soft) +
+                   "); lower the chunk or the secondaries budget");
 }
 
 int add_pass_time(Workspace* w, int type, hipEvent_t t0, hipEvent_t t1) {
@@ -526,10 +534,12 @@ int engine_setup(Workspace* w, Engine& E, const Job& J, const Tune& tu) {
   E.total[0] = J.total[0];
   E.total[1] = J.total[1];
   const int n_mat = J.T->host.n_mat;
-  uint32_t cap = 0, stg = 0;
-  queue_sizes(w, tu, n_mat, &cap, &stg);
+  uint32_t cap = 0, soft = 0, stg = 0;
+  queue_sizes(w, tu, n_mat, &cap, &soft, &stg);
+  if ((uint64_t)cap * Q_FIELDS >= (1ull << 32)) return wfail(w, GMC_EOVERFLOW, "queue capacity too large");
   int rc = ensure_queues(w, cap);
   if (rc) return rc;
+  w->cap_soft = soft;
   rc = ensure_staging(w, stg);
   if (rc) return rc;
   for (int t = 0; t < 2; ++t) {

@@ -47,8 +47,8 @@ struct QueueBuf {
   void* base = nullptr;
 };
 
-constexpr uint32_t kDefaultCap = 1u << 23;
-constexpr uint32_t kMaxCap = 1u << 26;
+constexpr uint32_t kMinSoftCap = 1u << 22;
+constexpr uint32_t kMaxSoftCap = 1u << 25;
 constexpr uint32_t kMaxWaves = 1u << 15;
 constexpr double kAutotuneBudgetS = 3.0;   // default wall-clock budget of one tuning
 
@@ -74,7 +74,8 @@ struct Workspace {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
-  uint32_t cap = 0;
+  uint32_t cap = 0;              // allocated particles per queue buffer
+  uint32_t cap_soft = 0;         // what admission and other-type outputs may fill
   QueueBuf qbuf[2][2];          // [type: 0 photon, 1 electron][2 buffers]
   int acc[2] = {0, 0};          // buffer of each type that accumulates
   QueueBuf stg[2];              // staging: [0] same type, [1] other type
@@ -133,8 +134,8 @@ struct Tune {
 Tune resolve_tuning(const gmc_tuning* t);
 gmc_tuning default_tuning();
 
-// Queue capacity and staging slots the engine allocates for a tuning.
-void queue_sizes(Workspace* w, const Tune& tu, int n_mat, uint32_t* cap, uint32_t* stg);
+// Queue capacity (allocated and soft) and staging slots the engine uses for a tuning.
+void queue_sizes(Workspace* w, const Tune& tu, int n_mat, uint32_t* cap, uint32_t* cap_soft, uint32_t* stg);
 
 int check_source(std::string* err, const gmc_source* s);
 uint32_t mev_to_lsb(double e);

@@ -119,7 +119,8 @@ struct PlanArgs {
   const uint32_t* n_work;       // count of the work buffer
   const uint32_t* n_other;      // count of the other type's accumulating buffer
   PassPlan* plan;
-  uint32_t cap;                 // queue capacity
+  uint32_t cap;                 // allocated queue capacity (bounds this type's own outputs)
+  uint32_t cap_other;           // soft capacity the outputs to the other type must respect
   uint32_t max_items;           // most particles per pass
   uint32_t waves;               // wavefronts in the pass grid
   uint32_t min_per_wave;        // fewest particles per wavefront (64: one per lane)
@@ -180,7 +181,7 @@ struct AdmitPlanArgs {
   uint32_t* count0;             // accumulating photon count
   uint32_t* count1;             // accumulating electron count
   AdmitPlan* out;               // [2]
-  uint32_t cap, chunk;
+  uint32_t cap, chunk;          // cap: the soft queue capacity
 };
 
 struct AdmitArgs {

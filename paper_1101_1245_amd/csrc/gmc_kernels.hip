@@ -59,7 +59,7 @@ __global__ void k_admit_plan(AdmitPlanArgs a) {
     uint32_t take = 0;
     if (have < a.chunk) {
       take = min(left, a.chunk);
-      take = min(take, a.cap - have);
+      take = have < a.cap ? min(take, a.cap - have) : 0u;
     }
     a.out[t].base = have;
     a.out[t].count = take;
@@ -687,12 +687,15 @@ __global__ void k_plan_pass(PlanArgs a) {
   const uint32_t n = *a.n_work;
   const uint32_t no = *a.n_other;
   uint64_t m = n < a.max_items ? n : a.max_items;
+  // own outputs (carry-over + per-visit budget) must fit the allocated
+  // buffer; outputs to the other type only fill it up to its soft capacity,
+  // which leaves every type room for a full pass of its own outputs
   if (a.bud_same > 1) {
-    const uint64_t lim = (uint64_t)(a.cap - n) / (a.bud_same - 1);
+    const uint64_t lim = n < a.cap ? (uint64_t)(a.cap - n) / (a.bud_same - 1) : 0u;
     if (m > lim) m = lim;
   }
   if (a.bud_other > 0) {
-    const uint64_t lim = (uint64_t)(a.cap - no) / a.bud_other;
+    const uint64_t lim = no < a.cap_other ? (uint64_t)(a.cap_other - no) / a.bud_other : 0u;
     if (m > lim) m = lim;
   }
   uint32_t q = (uint32_t)((m + a.waves - 1) / a.waves);

@@ -320,8 +320,8 @@ int gmc_server_start(gmc_context* c, const gmc_server_config* cfg) {
   // queues and staging of one slot at the default tuning
   Workspace probe;
   probe.device = c->device;
-  uint32_t cap = 0, stg = 0;
-  queue_sizes(&probe, resolve_tuning(nullptr), kMaxMat, &cap, &stg);
+  uint32_t cap = 0, soft = 0, stg = 0;
+  queue_sizes(&probe, resolve_tuning(nullptr), kMaxMat, &cap, &soft, &stg);
   s->slot_fixed = (size_t)Q_FIELDS * sizeof(uint32_t) * (4ull * cap + 2ull * stg);
   for (int i = 0; i < s->max_slots; ++i) s->slots.push_back(std::make_unique<Slot>());
   s->running = true;

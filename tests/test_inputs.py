@@ -1,0 +1,81 @@
+"""CPU: the seeded input generators (phantoms, beamlet batches, request streams).
+
+These feed both the oracle and the HIP path, so they must be deterministic and
+have the shapes and distributions the workloads state.
+"""
+import numpy as np
+
+from paper_1101_1245_amd import inputs as I
+
+
+def _ellipsoids_full_grid(n, voxel, seed, count=12, rho_range=(0.2, 1.9), axis_frac=(0.05, 0.35)):
+    # the same draws evaluated over the whole grid for every ellipsoid
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else tuple(n)
+    rng = np.random.default_rng(seed)
+    ext = np.array([nx, ny, nz], np.float64) * voxel
+    rho = np.ones((nz, ny, nx), np.float32)
+    zc = ((np.arange(nz) + 0.5) * voxel)[:, None, None]
+    yc = ((np.arange(ny) + 0.5) * voxel)[None, :, None]
+    xc = ((np.arange(nx) + 0.5) * voxel)[None, None, :]
+    for _ in range(count):
+        c = rng.uniform(0, 1, 3) * ext
+        a = rng.uniform(axis_frac[0], axis_frac[1], 3) * ext
+        d = rng.uniform(*rho_range)
+        rho[((xc - c[0]) / a[0]) ** 2 + ((yc - c[1]) / a[1]) ** 2 + ((zc - c[2]) / a[2]) ** 2 <= 1.0] = d
+    return rho
+
+
+def test_ellipsoids_bounding_box_evaluation_is_exact():
+    for n, voxel, seed in (((48, 48, 40), 0.5, 7), (33, 0.31, 3), ((64, 50, 70), 0.25, 11), (97, 0.45, 2)):
+        ph = I.ellipsoids(n, voxel, seed)
+        assert np.array_equal(ph.rho, _ellipsoids_full_grid(n, voxel, seed))
+        assert np.array_equal(ph.mat, I.material_from_density(ph.rho))
+        assert ph.rho.min() >= 0.2 - 1e-6 and ph.rho.max() <= 1.9 + 1e-6
+
+
+def test_beamlet_job_shapes_and_mix():
+    j = I.beamlet_job()
+    assert j.phantom.shape == (160, 200, 200) and j.phantom.voxel == (0.25, 0.25, 0.25)
+    assert len(j.sources) == 256 and len(j.counts) == 256
+    kinds = np.array([s.particle for s in j.sources])
+    assert (kinds == I.PHOTON).sum() == 192 and (kinds == I.ELECTRON).sum() == 64
+    assert j.counts.min() >= 10 ** 4 and j.counts.max() <= 10 ** 6
+    assert 4e7 < j.counts.sum() < 7e7
+    energies = np.array([s.e for s in j.sources])
+    assert energies.min() >= 1.0 and energies.max() <= 20.0
+    assert sorted(s.beam_id for s in j.sources) == list(range(256))
+    # centred 16 x 16 grid at 1 cm pitch
+    cx = np.array([s.cx for s in j.sources])
+    assert np.isclose(cx.mean(), 25.0) and np.isclose(cx.max() - cx.min(), 15.0)
+    small = I.beamlet_job(16, (48, 48, 40), 0.5, count_scale=0.01, min_count=200)
+    assert small.counts.min() >= 200 and np.array_equal(small.counts, I.beamlet_job(16, (48, 48, 40), 0.5, 0.01, 200).counts)
+
+
+def test_request_stream_is_seeded_and_in_range():
+    pool, reqs = I.request_stream(seed=13, n_requests=200, n_phantoms=6, grid=(32, 64))
+    pool2, reqs2 = I.request_stream(seed=13, n_requests=200, n_phantoms=6, grid=(32, 64))
+    assert all(np.array_equal(a.rho, b.rho) for a, b in zip(pool, pool2))
+    assert [(r.phantom, r.n_hist, r.seed, r.source.e) for r in reqs] == [(r.phantom, r.n_hist, r.seed, r.source.e)
+                                                                         for r in reqs2]
+    assert all(32 <= p.shape[0] <= 64 and p.shape[0] == p.shape[1] == p.shape[2] for p in pool)
+    assert all(0.25 <= p.voxel[0] <= 0.5 for p in pool)
+    n = np.array([r.n_hist for r in reqs])
+    assert n.min() >= 10 ** 5 and n.max() <= 10 ** 8
+    electrons = sum(r.source.particle == I.ELECTRON for r in reqs)
+    assert 25 <= electrons <= 75                          # 3:1 photons to electrons, binomial spread
+    tri = [r for r in reqs if r.source.spectrum == I.TRIANGULAR]
+    assert 70 <= len(tri) <= 130
+    assert all((r.source.e_lo, r.source.e_mode, r.source.e_hi) == (2.0, 10.0, 18.0) for r in tri)
+    for r in reqs:
+        ex, ey, _ = pool[r.phantom].extent
+        assert np.isclose(r.source.cx, ex / 2) and np.isclose(r.source.cy, ey / 2)
+        assert 1.0 <= r.source.wx <= 10.0 and r.source.wx == r.source.wy
+    assert len({r.source.beam_id for r in reqs}) == len(reqs)
+
+
+def test_poisson_arrivals():
+    t = I.poisson_arrivals(50.0, 20000, seed=3)
+    assert t[0] == 0.0 and np.all(np.diff(t) >= 0)
+    gaps = np.diff(t)
+    assert abs(gaps.mean() - 1 / 50.0) < 4 * (1 / 50.0) / np.sqrt(gaps.size)
+    assert abs(gaps.std() / gaps.mean() - 1.0) < 0.05      # exponential gaps: coefficient of variation 1
