@@ -28,8 +28,8 @@ gmc_run_beams call with per-beamlet doses.
 
 Prints one JSON line with the throughput, the roofline of the dominant kernel
 (average launch duration from the HIP event pairs around every pass launch in
-the timed regions of all legs) and, for the default workload, the oracle's CPU
-rate on a bounded sample.
+the timed plain and batched legs) and, for the default workload, the oracle's
+CPU rate on a bounded sample.
 """
 import argparse
 import json
@@ -374,6 +374,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form leg")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
+                    help="first run one device-to-device copy of MIB MiB: a kernel of known traffic that "
+                         "hardware byte counters can be scaled by")
     ap.add_argument("--target", type=float, default=0.01, help="statistical uncertainty s of Eq. 12")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -385,13 +388,26 @@ def main():
     from paper_1101_1245_amd import gpumcd as G
     from paper_1101_1245_amd import inputs as I
 
+    if args.copy_reference > 0:
+        import torch
+        src = torch.ones(args.copy_reference << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     if args.workload == "water":
         out, acc = bench_water(args, G, E, I)
-        if not args.no_serve:
-            out["served"], acc_s = bench_serve(args, G, I)
-            acc.merge(acc_s)
+        # the roofline covers the plain and batched legs, where each pass kernel has
+        # the GPU to itself; served requests overlap on purpose (up to 4 slots), which
+        # stretches every kernel's duration
         out["roofline"] = roofline(acc)
         out["ledger_residual_lsb"] = acc.resid
+        if not args.no_serve:
+            out["served"], acc_s = bench_serve(args, G, I)
+            out["served"]["electron_pass_launches"] = acc_s.n[1]
+            out["served"]["electron_pass_ms_mean_overlapped"] = acc_s.t[1] / max(acc_s.n[1], 1) * 1e3
+            out["ledger_residual_lsb"] |= acc_s.resid
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline()
     else:

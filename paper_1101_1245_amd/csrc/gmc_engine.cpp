@@ -229,14 +229,14 @@ gmc_tuning default_tuning() {
 }
 
 // Queue capacity.  Soft: what admission and the outputs of the other type
-// may fill -- four admission chunks, at least 2^22 and at most 2^25
+// may fill -- eight admission chunks, at least 2^23 and at most 2^25
 // particles.  Allocated: the soft capacity plus a full pass of this type's
 // own per-visit outputs, so a pass is never shrunk by its own backlog (a
 // type whose pass could only take a sliver of its queue would fall behind
 // the other type feeding it).  Staging: every wavefront of the pass grid
 // gets segments for its largest share of a pass times the per-visit budget.
 void queue_sizes(Workspace* w, const Tune& tu, int n_mat, uint32_t* cap, uint32_t* cap_soft, uint32_t* stg) {
-  const uint64_t soft = std::max<uint64_t>(kMinSoftCap, std::min<uint64_t>(4ull * (uint64_t)tu.chunk, kMaxSoftCap));
+  const uint64_t soft = std::max<uint64_t>(kMinSoftCap, std::min<uint64_t>(8ull * (uint64_t)tu.chunk, kMaxSoftCap));
   *cap_soft = (uint32_t)soft;
   *cap = (uint32_t)(soft + (uint64_t)tu.secondaries * (uint64_t)tu.pass_items);
   uint32_t s = 0;

@@ -47,7 +47,7 @@ struct QueueBuf {
   void* base = nullptr;
 };
 
-constexpr uint32_t kMinSoftCap = 1u << 22;
+constexpr uint32_t kMinSoftCap = 1u << 23;
 constexpr uint32_t kMaxSoftCap = 1u << 25;
 constexpr uint32_t kMaxWaves = 1u << 15;
 constexpr double kAutotuneBudgetS = 3.0;   // default wall-clock budget of one tuning
