@@ -195,6 +195,32 @@ __device__ __forceinline__ void deposit(const Lane& L, int v, uint32_t e) {
   if (L.tb) atomicAdd(L.tb + v, (unsigned long long)e);
 }
 
+// An electron usually takes several steps in one voxel (a boundary-limited
+// step stops a hair short of the face, the next one crosses it), so the
+// electron pass keeps one pending deposit per lane and adds it to the tally
+// when the electron deposits elsewhere or leaves the lane.  The sum of a
+// particle's deposits never exceeds its energy (< 2^32 units), and integer
+// addition makes the result independent of when the additions happen.
+struct Pending {
+  int v = -1;
+  uint32_t e = 0;
+};
+
+__device__ __forceinline__ void flush(const Lane& L, Pending& p) {
+  if (p.e) deposit(L, p.v, p.e);
+  p.e = 0;
+  p.v = -1;
+}
+
+__device__ __forceinline__ void deposit_later(const Lane& L, Pending& p, int v, uint32_t e) {
+  if (!e) return;
+  if (v != p.v) {
+    flush(L, p);
+    p.v = v;
+  }
+  p.e += e;
+}
+
 // One photon flight and interaction decision (Sec. II.A, Eqs. 1-3): free path
 // with the majorant, then one uniform against the cumulative Compton,
 // photoelectric, pair partials of the voxel; fictitious otherwise.
@@ -400,6 +426,7 @@ __global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
   WaveRange range = wave_range(P, wave);
   WaveSeg gsame{wave * P.seg_same, P.seg_same, 0u}, gother{wave * P.seg_other, P.seg_other, 0u};
   Lane L;
+  Pending pend;
   bool have = false;
   int events = 0, pushes = 0;
   unsigned long long acc_esc = 0;
@@ -423,7 +450,7 @@ __global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
         const float rho0 = __uint_as_float(vx.x);
         const int base0 = (int)vx.y * kNE;
         if (L.e < a.cut.ecut_lsb) {
-          deposit(L, v0, L.e);
+          deposit_later(L, pend, v0, L.e);
           have = false;
         } else {
           ++c_steps;
@@ -451,7 +478,7 @@ __global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
           L.z = fmaf(s1, L.w, L.z);
           const uint32_t dl = to_lsb(de);
           if (dl >= L.e || L.e - dl < a.cut.ecut_lsb) {
-            deposit(L, v0, L.e);
+            deposit_later(L, pend, v0, L.e);
             have = false;
           } else {
             const uint32_t e1 = L.e - dl;
@@ -465,7 +492,7 @@ __global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
               const float cost = wentzel_cos(a.tab, ms, g1, ua);
               rotate(L.u, L.v, L.w, cost, kTwoPi * uphi);
             }
-            deposit(L, v0, dl);
+            deposit_later(L, pend, v0, dl);
             L.e = e1;
             const float s2 = (1.0f - zeta) * es;
             L.x = fmaf(s2, L.u, L.x);
@@ -502,11 +529,11 @@ __global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
                   child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
                   ctype = 1;
                 } else {
-                  deposit(L, v1, wl);
+                  deposit_later(L, pend, v1, wl);
                 }
                 L.e = tp;
                 if (tp < a.cut.ecut_lsb) {
-                  deposit(L, v1, tp);
+                  deposit_later(L, pend, v1, tp);
                   have = false;
                 }
               } else if (r < sm + sb) {
@@ -522,11 +549,11 @@ __global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
                   child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
                   ctype = 0;
                 } else {
-                  deposit(L, v1, kl);
+                  deposit_later(L, pend, v1, kl);
                 }
                 L.e -= kl;
                 if (L.e < a.cut.ecut_lsb) {
-                  deposit(L, v1, L.e);
+                  deposit_later(L, pend, v1, L.e);
                   have = false;
                 }
               }
@@ -542,6 +569,7 @@ __global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
           have = false;
         }
       }
+      if (!have) flush(L, pend);   // before the lane takes another particle
     }
     {
       // delta rays and survivors to the electron staging segment, photons to the photon one
