@@ -48,6 +48,23 @@ OPS_PER_E_STEP = 400.0
 OPS_PER_PH_EVENT = 175.0
 # 32-bit VALU lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (no packed FP32).
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# HBM bytes per launch of the pass kernels on the default workload, from two
+# rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE; fetched bytes scaled x2.0 and
+# written x1.0 by a 1 GiB copy in the same runs), taken on the kernel sources
+# with this digest; any other sources report null.
+TRAFFIC = {"sources_sha256": "71d9865785a73cc8031f1dd582a1c7d16bfc78ee9fd3cd2a1175d849740903e1",
+           "k_electron_pass": 315.0e6, "k_photon_pass": 161.7e6}
+KERNEL_SOURCES = ("paper_1101_1245_amd/csrc/gmc_kernels.hip", "paper_1101_1245_amd/csrc/gmc_device.hpp",
+                  "paper_1101_1245_amd/csrc/gmc_internal.hpp")
+
+
+def measured_traffic(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return TRAFFIC.get(kernel) if h.hexdigest() == TRAFFIC["sources_sha256"] else None
 
 
 def cpu_baseline():
@@ -98,7 +115,7 @@ class Acc:
         self.hist += o.hist
 
 
-def roofline(acc):
+def roofline(acc, workload="water"):
     """Dominant pass kernel (most device time), its average launch duration and
     algorithmic lane-ops per launch against the VALU lane-op peak."""
     if acc.t[1] >= acc.t[0]:
@@ -109,9 +126,15 @@ def roofline(acc):
     avg = t / n
     achieved = ops / n / avg / 1e12 if avg > 0 else 0.0
     peak = PEAK_LANE_OPS / 1e12
-    return {"bound": "alu", "kernel": name, "achieved": achieved, "peak": peak, "unit": "TOP/s",
-            "frac": achieved / peak, "traffic": None, "avg_launch_ms": avg * 1e3, "launches": n,
-            "share_of_pass_time": t / max(acc.t[0] + acc.t[1], 1e-30)}
+    traffic = measured_traffic(name) if workload == "water" else None
+    out = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": peak, "unit": "TOP/s",
+           "frac": achieved / peak, "traffic": traffic, "avg_launch_ms": avg * 1e3, "launches": n,
+           "share_of_pass_time": t / max(acc.t[0] + acc.t[1], 1e-30)}
+    if traffic:
+        out["traffic_unit"] = "bytes per launch"
+        out["hbm_GBps"] = traffic / avg / 1e9
+        out["hbm_frac"] = traffic / avg / 8.0e12
+    return out
 
 
 def sync():
@@ -284,7 +307,7 @@ def bench_beamlets(args, G, E, I):
         },
         "plain": {"value": acc_p.hist / el_p, "ms_per_step": el_p / args.steps * 1e3},
         "batched_over_plain": (acc_b.hist / el_b) / (acc_p.hist / el_p),
-        "roofline": roofline(both),
+        "roofline": roofline(both, "beamlets"),
         "ledger_residual_lsb": both.resid,
     }
     ctx.close()
