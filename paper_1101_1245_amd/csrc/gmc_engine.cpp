@@ -78,16 +78,36 @@ int ensure_graph_events(Workspace* w, size_t n) {
 }
 
 int resident_blocks(Workspace* w, int kernel, int block, int n_mat) {
-  if (w->resident[kernel] == 0 || w->resident_block[kernel] != block || w->resident_nmat[kernel] != n_mat) {
-    const size_t lds = kernel == 0 ? photon_lds_bytes(n_mat) : electron_lds_bytes(n_mat);
-    w->resident[kernel] = max_resident_blocks(kernel, block, lds);
-    w->resident_block[kernel] = block;
-    w->resident_nmat[kernel] = n_mat;
-  }
-  return w->resident[kernel];
+  const std::vector<int> key{kernel, block, n_mat};
+  auto it = w->resident.find(key);
+  if (it != w->resident.end()) return it->second;
+  const size_t lds = kernel == 0 ? photon_lds_bytes(n_mat) : electron_lds_bytes(n_mat);
+  const int r = max_resident_blocks(kernel, block, lds);
+  w->resident[key] = r;
+  return r;
 }
 
 }  // namespace
+
+uint32_t pass_waves(Workspace* w, int kernel, int block, int n_mat) {
+  const uint32_t wpb = (uint32_t)block / 64u;
+  const uint32_t res = (uint32_t)resident_blocks(w, kernel, block, n_mat);
+  return std::max<uint32_t>(1u, std::min<uint32_t>(res, kMaxWaves / wpb)) * wpb;
+}
+
+int pass_block(Workspace* w, int kernel, int requested, int n_mat) {
+  if (requested > 0) return requested;
+  int best = 256;
+  uint32_t best_waves = 0;
+  for (int b : {256, 512, 1024}) {
+    const uint32_t waves = pass_waves(w, kernel, b, n_mat);
+    if (waves > best_waves) {
+      best_waves = waves;
+      best = b;
+    }
+  }
+  return best;
+}
 
 int ws_init(Workspace* w, int device, hipStream_t stream) {
   w->device = device;
@@ -200,12 +220,12 @@ int ws_ensure_beams(Workspace* w, size_t n) {
 
 // ---------------------------------------------------------------- settings
 Tune resolve_tuning(const gmc_tuning* t) {
-  Tune r{64, 4, 1 << 20, 256, 1 << 21, 64, 4, 1};
+  Tune r{64, 4, 1 << 20, 0, 1 << 21, 64, 4, 1};
   if (t) {
     if (t->events_per_visit > 0) r.events = t->events_per_visit;
     if (t->secondaries_per_visit >= 2) r.secondaries = std::min(t->secondaries_per_visit, 64);
     if (t->chunk > 0) r.chunk = std::min(t->chunk, 1 << 24);
-    if (t->wg_size >= 64 && t->wg_size <= 256 && t->wg_size % 64 == 0) r.block = t->wg_size;
+    if (t->wg_size >= 64 && t->wg_size <= 1024 && t->wg_size % 64 == 0) r.block = t->wg_size;
     if (t->pass_items > 0) r.pass_items = std::min(std::max(t->pass_items, 1024), 1 << 23);
     if (t->wave_items > 0) r.wave_items = std::min(std::max(t->wave_items, 64), 1 << 16);
     if (t->rounds_per_check > 0) r.rounds = std::min(t->rounds_per_check, 1024);
@@ -242,9 +262,7 @@ void queue_sizes(Workspace* w, const Tune& tu, int n_mat, uint32_t* cap, uint32_
   uint32_t s = 0;
   for (int t = 0; t < 2; ++t) {
     const uint32_t bud = t == 0 ? (uint32_t)tu.secondaries : (uint32_t)tu.secondaries + 1u;
-    const uint32_t wpb = (uint32_t)tu.block / 64u;
-    const uint32_t res = (uint32_t)resident_blocks(w, t, tu.block, n_mat);
-    const uint32_t waves = std::max<uint32_t>(1u, std::min<uint32_t>(res, kMaxWaves / wpb)) * wpb;
+    const uint32_t waves = pass_waves(w, t, pass_block(w, t, tu.block, n_mat), n_mat);
     const uint32_t qmax = std::max<uint32_t>((uint32_t)tu.wave_items, ((uint32_t)tu.pass_items + waves - 1) / waves);
     s = std::max<uint32_t>(s, waves * qmax * bud);
   }
@@ -446,8 +464,8 @@ int enqueue_pass(Engine& E, int type, hipEvent_t t0, hipEvent_t t1, bool capturi
   a.used_same = w->d_used;
   a.used_other = w->d_used + kMaxWaves;
   WS_TRY(w, record_event(w->stream, t0, capturing));
-  hipError_t e = type == 0 ? launch_photon_pass(a, (int)E.blocks[0], E.tu.block, w->stream)
-                           : launch_electron_pass(a, (int)E.blocks[1], E.tu.block, w->stream);
+  hipError_t e = type == 0 ? launch_photon_pass(a, (int)E.blocks[0], E.block[0], w->stream)
+                           : launch_electron_pass(a, (int)E.blocks[1], E.block[1], w->stream);
   if (e != hipSuccess) return wfail(w, GMC_EDEVICE, std::string("pass launch: ") + hipGetErrorString(e));
   WS_TRY(w, record_event(w->stream, t1, capturing));
   for (int d = 0; d < 2; ++d) {
@@ -545,10 +563,9 @@ int engine_setup(Workspace* w, Engine& E, const Job& J, const Tune& tu) {
   for (int t = 0; t < 2; ++t) {
     E.bud_same[t] = t == 0 ? 1u : (uint32_t)tu.secondaries + 1u;
     E.bud_other[t] = (uint32_t)tu.secondaries;
-    const uint32_t wpb = (uint32_t)tu.block / 64u;
-    const uint32_t res = (uint32_t)resident_blocks(w, t, tu.block, n_mat);
-    E.blocks[t] = std::max<uint32_t>(1u, std::min<uint32_t>(res, kMaxWaves / wpb));
-    E.waves[t] = E.blocks[t] * wpb;
+    E.block[t] = pass_block(w, t, tu.block, n_mat);
+    E.waves[t] = pass_waves(w, t, E.block[t], n_mat);
+    E.blocks[t] = E.waves[t] / ((uint32_t)E.block[t] / 64u);
   }
   const size_t nb = J.beams.size();
   rc = ws_ensure_beams(w, nb);
@@ -1032,7 +1049,7 @@ int autotune(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_so
       {&gmc_tuning::chunk, {1 << 18, 1 << 19, 1 << 20, 1 << 21, 1 << 22}},
       {&gmc_tuning::pass_items, {1 << 20, 1 << 21, 1 << 22}},
       {&gmc_tuning::events_per_visit, {16, 32, 64, 128}},
-      {&gmc_tuning::wg_size, {128, 256}},
+      {&gmc_tuning::wg_size, {256, 512, 1024}},
       {&gmc_tuning::wave_items, {64, 128, 256}},
       {&gmc_tuning::refill_lanes, {1, 4, 8}},
       {&gmc_tuning::rounds_per_check, {2, 4, 8}},

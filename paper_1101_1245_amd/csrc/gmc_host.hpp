@@ -98,7 +98,7 @@ struct Workspace {
   double* d_dose = nullptr;
   double* d_sigma = nullptr;
   size_t out_elems = 0;
-  int resident[2] = {0, 0}, resident_block[2] = {0, 0}, resident_nmat[2] = {0, 0};
+  std::map<std::vector<int>, int> resident;    // (kernel, block, materials) -> resident workgroups
   hipEvent_t ev0 = nullptr, ev1 = nullptr;     // around a whole job
   hipEvent_t kev0 = nullptr, kev1 = nullptr;   // around a pass launch (plain form)
   hipEvent_t ev_ctl = nullptr;                 // after a control-block copy
@@ -171,9 +171,19 @@ void build_job(Job* J, Workspace* w, const PhantomObj& P, const TablesObj& T, co
                const gmc_source* srcs, const uint64_t* n_hist, int n_beams, uint64_t seed, TallyMode mode);
 size_t job_tally_elems(TallyMode mode, size_t nvox, uint32_t K, size_t n_beams);
 
+// Workgroup size of a pass kernel: the requested one, or (requested 0) the
+// smallest of 256 / 512 / 1024 threads that keeps the most wavefronts
+// resident (with many materials the LDS tables, one copy per workgroup,
+// limit 256-thread workgroups to half the occupancy registers allow).
+int pass_block(Workspace* w, int kernel, int requested, int n_mat);
+// Wavefronts of a pass grid (resident workgroups x waves per workgroup, at
+// most kMaxWaves).
+uint32_t pass_waves(Workspace* w, int kernel, int block, int n_mat);
+
 struct Engine {
   Workspace* w = nullptr;
   Tune tu{};
+  int block[2] = {0, 0};          // workgroup size of each pass kernel
   PassArgs proto{};
   AdmitArgs adm[2]{};
   uint32_t total[2] = {0, 0};

@@ -254,7 +254,7 @@ __device__ __forceinline__ int photon_flight(Lane& L, const PassArgs& a, const f
 }
 
 // ------------------------------------------------------------ photon pass
-__global__ void __launch_bounds__(256) k_photon_pass(PassArgs a) {
+__global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
   extern __shared__ float4 smem[];
   const int nt = a.tab.n_mat * kNE;
   for (int i = threadIdx.x; i < nt; i += blockDim.x) smem[i] = a.tab.ph[i];
@@ -410,7 +410,7 @@ __global__ void __launch_bounds__(256) k_photon_pass(PassArgs a) {
 // deposited in the step-start voxel; after the second leg a hard-event
 // candidate is accepted with Sigma(end)/Sigma_hat and split into Moller or
 // bremsstrahlung.
-__global__ void __launch_bounds__(256) k_electron_pass(PassArgs a) {
+__global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
   extern __shared__ float4 smem[];
   const int nt = a.tab.n_mat * kNE;
   for (int i = threadIdx.x; i < nt; i += blockDim.x) smem[i] = a.tab.el[i];
