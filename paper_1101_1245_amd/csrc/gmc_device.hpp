@@ -151,9 +151,9 @@ __device__ __forceinline__ float dist_boundary(const DevPhantom& P, float x, flo
 
 // New direction at polar cosine cost and azimuth phi about (u, v, w),
 // renormalised.
-__device__ __forceinline__ void rotate(float& u, float& v, float& w, float cost, float phi) {
-  cost = fminf(fmaxf(cost, -1.0f), 1.0f);
-  const float sint = sqrtf((1.0f - cost) * (1.0f + cost));
+// Turn (u, v, w) by the polar angle with cosine cost and sine sint about the
+// old direction, azimuth phi.
+__device__ __forceinline__ void rotate_cs(float& u, float& v, float& w, float cost, float sint, float phi) {
   float sp, cp;
   __sincosf(phi, &sp, &cp);
   const float rho2 = u * u + v * v;
@@ -171,6 +171,19 @@ __device__ __forceinline__ void rotate(float& u, float& v, float& w, float cost,
   }
   const float inv = rsqrtf(nu * nu + nv * nv + nw * nw);
   u = nu * inv; v = nv * inv; w = nw * inv;
+}
+
+__device__ __forceinline__ void rotate(float& u, float& v, float& w, float cost, float phi) {
+  cost = fminf(fmaxf(cost, -1.0f), 1.0f);
+  rotate_cs(u, v, w, cost, sqrtf((1.0f - cost) * (1.0f + cost)), phi);
+}
+
+// The same by om = 1 - cos(theta): for the small angles of a multiple-
+// scattering step, cos(theta) rounded to FP32 keeps few digits of om, so the
+// sine is formed from om itself, sin = sqrt(om (2 - om)).
+__device__ __forceinline__ void rotate_om(float& u, float& v, float& w, float om, float phi) {
+  om = fminf(fmaxf(om, 0.0f), 2.0f);
+  rotate_cs(u, v, w, 1.0f - om, sqrtf(om * (2.0f - om)), phi);
 }
 
 __device__ __forceinline__ uint32_t to_lsb(float mev) {
@@ -263,11 +276,16 @@ __device__ __forceinline__ float screening_A(const DevTables& T, const float* ms
 }
 
 // Polar cosine of one condensed step: w = 1 - cos = 2 A u / (1 + A - u).
-__device__ __forceinline__ float wentzel_cos(const DevTables& T, const float* ms, float g1, float u) {
-  if (!(g1 > 0.0f)) return 1.0f;
-  if (g1 >= kG1Iso) return 1.0f - 2.0f * u;
+// 1 - cos(theta) of a multiple-scattering step (Wentzel shape with screening
+// A from G1): om = 2 A u / (1 + A - u); isotropic above the G1 limit.  The
+// denominator is formed as (1 - u) + A: u is an odd multiple of 2^-24, so
+// 1 - u is exact in FP32, whereas 1 + A rounds A away when A < 2^-24 (short
+// steps, low density) and fattens the large-angle tail.
+__device__ __forceinline__ float wentzel_om(const DevTables& T, const float* ms, float g1, float u) {
+  if (!(g1 > 0.0f)) return 0.0f;
+  if (g1 >= kG1Iso) return 2.0f * u;
   const float a = screening_A(T, ms, g1);
-  return 1.0f - 2.0f * a * u / (1.0f + a - u);
+  return 2.0f * a * u / ((1.0f - u) + a);
 }
 
 // ---------------------------------------------------------------- wave helpers

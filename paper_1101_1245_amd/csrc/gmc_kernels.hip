@@ -489,8 +489,7 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
               const float xx = es * rho0 * il;
               // G1 = 1 - exp(-x), by its series where the subtraction would cancel
               const float g1 = xx < 1e-3f ? xx * (1.0f - 0.5f * xx * (1.0f - xx * (1.0f / 3.0f))) : 1.0f - __expf(-xx);
-              const float cost = wentzel_cos(a.tab, ms, g1, ua);
-              rotate(L.u, L.v, L.w, cost, kTwoPi * uphi);
+              rotate_om(L.u, L.v, L.w, wentzel_om(a.tab, ms, g1, ua), kTwoPi * uphi);
             }
             deposit_later(L, pend, v0, dl);
             L.e = e1;

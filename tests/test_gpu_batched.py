@@ -218,7 +218,7 @@ def test_autotuner_choice_is_cached_and_result_invariant(ctx, G, small_job, load
     tun, rep = ctx.autotune(pid, tid, j.sources, counts, budget_s=20.0)
     assert rep["from_cache"] == 0 and rep["trials"] >= 3 and rep["complete"] == 1
     assert rep["t_best_s"] <= rep["t_default_s"]
-    assert tun["wg_size"] in (128, 256) and 1 <= tun["refill_lanes"] <= 64 and tun["chunk"] > 0
+    assert tun["wg_size"] in (0, 256, 512, 1024) and 1 <= tun["refill_lanes"] <= 64 and tun["chunk"] > 0
     tun2, rep2 = ctx.autotune(pid, tid, j.sources, counts)
     assert rep2["from_cache"] == 1 and rep2["trials"] == 0 and tun2 == tun
     # tuning=None runs with the cached choice; the result does not depend on it
