@@ -68,10 +68,15 @@ int ensure_staging(Workspace* w, uint32_t slots) {
   return GMC_OK;
 }
 
+// Events that only time the pass kernels: without the system-scope fence an
+// event record does not wait for the caches to be written back, which would
+// add several microseconds between the kernels it separates.
+hipError_t create_timing_event(hipEvent_t* e) { return hipEventCreateWithFlags(e, hipEventDisableSystemFence); }
+
 int ensure_graph_events(Workspace* w, size_t n) {
   while (w->gev.size() < n) {
     hipEvent_t e = nullptr;
-    WS_TRY(w, hipEventCreate(&e));
+    WS_TRY(w, create_timing_event(&e));
     w->gev.push_back(e);
   }
   return GMC_OK;
@@ -127,8 +132,8 @@ int ws_init(Workspace* w, int device, hipStream_t stream) {
   WS_TRY(w, hipMalloc(&w->d_offsets, 2 * (kMaxWaves + 1) * sizeof(uint32_t)));
   WS_TRY(w, hipEventCreate(&w->ev0));
   WS_TRY(w, hipEventCreate(&w->ev1));
-  WS_TRY(w, hipEventCreate(&w->kev0));
-  WS_TRY(w, hipEventCreate(&w->kev1));
+  WS_TRY(w, create_timing_event(&w->kev0));
+  WS_TRY(w, create_timing_event(&w->kev1));
   WS_TRY(w, hipEventCreateWithFlags(&w->ev_ctl, hipEventDisableTiming));
   return GMC_OK;
 }
@@ -468,24 +473,23 @@ int enqueue_pass(Engine& E, int type, hipEvent_t t0, hipEvent_t t1, bool capturi
                            : launch_electron_pass(a, (int)E.blocks[1], E.block[1], w->stream);
   if (e != hipSuccess) return wfail(w, GMC_EDEVICE, std::string("pass launch: ") + hipGetErrorString(e));
   WS_TRY(w, record_event(w->stream, t1, capturing));
+  CompactArgs ca;
   for (int d = 0; d < 2; ++d) {
     const int dt = d == 0 ? type : other;
     const int dbuf = d == 0 ? ni : w->acc[other];
-    CompactArgs ca;
-    ca.stg = w->stg[d].q;
-    ca.plan = w->d_ctl->plan + type;
-    ca.same = d == 0;
-    ca.used = d == 0 ? a.used_same : a.used_other;
-    ca.waves = E.waves[type];
-    ca.offsets = w->d_offsets + d * (kMaxWaves + 1);
-    ca.dst = w->qbuf[dt][dbuf].q;
-    ca.dst_count = count_ptr(w, dt, dbuf);
-    ca.work = w->qbuf[type][wi].q;
-    ca.work_count = count_ptr(w, type, wi);
-    ca.ctr = w->d_ctr;
-    e = launch_compact(ca, w->stream);
-    if (e != hipSuccess) return wfail(w, GMC_EDEVICE, std::string("compaction launch: ") + hipGetErrorString(e));
+    ca.stg[d] = w->stg[d].q;
+    ca.used[d] = d == 0 ? a.used_same : a.used_other;
+    ca.dst[d] = w->qbuf[dt][dbuf].q;
+    ca.dst_count[d] = count_ptr(w, dt, dbuf);
   }
+  ca.plan = w->d_ctl->plan + type;
+  ca.waves = E.waves[type];
+  ca.offsets = w->d_offsets;
+  ca.work = w->qbuf[type][wi].q;
+  ca.work_count = count_ptr(w, type, wi);
+  ca.ctr = w->d_ctr;
+  e = launch_compact(ca, w->stream);
+  if (e != hipSuccess) return wfail(w, GMC_EDEVICE, std::string("compaction launch: ") + hipGetErrorString(e));
   return GMC_OK;
 }
 

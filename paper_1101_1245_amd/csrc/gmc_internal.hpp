@@ -153,17 +153,19 @@ struct PassArgs {
 // Packing of wave segments into an accumulating queue.  For the same-type
 // destination the particles the pass did not transport (m..n-1 of the work
 // buffer) are copied first, and the work buffer's count is cleared.
+// Compaction of one pass's outputs: destination 0 is the pass type's new
+// accumulating buffer (carried-over particles first), destination 1 the
+// other type's accumulating buffer.
 struct CompactArgs {
-  DevQueue stg;
+  DevQueue stg[2];               // staging queues of the two destinations
   const PassPlan* plan;
-  int same;                // 1: same-type destination
-  const uint32_t* used;    // [waves]
+  const uint32_t* used[2];       // [waves] entries each wave segment holds
   uint32_t waves;
-  uint32_t* offsets;       // [waves + 1] destination of each segment, then the carry-over
-  DevQueue dst;
-  uint32_t* dst_count;     // accumulating count, advanced by the total
-  DevQueue work;           // the pass's work buffer (same-type only)
-  uint32_t* work_count;    // cleared (same-type only)
+  uint32_t* offsets;             // [2][waves + 1] destination of each segment; [0][waves]: of the carry-over
+  DevQueue dst[2];
+  uint32_t* dst_count[2];        // accumulating counts, advanced by the totals
+  DevQueue work;                 // the pass's work buffer, source of the carry-over
+  uint32_t* work_count;          // cleared
   unsigned long long* ctr;
 };
 

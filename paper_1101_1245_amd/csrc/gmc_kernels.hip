@@ -737,62 +737,78 @@ __global__ void k_plan_pass(PlanArgs a) {
 }
 
 // -------------------------------------------------------------- compaction
-// Exclusive scan of the per-wave counts (one workgroup of 1024 lanes) giving
-// each segment's destination after the accumulating queue's current end; for
-// the same-type destination the carried-over particles go first.
+// Exclusive scans of the per-wave counts of both destinations (one workgroup
+// of 1024 lanes) giving each segment's place after its accumulating queue's
+// current end; in the pass type's own queue the carried-over particles go
+// first.
 __global__ void __launch_bounds__(1024) k_compact_scan(CompactArgs a) {
-  __shared__ uint32_t part[1024];
+  __shared__ uint32_t part[2][1024];
   const PassPlan P = *a.plan;
-  const uint32_t seg = a.same ? P.seg_same : P.seg_other;
-  const uint32_t carry = a.same ? P.n - P.m : 0u;
+  const uint32_t seg[2] = {P.seg_same, P.seg_other};
+  const uint32_t carry = P.n - P.m;
   const uint32_t t = threadIdx.x;
   const uint32_t per = (a.waves + 1023u) / 1024u;
   const uint32_t lo = min(t * per, a.waves), hi = min(lo + per, a.waves);
-  uint32_t sum = 0;
-  for (uint32_t w = lo; w < hi; ++w) sum += min(a.used[w], seg);
-  part[t] = sum;
-  const uint32_t base = *a.dst_count;
+  uint32_t sum[2] = {0u, 0u};
+  for (uint32_t w = lo; w < hi; ++w) {
+    sum[0] += min(a.used[0][w], seg[0]);
+    sum[1] += min(a.used[1][w], seg[1]);
+  }
+  part[0][t] = sum[0];
+  part[1][t] = sum[1];
+  const uint32_t base[2] = {*a.dst_count[0], *a.dst_count[1]};
   __syncthreads();
   for (uint32_t off = 1; off < 1024u; off <<= 1) {
-    const uint32_t v = t >= off ? part[t - off] : 0u;
+    const uint32_t v0 = t >= off ? part[0][t - off] : 0u;
+    const uint32_t v1 = t >= off ? part[1][t - off] : 0u;
     __syncthreads();
-    part[t] += v;
+    part[0][t] += v0;
+    part[1][t] += v1;
     __syncthreads();
   }
-  uint32_t run = base + carry + (t ? part[t - 1] : 0u);
-  for (uint32_t w = lo; w < hi; ++w) {
-    a.offsets[w] = run;
-    run += min(a.used[w], seg);
+  for (int d = 0; d < 2; ++d) {
+    uint32_t run = base[d] + (d == 0 ? carry : 0u) + (t ? part[d][t - 1] : 0u);
+    uint32_t* off = a.offsets + d * (a.waves + 1u);
+    for (uint32_t w = lo; w < hi; ++w) {
+      off[w] = run;
+      run += min(a.used[d][w], seg[d]);
+    }
   }
   if (t == 1023u) {
-    a.offsets[a.waves] = base;   // destination of the carried-over particles
-    a.dst_count[0] = base + carry + part[1023];
-    if (a.same) a.work_count[0] = 0u;
+    a.offsets[a.waves] = base[0];   // destination of the carried-over particles
+    a.dst_count[0][0] = base[0] + carry + part[0][1023];
+    a.dst_count[1][0] = base[1] + part[1][1023];
+    a.work_count[0] = 0u;
   }
 }
 
-// One workgroup per wave segment copies its entries to their destination;
-// the carried-over particles are copied grid-stride by all workgroups.
+// One wavefront per pass wave copies that wave's two staging segments to
+// their destinations; the carried-over particles are copied grid-stride by
+// all lanes.
 __global__ void __launch_bounds__(256) k_compact_copy(CompactArgs a) {
   const PassPlan P = *a.plan;
-  const uint32_t seg = a.same ? P.seg_same : P.seg_other;
-  const uint32_t w = blockIdx.x;
-  const uint32_t n = min(a.used[w], seg);
-  const uint32_t src0 = w * seg, dst0 = a.offsets[w];
-  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-    const uint32_t s = src0 + i, d = dst0 + i;
-    if (d >= a.dst.cap) { ctr_add(a.ctr, C_OVERFLOW, 1ull); continue; }
+  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t w = gid >> 6, lane = gid & 63u;
+  if (w < a.waves) {
 #pragma unroll
-    for (int f = 0; f < Q_FIELDS; ++f) qf(a.dst, f, d) = qf(a.stg, f, s);
-  }
-  if (a.same) {
-    const uint32_t carry = P.n - P.m, cbase = a.offsets[a.waves];
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < carry; i += gridDim.x * blockDim.x) {
-      const uint32_t s = P.m + i, d = cbase + i;
-      if (d >= a.dst.cap) { ctr_add(a.ctr, C_OVERFLOW, 1ull); continue; }
+    for (int d = 0; d < 2; ++d) {
+      const uint32_t seg = d == 0 ? P.seg_same : P.seg_other;
+      const uint32_t n = min(a.used[d][w], seg);
+      const uint32_t src0 = w * seg, dst0 = a.offsets[d * (a.waves + 1u) + w];
+      for (uint32_t i = lane; i < n; i += 64u) {
+        const uint32_t s = src0 + i, t = dst0 + i;
+        if (t >= a.dst[d].cap) { ctr_add(a.ctr, C_OVERFLOW, 1ull); continue; }
 #pragma unroll
-      for (int f = 0; f < Q_FIELDS; ++f) qf(a.dst, f, d) = qf(a.work, f, s);
+        for (int f = 0; f < Q_FIELDS; ++f) qf(a.dst[d], f, t) = qf(a.stg[d], f, s);
+      }
     }
+  }
+  const uint32_t carry = P.n - P.m, cbase = a.offsets[a.waves];
+  for (uint32_t i = gid; i < carry; i += gridDim.x * blockDim.x) {
+    const uint32_t s = P.m + i, t = cbase + i;
+    if (t >= a.dst[0].cap) { ctr_add(a.ctr, C_OVERFLOW, 1ull); continue; }
+#pragma unroll
+    for (int f = 0; f < Q_FIELDS; ++f) qf(a.dst[0], f, t) = qf(a.work, f, s);
   }
 }
 
@@ -895,7 +911,7 @@ hipError_t launch_compact(const CompactArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_compact_copy, dim3(a.waves), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_compact_copy, dim3((a.waves + 3u) / 4u), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
