@@ -134,20 +134,20 @@ typedef struct {
  *   secondaries_per_visit: secondaries a particle may create per visit
  *     (2..64, default 4);
  *   chunk: primaries admitted per admission step while a particle type's
- *     array holds fewer (default 2^20, at most 2^24);
+ *     array holds fewer (default 2^21, at most 2^24);
  *   wg_size: threads per workgroup of the pass kernels (64..1024, multiple
  *     of 64; default: per pass kernel, the smallest of 256, 512 and 1024 that
  *     keeps the most wavefronts resident -- each workgroup stages its own
  *     copy of the tables in LDS, so with several materials larger workgroups
  *     keep more wavefronts per compute unit);
  *   pass_items: most particles one pass launch transports (1024..2^23,
- *     default 2^21); the rest is carried to the next pass;
+ *     default 2^22); the rest is carried to the next pass;
  *   wave_items: fewest particles a wavefront owns in a pass (64..2^16,
  *     default 64);
  *   rounds_per_check: batched form only; the captured graph holds
  *     2 x rounds_per_check rounds and the host reads the particle counts
  *     once per replay (1..1024, default 4);
- *   refill_lanes: idle lanes of a wavefront (1..64, default 1) before they
+ *   refill_lanes: idle lanes of a wavefront (1..64, default 4) before they
  *     take new particles from the wavefront's range.
  * No tuning changes any result: the dose is bit-identical for every choice. */
 typedef struct {
@@ -200,13 +200,14 @@ int gmc_run_beams(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const
 /* Autotuner of the batched form.  Picks the admission chunk, the pass size,
  * the events per visit, the workgroup size, the particles per wavefront,
  * the refill threshold and the rounds per status check by coordinate
- * descent: each candidate runs a sample of the job (the first histories of
- * every beam, in proportion: about 5% of the job and at least 2^20
- * histories) and is timed on the device; a change is kept when it saves at
- * least 2%.  Choices are cached in the context per job class (grid size,
+ * descent, starting with the admission chunk and the pass size together
+ * (pass = 2 x chunk): each candidate runs a sample of the job (the first
+ * histories of every beam, in proportion: 5% of the job but at least 2^25
+ * histories, or the whole job if smaller) and is timed on the device; a
+ * change is kept when it saves at least 2%.  Choices are cached in the context per job class (grid size,
  * mean energy, electron fraction, field area, history count and material
  * count on coarse logarithmic scales); a cached class returns at once.
- * budget_s bounds the search's wall time (<= 0: 3 s).  gmc_run_beams with
+ * budget_s bounds the search's wall time (<= 0: 5 s).  gmc_run_beams with
  * tuning NULL calls this first.  *out receives the choice; report may be
  * NULL. */
 typedef struct {

@@ -225,7 +225,7 @@ int ws_ensure_beams(Workspace* w, size_t n) {
 
 // ---------------------------------------------------------------- settings
 Tune resolve_tuning(const gmc_tuning* t) {
-  Tune r{64, 4, 1 << 20, 0, 1 << 21, 64, 4, 1};
+  Tune r{64, 4, 1 << 21, 0, 1 << 22, 64, 4, 4};
   if (t) {
     if (t->events_per_visit > 0) r.events = t->events_per_visit;
     if (t->secondaries_per_visit >= 2) r.secondaries = std::min(t->secondaries_per_visit, 64);
@@ -1018,7 +1018,11 @@ int autotune(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_so
       return GMC_OK;
     }
   }
-  const uint64_t want = std::min<uint64_t>(n_total, std::max<uint64_t>(1ull << 20, n_total / 20));
+  // A sample must hold several admission chunks of the largest candidate:
+  // queue occupancy, and with it the pass sizes and lane fill, only settles
+  // after a few rounds, and a sample too short for that ranks large passes
+  // wrongly.
+  const uint64_t want = std::min<uint64_t>(n_total, std::max<uint64_t>(kTuneMinSample, n_total / 20));
   const double f = (double)want / (double)n_total;
   std::vector<uint64_t> ns(n_beams);
   uint64_t n_sample = 0;
@@ -1045,30 +1049,35 @@ int autotune(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_so
   if (rc == GMC_OK) rc = trial(best, &t_best);
   if (rc) return rc;
   r.t_default_s = t_best;
+  // twin: a second field set to twice the value (admission chunk and pass
+  // size move together first: a pass should hold about two chunks)
   struct Dim {
     int gmc_tuning::*field;
     std::vector<int> values;
+    int gmc_tuning::*twin;
   };
   const std::vector<Dim> dims = {
-      {&gmc_tuning::chunk, {1 << 18, 1 << 19, 1 << 20, 1 << 21, 1 << 22}},
-      {&gmc_tuning::pass_items, {1 << 20, 1 << 21, 1 << 22}},
-      {&gmc_tuning::events_per_visit, {16, 32, 64, 128}},
-      {&gmc_tuning::wg_size, {256, 512, 1024}},
-      {&gmc_tuning::wave_items, {64, 128, 256}},
-      {&gmc_tuning::refill_lanes, {1, 4, 8}},
-      {&gmc_tuning::rounds_per_check, {2, 4, 8}},
+      {&gmc_tuning::chunk, {1 << 19, 1 << 20, 1 << 21, 1 << 22}, &gmc_tuning::pass_items},
+      {&gmc_tuning::chunk, {1 << 19, 1 << 20, 1 << 21, 1 << 22}, nullptr},
+      {&gmc_tuning::pass_items, {1 << 20, 1 << 21, 1 << 22, 1 << 23}, nullptr},
+      {&gmc_tuning::events_per_visit, {32, 64, 128}, nullptr},
+      {&gmc_tuning::wg_size, {256, 512, 1024}, nullptr},
+      {&gmc_tuning::wave_items, {64, 128, 256}, nullptr},
+      {&gmc_tuning::refill_lanes, {1, 4, 8, 16}, nullptr},
+      {&gmc_tuning::rounds_per_check, {2, 4, 8}, nullptr},
   };
   bool out_of_time = false;
   for (const Dim& d : dims) {
     const int cur = best.*(d.field);
     for (int v : d.values) {
-      if (v == cur) continue;
+      if (v == cur && (!d.twin || best.*(d.twin) == 2 * v)) continue;
       if (std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > budget_s) {
         out_of_time = true;
         break;
       }
       gmc_tuning cand = best;
       cand.*(d.field) = v;
+      if (d.twin) cand.*(d.twin) = 2 * v;
       double t = 0.0;
       rc = trial(cand, &t);
       if (rc) return rc;

@@ -50,7 +50,8 @@ struct QueueBuf {
 constexpr uint32_t kMinSoftCap = 1u << 23;
 constexpr uint32_t kMaxSoftCap = 1u << 25;
 constexpr uint32_t kMaxWaves = 1u << 15;
-constexpr double kAutotuneBudgetS = 3.0;   // default wall-clock budget of one tuning
+constexpr double kAutotuneBudgetS = 5.0;   // default wall-clock budget of one tuning
+constexpr uint64_t kTuneMinSample = 1ull << 25;   // 8 chunks of the largest candidate
 
 // Device control block of a workspace: queue counts [type][buffer],
 // admission cursor and histories per type, the last pass plans and
