@@ -75,6 +75,15 @@ struct Stream {
     return wd;
   }
   __device__ __forceinline__ float uniform() { return to_uniform(word()); }
+  // After a reload between two words of a block: recompute the cached block
+  // the next draws come from (a particle stored at a block boundary needs
+  // nothing).
+  __device__ __forceinline__ void resume() {
+    if (n & 3u) {
+      const Block b = philox(n >> 2, plo, phi, hist, k0, k1);
+      b0 = b.w0; b1 = b.w1; b2 = b.w2; b3 = b.w3;
+    }
+  }
 };
 
 // ---------------------------------------------------------------- tables

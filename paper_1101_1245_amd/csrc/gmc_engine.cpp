@@ -36,9 +36,9 @@ void free_queue(QueueBuf& b) {
   b = QueueBuf{};
 }
 
-hipError_t alloc_queue(QueueBuf& b, uint32_t cap) {
+hipError_t alloc_queue(QueueBuf& b, uint32_t cap, int fields) {
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, (size_t)Q_FIELDS * cap * sizeof(uint32_t));
+  hipError_t e = hipMalloc(&p, (size_t)fields * cap * sizeof(uint32_t));
   if (e != hipSuccess) return e;
   b.base = p;
   b.q.base = static_cast<uint32_t*>(p);
@@ -53,17 +53,17 @@ int ensure_queues(Workspace* w, uint32_t cap) {
     for (auto& b : t) free_queue(b);
   w->cap = 0;
   for (auto& t : w->qbuf)
-    for (auto& b : t) WS_TRY(w, alloc_queue(b, cap));
+    for (auto& b : t) WS_TRY(w, alloc_queue(b, cap, Q_FIELDS));
   w->cap = cap;
   return GMC_OK;
 }
 
 int ensure_staging(Workspace* w, uint32_t slots) {
   if (w->stg_cap >= slots) return GMC_OK;
-  if ((uint64_t)slots * Q_FIELDS >= (1ull << 32)) return wfail(w, GMC_EOVERFLOW, "staging queue too large");
+  if ((uint64_t)slots * kStgFields >= (1ull << 32)) return wfail(w, GMC_EOVERFLOW, "staging queue too large");
   for (auto& b : w->stg) free_queue(b);
   w->stg_cap = 0;
-  for (auto& b : w->stg) WS_TRY(w, alloc_queue(b, slots));
+  for (auto& b : w->stg) WS_TRY(w, alloc_queue(b, slots, kStgFields));
   w->stg_cap = slots;
   return GMC_OK;
 }
@@ -180,7 +180,7 @@ void ws_free(Workspace* w) {
 }
 
 size_t ws_device_bytes(const Workspace& w) {
-  return (size_t)Q_FIELDS * sizeof(uint32_t) * (4ull * w.cap + 2ull * w.stg_cap) +
+  return sizeof(uint32_t) * ((size_t)Q_FIELDS * 4ull * w.cap + (size_t)kStgFields * 2ull * w.stg_cap) +
          w.tally_elems * sizeof(unsigned long long) + 2 * w.out_elems * sizeof(double) +
          w.beams_cap * (sizeof(DevBeam) + sizeof(DevSource) + 4 * sizeof(uint32_t));
 }
@@ -266,7 +266,9 @@ void queue_sizes(Workspace* w, const Tune& tu, int n_mat, uint32_t* cap, uint32_
   *cap = (uint32_t)(soft + (uint64_t)tu.secondaries * (uint64_t)tu.pass_items);
   uint32_t s = 0;
   for (int t = 0; t < 2; ++t) {
-    const uint32_t bud = t == 0 ? (uint32_t)tu.secondaries : (uint32_t)tu.secondaries + 1u;
+    // largest segment per particle: photon pass, its electrons; electron
+    // pass, survivor + secondaries + one parked entry
+    const uint32_t bud = t == 0 ? (uint32_t)tu.secondaries : (uint32_t)tu.secondaries + 2u;
     const uint32_t waves = pass_waves(w, t, pass_block(w, t, tu.block, n_mat), n_mat);
     const uint32_t qmax = std::max<uint32_t>((uint32_t)tu.wave_items, ((uint32_t)tu.pass_items + waves - 1) / waves);
     s = std::max<uint32_t>(s, waves * qmax * bud);
@@ -460,6 +462,7 @@ int enqueue_pass(Engine& E, int type, hipEvent_t t0, hipEvent_t t1, bool capturi
   pa.min_per_wave = (uint32_t)E.tu.wave_items;
   pa.bud_same = E.bud_same[type];
   pa.bud_other = E.bud_other[type];
+  pa.park_slots = type == 1 ? 1u : 0u;
   WS_TRY(w, launch_plan_pass(pa, w->stream));
   PassArgs a = E.proto;
   a.work = w->qbuf[type][wi].q;
@@ -600,6 +603,7 @@ int engine_setup(Workspace* w, Engine& E, const Job& J, const Tune& tu) {
   E.proto.max_events = tu.events;
   E.proto.max_secondaries = tu.secondaries;
   E.proto.refill_lanes = tu.refill;
+  E.proto.resume_lanes = kResumeLanes;
   for (int t = 0; t < 2; ++t) {
     AdmitArgs& a = E.adm[t];
     a = AdmitArgs{};

@@ -52,6 +52,9 @@ constexpr uint32_t kMaxSoftCap = 1u << 25;
 constexpr uint32_t kMaxWaves = 1u << 15;
 constexpr double kAutotuneBudgetS = 5.0;   // default wall-clock budget of one tuning
 constexpr uint64_t kTuneMinSample = 1ull << 25;   // 8 chunks of the largest candidate
+// Idle lanes of an electron-pass wavefront, its range done, that take back
+// parked electrons together (their hard events then run on that many lanes).
+constexpr int kResumeLanes = 32;
 
 // Device control block of a workspace: queue counts [type][buffer],
 // admission cursor and histories per type, the last pass plans and

@@ -66,6 +66,12 @@ struct DevCuts {
 // bits), kinetic energy in 2^-27 MeV units, history index, stream path (two
 // words), stream word counter, beam index.
 enum QueueField { Q_X = 0, Q_Y, Q_Z, Q_U, Q_V, Q_W, Q_E, Q_HIST, Q_PLO, Q_PHI, Q_N, Q_BEAM, Q_FIELDS };
+// Staging entries carry two words more for an electron parked at a
+// hard-event candidate: the step-start majorant (float bits) and its visit
+// counters (events | pushes << 16).
+constexpr int Q_AUX = Q_FIELDS;
+constexpr int Q_AUX2 = Q_FIELDS + 1;
+constexpr int kStgFields = Q_FIELDS + 2;
 struct DevQueue {
   uint32_t* base;
   uint32_t stride;
@@ -125,6 +131,7 @@ struct PlanArgs {
   uint32_t waves;               // wavefronts in the pass grid
   uint32_t min_per_wave;        // fewest particles per wavefront (64: one per lane)
   uint32_t bud_same, bud_other; // per-visit output budgets per particle
+  uint32_t park_slots;          // same-type staging slots per particle for parked electrons
 };
 
 // A pass kernel's work: wave w of the grid owns items [w q, (w+1) q) of the
@@ -148,11 +155,9 @@ struct PassArgs {
   int max_events;
   int max_secondaries;
   int refill_lanes;          // idle lanes (1..64) that trigger a refill
+  int resume_lanes;          // idle lanes (1..64) that take back parked electrons
 };
 
-// Packing of wave segments into an accumulating queue.  For the same-type
-// destination the particles the pass did not transport (m..n-1 of the work
-// buffer) are copied first, and the work buffer's count is cleared.
 // Compaction of one pass's outputs: destination 0 is the pass type's new
 // accumulating buffer (carried-over particles first), destination 1 the
 // other type's accumulating buffer.

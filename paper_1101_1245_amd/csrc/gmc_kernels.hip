@@ -403,13 +403,89 @@ __global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
 }
 
 // ---------------------------------------------------------- electron pass
+// Hard-event candidate at the end of a step (Sec. II.B.3): accepted with
+// Sigma(end) / Sigma_hat, Sigma_hat being the majorant at the step-start
+// energy, and split into Moller or bremsstrahlung.  The electron stands at
+// the step's end point in voxel v1 with its energy after the step's loss;
+// energy below the cutoffs is deposited in v1.  Returns whether the electron
+// lives on; a secondary above its cutoff is left in c0 (ctype 0 photon, 1
+// electron).
+__device__ __forceinline__ bool hard_event(Lane& L, const PassArgs& a, const float4* smem, float sh, int v1,
+                                           Child& c0, int& ctype, uint32_t& c_hard, uint32_t& c_viol) {
+  const float t1f = (float)L.e * kLsbF;
+  const float ur = L.s.uniform();
+  const uint2 vy = a.ph.vox[v1];
+  const float rho1 = __uint_as_float(vy.x);
+  const float4 t1 = lerp4(smem, (int)vy.y * kNE, tpos(a.tab, t1f));
+  const float sm = (L.e > a.cut.kcut2_lsb) ? rho1 * t1.y : 0.0f;
+  const float sb = (L.e > a.cut.kc_lsb) ? rho1 * t1.z : 0.0f;
+  if (sm + sb > sh) ++c_viol;
+  const float r = ur * sh;
+  if (r < sm) {
+    // Moller: binary collision with a free electron at rest
+    ++c_hard;
+    const float eps = sample_moller(t1f, a.cut.kcut, L.s);
+    const uint32_t wl = min(to_lsb(eps * t1f), L.e);
+    const uint32_t tp = L.e - wl;
+    const float wf = (float)wl * kLsbF, tpf = (float)tp * kLsbF;
+    const float cd = sqrtf(wf * (t1f + 2.0f * kMc2) / (t1f * (wf + 2.0f * kMc2)));
+    const float cpp = sqrtf(tpf * (t1f + 2.0f * kMc2) / (t1f * (tpf + 2.0f * kMc2)));
+    const float phi = kTwoPi * L.s.uniform();
+    c0.u = L.u; c0.v = L.v; c0.w = L.w;
+    rotate(c0.u, c0.v, c0.w, cd, phi);
+    rotate(L.u, L.v, L.w, cpp, phi + kPi);
+    if (wl >= a.cut.ecut_lsb) {
+      c0.e = wl;
+      child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
+      ctype = 1;
+    } else {
+      deposit(L, v1, wl);
+    }
+    L.e = tp;
+  } else if (r < sm + sb) {
+    // bremsstrahlung: electron direction unchanged, photon at mc^2/E
+    ++c_hard;
+    const float k = sample_brems(t1f, a.cut.kc, L.s);
+    const float phi = kTwoPi * L.s.uniform();
+    const uint32_t kl = min(to_lsb(k), L.e);
+    c0.u = L.u; c0.v = L.v; c0.w = L.w;
+    rotate(c0.u, c0.v, c0.w, __cosf(kMc2 / (t1f + kMc2)), phi);
+    if (kl >= a.cut.pcut_lsb) {
+      c0.e = kl;
+      child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
+      ctype = 0;
+    } else {
+      deposit(L, v1, kl);
+    }
+    L.e -= kl;
+  }
+  if (L.e < a.cut.ecut_lsb) {
+    deposit(L, v1, L.e);
+    return false;
+  }
+  return true;
+}
+
 // One condensed step per iteration (Sec. II.B.3): e_s = min{d_vox, e_s-max,
 // e_hard} (Eq. 4) with e_hard from the majorant at the step-start energy;
 // energy loss of Eq. 8 read with the factor s; random hinge at zeta e_s with
 // the deflection energy taken before or after the loss at random; the loss is
-// deposited in the step-start voxel; after the second leg a hard-event
-// candidate is accepted with Sigma(end)/Sigma_hat and split into Moller or
-// bremsstrahlung.
+// deposited in the step-start voxel.
+//
+// A step that ends at a hard-event candidate parks the electron on a stack at
+// the top of the wavefront's electron staging segment (with the step-start
+// majorant and its visit counters), and its lane takes the next particle of
+// the range.  Once the range is done, idle lanes take parked electrons back
+// -- at least resume_lanes of them at a time, or all that remain when every
+// lane is idle -- sample their hard events together and step on.  Sampling a
+// hard event where it occurs would run the Moller and bremsstrahlung code in
+// most iterations with a few lanes each.  A particle's draws and operations,
+// and so the dose, are the same either way.
+//
+// Segment bound: each particle of the range (at most per_wave) leaves at most
+// max_secondaries secondaries and one survivor at the bottom, and is parked
+// at most once at a time, so a segment of per_wave x (max_secondaries + 2)
+// slots holds bottom and stack without overlap.
 __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
   extern __shared__ float4 smem[];
   const int nt = a.tab.n_mat * kNE;
@@ -429,16 +505,65 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
   Pending pend;
   bool have = false;
   int events = 0, pushes = 0;
+  uint32_t npark = 0;   // parked electrons on the stack, wave-uniform
   unsigned long long acc_esc = 0;
   uint32_t c_steps = 0, c_hard = 0, c_viol = 0, c_sec = 0;
   const float emin = a.cut.emin;
 
   for (;;) {
     refill(L, have, events, pushes, range, a, nvox);
-    if (!__any(have)) break;
-    int ctype = -1;   // 0 photon child, 1 electron child
-    Child c0;
-    bool surv = false;
+    // range done: idle lanes take back parked electrons, newest first
+    bool hd = false;
+    float hsh = 0.0f;
+    if (npark && range.next >= range.end) {
+      const unsigned long long need = __ballot(!have);
+      const uint32_t nn = (uint32_t)__popcll(need);
+      if (nn >= (uint32_t)a.resume_lanes || nn == 64u) {
+        const uint32_t take = min(nn, npark);
+        if (!have) {
+          const uint32_t r = (uint32_t)__popcll(need & lanes_below());
+          if (r < take) {
+            const uint32_t slot = gsame.base + gsame.cap - npark + r;
+            load_lane(L, a.stg_same, slot, a.beams, nvox);
+            L.s.resume();
+            hsh = __uint_as_float(qf(a.stg_same, Q_AUX, slot));
+            const uint32_t cnt = qf(a.stg_same, Q_AUX2, slot);
+            events = (int)(cnt & 0xffffu);
+            pushes = (int)(cnt >> 16);
+            hd = true;
+          }
+        }
+        npark -= take;
+      }
+    }
+    if (!__any(have || hd)) break;
+    if (__any(hd)) {
+      int ctype = -1;
+      Child c0;
+      if (hd) {
+        int jx, jy, jz, v1;
+        if (electron_voxel(a.ph, L.x, L.y, L.z, L.u, L.v, L.w, jx, jy, jz, v1)) {   // inside when it was parked
+          have = hard_event(L, a, smem, hsh, v1, c0, ctype, c_hard, c_viol);
+        } else {
+          acc_esc += L.e;
+        }
+        if (ctype >= 0) { ++pushes; ++c_sec; }
+      }
+      // delta rays to the electron staging segment, photons to the photon one
+      const WaveSeg::Slots se = gsame.append(ctype == 1, false);
+      if (ctype == 1 && seg_ok(gsame, se.s0, a.ctr))
+        put(a.stg_same, gsame.base + se.s0, L.x, L.y, L.z, c0.u, c0.v, c0.w, c0.e, L.s.hist, c0.plo, c0.phi, 0u, L.beam);
+      const WaveSeg::Slots sg = gother.append(ctype == 0, false);
+      if (ctype == 0 && seg_ok(gother, sg.s0, a.ctr))
+        put(a.stg_other, gother.base + sg.s0, L.x, L.y, L.z, c0.u, c0.v, c0.w, c0.e, L.s.hist, c0.plo, c0.phi, 0u, L.beam);
+    }
+    bool surv = false, park = false;
+    float sh = 0.0f;
+    if (have && (events >= a.max_events || pushes + 1 > a.max_secondaries)) {
+      // visit budget spent (after a hard event): requeued
+      surv = true;
+      have = false;
+    }
     if (have) {
       L.s.align();
       int ix, iy, iz, v0;
@@ -456,7 +581,7 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
           ++c_steps;
           const float tf = (float)L.e * kLsbF;
           const TPos p0 = tpos(a.tab, tf);
-          const float sh = maje[p0.i];
+          sh = maje[p0.i];
           const float uh = L.s.uniform();
           const float ehard = (a.cut.mode == 2 || !(sh > 0.0f)) ? kInf : -__logf(uh) / sh;
           const float dv = fmaxf(dist_boundary(a.ph, L.x, L.y, L.z, L.u, L.v, L.w, ix, iy, iz), a.ph.skin);
@@ -502,68 +627,15 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
               acc_esc += L.e;
               have = false;
             } else if (hard) {
-              const float ur = L.s.uniform();
-              const uint2 vy = a.ph.vox[v1];
-              const float rho1 = __uint_as_float(vy.x);
-              const float4 t1 = lerp4(smem, (int)vy.y * kNE, tpos(a.tab, t1f));
-              const float sm = (L.e > a.cut.kcut2_lsb) ? rho1 * t1.y : 0.0f;
-              const float sb = (L.e > a.cut.kc_lsb) ? rho1 * t1.z : 0.0f;
-              if (sm + sb > sh) ++c_viol;
-              const float r = ur * sh;
-              if (r < sm) {
-                // Moller: binary collision with a free electron at rest
-                ++c_hard;
-                const float eps = sample_moller(t1f, a.cut.kcut, L.s);
-                const uint32_t wl = min(to_lsb(eps * t1f), L.e);
-                const uint32_t tp = L.e - wl;
-                const float wf = (float)wl * kLsbF, tpf = (float)tp * kLsbF;
-                const float cd = sqrtf(wf * (t1f + 2.0f * kMc2) / (t1f * (wf + 2.0f * kMc2)));
-                const float cpp = sqrtf(tpf * (t1f + 2.0f * kMc2) / (t1f * (tpf + 2.0f * kMc2)));
-                const float phi = kTwoPi * L.s.uniform();
-                c0.u = L.u; c0.v = L.v; c0.w = L.w;
-                rotate(c0.u, c0.v, c0.w, cd, phi);
-                rotate(L.u, L.v, L.w, cpp, phi + kPi);
-                if (wl >= a.cut.ecut_lsb) {
-                  c0.e = wl;
-                  child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
-                  ctype = 1;
-                } else {
-                  deposit_later(L, pend, v1, wl);
-                }
-                L.e = tp;
-                if (tp < a.cut.ecut_lsb) {
-                  deposit_later(L, pend, v1, tp);
-                  have = false;
-                }
-              } else if (r < sm + sb) {
-                // bremsstrahlung: electron direction unchanged, photon at mc^2/E
-                ++c_hard;
-                const float k = sample_brems(t1f, a.cut.kc, L.s);
-                const float phi = kTwoPi * L.s.uniform();
-                const uint32_t kl = min(to_lsb(k), L.e);
-                c0.u = L.u; c0.v = L.v; c0.w = L.w;
-                rotate(c0.u, c0.v, c0.w, __cosf(kMc2 / (t1f + kMc2)), phi);
-                if (kl >= a.cut.pcut_lsb) {
-                  c0.e = kl;
-                  child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
-                  ctype = 0;
-                } else {
-                  deposit_later(L, pend, v1, kl);
-                }
-                L.e -= kl;
-                if (L.e < a.cut.ecut_lsb) {
-                  deposit_later(L, pend, v1, L.e);
-                  have = false;
-                }
-              }
+              park = true;
+              have = false;
             }
           }
         }
       }
-      if (ctype >= 0) { ++pushes; ++c_sec; }
-      if (have) {
+      if (have || park) {
         ++events;
-        if (events >= a.max_events || pushes + 1 > a.max_secondaries) {
+        if (have && events >= a.max_events) {
           surv = true;
           have = false;
         }
@@ -571,14 +643,24 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
       if (!have) flush(L, pend);   // before the lane takes another particle
     }
     {
-      // delta rays and survivors to the electron staging segment, photons to the photon one
-      const WaveSeg::Slots se = gsame.append(ctype == 1, surv);
-      if (ctype == 1 && seg_ok(gsame, se.s0, a.ctr))
-        put(a.stg_same, gsame.base + se.s0, L.x, L.y, L.z, c0.u, c0.v, c0.w, c0.e, L.s.hist, c0.plo, c0.phi, 0u, L.beam);
-      if (surv && seg_ok(gsame, se.s1, a.ctr)) store_lane(L, a.stg_same, gsame.base + se.s1);
-      const WaveSeg::Slots sg = gother.append(ctype == 0, false);
-      if (ctype == 0 && seg_ok(gother, sg.s0, a.ctr))
-        put(a.stg_other, gother.base + sg.s0, L.x, L.y, L.z, c0.u, c0.v, c0.w, c0.e, L.s.hist, c0.plo, c0.phi, 0u, L.beam);
+      // survivors to the bottom of the electron staging segment, parked electrons onto its stack
+      const WaveSeg::Slots se = gsame.append(surv, false);
+      if (surv && seg_ok(gsame, se.s0, a.ctr)) store_lane(L, a.stg_same, gsame.base + se.s0);
+      const unsigned long long pm = __ballot(park);
+      if (park) {
+        const uint32_t k = npark + (uint32_t)__popcll(pm & lanes_below());
+        if (k < gsame.cap && gsame.cap - 1u - k >= gsame.used) {
+          const uint32_t slot = gsame.base + gsame.cap - 1u - k;
+          store_lane(L, a.stg_same, slot);
+          qf(a.stg_same, Q_AUX, slot) = __float_as_uint(sh);
+          qf(a.stg_same, Q_AUX2, slot) = (uint32_t)events | ((uint32_t)pushes << 16);
+        } else {
+          ctr_add(a.ctr, C_OVERFLOW, 1ull);
+        }
+      }
+      npark += (uint32_t)__popcll(pm);
+      // a lane that reads a parked entry may not be the lane that wrote it
+      if (pm) __threadfence_block();
     }
   }
   if (lane_id() == 0) {
@@ -731,7 +813,7 @@ __global__ void k_plan_pass(PlanArgs a) {
   P.n = n;
   P.m = (uint32_t)m;
   P.per_wave = q;
-  P.seg_same = q * a.bud_same;
+  P.seg_same = q * (a.bud_same + a.park_slots);
   P.seg_other = q * a.bud_other;
   *a.plan = P;
 }

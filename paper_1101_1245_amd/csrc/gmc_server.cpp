@@ -322,7 +322,7 @@ int gmc_server_start(gmc_context* c, const gmc_server_config* cfg) {
   probe.device = c->device;
   uint32_t cap = 0, soft = 0, stg = 0;
   queue_sizes(&probe, resolve_tuning(nullptr), kMaxMat, &cap, &soft, &stg);
-  s->slot_fixed = (size_t)Q_FIELDS * sizeof(uint32_t) * (4ull * cap + 2ull * stg);
+  s->slot_fixed = sizeof(uint32_t) * ((size_t)Q_FIELDS * 4ull * cap + (size_t)kStgFields * 2ull * stg);
   for (int i = 0; i < s->max_slots; ++i) s->slots.push_back(std::make_unique<Slot>());
   s->running = true;
   Server* sp = s.release();
