@@ -266,9 +266,10 @@ void queue_sizes(Workspace* w, const Tune& tu, int n_mat, uint32_t* cap, uint32_
   *cap = (uint32_t)(soft + (uint64_t)tu.secondaries * (uint64_t)tu.pass_items);
   uint32_t s = 0;
   for (int t = 0; t < 2; ++t) {
-    // largest segment per particle: photon pass, its electrons; electron
-    // pass, survivor + secondaries + one parked entry
-    const uint32_t bud = t == 0 ? (uint32_t)tu.secondaries : (uint32_t)tu.secondaries + 2u;
+    // largest segment per particle: photon pass, its electrons (or survivor
+    // + one parked entry); electron pass, survivor + secondaries + one
+    // parked entry
+    const uint32_t bud = t == 0 ? std::max<uint32_t>((uint32_t)tu.secondaries, 2u) : (uint32_t)tu.secondaries + 2u;
     const uint32_t waves = pass_waves(w, t, pass_block(w, t, tu.block, n_mat), n_mat);
     const uint32_t qmax = std::max<uint32_t>((uint32_t)tu.wave_items, ((uint32_t)tu.pass_items + waves - 1) / waves);
     s = std::max<uint32_t>(s, waves * qmax * bud);
@@ -462,7 +463,7 @@ int enqueue_pass(Engine& E, int type, hipEvent_t t0, hipEvent_t t1, bool capturi
   pa.min_per_wave = (uint32_t)E.tu.wave_items;
   pa.bud_same = E.bud_same[type];
   pa.bud_other = E.bud_other[type];
-  pa.park_slots = type == 1 ? 1u : 0u;
+  pa.park_slots = 1u;   // one parked entry per particle: electrons at hard events, photons at absorption
   WS_TRY(w, launch_plan_pass(pa, w->stream));
   PassArgs a = E.proto;
   a.work = w->qbuf[type][wi].q;

@@ -253,7 +253,78 @@ __device__ __forceinline__ int photon_flight(Lane& L, const PassArgs& a, const f
   return PH_PAIR;
 }
 
+// Photon absorbed in voxel v0 (Sec. II.B.2): photoelectric effect, one
+// electron with the whole energy in the Sauter direction; or pair production,
+// two electrons sharing E - 2 mc^2 uniformly at opposite azimuths, 2 mc^2 to
+// the sink.  Electrons below the cutoff are deposited in v0; those above are
+// left in c0 (and c1), nchild of them.
+__device__ __forceinline__ void absorb_photon(Lane& L, const PassArgs& a, int kind, int v0, Child& c0, Child& c1,
+                                              int& nchild, unsigned long long& acc_sink) {
+  if (kind == PH_PHOTO) {
+    const float ef = (float)L.e * kLsbF;
+    const float cost = sample_sauter(ef, L.s);
+    const float phi = kTwoPi * L.s.uniform();
+    c0.u = L.u; c0.v = L.v; c0.w = L.w;
+    rotate(c0.u, c0.v, c0.w, cost, phi);
+    if (L.e >= a.cut.ecut_lsb) {
+      c0.e = L.e;
+      child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
+      nchild = 1;
+    } else {
+      deposit(L, v0, L.e);
+    }
+    return;
+  }
+  const uint32_t avail = L.e - a.cut.two_mc2_lsb;
+  const uint32_t t1 = min((uint32_t)fminf(L.s.uniform() * (float)avail, kMaxLsbF), avail);
+  const uint32_t t2 = avail - t1;
+  const float cs1 = pair_cos((float)t1 * kLsbF, L.s.uniform());
+  const float cs2 = pair_cos((float)t2 * kLsbF, L.s.uniform());
+  const float phi = kTwoPi * L.s.uniform();
+  acc_sink += a.cut.two_mc2_lsb;
+  c0.u = L.u; c0.v = L.v; c0.w = L.w;
+  rotate(c0.u, c0.v, c0.w, cs1, phi);
+  c1.u = L.u; c1.v = L.v; c1.w = L.w;
+  rotate(c1.u, c1.v, c1.w, cs2, phi + kPi);
+  if (t1 >= a.cut.ecut_lsb) {
+    c0.e = t1;
+    child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
+    nchild = 1;
+  } else {
+    deposit(L, v0, t1);
+  }
+  if (t2 >= a.cut.ecut_lsb) {
+    c1.e = t2;
+    child_path(L.s.plo, L.s.phi, L.s.n, 1u, c1.plo, c1.phi);
+    if (nchild == 0) c0 = c1;   // keep the pushed children contiguous
+    ++nchild;
+  } else {
+    deposit(L, v0, t2);
+  }
+}
+
+// Push the children of one event (nchild of c0, c1 per lane) to the wave's
+// electron staging segment.
+__device__ __forceinline__ void push_electrons(const Lane& L, const PassArgs& a, WaveSeg& g, int nchild,
+                                               const Child& c0, const Child& c1) {
+  const WaveSeg::Slots sl = g.append(nchild >= 1, nchild >= 2);
+  const uint32_t hist = L.s.hist;
+  if (nchild >= 1 && seg_ok(g, sl.s0, a.ctr))
+    put(a.stg_other, g.base + sl.s0, L.x, L.y, L.z, c0.u, c0.v, c0.w, c0.e, hist, c0.plo, c0.phi, 0u, L.beam);
+  if (nchild >= 2 && seg_ok(g, sl.s1, a.ctr))
+    put(a.stg_other, g.base + sl.s1, L.x, L.y, L.z, c1.u, c1.v, c1.w, c1.e, hist, c1.plo, c1.phi, 0u, L.beam);
+}
+
 // ------------------------------------------------------------ photon pass
+// One Woodcock flight per iteration (Sec. II.B.2).  Photoelectric and pair
+// events end the photon: it is parked on a stack at the top of the
+// wavefront's photon staging segment (with the interaction type) and the
+// lane takes the next photon; once the range is done the wavefront samples
+// the parked absorptions 64 at a time, so those two rarer branches do not run
+// in most iterations with a few lanes each.  Each photon draws the same words
+// in the same order either way.  Segment bound: each photon of the range
+// leaves at most one survivor and is parked at most once, within per_wave x 2
+// slots.
 __global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
   extern __shared__ float4 smem[];
   const int nt = a.tab.n_mat * kNE;
@@ -272,16 +343,18 @@ __global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
   int events = 0, pushes = 0;
   unsigned long long acc_esc = 0, acc_sink = 0;
   uint32_t c_ev = 0, c_fict = 0, c_viol = 0, c_sec = 0;
+  uint32_t npark = 0;   // parked absorptions on the stack, wave-uniform
 
   for (;;) {
     refill(L, have, events, pushes, range, a, nvox);
     if (!__any(have)) break;
     int nchild = 0;
     Child c0, c1;
-    bool surv = false;
+    bool surv = false, park = false;
+    int kind = PH_ESCAPE;
     if (have) {
       int v0 = 0;
-      const int kind = photon_flight(L, a, smem, majg, v0, c_viol);
+      kind = photon_flight(L, a, smem, majg, v0, c_viol);
       ++c_ev;
       if (kind == PH_ESCAPE) {
         acc_esc += L.e;
@@ -318,49 +391,9 @@ __global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
           deposit(L, v0, e1);
           have = false;
         }
-      } else if (kind == PH_PHOTO) {
-        // one electron with the whole photon energy, Sauter direction
-        const float ef = (float)L.e * kLsbF;
-        const float cost = sample_sauter(ef, L.s);
-        const float phi = kTwoPi * L.s.uniform();
-        c0.u = L.u; c0.v = L.v; c0.w = L.w;
-        rotate(c0.u, c0.v, c0.w, cost, phi);
-        if (L.e >= a.cut.ecut_lsb) {
-          c0.e = L.e;
-          child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
-          nchild = 1;
-        } else {
-          deposit(L, v0, L.e);
-        }
-        have = false;
       } else {
-        // pair: two electrons, uniform split, opposite azimuths; 2 mc^2 to the sink
-        const uint32_t avail = L.e - a.cut.two_mc2_lsb;
-        const uint32_t t1 = min((uint32_t)fminf(L.s.uniform() * (float)avail, kMaxLsbF), avail);
-        const uint32_t t2 = avail - t1;
-        const float cs1 = pair_cos((float)t1 * kLsbF, L.s.uniform());
-        const float cs2 = pair_cos((float)t2 * kLsbF, L.s.uniform());
-        const float phi = kTwoPi * L.s.uniform();
-        acc_sink += a.cut.two_mc2_lsb;
-        c0.u = L.u; c0.v = L.v; c0.w = L.w;
-        rotate(c0.u, c0.v, c0.w, cs1, phi);
-        c1.u = L.u; c1.v = L.v; c1.w = L.w;
-        rotate(c1.u, c1.v, c1.w, cs2, phi + kPi);
-        if (t1 >= a.cut.ecut_lsb) {
-          c0.e = t1;
-          child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
-          nchild = 1;
-        } else {
-          deposit(L, v0, t1);
-        }
-        if (t2 >= a.cut.ecut_lsb) {
-          c1.e = t2;
-          child_path(L.s.plo, L.s.phi, L.s.n, 1u, c1.plo, c1.phi);
-          if (nchild == 0) c0 = c1;   // keep the pushed children contiguous
-          ++nchild;
-        } else {
-          deposit(L, v0, t2);
-        }
+        // photoelectric absorption or pair production: parked, sampled in the wave's last phase
+        park = true;
         have = false;
       }
       pushes += nchild;
@@ -373,17 +406,42 @@ __global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
         }
       }
     }
-    // secondary electrons to the electron staging segment, survivors to the photon one
-    {
-      const WaveSeg::Slots sl = gother.append(nchild >= 1, nchild >= 2);
-      const uint32_t hist = L.s.hist;
-      if (nchild >= 1 && seg_ok(gother, sl.s0, a.ctr))
-        put(a.stg_other, gother.base + sl.s0, L.x, L.y, L.z, c0.u, c0.v, c0.w, c0.e, hist, c0.plo, c0.phi, 0u, L.beam);
-      if (nchild >= 2 && seg_ok(gother, sl.s1, a.ctr))
-        put(a.stg_other, gother.base + sl.s1, L.x, L.y, L.z, c1.u, c1.v, c1.w, c1.e, hist, c1.plo, c1.phi, 0u, L.beam);
-      const WaveSeg::Slots ss = gsame.append(surv, false);
-      if (surv && seg_ok(gsame, ss.s0, a.ctr)) store_lane(L, a.stg_same, gsame.base + ss.s0);
+    // secondary electrons to the electron staging segment, survivors to the
+    // bottom of the photon one, absorbed photons onto its stack
+    push_electrons(L, a, gother, nchild, c0, c1);
+    const WaveSeg::Slots ss = gsame.append(surv, false);
+    if (surv && seg_ok(gsame, ss.s0, a.ctr)) store_lane(L, a.stg_same, gsame.base + ss.s0);
+    const unsigned long long pm = __ballot(park);
+    if (park) {
+      const uint32_t k = npark + (uint32_t)__popcll(pm & lanes_below());
+      if (k < gsame.cap && gsame.cap - 1u - k >= gsame.used) {
+        const uint32_t slot = gsame.base + gsame.cap - 1u - k;
+        store_lane(L, a.stg_same, slot);
+        qf(a.stg_same, Q_AUX, slot) = (uint32_t)kind;
+      } else {
+        ctr_add(a.ctr, C_OVERFLOW, 1ull);
+      }
     }
+    npark += (uint32_t)__popcll(pm);
+  }
+
+  // last phase: the parked absorptions with every lane busy
+  if (npark) __threadfence_block();   // a lane may read an entry another lane wrote
+  for (uint32_t k0 = 0; k0 < npark; k0 += 64u) {
+    const uint32_t k = k0 + lane_id();
+    int nchild = 0;
+    Child c0, c1;
+    if (k < npark) {
+      const uint32_t slot = gsame.base + gsame.cap - 1u - k;
+      load_lane(L, a.stg_same, slot, a.beams, nvox);
+      L.s.resume();
+      const int kind = (int)qf(a.stg_same, Q_AUX, slot);
+      int ix, iy, iz;
+      const int v0 = voxel(a.ph, L.x, L.y, L.z, ix, iy, iz);
+      absorb_photon(L, a, kind, v0, c0, c1, nchild, acc_sink);
+      c_sec += nchild;
+    }
+    push_electrons(L, a, gother, nchild, c0, c1);
   }
   if (lane_id() == 0) {
     a.used_same[wave] = gsame.used;
