@@ -48,20 +48,25 @@ OPS_PER_E_STEP = 400.0
 OPS_PER_PH_EVENT = 175.0
 # 32-bit VALU lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (no packed FP32).
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
-# HBM bytes per launch of the pass kernels on the default workload, from two
-# rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE; fetched bytes scaled x2.0 and
-# written x1.0 by a 1 GiB copy in the same runs), taken on the kernel sources
-# with this digest; any other sources report null.
-TRAFFIC = {"sources_sha256": "71d9865785a73cc8031f1dd582a1c7d16bfc78ee9fd3cd2a1175d849740903e1",
-           "k_electron_pass": 315.0e6, "k_photon_pass": 161.7e6}
-KERNEL_SOURCES = ("paper_1101_1245_amd/csrc/gmc_kernels.hip", "paper_1101_1245_amd/csrc/gmc_device.hpp",
-                  "paper_1101_1245_amd/csrc/gmc_internal.hpp")
+# HBM bytes per unit of algorithmic work (electron step / photon event) of the
+# pass kernels, from two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE)
+# over the timed legs of the water workload, each scaled by the same counter
+# on a 1 GiB device copy (fetched bytes x2.0, written x1.0).  Valid only for the kernel and engine sources they
+# were measured on (their digest); per launch they are multiplied by this
+# run's work per launch.
+TRAFFIC = {"sources_sha256": "da236ab88e9eaeea9683b51347f2a1f828d6e5c8be10a0696e6316c755acd59a",
+           "k_electron_pass": 46.65}
+MEASURED_SOURCES = ("paper_1101_1245_amd/csrc/gmc_kernels.hip",
+                    "paper_1101_1245_amd/csrc/gmc_device.hpp",
+                    "paper_1101_1245_amd/csrc/gmc_internal.hpp",
+                    "paper_1101_1245_amd/csrc/gmc_engine.cpp",
+                    "paper_1101_1245_amd/csrc/gmc_host.hpp")
 
 
 def measured_traffic(kernel):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in MEASURED_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return TRAFFIC.get(kernel) if h.hexdigest() == TRAFFIC["sources_sha256"] else None
@@ -126,12 +131,14 @@ def roofline(acc, workload="water"):
     avg = t / n
     achieved = ops / n / avg / 1e12 if avg > 0 else 0.0
     peak = PEAK_LANE_OPS / 1e12
-    traffic = measured_traffic(name) if workload == "water" else None
+    per_unit = measured_traffic(name) if workload == "water" else None
+    units = (acc.steps if name == "k_electron_pass" else acc.events) / n
+    traffic = per_unit * units if per_unit else None
     out = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": peak, "unit": "TOP/s",
            "frac": achieved / peak, "traffic": traffic, "avg_launch_ms": avg * 1e3, "launches": n,
            "share_of_pass_time": t / max(acc.t[0] + acc.t[1], 1e-30)}
     if traffic:
-        out["traffic_unit"] = "bytes per launch"
+        out["traffic_unit"] = "HBM bytes per launch (%.2f per unit of work x %.3g units)" % (per_unit, units)
         out["hbm_GBps"] = traffic / avg / 1e9
         out["hbm_frac"] = traffic / avg / 8.0e12
     return out
