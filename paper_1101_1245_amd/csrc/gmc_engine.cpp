@@ -128,8 +128,6 @@ int ws_init(Workspace* w, int device, hipStream_t stream) {
   WS_TRY(w, hipHostMalloc(&w->h_ctr, C_COUNT * kCtrSlots * sizeof(unsigned long long), hipHostMallocDefault));
   WS_TRY(w, hipMalloc(&w->d_nk, kMaxBatches * sizeof(double)));
   WS_TRY(w, hipHostMalloc(&w->h_nk, kMaxBatches * sizeof(double), hipHostMallocDefault));
-  WS_TRY(w, hipMalloc(&w->d_used, 2 * kMaxWaves * sizeof(uint32_t)));
-  WS_TRY(w, hipMalloc(&w->d_offsets, 2 * (kMaxWaves + 1) * sizeof(uint32_t)));
   WS_TRY(w, hipEventCreate(&w->ev0));
   WS_TRY(w, hipEventCreate(&w->ev1));
   WS_TRY(w, create_timing_event(&w->kev0));
@@ -155,14 +153,13 @@ void ws_free(Workspace* w) {
     for (auto& b : t) free_queue(b);
   for (auto& b : w->stg) free_queue(b);
   w->cap = w->stg_cap = 0;
-  for (void* p : {(void*)w->d_ctl, (void*)w->d_used, (void*)w->d_offsets, (void*)w->d_ctr, (void*)w->d_beams,
+  for (void* p : {(void*)w->d_ctl, (void*)w->d_ctr, (void*)w->d_beams,
                   (void*)w->d_sources, (void*)w->d_start, (void*)w->d_beam_of, (void*)w->d_nk})
     if (p) (void)hipFree(p);
   for (void* p : {(void*)w->h_ctl, (void*)w->h_ctr, (void*)w->h_nk})
     if (p) (void)hipHostFree(p);
   w->d_ctl = nullptr;
   w->h_ctl = nullptr;
-  w->d_used = w->d_offsets = nullptr;
   w->d_ctr = w->h_ctr = nullptr;
   w->d_beams = nullptr;
   w->d_sources = nullptr;
@@ -442,9 +439,10 @@ hipError_t record_event(hipStream_t s, hipEvent_t ev, bool capturing) {
   return hipStreamUpdateCaptureDependencies(s, &node, 1, hipStreamSetCaptureDependencies);
 }
 
-// Enqueue plan, pass and the two compactions of `type` over its accumulating
-// buffer, which becomes the work buffer; the other buffer accumulates from
-// then on.  The pass kernel is bracketed by the events t0 / t1 (recorded as
+// Enqueue the plan and the pass of `type` over its accumulating buffer, which
+// becomes the work buffer; the other buffer accumulates from then on (the
+// pass appends its outputs to it and to the other type's accumulating
+// buffer).  The pass kernel is bracketed by the events t0 / t1 (recorded as
 // graph event nodes while the stream is being captured).
 int enqueue_pass(Engine& E, int type, hipEvent_t t0, hipEvent_t t1, bool capturing) {
   Workspace* w = E.w;
@@ -454,6 +452,7 @@ int enqueue_pass(Engine& E, int type, hipEvent_t t0, hipEvent_t t1, bool capturi
   const int ni = w->acc[type];
   PlanArgs pa;
   pa.n_work = count_ptr(w, type, wi);
+  pa.n_new = count_ptr(w, type, ni);
   pa.n_other = count_ptr(w, other, w->acc[other]);
   pa.plan = w->d_ctl->plan + type;
   pa.cap = w->cap;
@@ -470,30 +469,15 @@ int enqueue_pass(Engine& E, int type, hipEvent_t t0, hipEvent_t t1, bool capturi
   a.plan = w->d_ctl->plan + type;
   a.stg_same = w->stg[0].q;
   a.stg_other = w->stg[1].q;
-  a.used_same = w->d_used;
-  a.used_other = w->d_used + kMaxWaves;
+  a.dst_same = w->qbuf[type][ni].q;
+  a.dst_other = w->qbuf[other][w->acc[other]].q;
+  a.cnt_same = count_ptr(w, type, ni);
+  a.cnt_other = count_ptr(w, other, w->acc[other]);
   WS_TRY(w, record_event(w->stream, t0, capturing));
   hipError_t e = type == 0 ? launch_photon_pass(a, (int)E.blocks[0], E.block[0], w->stream)
                            : launch_electron_pass(a, (int)E.blocks[1], E.block[1], w->stream);
   if (e != hipSuccess) return wfail(w, GMC_EDEVICE, std::string("pass launch: ") + hipGetErrorString(e));
   WS_TRY(w, record_event(w->stream, t1, capturing));
-  CompactArgs ca;
-  for (int d = 0; d < 2; ++d) {
-    const int dt = d == 0 ? type : other;
-    const int dbuf = d == 0 ? ni : w->acc[other];
-    ca.stg[d] = w->stg[d].q;
-    ca.used[d] = d == 0 ? a.used_same : a.used_other;
-    ca.dst[d] = w->qbuf[dt][dbuf].q;
-    ca.dst_count[d] = count_ptr(w, dt, dbuf);
-  }
-  ca.plan = w->d_ctl->plan + type;
-  ca.waves = E.waves[type];
-  ca.offsets = w->d_offsets;
-  ca.work = w->qbuf[type][wi].q;
-  ca.work_count = count_ptr(w, type, wi);
-  ca.ctr = w->d_ctr;
-  e = launch_compact(ca, w->stream);
-  if (e != hipSuccess) return wfail(w, GMC_EDEVICE, std::string("compaction launch: ") + hipGetErrorString(e));
   return GMC_OK;
 }
 

@@ -86,8 +86,6 @@ struct Workspace {
   uint32_t stg_cap = 0;
   Control* d_ctl = nullptr;
   Control* h_ctl = nullptr;     // pinned host copy
-  uint32_t* d_used = nullptr;   // [2][kMaxWaves]
-  uint32_t* d_offsets = nullptr;   // [2][kMaxWaves + 1]
   unsigned long long* d_ctr = nullptr;   // [C_COUNT][kCtrSlots]
   unsigned long long* h_ctr = nullptr;   // pinned host copy
   unsigned long long* d_tally = nullptr;

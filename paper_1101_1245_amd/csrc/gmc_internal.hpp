@@ -122,7 +122,8 @@ struct PassPlan {
 };
 
 struct PlanArgs {
-  const uint32_t* n_work;       // count of the work buffer
+  uint32_t* n_work;             // count of the work buffer (read, then cleared)
+  uint32_t* n_new;              // count of the type's new accumulating buffer: set to the carry-over
   const uint32_t* n_other;      // count of the other type's accumulating buffer
   PassPlan* plan;
   uint32_t cap;                 // allocated queue capacity (bounds this type's own outputs)
@@ -137,9 +138,13 @@ struct PlanArgs {
 // A pass kernel's work: wave w of the grid owns items [w q, (w+1) q) of the
 // work queue (q = per_wave), refills its lanes from that range, and appends
 // survivors and secondaries to its own segments of two staging queues
-// (same type / other type) -- no atomics on shared counters.  At exit each
-// wave stores how many entries it wrote; a compaction then packs the
-// segments into the accumulating queues.
+// (same type / other type) -- no atomics on shared counters while it
+// transports.  When a workgroup is done, one atomic per destination reserves
+// room for all of its waves' entries in the accumulating queues and each
+// wave copies its segments there; particles the pass did not take (m..n-1)
+// are copied to the front of the type's new queue.  Queue order then depends
+// on which workgroups finish first; no result does (every particle carries its
+// own stream and tallies are integer sums).
 struct PassArgs {
   DevPhantom ph;
   DevTables tab;
@@ -148,30 +153,16 @@ struct PassArgs {
   const PassPlan* plan;
   DevQueue stg_same;       // survivors and same-type secondaries
   DevQueue stg_other;      // other-type secondaries
-  uint32_t* used_same;     // [waves]
-  uint32_t* used_other;    // [waves]
+  DevQueue dst_same;       // the type's new accumulating queue (carry-over in front)
+  DevQueue dst_other;      // the other type's accumulating queue
+  uint32_t* cnt_same;      // their counts
+  uint32_t* cnt_other;
   const DevBeam* beams;
   unsigned long long* ctr;   // [C_COUNT][kCtrSlots]
   int max_events;
   int max_secondaries;
   int refill_lanes;          // idle lanes (1..64) that trigger a refill
   int resume_lanes;          // idle lanes (1..64) that take back parked electrons
-};
-
-// Compaction of one pass's outputs: destination 0 is the pass type's new
-// accumulating buffer (carried-over particles first), destination 1 the
-// other type's accumulating buffer.
-struct CompactArgs {
-  DevQueue stg[2];               // staging queues of the two destinations
-  const PassPlan* plan;
-  const uint32_t* used[2];       // [waves] entries each wave segment holds
-  uint32_t waves;
-  uint32_t* offsets;             // [2][waves + 1] destination of each segment; [0][waves]: of the carry-over
-  DevQueue dst[2];
-  uint32_t* dst_count[2];        // accumulating counts, advanced by the totals
-  DevQueue work;                 // the pass's work buffer, source of the carry-over
-  uint32_t* work_count;          // cleared
-  unsigned long long* ctr;
 };
 
 // Admission of primaries of one particle type.  The histories of all beams of
@@ -224,7 +215,6 @@ size_t electron_lds_bytes(int n_mat);
 hipError_t launch_plan_pass(const PlanArgs& a, hipStream_t s);
 hipError_t launch_photon_pass(const PassArgs& a, int grid, int block, hipStream_t s);
 hipError_t launch_electron_pass(const PassArgs& a, int grid, int block, hipStream_t s);
-hipError_t launch_compact(const CompactArgs& a, hipStream_t s);
 hipError_t launch_admit_plan(const AdmitPlanArgs& a, hipStream_t s);
 hipError_t launch_admit(const AdmitArgs& a, uint32_t max_count, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);

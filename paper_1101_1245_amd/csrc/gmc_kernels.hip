@@ -253,6 +253,51 @@ __device__ __forceinline__ int photon_flight(Lane& L, const PassArgs& a, const f
   return PH_PAIR;
 }
 
+// End of a pass kernel's workgroup (every thread calls it once, after its
+// wavefront's loop): particles m..n-1 of the work queue go to the front of
+// the type's new queue (grid-stride over all threads), then one atomic per
+// destination reserves room for the workgroup's staged entries and each
+// wavefront copies its own segments.  Entries beyond a queue's capacity are
+// counted, not written.
+__device__ __forceinline__ void copy_entry(const DevQueue& dst, uint32_t d, const DevQueue& src, uint32_t s,
+                                           unsigned long long* ctr) {
+  if (d >= dst.cap) {
+    ctr_add(ctr, C_OVERFLOW, 1ull);
+    return;
+  }
+#pragma unroll
+  for (int f = 0; f < Q_FIELDS; ++f) qf(dst, f, d) = qf(src, f, s);
+}
+
+__device__ __forceinline__ void append_outputs(const PassArgs& a, const PassPlan& P, const WaveSeg& gs,
+                                               const WaveSeg& go) {
+  __shared__ uint32_t s_used[2][16];
+  __shared__ uint32_t s_base[2];
+  const uint32_t carry = P.n - P.m;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < carry; i += gridDim.x * blockDim.x)
+    copy_entry(a.dst_same, i, a.work, P.m + i, a.ctr);
+  const uint32_t wl = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const uint32_t n0 = min(gs.used, gs.cap), n1 = min(go.used, go.cap);
+  if (lane_id() == 0) {
+    s_used[0][wl] = n0;
+    s_used[1][wl] = n1;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2u) {
+    uint32_t tot = 0;
+    for (uint32_t w = 0; w < nw; ++w) tot += s_used[threadIdx.x][w];
+    s_base[threadIdx.x] = tot ? atomicAdd(threadIdx.x == 0 ? a.cnt_same : a.cnt_other, tot) : 0u;
+  }
+  __syncthreads();
+  uint32_t o0 = s_base[0], o1 = s_base[1];
+  for (uint32_t w = 0; w < wl; ++w) {
+    o0 += s_used[0][w];
+    o1 += s_used[1][w];
+  }
+  for (uint32_t i = lane_id(); i < n0; i += 64u) copy_entry(a.dst_same, o0 + i, a.stg_same, gs.base + i, a.ctr);
+  for (uint32_t i = lane_id(); i < n1; i += 64u) copy_entry(a.dst_other, o1 + i, a.stg_other, go.base + i, a.ctr);
+}
+
 // Photon absorbed in voxel v0 (Sec. II.B.2): photoelectric effect, one
 // electron with the whole energy in the Sauter direction; or pair production,
 // two electrons sharing E - 2 mc^2 uniformly at opposite azimuths, 2 mc^2 to
@@ -443,10 +488,7 @@ __global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
     }
     push_electrons(L, a, gother, nchild, c0, c1);
   }
-  if (lane_id() == 0) {
-    a.used_same[wave] = gsame.used;
-    a.used_other[wave] = gother.used;
-  }
+  append_outputs(a, P, gsame, gother);
   const unsigned long long s_esc = wave_sum(acc_esc), s_sink = wave_sum(acc_sink);
   const unsigned long long s_ev = wave_sum(c_ev), s_fict = wave_sum(c_fict), s_viol = wave_sum(c_viol),
                            s_sec = wave_sum(c_sec);
@@ -721,10 +763,7 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
       if (pm) __threadfence_block();
     }
   }
-  if (lane_id() == 0) {
-    a.used_same[wave] = gsame.used;
-    a.used_other[wave] = gother.used;
-  }
+  append_outputs(a, P, gsame, gother);
   const unsigned long long s_esc = wave_sum(acc_esc);
   const unsigned long long s_steps = wave_sum(c_steps), s_hard = wave_sum(c_hard), s_viol = wave_sum(c_viol),
                            s_sec = wave_sum(c_sec);
@@ -870,86 +909,12 @@ __global__ void k_plan_pass(PlanArgs a) {
   PassPlan P;
   P.n = n;
   P.m = (uint32_t)m;
+  *a.n_work = 0u;                 // the work buffer is consumed by this pass
+  *a.n_new = n - (uint32_t)m;     // carried-over particles go to the front of the new buffer
   P.per_wave = q;
   P.seg_same = q * (a.bud_same + a.park_slots);
   P.seg_other = q * a.bud_other;
   *a.plan = P;
-}
-
-// -------------------------------------------------------------- compaction
-// Exclusive scans of the per-wave counts of both destinations (one workgroup
-// of 1024 lanes) giving each segment's place after its accumulating queue's
-// current end; in the pass type's own queue the carried-over particles go
-// first.
-__global__ void __launch_bounds__(1024) k_compact_scan(CompactArgs a) {
-  __shared__ uint32_t part[2][1024];
-  const PassPlan P = *a.plan;
-  const uint32_t seg[2] = {P.seg_same, P.seg_other};
-  const uint32_t carry = P.n - P.m;
-  const uint32_t t = threadIdx.x;
-  const uint32_t per = (a.waves + 1023u) / 1024u;
-  const uint32_t lo = min(t * per, a.waves), hi = min(lo + per, a.waves);
-  uint32_t sum[2] = {0u, 0u};
-  for (uint32_t w = lo; w < hi; ++w) {
-    sum[0] += min(a.used[0][w], seg[0]);
-    sum[1] += min(a.used[1][w], seg[1]);
-  }
-  part[0][t] = sum[0];
-  part[1][t] = sum[1];
-  const uint32_t base[2] = {*a.dst_count[0], *a.dst_count[1]};
-  __syncthreads();
-  for (uint32_t off = 1; off < 1024u; off <<= 1) {
-    const uint32_t v0 = t >= off ? part[0][t - off] : 0u;
-    const uint32_t v1 = t >= off ? part[1][t - off] : 0u;
-    __syncthreads();
-    part[0][t] += v0;
-    part[1][t] += v1;
-    __syncthreads();
-  }
-  for (int d = 0; d < 2; ++d) {
-    uint32_t run = base[d] + (d == 0 ? carry : 0u) + (t ? part[d][t - 1] : 0u);
-    uint32_t* off = a.offsets + d * (a.waves + 1u);
-    for (uint32_t w = lo; w < hi; ++w) {
-      off[w] = run;
-      run += min(a.used[d][w], seg[d]);
-    }
-  }
-  if (t == 1023u) {
-    a.offsets[a.waves] = base[0];   // destination of the carried-over particles
-    a.dst_count[0][0] = base[0] + carry + part[0][1023];
-    a.dst_count[1][0] = base[1] + part[1][1023];
-    a.work_count[0] = 0u;
-  }
-}
-
-// One wavefront per pass wave copies that wave's two staging segments to
-// their destinations; the carried-over particles are copied grid-stride by
-// all lanes.
-__global__ void __launch_bounds__(256) k_compact_copy(CompactArgs a) {
-  const PassPlan P = *a.plan;
-  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t w = gid >> 6, lane = gid & 63u;
-  if (w < a.waves) {
-#pragma unroll
-    for (int d = 0; d < 2; ++d) {
-      const uint32_t seg = d == 0 ? P.seg_same : P.seg_other;
-      const uint32_t n = min(a.used[d][w], seg);
-      const uint32_t src0 = w * seg, dst0 = a.offsets[d * (a.waves + 1u) + w];
-      for (uint32_t i = lane; i < n; i += 64u) {
-        const uint32_t s = src0 + i, t = dst0 + i;
-        if (t >= a.dst[d].cap) { ctr_add(a.ctr, C_OVERFLOW, 1ull); continue; }
-#pragma unroll
-        for (int f = 0; f < Q_FIELDS; ++f) qf(a.dst[d], f, t) = qf(a.stg[d], f, s);
-      }
-    }
-  }
-  const uint32_t carry = P.n - P.m, cbase = a.offsets[a.waves];
-  for (uint32_t i = gid; i < carry; i += gridDim.x * blockDim.x) {
-    const uint32_t s = P.m + i, t = cbase + i;
-    if (t >= a.dst[0].cap) { ctr_add(a.ctr, C_OVERFLOW, 1ull); continue; }
-#pragma unroll
-    for (int f = 0; f < Q_FIELDS; ++f) qf(a.dst[0], f, t) = qf(a.work, f, s);
-  }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1043,15 +1008,6 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v
   size_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_compact(const CompactArgs& a, hipStream_t s) {
-  if (a.waves == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_compact_copy, dim3((a.waves + 3u) / 4u), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
