@@ -48,6 +48,15 @@ __device__ __forceinline__ unsigned long long* tally_slice(const DevTally& t, ui
   return t.base + (size_t)k * nvox;
 }
 
+// Tally addition through the global address space: the tally pointers come
+// from the beam table, so the compiler cannot tell their address space and
+// would issue a flat atomic, which also holds the LDS counter -- every later
+// table read in LDS would then wait for the atomic to be acknowledged.
+__device__ __forceinline__ void tally_add(unsigned long long* p, unsigned long long v) {
+  typedef __attribute__((address_space(1))) unsigned long long global_u64;
+  __hip_atomic_fetch_add((global_u64*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Admission sizes for both particle types: take the next histories of each
 // type while its accumulating buffer holds fewer than `chunk` particles.
 __global__ void k_admit_plan(AdmitPlanArgs a) {
@@ -105,8 +114,8 @@ __global__ void __launch_bounds__(256) k_admit(AdmitArgs a) {
     const DevBeam b = a.beams[beam];
     unsigned long long* ta = tally_slice(b.a, h, a.nvox);
     unsigned long long* tb = tally_slice(b.b, h, a.nvox);
-    if (ta && p.e) atomicAdd(ta + v, (unsigned long long)p.e);
-    if (tb && p.e) atomicAdd(tb + v, (unsigned long long)p.e);
+    if (ta && p.e) tally_add(ta + v, (unsigned long long)p.e);
+    if (tb && p.e) tally_add(tb + v, (unsigned long long)p.e);
   }
   if (valid) {
     const uint32_t slot = pl.base + i;
@@ -191,8 +200,8 @@ __device__ __forceinline__ bool seg_ok(const WaveSeg& g, uint32_t slot, unsigned
 
 __device__ __forceinline__ void deposit(const Lane& L, int v, uint32_t e) {
   if (!e) return;
-  atomicAdd(L.ta + v, (unsigned long long)e);
-  if (L.tb) atomicAdd(L.tb + v, (unsigned long long)e);
+  tally_add(L.ta + v, (unsigned long long)e);
+  if (L.tb) tally_add(L.tb + v, (unsigned long long)e);
 }
 
 // An electron usually takes several steps in one voxel (a boundary-limited
