@@ -584,6 +584,7 @@ int engine_setup(Workspace* w, Engine& E, const Job& J, const Tune& tu) {
   E.proto.tab = dev_tables(*J.T, J.maj);
   E.proto.cut = cuts;
   E.proto.beams = w->d_beams;
+  E.proto.n_beams = (int)J.beams.size();
   E.proto.ctr = w->d_ctr;
   E.proto.max_events = tu.events;
   E.proto.max_secondaries = tu.secondaries;

@@ -94,6 +94,10 @@ struct DevBeam {
   uint32_t key0, key1;          // Philox key (seed lo, seed hi ^ beam id)
   DevTally a, b;
 };
+// Beams whose table the pass kernels keep in LDS (beside the physics tables):
+// a particle's refill then reads its beam's key and tally slices without a
+// second dependent global load.  Jobs with more beams read it from memory.
+constexpr int kLdsBeams = 256;
 
 // A beam's source, on the device for the admission kernel.
 struct DevSource {
@@ -158,6 +162,7 @@ struct PassArgs {
   uint32_t* cnt_same;      // their counts
   uint32_t* cnt_other;
   const DevBeam* beams;
+  int n_beams;
   unsigned long long* ctr;   // [C_COUNT][kCtrSlots]
   int max_events;
   int max_secondaries;

@@ -139,14 +139,14 @@ struct Lane {
   unsigned long long* tb;      // of target b (null when the beam has none)
 };
 
-__device__ __forceinline__ void load_lane(Lane& L, const DevQueue& q, uint32_t i, const DevBeam* beams,
-                                          uint32_t nvox) {
+__device__ __forceinline__ void load_lane(Lane& L, const DevQueue& q, uint32_t i, const PassArgs& a,
+                                          const DevBeam* lbeams, uint32_t nvox) {
   L.x = __uint_as_float(qf(q, Q_X, i)); L.y = __uint_as_float(qf(q, Q_Y, i)); L.z = __uint_as_float(qf(q, Q_Z, i));
   L.u = __uint_as_float(qf(q, Q_U, i)); L.v = __uint_as_float(qf(q, Q_V, i)); L.w = __uint_as_float(qf(q, Q_W, i));
   L.e = qf(q, Q_E, i);
   L.beam = qf(q, Q_BEAM, i);
   L.s.hist = qf(q, Q_HIST, i); L.s.plo = qf(q, Q_PLO, i); L.s.phi = qf(q, Q_PHI, i); L.s.n = qf(q, Q_N, i);
-  const DevBeam b = beams[L.beam];
+  const DevBeam b = a.n_beams <= kLdsBeams ? lbeams[L.beam] : a.beams[L.beam];
   L.s.k0 = b.key0; L.s.k1 = b.key1;
   L.ta = tally_slice(b.a, L.s.hist, nvox);
   L.tb = tally_slice(b.b, L.s.hist, nvox);
@@ -174,13 +174,13 @@ __device__ __forceinline__ WaveRange wave_range(const PassPlan& P, uint32_t wave
 // load latency for many lanes; with every lane idle it always proceeds).
 // Entries with zero energy (primaries settled by the source) are skipped.
 __device__ __forceinline__ void refill(Lane& L, bool& have, int& events, int& pushes, WaveRange& r,
-                                       const PassArgs& a, uint32_t nvox) {
+                                       const PassArgs& a, const DevBeam* lbeams, uint32_t nvox) {
   const unsigned long long need = __ballot(!have);
   if (need == 0 || r.next >= r.end || __popcll(need) < a.refill_lanes) return;
   if (!have) {
     const uint32_t it = r.next + (uint32_t)__popcll(need & lanes_below());
     if (it < r.end) {
-      load_lane(L, a.work, it, a.beams, nvox);
+      load_lane(L, a.work, it, a, lbeams, nvox);
       have = L.e != 0;
       events = 0;
       pushes = 0;
@@ -385,6 +385,9 @@ __global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
   for (int i = threadIdx.x; i < nt; i += blockDim.x) smem[i] = a.tab.ph[i];
   float* majg = reinterpret_cast<float*>(smem + nt);
   for (int i = threadIdx.x; i < kNE; i += blockDim.x) majg[i] = a.tab.maj_g[i];
+  DevBeam* lbeams = reinterpret_cast<DevBeam*>(majg + kNE);
+  if (a.n_beams <= kLdsBeams)
+    for (int i = threadIdx.x; i < a.n_beams; i += blockDim.x) lbeams[i] = a.beams[i];
   __syncthreads();
 
   const uint32_t nvox = (uint32_t)(a.ph.nx * a.ph.ny * a.ph.nz);
@@ -400,7 +403,7 @@ __global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
   uint32_t npark = 0;   // parked absorptions on the stack, wave-uniform
 
   for (;;) {
-    refill(L, have, events, pushes, range, a, nvox);
+    refill(L, have, events, pushes, range, a, lbeams, nvox);
     if (!__any(have)) break;
     int nchild = 0;
     Child c0, c1;
@@ -487,7 +490,7 @@ __global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
     Child c0, c1;
     if (k < npark) {
       const uint32_t slot = gsame.base + gsame.cap - 1u - k;
-      load_lane(L, a.stg_same, slot, a.beams, nvox);
+      load_lane(L, a.stg_same, slot, a, lbeams, nvox);
       L.s.resume();
       const int kind = (int)qf(a.stg_same, Q_AUX, slot);
       int ix, iy, iz;
@@ -603,6 +606,9 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
   float* ms = maje + kNE;
   for (int i = threadIdx.x; i < kNE; i += blockDim.x) maje[i] = a.tab.maj_e[i];
   for (int i = threadIdx.x; i < kNms; i += blockDim.x) ms[i] = a.tab.ms[i];
+  DevBeam* lbeams = reinterpret_cast<DevBeam*>(ms + kNms);
+  if (a.n_beams <= kLdsBeams)
+    for (int i = threadIdx.x; i < a.n_beams; i += blockDim.x) lbeams[i] = a.beams[i];
   __syncthreads();
 
   const uint32_t nvox = (uint32_t)(a.ph.nx * a.ph.ny * a.ph.nz);
@@ -620,7 +626,7 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
   const float emin = a.cut.emin;
 
   for (;;) {
-    refill(L, have, events, pushes, range, a, nvox);
+    refill(L, have, events, pushes, range, a, lbeams, nvox);
     // range done: idle lanes take back parked electrons, newest first
     bool hd = false;
     float hsh = 0.0f;
@@ -633,7 +639,7 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
           const uint32_t r = (uint32_t)__popcll(need & lanes_below());
           if (r < take) {
             const uint32_t slot = gsame.base + gsame.cap - npark + r;
-            load_lane(L, a.stg_same, slot, a.beams, nvox);
+            load_lane(L, a.stg_same, slot, a, lbeams, nvox);
             L.s.resume();
             hsh = __uint_as_float(qf(a.stg_same, Q_AUX, slot));
             const uint32_t cnt = qf(a.stg_same, Q_AUX2, slot);
@@ -927,9 +933,13 @@ __global__ void k_plan_pass(PlanArgs a) {
 }
 
 // ---------------------------------------------------------------- launchers
-size_t photon_lds_bytes(int n_mat) { return (size_t)n_mat * kNE * sizeof(float4) + kNE * sizeof(float); }
+// Tables, majorant, (screening table,) beam table.
+size_t photon_lds_bytes(int n_mat) {
+  return (size_t)n_mat * kNE * sizeof(float4) + kNE * sizeof(float) + kLdsBeams * sizeof(DevBeam);
+}
 size_t electron_lds_bytes(int n_mat) {
-  return (size_t)n_mat * kNE * sizeof(float4) + kNE * sizeof(float) + kNms * sizeof(float);
+  return (size_t)n_mat * kNE * sizeof(float4) + kNE * sizeof(float) + kNms * sizeof(float) +
+         kLdsBeams * sizeof(DevBeam);
 }
 
 // The pass kernels' dynamic-LDS limit is raised once, to what the largest

@@ -298,6 +298,7 @@ int gmc_first_events(gmc_context* c, int32_t phantom_id, int32_t tables_id, cons
   a.tab = dev_tables(*tp, maj);
   a.cut = dev_cuts(*tp);
   a.beams = w->d_beams;
+  a.n_beams = 1;
   const DevSource ds = dev_source(*src);
   float* dx = nullptr;
   uint32_t* dn = nullptr;
