@@ -12,6 +12,8 @@ Bars:
   one, or the combined one alone);
 * the combined dose agrees with the oracle's combined dose by the
   same-stream z-test;
+* with more beams than the kernels keep in LDS (300), per-beam results stay
+  bit-identical to the plain form's;
 * at the full beamlet size (256 beamlets, 200x200x160, about 5.8e7
   histories, default tuning as timed by the benchmark): the integer ledger
   closes, no majorant is violated, and sampled beams are bit-identical to
@@ -176,6 +178,24 @@ def test_errors(ctx, G, small_job, loaded):
         ctx.run_beams(pid, tid, j.sources[:2], [100], 1, shape=j.phantom.shape)
     with pytest.raises(ValueError):
         ctx.run_beams(pid, tid, j.sources[:1], [100], 1, shape=j.phantom.shape, tuning={"chunks": 5})
+
+
+def test_more_beams_than_the_lds_beam_table(ctx):
+    """Jobs of more than 256 beams read the beam table from memory instead of
+    LDS: per-beam results stay bit-identical to the plain form's."""
+    j = I.beamlet_job(300, (48, 48, 40), 0.5, count_scale=0.002, min_count=100)
+    tid = ctx.load_tables(j.materials, j.physics)
+    pid = ctx.load_phantom(j.phantom)
+    try:
+        pb, ps, d, s, st = ctx.run_beams(pid, tid, j.sources, j.counts, j.seed, shape=j.phantom.shape,
+                                         per_beam=True, per_beam_sigma=True)
+        assert st["ledger_residual_lsb"] == 0 and st["n_majorant_violations"] == 0
+        for b in (0, 1, 255, 256, 299):
+            db, sb, _ = ctx.run_beam(pid, tid, j.sources[b], int(j.counts[b]), j.seed, shape=j.phantom.shape)
+            assert np.array_equal(pb[b], db) and np.array_equal(ps[b], sb), b
+    finally:
+        ctx.release(pid)
+        ctx.release(tid)
 
 
 def test_full_beamlet_job(ctx, oracle):
