@@ -66,12 +66,14 @@ struct DevCuts {
 // bits), kinetic energy in 2^-27 MeV units, history index, stream path (two
 // words), stream word counter, beam index.
 enum QueueField { Q_X = 0, Q_Y, Q_Z, Q_U, Q_V, Q_W, Q_E, Q_HIST, Q_PLO, Q_PHI, Q_N, Q_BEAM, Q_FIELDS };
-// Staging entries carry two words more for an electron parked at a
-// hard-event candidate: the step-start majorant (float bits) and its visit
-// counters (events | pushes << 16).
+// Staging entries carry four words more for an electron parked at a
+// hard-event candidate: the step-start majorant (float bits), its visit
+// counters (events | pushes << 16) and its pending deposit (voxel, energy).
 constexpr int Q_AUX = Q_FIELDS;
 constexpr int Q_AUX2 = Q_FIELDS + 1;
-constexpr int kStgFields = Q_FIELDS + 2;
+constexpr int Q_PV = Q_FIELDS + 2;
+constexpr int Q_PE = Q_FIELDS + 3;
+constexpr int kStgFields = Q_FIELDS + 4;
 struct DevQueue {
   uint32_t* base;
   uint32_t stride;

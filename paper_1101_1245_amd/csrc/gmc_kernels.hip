@@ -645,6 +645,8 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
             const uint32_t cnt = qf(a.stg_same, Q_AUX2, slot);
             events = (int)(cnt & 0xffffu);
             pushes = (int)(cnt >> 16);
+            pend.v = (int)qf(a.stg_same, Q_PV, slot);
+            pend.e = qf(a.stg_same, Q_PE, slot);
             hd = true;
           }
         }
@@ -679,6 +681,9 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
       surv = true;
       have = false;
     }
+    // a resumed electron that ended at its hard event, or is requeued, adds
+    // the pending deposit it brought back (idle lanes hold none)
+    if (!have) flush(L, pend);
     if (have) {
       L.s.align();
       int ix, iy, iz, v0;
@@ -755,7 +760,10 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
           have = false;
         }
       }
-      if (!have) flush(L, pend);   // before the lane takes another particle
+      // before the lane takes another particle; a parked electron keeps its
+      // pending deposit (pencil beams concentrate deposits on few voxels,
+      // where every extra atomic costs)
+      if (!have && !park) flush(L, pend);
     }
     {
       // survivors to the bottom of the electron staging segment, parked electrons onto its stack
@@ -769,8 +777,12 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
           store_lane(L, a.stg_same, slot);
           qf(a.stg_same, Q_AUX, slot) = __float_as_uint(sh);
           qf(a.stg_same, Q_AUX2, slot) = (uint32_t)events | ((uint32_t)pushes << 16);
+          qf(a.stg_same, Q_PV, slot) = (uint32_t)pend.v;
+          qf(a.stg_same, Q_PE, slot) = pend.e;
+          pend = Pending{};
         } else {
           ctr_add(a.ctr, C_OVERFLOW, 1ull);
+          flush(L, pend);
         }
       }
       npark += (uint32_t)__popcll(pm);
