@@ -54,8 +54,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # on a 1 GiB device copy (fetched bytes x2.0, written x1.0).  Valid only for the kernel and engine sources they
 # were measured on (their digest); per launch they are multiplied by this
 # run's work per launch.
-TRAFFIC = {"sources_sha256": "da236ab88e9eaeea9683b51347f2a1f828d6e5c8be10a0696e6316c755acd59a",
-           "k_electron_pass": 46.65}
+TRAFFIC = {"sources_sha256": "10d32c34d5edcc372afca0c07c45848edd3868b4eb24ccc1578b337a192a52b1",
+           "k_electron_pass": 55.19}
 MEASURED_SOURCES = ("paper_1101_1245_amd/csrc/gmc_kernels.hip",
                     "paper_1101_1245_amd/csrc/gmc_device.hpp",
                     "paper_1101_1245_amd/csrc/gmc_internal.hpp",
