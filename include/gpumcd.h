@@ -201,13 +201,16 @@ int gmc_run_beams(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const
  * the events per visit, the workgroup size, the particles per wavefront,
  * the refill threshold and the rounds per status check by coordinate
  * descent, starting with the admission chunk and the pass size together
- * (pass = 2 x chunk): each candidate runs a sample of the job (the first
- * histories of every beam, in proportion: 5% of the job but at least 2^25
- * histories, or the whole job if smaller) and is timed on the device; a
- * change is kept when it saves at least 2%.  Choices are cached in the context per job class (grid size,
+ * (pass = 2 x chunk): each candidate runs the whole job when about 24 such
+ * runs fit the budget, else a sample (the first histories of every beam, in
+ * proportion: 5% of the job but at least 2^25 histories), and is timed on
+ * the device; a change is kept when it saves at least 2%.  Choices are cached in the context per job class (grid size,
  * mean energy, electron fraction, field area, history count and material
  * count on coarse logarithmic scales); a cached class returns at once.
- * budget_s bounds the search's wall time (<= 0: 5 s).  gmc_run_beams with
+ * gmc_autotune tunes the job with combined outputs only; gmc_run_beams with
+ * tuning NULL and per-beam outputs tunes (and caches) the job as it runs
+ * it, with per-beam tallies.
+ * budget_s bounds the search's wall time (<= 0: 10 s).  gmc_run_beams with
  * tuning NULL calls this first.  *out receives the choice; report may be
  * NULL. */
 typedef struct {

@@ -976,7 +976,7 @@ std::vector<int> job_class(const PhantomObj& P, const TablesObj& T, const gmc_so
 // least 2^20 histories), each candidate timed on the device from the
 // admission to the finalize; a change is kept when it saves at least 2%.
 int autotune(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_source* srcs, const uint64_t* n_hist,
-             int n_beams, double budget_s, gmc_tuning* out, gmc_autotune_report* rep) {
+             int n_beams, double budget_s, gmc_tuning* out, gmc_autotune_report* rep, bool per_beam) {
   if (n_beams < 1 || !srcs || !n_hist || !out) return cfail(c, GMC_EINVAL, "bad autotune arguments");
   const PhantomObj* pp = nullptr;
   const TablesObj* tp = nullptr;
@@ -996,7 +996,8 @@ int autotune(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_so
     n_total += n_hist[b];
   }
   if (n_total >= (1ull << 32)) return cfail(c, GMC_EINVAL, "total histories must be < 2^32");
-  const std::vector<int> key = job_class(*pp, *tp, srcs, n_hist, n_beams);
+  std::vector<int> key = job_class(*pp, *tp, srcs, n_hist, n_beams);
+  key.push_back(per_beam ? 1 : 0);
   gmc_autotune_report r{};
   {
     std::lock_guard<std::mutex> lk(c->mu);
@@ -1025,19 +1026,38 @@ int autotune(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_so
   int rc = ws_ensure_out(&c->ws, pp->nvox());
   if (rc) return cfail(c, rc, c->ws.err);
   const auto t0 = std::chrono::steady_clock::now();
+  // with per-beam outputs every beam's dose lands in the same scratch buffer
+  std::vector<double*> pb(per_beam ? (size_t)n_beams : 0u, c->ws.d_dose);
+  // A candidate that needs larger queues allocates them inside its timed
+  // run; run it again then, so that it is timed on its own work.
   auto trial = [&](const gmc_tuning& t, double* sec) -> int {
-    gmc_run_stats st{};
-    const int e = run_job(c, phantom_id, tables_id, srcs, ns.data(), n_beams, 0x5eedull, nullptr, nullptr,
-                          c->ws.d_dose, nullptr, GMC_DEVICE, &t, &st, true);
-    ++r.trials;
-    *sec = st.t_device_s;
-    return e;
+    for (int rep = 0; rep < 2; ++rep) {
+      const uint32_t cap0 = c->ws.cap, stg0 = c->ws.stg_cap;
+      gmc_run_stats st{};
+      const int e = run_job(c, phantom_id, tables_id, srcs, ns.data(), n_beams, 0x5eedull,
+                            per_beam ? pb.data() : nullptr, nullptr, c->ws.d_dose, nullptr, GMC_DEVICE, &t, &st,
+                            true);
+      ++r.trials;
+      *sec = st.t_device_s;
+      if (e != GMC_OK || (c->ws.cap == cap0 && c->ws.stg_cap == stg0)) return e;
+    }
+    return GMC_OK;
   };
   gmc_tuning best = default_tuning();
   double t_best = 0.0;
   rc = trial(best, &t_best);   // the first run sizes the buffers; time a second one
   if (rc == GMC_OK) rc = trial(best, &t_best);
   if (rc) return rc;
+  // When the whole job's trials fit the budget, tune on the whole job: even
+  // a sample of several chunks ranks the largest chunks and passes lower
+  // than the job itself does.
+  if (n_sample < n_total && t_best * ((double)n_total / (double)n_sample) * kTuneTrials <= budget_s) {
+    for (int b = 0; b < n_beams; ++b) ns[b] = n_hist[b];
+    n_sample = n_total;
+    rc = trial(best, &t_best);
+    if (rc == GMC_OK) rc = trial(best, &t_best);
+    if (rc) return rc;
+  }
   r.t_default_s = t_best;
   // twin: a second field set to twice the value (admission chunk and pass
   // size move together first: a pass should hold about two chunks)

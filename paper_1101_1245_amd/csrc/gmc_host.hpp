@@ -50,7 +50,8 @@ struct QueueBuf {
 constexpr uint32_t kMinSoftCap = 1u << 23;
 constexpr uint32_t kMaxSoftCap = 1u << 25;
 constexpr uint32_t kMaxWaves = 1u << 15;
-constexpr double kAutotuneBudgetS = 5.0;   // default wall-clock budget of one tuning
+constexpr double kAutotuneBudgetS = 10.0;   // default wall-clock budget of one tuning
+constexpr double kTuneTrials = 24.0;        // about how many candidates one tuning runs
 constexpr uint64_t kTuneMinSample = 1ull << 25;   // 8 chunks of the largest candidate
 // Idle lanes of an electron-pass wavefront, its range done, that take back
 // parked electrons together (their hard events then run on that many lanes).
@@ -258,8 +259,10 @@ int get_majorants(gmc_context* c, int32_t pid, int32_t tid, const PhantomObj& p,
 int run_job(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_source* srcs, const uint64_t* n_hist,
             int n_beams, uint64_t seed, double* const* dose_per_beam, double* const* sigma_per_beam, double* dose,
             double* sigma, int out_kind, const gmc_tuning* tuning, gmc_run_stats* stats, bool batched);
+// per_beam: tune the job as run with per-beam outputs (their tally layout),
+// a job class of its own.
 int autotune(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_source* srcs, const uint64_t* n_hist,
-             int n_beams, double budget_s, gmc_tuning* out, gmc_autotune_report* rep);
+             int n_beams, double budget_s, gmc_tuning* out, gmc_autotune_report* rep, bool per_beam = false);
 // Served form (gmc_server.cpp).
 void server_destroy(gmc_context* c);
 }  // namespace gmc

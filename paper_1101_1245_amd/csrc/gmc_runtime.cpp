@@ -194,7 +194,8 @@ int gmc_run_beams(gmc_context* c, int32_t phantom_id, int32_t tables_id, const g
   if (!c) return GMC_EINVAL;
   gmc_tuning tuned;
   if (!tuning && srcs && n_hist && n_beams >= 1) {
-    const int rc = autotune(c, phantom_id, tables_id, srcs, n_hist, n_beams, kAutotuneBudgetS, &tuned, nullptr);
+    const int rc = autotune(c, phantom_id, tables_id, srcs, n_hist, n_beams, kAutotuneBudgetS, &tuned, nullptr,
+                            dose_per_beam != nullptr || sigma_per_beam != nullptr);
     if (rc) return rc;
     tuning = &tuned;
   }
