@@ -1,6 +1,6 @@
 // gmc_engine.cpp -- the transport engine on the host side: workspaces, job
-// construction, the rounds of [admit primaries -> electron pass ->
-// compaction -> photon pass -> compaction] (Sec. II.C.2: photons and
+// construction, the rounds of [admit primaries -> electron pass -> photon
+// pass] (each pass appending its outputs to the queues; Sec. II.C.2: photons and
 // electrons are simulated in alternating passes; the leftover threshold is
 // zero, so no particle is ever dropped), the finalize (Sec. II.D), the
 // blocking plain and batched forms and the autotuner.

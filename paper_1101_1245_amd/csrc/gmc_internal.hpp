@@ -12,7 +12,7 @@
 //  * tallies: uint64 fixed-point energy (2^-27 MeV) per (batch, voxel).
 //
 // Pass sizes live on the device: a one-lane planning kernel reads the queue
-// counts and writes a PassPlan that the pass and compaction kernels read, so
+// counts and writes a PassPlan that the pass kernel reads, so
 // a sequence of passes can be enqueued (or captured in a graph) without the
 // host reading counts in between.
 #pragma once

@@ -8,8 +8,11 @@
 // budget, and then takes the next particle of the range (lane-level refill,
 // the "pool" idea of Sec. II.C.3 inside one launch).  Survivors and
 // secondaries go to the wavefront's private segments of two staging queues,
-// so no lane ever waits on a shared counter; a compaction kernel then packs
-// the segments into the pending queues (the stream compaction of Sec. II.C.3).
+// so no lane ever waits on a shared counter; when a workgroup is done, its
+// wavefronts copy their segments into the accumulating queues, one atomic per
+// workgroup and queue reserving the room (the stream compaction of Sec.
+// II.C.3).  Rare, costly events (electron hard events, photon absorptions)
+// are parked and sampled by many lanes together.
 // Deposits are uint64 fixed-point atomics, so the dose is an exact integer
 // sum independent of thread order.  Cross-section and stopping-power tables
 // are staged in LDS by every workgroup.
