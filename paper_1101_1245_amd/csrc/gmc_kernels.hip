@@ -142,6 +142,22 @@ struct Lane {
   unsigned long long* tb;      // of target b (null when the beam has none)
 };
 
+// A beam-table entry read member by member through a pointer of a given
+// address space.
+template <typename P>
+__device__ __forceinline__ DevBeam read_beam(P p) {
+  DevBeam b;
+  b.key0 = p->key0;
+  b.key1 = p->key1;
+  b.a.base = p->a.base;
+  b.a.K = p->a.K;
+  b.a.off = p->a.off;
+  b.b.base = p->b.base;
+  b.b.K = p->b.K;
+  b.b.off = p->b.off;
+  return b;
+}
+
 __device__ __forceinline__ void load_lane(Lane& L, const DevQueue& q, uint32_t i, const PassArgs& a,
                                           const DevBeam* lbeams, uint32_t nvox) {
   L.x = __uint_as_float(qf(q, Q_X, i)); L.y = __uint_as_float(qf(q, Q_Y, i)); L.z = __uint_as_float(qf(q, Q_Z, i));
@@ -149,7 +165,12 @@ __device__ __forceinline__ void load_lane(Lane& L, const DevQueue& q, uint32_t i
   L.e = qf(q, Q_E, i);
   L.beam = qf(q, Q_BEAM, i);
   L.s.hist = qf(q, Q_HIST, i); L.s.plo = qf(q, Q_PLO, i); L.s.phi = qf(q, Q_PHI, i); L.s.n = qf(q, Q_N, i);
-  const DevBeam b = a.n_beams <= kLdsBeams ? lbeams[L.beam] : a.beams[L.beam];
+  // explicit address spaces: a merged pointer would make this a flat load,
+  // which waits on both the LDS and the memory counters
+  typedef __attribute__((address_space(3))) const DevBeam lds_beam;
+  typedef __attribute__((address_space(1))) const DevBeam global_beam;
+  const DevBeam b = a.n_beams <= kLdsBeams ? read_beam((lds_beam*)lbeams + L.beam)
+                                           : read_beam((global_beam*)a.beams + L.beam);
   L.s.k0 = b.key0; L.s.k1 = b.key1;
   L.ta = tally_slice(b.a, L.s.hist, nvox);
   L.tb = tally_slice(b.b, L.s.hist, nvox);
