@@ -268,7 +268,8 @@ void queue_sizes(Workspace* w, const Tune& tu, int n_mat, uint32_t* cap, uint32_
     // parked entry
     const uint32_t bud = t == 0 ? std::max<uint32_t>((uint32_t)tu.secondaries, 2u) : (uint32_t)tu.secondaries + 2u;
     const uint32_t waves = pass_waves(w, t, pass_block(w, t, tu.block, n_mat), n_mat);
-    const uint32_t qmax = std::max<uint32_t>((uint32_t)tu.wave_items, ((uint32_t)tu.pass_items + waves - 1) / waves);
+    const uint32_t chunks = ((uint32_t)tu.pass_items + 63u) / 64u;   // items go to wavefronts in chunks of 64
+    const uint32_t qmax = std::max<uint32_t>((uint32_t)tu.wave_items, (chunks + waves - 1) / waves * 64u);
     s = std::max<uint32_t>(s, waves * qmax * bud);
   }
   *stg = s;

@@ -120,9 +120,10 @@ enum CounterIndex {
 constexpr int kCtrSlots = 256;
 
 // Sizes of one pass, written by k_plan_pass.  The work buffer holds n
-// particles; this pass transports the first m; wavefront w owns items
-// [w per_wave, (w+1) per_wave) and staging segments of seg_same / seg_other
-// slots.  Particles m..n-1 are carried over to the next buffer.
+// particles; this pass transports the first m, dealt to the wavefronts in
+// chunks of 64 (chunk c to wavefront c mod W), at most per_wave each; each
+// wavefront has staging segments of seg_same / seg_other slots.  Particles
+// m..n-1 are carried over to the next buffer.
 struct PassPlan {
   uint32_t n, m, per_wave, seg_same, seg_other;
 };
@@ -141,8 +142,8 @@ struct PlanArgs {
   uint32_t park_slots;          // same-type staging slots per particle for parked electrons
 };
 
-// A pass kernel's work: wave w of the grid owns items [w q, (w+1) q) of the
-// work queue (q = per_wave), refills its lanes from that range, and appends
+// A pass kernel's work: each wave of the grid owns its chunks of the work
+// queue (at most per_wave items), refills its lanes from them, and appends
 // survivors and secondaries to its own segments of two staging queues
 // (same type / other type) -- no atomics on shared counters while it
 // transports.  When a workgroup is done, one atomic per destination reserves

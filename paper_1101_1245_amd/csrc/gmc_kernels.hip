@@ -182,15 +182,29 @@ __device__ __forceinline__ void store_lane(const Lane& L, const DevQueue& q, uin
 
 struct Child { float u, v, w; uint32_t e, plo, phi; };
 
-// Wave-uniform cursor over the wavefront's range [next, end) of the work queue.
-struct WaveRange { uint32_t next, end; };
+// A wavefront's share of the pass: the work queue's items m are cut into
+// chunks of 64 and chunk c goes to wavefront c mod W, so that every
+// wavefront gets a slice of every part of the queue -- carried-over
+// particles, survivors, the other type's secondaries, new primaries -- whose
+// lives differ widely; contiguous shares left many wavefronts idle while a
+// few finished theirs.  Loads stay coalesced within a chunk.  [next, end) is
+// the wave-uniform cursor over the wavefront's own items, numbered 0..end-1.
+struct WaveRange { uint32_t next, end, wave, waves; };
 
-__device__ __forceinline__ WaveRange wave_range(const PassPlan& P, uint32_t wave) {
-  const uint64_t lo = (uint64_t)wave * P.per_wave;
-  WaveRange r;
-  r.next = (uint32_t)(lo < P.m ? lo : P.m);
-  r.end = (uint32_t)(lo + P.per_wave < P.m ? lo + P.per_wave : P.m);
+__device__ __forceinline__ WaveRange wave_range(const PassPlan& P, uint32_t wave, uint32_t waves) {
+  const uint32_t chunks = (P.m + 63u) >> 6;
+  WaveRange r{0u, 0u, wave, waves};
+  if (wave < chunks) {
+    const uint32_t own = (chunks - 1u - wave) / waves + 1u;
+    r.end = own << 6;
+    if ((chunks - 1u) % waves == wave) r.end -= (chunks << 6) - P.m;   // the last chunk may be partial
+  }
   return r;
+}
+
+// Work-queue index of the wavefront's item j.
+__device__ __forceinline__ uint32_t range_item(const WaveRange& r, uint32_t j) {
+  return (((j >> 6) * r.waves + r.wave) << 6) + (j & 63u);
 }
 
 // Lanes without a particle take the next items of the range, in lane order,
@@ -204,7 +218,7 @@ __device__ __forceinline__ void refill(Lane& L, bool& have, int& events, int& pu
   if (!have) {
     const uint32_t it = r.next + (uint32_t)__popcll(need & lanes_below());
     if (it < r.end) {
-      load_lane(L, a.work, it, a, lbeams, nvox);
+      load_lane(L, a.work, range_item(r, it), a, lbeams, nvox);
       have = L.e != 0;
       events = 0;
       pushes = 0;
@@ -417,7 +431,7 @@ __global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
   const uint32_t nvox = (uint32_t)(a.ph.nx * a.ph.ny * a.ph.nz);
   const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const PassPlan P = *a.plan;
-  WaveRange range = wave_range(P, wave);
+  WaveRange range = wave_range(P, wave, (gridDim.x * blockDim.x) >> 6);
   WaveSeg gsame{wave * P.seg_same, P.seg_same, 0u}, gother{wave * P.seg_other, P.seg_other, 0u};
   Lane L;
   bool have = false;
@@ -638,7 +652,7 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
   const uint32_t nvox = (uint32_t)(a.ph.nx * a.ph.ny * a.ph.nz);
   const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const PassPlan P = *a.plan;
-  WaveRange range = wave_range(P, wave);
+  WaveRange range = wave_range(P, wave, (gridDim.x * blockDim.x) >> 6);
   WaveSeg gsame{wave * P.seg_same, P.seg_same, 0u}, gother{wave * P.seg_other, P.seg_other, 0u};
   Lane L;
   Pending pend;
@@ -955,7 +969,9 @@ __global__ void k_plan_pass(PlanArgs a) {
     const uint64_t lim = no < a.cap_other ? (uint64_t)(a.cap_other - no) / a.bud_other : 0u;
     if (m > lim) m = lim;
   }
-  uint32_t q = (uint32_t)((m + a.waves - 1) / a.waves);
+  // most items a wavefront gets (whole 64-item chunks, dealt round-robin)
+  const uint64_t chunks = (m + 63u) >> 6;
+  uint32_t q = (uint32_t)(((chunks + a.waves - 1) / a.waves) << 6);
   if (q < a.min_per_wave) q = a.min_per_wave;
   PassPlan P;
   P.n = n;
