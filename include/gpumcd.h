@@ -142,7 +142,8 @@ typedef struct {
  *     keep more wavefronts per compute unit);
  *   pass_items: most particles one pass launch transports (1024..2^23,
  *     default 2^22); the rest is carried to the next pass;
- *   wave_items: fewest particles a wavefront owns in a pass (64..2^16,
+ *   wave_items: particles per chunk when a pass deals its particles to the
+ *     wavefronts round-robin (64..1024, rounded down to a power of two;
  *     default 64);
  *   rounds_per_check: batched form only; the captured graph holds
  *     2 x rounds_per_check rounds and the host reads the particle counts

@@ -229,7 +229,12 @@ Tune resolve_tuning(const gmc_tuning* t) {
     if (t->chunk > 0) r.chunk = std::min(t->chunk, 1 << 24);
     if (t->wg_size >= 64 && t->wg_size <= 1024 && t->wg_size % 64 == 0) r.block = t->wg_size;
     if (t->pass_items > 0) r.pass_items = std::min(std::max(t->pass_items, 1024), 1 << 23);
-    if (t->wave_items > 0) r.wave_items = std::min(std::max(t->wave_items, 64), 1 << 16);
+    if (t->wave_items > 0) {
+      // a power of two in [64, 1024]
+      int c = 64;
+      while (c * 2 <= std::min(t->wave_items, 1024)) c *= 2;
+      r.wave_items = c;
+    }
     if (t->rounds_per_check > 0) r.rounds = std::min(t->rounds_per_check, 1024);
     if (t->refill_lanes > 0) r.refill = std::min(t->refill_lanes, 64);
   }
@@ -268,8 +273,10 @@ void queue_sizes(Workspace* w, const Tune& tu, int n_mat, uint32_t* cap, uint32_
     // parked entry
     const uint32_t bud = t == 0 ? std::max<uint32_t>((uint32_t)tu.secondaries, 2u) : (uint32_t)tu.secondaries + 2u;
     const uint32_t waves = pass_waves(w, t, pass_block(w, t, tu.block, n_mat), n_mat);
-    const uint32_t chunks = ((uint32_t)tu.pass_items + 63u) / 64u;   // items go to wavefronts in chunks of 64
-    const uint32_t qmax = std::max<uint32_t>((uint32_t)tu.wave_items, (chunks + waves - 1) / waves * 64u);
+    // items go to wavefronts in chunks of wave_items
+    const uint32_t cs = (uint32_t)tu.wave_items;
+    const uint32_t chunks = ((uint32_t)tu.pass_items + cs - 1u) / cs;
+    const uint32_t qmax = (chunks + waves - 1) / waves * cs;
     s = std::max<uint32_t>(s, waves * qmax * bud);
   }
   *stg = s;
@@ -460,7 +467,8 @@ int enqueue_pass(Engine& E, int type, hipEvent_t t0, hipEvent_t t1, bool capturi
   pa.cap_other = w->cap_soft;
   pa.max_items = (uint32_t)E.tu.pass_items;
   pa.waves = E.waves[type];
-  pa.min_per_wave = (uint32_t)E.tu.wave_items;
+  pa.chunk_log2 = 0;
+  while ((1u << pa.chunk_log2) < (uint32_t)E.tu.wave_items) ++pa.chunk_log2;
   pa.bud_same = E.bud_same[type];
   pa.bud_other = E.bud_other[type];
   pa.park_slots = 1u;   // one parked entry per particle: electrons at hard events, photons at absorption

@@ -121,11 +121,11 @@ constexpr int kCtrSlots = 256;
 
 // Sizes of one pass, written by k_plan_pass.  The work buffer holds n
 // particles; this pass transports the first m, dealt to the wavefronts in
-// chunks of 64 (chunk c to wavefront c mod W), at most per_wave each; each
-// wavefront has staging segments of seg_same / seg_other slots.  Particles
-// m..n-1 are carried over to the next buffer.
+// chunks of 2^chunk_log2 (chunk c to wavefront c mod W), at most per_wave
+// each; each wavefront has staging segments of seg_same / seg_other slots.
+// Particles m..n-1 are carried over to the next buffer.
 struct PassPlan {
-  uint32_t n, m, per_wave, seg_same, seg_other;
+  uint32_t n, m, per_wave, seg_same, seg_other, chunk_log2;
 };
 
 struct PlanArgs {
@@ -137,7 +137,7 @@ struct PlanArgs {
   uint32_t cap_other;           // soft capacity the outputs to the other type must respect
   uint32_t max_items;           // most particles per pass
   uint32_t waves;               // wavefronts in the pass grid
-  uint32_t min_per_wave;        // fewest particles per wavefront (64: one per lane)
+  uint32_t chunk_log2;          // items per chunk dealt to a wavefront: 2^chunk_log2 (>= 64)
   uint32_t bud_same, bud_other; // per-visit output budgets per particle
   uint32_t park_slots;          // same-type staging slots per particle for parked electrons
 };

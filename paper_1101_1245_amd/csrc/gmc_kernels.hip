@@ -183,28 +183,29 @@ __device__ __forceinline__ void store_lane(const Lane& L, const DevQueue& q, uin
 struct Child { float u, v, w; uint32_t e, plo, phi; };
 
 // A wavefront's share of the pass: the work queue's items m are cut into
-// chunks of 64 and chunk c goes to wavefront c mod W, so that every
+// chunks (64 items by default) and chunk c goes to wavefront c mod W, so that every
 // wavefront gets a slice of every part of the queue -- carried-over
 // particles, survivors, the other type's secondaries, new primaries -- whose
 // lives differ widely; contiguous shares left many wavefronts idle while a
 // few finished theirs.  Loads stay coalesced within a chunk.  [next, end) is
 // the wave-uniform cursor over the wavefront's own items, numbered 0..end-1.
-struct WaveRange { uint32_t next, end, wave, waves; };
+struct WaveRange { uint32_t next, end, wave, waves, lg; };
 
 __device__ __forceinline__ WaveRange wave_range(const PassPlan& P, uint32_t wave, uint32_t waves) {
-  const uint32_t chunks = (P.m + 63u) >> 6;
-  WaveRange r{0u, 0u, wave, waves};
+  const uint32_t lg = P.chunk_log2;
+  const uint32_t chunks = (uint32_t)(((uint64_t)P.m + (1u << lg) - 1u) >> lg);
+  WaveRange r{0u, 0u, wave, waves, lg};
   if (wave < chunks) {
     const uint32_t own = (chunks - 1u - wave) / waves + 1u;
-    r.end = own << 6;
-    if ((chunks - 1u) % waves == wave) r.end -= (chunks << 6) - P.m;   // the last chunk may be partial
+    r.end = own << lg;
+    if ((chunks - 1u) % waves == wave) r.end -= (chunks << lg) - P.m;   // the last chunk may be partial
   }
   return r;
 }
 
 // Work-queue index of the wavefront's item j.
 __device__ __forceinline__ uint32_t range_item(const WaveRange& r, uint32_t j) {
-  return (((j >> 6) * r.waves + r.wave) << 6) + (j & 63u);
+  return (((j >> r.lg) * r.waves + r.wave) << r.lg) + (j & ((1u << r.lg) - 1u));
 }
 
 // Lanes without a particle take the next items of the range, in lane order,
@@ -969,16 +970,17 @@ __global__ void k_plan_pass(PlanArgs a) {
     const uint64_t lim = no < a.cap_other ? (uint64_t)(a.cap_other - no) / a.bud_other : 0u;
     if (m > lim) m = lim;
   }
-  // most items a wavefront gets (whole 64-item chunks, dealt round-robin)
-  const uint64_t chunks = (m + 63u) >> 6;
-  uint32_t q = (uint32_t)(((chunks + a.waves - 1) / a.waves) << 6);
-  if (q < a.min_per_wave) q = a.min_per_wave;
+  // most items a wavefront gets (whole chunks, dealt round-robin)
+  const uint64_t chunks = (m + (1u << a.chunk_log2) - 1u) >> a.chunk_log2;
+  uint32_t q = (uint32_t)(((chunks + a.waves - 1) / a.waves) << a.chunk_log2);
+  if (q == 0u) q = 1u << a.chunk_log2;
   PassPlan P;
   P.n = n;
   P.m = (uint32_t)m;
   *a.n_work = 0u;                 // the work buffer is consumed by this pass
   *a.n_new = n - (uint32_t)m;     // carried-over particles go to the front of the new buffer
   P.per_wave = q;
+  P.chunk_log2 = a.chunk_log2;
   P.seg_same = q * (a.bud_same + a.park_slots);
   P.seg_other = q * a.bud_other;
   *a.plan = P;
