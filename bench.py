@@ -54,8 +54,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # on a 1 GiB device copy (fetched bytes x2.0, written x1.0).  Valid only for the kernel and engine sources they
 # were measured on (their digest); per launch they are multiplied by this
 # run's work per launch.
-TRAFFIC = {"sources_sha256": "f17a200721d12c8e80dac85a7ee99a30686d4954ca62f09efbd9ce52446d1a22",
-           "k_electron_pass": 54.41}
+TRAFFIC = {"sources_sha256": "ca8c86f4ab97f7980a673d41b2dce80f9da0f29a78e6bbe7cfe48190aadb5f88",
+           "k_electron_pass": 59.76}
 MEASURED_SOURCES = ("paper_1101_1245_amd/csrc/gmc_kernels.hip",
                     "paper_1101_1245_amd/csrc/gmc_device.hpp",
                     "paper_1101_1245_amd/csrc/gmc_internal.hpp",
