@@ -26,6 +26,12 @@ photons:electrons 3:1, 1e4-1e6 histories each) on a 200x200x160 ellipsoid
 phantom at 0.25 cm; plain = 256 gmc_run_beam calls, batched = one
 gmc_run_beams call with per-beamlet doses.
 
+``--workload geometries``: the paper's timing tables on this GPU -- one 15 MeV
+beam (1e6 electrons or 4e6 photons, 10 x 10 cm) on each of the three 64^3
+geometries (water, lung box, tissue-lung-bone slabs; Table IV), and on the lung
+box the base, compaction (N = 4, 16, 64), pool, combined and default
+settings (Table VI; A_comp is the best N).
+
 Prints one JSON line with the throughput, the roofline of the dominant kernel
 (average launch duration from the HIP event pairs around every pass launch in
 the timed plain and batched legs) and, for the default workload, the oracle's
@@ -321,6 +327,112 @@ def bench_beamlets(args, G, E, I):
     return out
 
 
+def bench_geometries(args, G, E, I):
+    """The paper's timing tables on this GPU: the time of one 15 MeV beam (1e6
+    electrons or 4e6 photons) on each of the three geometries (Table IV), and on
+    the lung box the divergence-reduction settings against the base one
+    (Table VI: A = T_base / T)."""
+    geoms = (("water", I.water_15mev), ("lung_box", I.lung_box), ("tissue_lung_bone", I.tissue_lung_bone))
+    reps = max(4 * args.steps, 10)
+    ctx = G.Context(0)
+    acc_all = Acc()
+
+    def timed(w, tuning):
+        tid = ctx.load_tables(w.materials, w.physics)
+        pid = ctx.load_phantom(w.phantom)
+        shape = w.phantom.shape
+        for i in range(args.warmup):
+            ctx.run_beam(pid, tid, w.source, w.n_hist, 100 + i, shape=shape, sigma=False, tuning=tuning,
+                         out="torch")
+        acc = Acc()
+        sync()
+        t0 = time.perf_counter()
+        for k in range(reps):
+            d, _, st = ctx.run_beam(pid, tid, w.source, w.n_hist, 1000 + k, shape=shape, sigma=False,
+                                    tuning=tuning, out="torch")
+            acc.add(st)
+        sync()
+        el = (time.perf_counter() - t0) / reps
+        acc_all.merge(acc)
+        ctx.release(pid)
+        ctx.release(tid)
+        return el, d, acc
+
+    table_iv = {}
+    hist = 0
+    secs = 0.0
+    for gname, make in geoms:
+        row = {}
+        for pname, p in (("electron", I.ELECTRON), ("photon", I.PHOTON)):
+            w = make(p)
+            el, _, acc = timed(w, None)
+            row[pname + "_s"] = el
+            hist += w.n_hist
+            secs += el
+            print("Table IV %-17s %-8s %8.2f ms  (%.3e histories/s)" % (gname, pname, el * 1e3, w.n_hist / el),
+                  file=sys.stderr, flush=True)
+        table_iv[gname] = row
+
+    table_vi = {}
+    identical = True
+    settings = list(I.ABLATION_TUNINGS.items()) + [("default", None)]
+    for pname, p in (("electron", I.ELECTRON), ("photon", I.PHOTON)):
+        w = I.lung_box(p)
+        t = {}
+        ref = None
+        for tname, tuning in settings:
+            el, d, acc = timed(w, tuning)
+            t[tname] = el
+            if ref is None:
+                ref = d
+            else:
+                identical &= bool(torch_equal(ref, d))
+            print("Table VI %-8s %-15s %8.2f ms  launches %d/%d" % (pname, tname, el * 1e3, acc.n[0], acc.n[1]),
+                  file=sys.stderr, flush=True)
+        comp = min((k for k in t if k.startswith("compaction")), key=lambda k: t[k])
+        table_vi[pname] = {
+            "T_base_s": t["base"],
+            "A_comp": t["base"] / t[comp], "A_comp_setting": comp,
+            "A_pool": t["base"] / t["pool"],
+            "A_both": t["base"] / t["both"],
+            "A_default": t["base"] / t["default"],
+            "T_s": t,
+        }
+
+    out = {
+        "metric": "histories/s over the three geometries' beams; Table IV times and Table VI factors",
+        "value": hist / secs,
+        "unit": "histories/s",
+        "n_gpus": 1,
+        "steps": reps,
+        "warmup": args.warmup,
+        "ms_per_step": secs * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "15 MeV parallel beams, 10x10 cm, 64^3 at 0.5 cm: water, water with a lung box, "
+                        "tissue-lung-bone slabs; 1e6 electrons or 4e6 photons per run; ECUT 0.7 / PCUT 0.01 "
+                        "MeV; one step = the six runs (plain form, engine defaults); outputs in device memory",
+            "ablation": "lung box, tunings " + json.dumps(I.ABLATION_TUNINGS),
+        },
+        "table_iv_s": table_iv,
+        "table_vi": table_vi,
+        "ablation_doses_bit_identical": identical,
+        "roofline": roofline(acc_all, "geometries"),
+        "ledger_residual_lsb": acc_all.resid,
+    }
+    ctx.close()
+    return out
+
+
+def torch_equal(a, b):
+    import torch
+    return torch.equal(a, b)
+
+
 def bench_serve(args, G, I):
     """Served form: a Poisson stream of dose requests at 0.7 x the capacity of
     a closed-loop pilot; latency from submission to result."""
@@ -399,7 +511,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("water", "beamlets"), default="water")
+    ap.add_argument("--workload", choices=("water", "beamlets", "geometries"), default="water")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form leg")
     ap.add_argument("--serve-requests", type=int, default=200)
@@ -440,8 +552,10 @@ def main():
             out["ledger_residual_lsb"] |= acc_s.resid
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline()
-    else:
+    elif args.workload == "beamlets":
         out = bench_beamlets(args, G, E, I)
+    else:
+        out = bench_geometries(args, G, E, I)
     print(json.dumps(out), flush=True)
 
 

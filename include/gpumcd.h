@@ -130,7 +130,8 @@ typedef struct {
  * choice in gmc_run_beams.
  *   events_per_visit: events a particle may take per kernel visit before it
  *     is requeued (the N of the stream-compaction scheme, Sec. II.C.3;
- *     default 64);
+ *     1..32768, default 64; an electron's events are its steps, a photon's
+ *     its interactions, fictitious ones included);
  *   secondaries_per_visit: secondaries a particle may create per visit
  *     (2..64, default 4);
  *   chunk: primaries admitted per admission step while a particle type's

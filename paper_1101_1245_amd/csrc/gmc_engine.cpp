@@ -224,7 +224,8 @@ int ws_ensure_beams(Workspace* w, size_t n) {
 Tune resolve_tuning(const gmc_tuning* t) {
   Tune r{64, 4, 1 << 21, 0, 1 << 22, 64, 4, 4};
   if (t) {
-    if (t->events_per_visit > 0) r.events = t->events_per_visit;
+    // an electron parked at a hard event keeps its visit's event count in 16 bits
+    if (t->events_per_visit > 0) r.events = std::min(t->events_per_visit, 1 << 15);
     if (t->secondaries_per_visit >= 2) r.secondaries = std::min(t->secondaries_per_visit, 64);
     if (t->chunk > 0) r.chunk = std::min(t->chunk, 1 << 24);
     if (t->wg_size >= 64 && t->wg_size <= 1024 && t->wg_size % 64 == 0) r.block = t->wg_size;

@@ -177,6 +177,74 @@ def water_15mev(particle: int, n_hist: int = None) -> Workload:
     return Workload(name, (WATER,), ph, src, Physics(ecut=0.7, pcut=0.01), n_hist)
 
 
+def lung_box(particle: int, n_hist: int = None, lung_density: float = 0.26) -> Workload:
+    """The paper's second geometry (Sec. III.A): 64^3 water at 0.5 cm with a lung
+    box centred on the beam axis, 4.5 x 4.5 cm across; for electrons 4 cm long
+    from a depth of 3 cm, for photons 6.5 cm long from 5.5 cm.  A voxel is lung
+    when its centre lies inside the box or on its faces; the lateral faces fall
+    on voxel centres of the 0.5 cm grid, so the box is 5 cm across here.  15 MeV, 10 x 10 cm field, 1e6
+    electrons or 4e6 photons, ECUT 0.7 (kinetic), PCUT 0.01.  The lung density
+    (not stated in the paper) is 0.26 g/cm^3, as in the slab phantom."""
+    ph = homogeneous(64, 0.5, 0)
+    z0, length = (3.0, 4.0) if particle == ELECTRON else (5.5, 6.5)
+    ex, ey, _ = ph.extent
+    nz, ny, nx = ph.shape
+    c = (np.arange(64) + 0.5) * 0.5
+    inx = np.abs(c - ex / 2.0) <= 2.25
+    iny = np.abs(c - ey / 2.0) <= 2.25
+    inz = (c >= z0) & (c < z0 + length)
+    box = inz[:, None, None] & iny[None, :, None] & inx[None, None, :]
+    ph.rho[box] = lung_density
+    ph.mat[box] = 1
+    src = centred(ph, Source(particle, MONO, 15.0, wx=10.0, wy=10.0))
+    if n_hist is None:
+        n_hist = 1_000_000 if particle == ELECTRON else 4_000_000
+    name = "%s_15MeV_lung_box_64^3" % ("electron" if particle == ELECTRON else "photon")
+    return Workload(name, (WATER, LUNG), ph, src, Physics(ecut=0.7, pcut=0.01), n_hist)
+
+
+def tissue_lung_bone(particle: int, n_hist: int = None, tissue_density: float = 1.0,
+                     lung_density: float = 0.26, bone_density: float = 1.85) -> Workload:
+    """The paper's third geometry (Sec. III.A): 64^3 slabs at 0.5 cm along the
+    beam, in the order the text gives (soft tissue, lung, bone, soft tissue):
+    for electrons 2 cm of tissue, 2 cm of lung and 2 cm of bone; for photons 3,
+    2 and 7 cm; soft tissue beyond.  15 MeV, 10 x 10 cm field, 1e6 electrons or
+    4e6 photons, ECUT 0.7 (kinetic), PCUT 0.01.  The densities are not stated:
+    soft tissue 1.0, lung 0.26 and bone 1.85 g/cm^3, as in the slab phantom."""
+    t, l, b = (2.0, 2.0, 2.0) if particle == ELECTRON else (3.0, 2.0, 7.0)
+    ph = z_slabs(64, 0.5, [(t, 0, tissue_density), (t + l, 1, lung_density), (t + l + b, 2, bone_density),
+                           (32.0, 0, tissue_density)])
+    src = centred(ph, Source(particle, MONO, 15.0, wx=10.0, wy=10.0))
+    if n_hist is None:
+        n_hist = 1_000_000 if particle == ELECTRON else 4_000_000
+    name = "%s_15MeV_tissue_lung_bone_64^3" % ("electron" if particle == ELECTRON else "photon")
+    return Workload(name, (SOFT_TISSUE, LUNG, BONE), ph, src, Physics(ecut=0.7, pcut=0.01), n_hist)
+
+
+# The paper's divergence-reduction study (Sec. II.C.3, Table VI) as tunings of
+# this engine.  "base": a particle stays on its lane until it ends and a
+# wavefront takes new particles only when all 64 lanes are idle;
+# "compaction_nN": particles are requeued after N events per visit (an
+# electron's events are its steps, a photon's its interactions; the paper does
+# not state its N); "pool": every lane takes the next particle as soon as it is
+# idle; "both": requeue cadence 64 and refills at 4 idle lanes (the engine's
+# defaults).  All of them allow 16 secondaries per visit (a particle that
+# creates more is requeued); hard-event and absorption parking are part of
+# every pass.
+def _ablation(events: int, refill: int) -> dict:
+    return {"events_per_visit": events, "secondaries_per_visit": 16, "refill_lanes": refill}
+
+
+ABLATION_TUNINGS = {
+    "base": _ablation(1 << 15, 64),
+    "compaction_n4": _ablation(4, 64),
+    "compaction_n16": _ablation(16, 64),
+    "compaction_n64": _ablation(64, 64),
+    "pool": _ablation(1 << 15, 1),
+    "both": _ablation(64, 4),
+}
+
+
 def slab_6mev(n_hist: int = 40_000_000) -> Workload:
     """6 MeV photons, 10 x 10 cm, 128^3 at 0.25 cm: water 0-3 cm, bone (1.85) 3-5,
     lung (0.26) 5-12, water to the end."""

@@ -79,3 +79,50 @@ def test_poisson_arrivals():
     gaps = np.diff(t)
     assert abs(gaps.mean() - 1 / 50.0) < 4 * (1 / 50.0) / np.sqrt(gaps.size)
     assert abs(gaps.std() / gaps.mean() - 1.0) < 0.05      # exponential gaps: coefficient of variation 1
+
+
+def test_lung_box_geometry():
+    zc = (np.arange(64) + 0.5) * 0.5
+    for p, z0, z1, nz in ((I.ELECTRON, 3.0, 7.0, 8), (I.PHOTON, 5.5, 12.0, 13)):
+        w = I.lung_box(p)
+        ph = w.phantom
+        assert ph.shape == (64, 64, 64) and ph.voxel == (0.5, 0.5, 0.5)
+        lung = ph.mat == 1
+        assert np.array_equal(lung, ph.rho < 0.5)
+        assert np.all(ph.rho[lung] == np.float32(0.26)) and np.all(ph.rho[~lung] == 1.0)
+        kz, ky, kx = np.nonzero(lung)
+        # lung voxels form one box: nz voxels deep, 10 x 10 across, centred on the beam axis
+        assert lung.sum() == nz * 100
+        assert zc[kz].min() >= z0 and zc[kz].max() < z1 and len(set(kz)) == nz
+        assert np.array_equal(lung, lung[:, ::-1, :]) and np.array_equal(lung, lung[:, :, ::-1])
+        assert np.abs(zc[kx] - 16.0).max() <= 2.25 and np.abs(zc[ky] - 16.0).max() <= 2.25
+        s = w.source
+        assert s.particle == p and s.e == 15.0 and (s.cx, s.cy, s.wx, s.wy) == (16.0, 16.0, 10.0, 10.0)
+        assert w.n_hist == (1_000_000 if p == I.ELECTRON else 4_000_000)
+        assert w.physics.ecut == 0.7 and w.physics.pcut == 0.01
+
+
+def test_tissue_lung_bone_geometry():
+    zc = (np.arange(64) + 0.5) * 0.5
+    for p, edges in ((I.ELECTRON, (2.0, 4.0, 6.0)), (I.PHOTON, (3.0, 5.0, 12.0))):
+        w = I.tissue_lung_bone(p)
+        ph = w.phantom
+        assert [m.name for m in w.materials] == ["soft_tissue", "lung", "bone"]
+        # laterally uniform slabs
+        assert np.all(ph.rho == ph.rho[:, :1, :1]) and np.all(ph.mat == ph.mat[:, :1, :1])
+        want = np.select([zc < edges[0], zc < edges[1], zc < edges[2]], [0, 1, 2], 0)
+        assert np.array_equal(ph.mat[:, 0, 0], want)
+        assert np.allclose(ph.rho[:, 0, 0], np.array([1.0, 0.26, 1.85])[want])
+
+
+def test_divergence_settings_are_valid_tunings():
+    from paper_1101_1245_amd.gpumcd import gmc_tuning
+    fields = {f for f, _ in gmc_tuning._fields_}
+    assert set(I.ABLATION_TUNINGS) == {"base", "compaction_n4", "compaction_n16", "compaction_n64", "pool", "both"}
+    for t in I.ABLATION_TUNINGS.values():
+        assert set(t) <= fields and 1 <= t["events_per_visit"] <= 1 << 15 and 1 <= t["refill_lanes"] <= 64
+    # base: no requeue cadence and whole-wavefront refills; pool: per-lane refills
+    assert I.ABLATION_TUNINGS["base"]["refill_lanes"] == 64 and I.ABLATION_TUNINGS["pool"]["refill_lanes"] == 1
+    for n in (4, 16, 64):
+        t = I.ABLATION_TUNINGS["compaction_n%d" % n]
+        assert t["events_per_visit"] == n and t["refill_lanes"] == 64
