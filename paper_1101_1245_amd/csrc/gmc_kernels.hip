@@ -443,7 +443,12 @@ __global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
 
   for (;;) {
     refill(L, have, events, pushes, range, a, lbeams, nvox);
-    if (!__any(have)) break;
+    // a refill may bring only zero-energy entries: the wavefront goes on
+    // until its range is done
+    if (!__any(have)) {
+      if (range.next >= range.end) break;
+      continue;
+    }
     int nchild = 0;
     Child c0, c1;
     bool surv = false, park = false;
@@ -692,7 +697,10 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
         npark -= take;
       }
     }
-    if (!__any(have || hd)) break;
+    if (!__any(have || hd)) {
+      if (range.next >= range.end) break;
+      continue;
+    }
     if (__any(hd)) {
       int ctype = -1;
       Child c0;

@@ -247,3 +247,28 @@ def test_autotuner_choice_is_cached_and_result_invariant(ctx, G, small_job, load
     pb2, ps2, d2, s2, _ = ctx.run_beams(pid, tid, j.sources, counts, j.seed, shape=j.phantom.shape, per_beam=True,
                                         per_beam_sigma=True, tuning={"chunk": 4099, "refill_lanes": 3})
     assert np.array_equal(pb, pb2) and np.array_equal(ps, ps2) and np.array_equal(d, d2) and np.array_equal(s, s2)
+
+
+def test_beam_outside_the_phantom_ahead_of_another(ctx):
+    """Primaries that start outside the phantom are stored with zero energy and
+    skipped.  A whole beam of them admitted ahead of another beam's primaries
+    fills many chunks with nothing to transport; every wavefront must go on to
+    the next chunk rather than stop, so that the other beam is transported in
+    full (closed ledger, dose bit-identical to its plain run)."""
+    from dataclasses import replace
+    w = I.water_15mev(I.ELECTRON)
+    tid = ctx.load_tables(w.materials, w.physics)
+    pid = ctx.load_phantom(w.phantom)
+    try:
+        outside = replace(w.source, cx=-40.0, beam_id=0)
+        inside = replace(w.source, beam_id=1)
+        pb, ps, d, s, st = ctx.run_beams(pid, tid, [outside, inside], [400_000, 600_000], 3,
+                                         shape=w.phantom.shape, per_beam=True, per_beam_sigma=True)
+        assert st["ledger_residual_lsb"] == 0 and st["n_majorant_violations"] == 0
+        assert not pb[0].any()
+        d1, s1, st1 = ctx.run_beam(pid, tid, inside, 600_000, 3, shape=w.phantom.shape)
+        assert np.array_equal(pb[1], d1) and np.array_equal(ps[1], s1)
+        assert st["n_e_steps"] == st1["n_e_steps"] and st["n_photon_events"] == st1["n_photon_events"]
+    finally:
+        ctx.release(pid)
+        ctx.release(tid)
