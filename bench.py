@@ -32,6 +32,10 @@ geometries (water, lung box, tissue-lung-bone slabs; Table IV), and on the lung
 box the base, compaction (N = 4, 16, 64), pool, combined and default
 settings (Table VI; A_comp is the best N).
 
+``--workload regroup``: energy regrouping before every pass against none, in
+the batched form (monoenergetic water beams, triangular-spectrum beams,
+beamlets).
+
 Prints one JSON line with the throughput, the roofline of the dominant kernel
 (average launch duration from the HIP event pairs around every pass launch in
 the timed plain and batched legs) and, for the default workload, the oracle's
@@ -428,6 +432,90 @@ def bench_geometries(args, G, E, I):
     return out
 
 
+def bench_regroup(args, G, E, I):
+    """Energy regrouping before every pass (the grouping of similar energies
+    that Sec. IV.B proposes for polyenergetic beams) against none, in the
+    batched form with one fixed tuning otherwise: the water beams at the
+    histories of 1% uncertainty (monoenergetic), the same phantom with
+    triangular 2-10-18 MeV spectra, and the 256 beamlets (1-20 MeV)."""
+    import torch
+    we, wg = I.water_15mev(I.ELECTRON), I.water_15mev(I.PHOTON)
+    tri = [I.centred(we.phantom, I.Source(p, I.TRIANGULAR, 10.0, e_lo=2.0, e_mode=10.0, e_hi=18.0,
+                                          wx=10.0, wy=10.0, beam_id=b)) for b, p in enumerate((I.ELECTRON, I.PHOTON))]
+    j = I.beamlet_job()
+    cases = (("water 15 MeV e + photons", we, [we.source, wg.source], [5_248_287, 64_951_300], False),
+             ("water 2-10-18 MeV e + photons", we, tri, [5_000_000, 50_000_000], False),
+             ("256 beamlets 1-20 MeV", j, j.sources, list(j.counts), True))
+    reps = max(args.steps, 2)
+    ctx = G.Context(0)
+    rows = {}
+    acc_all = Acc()
+    identical = True
+    for name, w, srcs, counts, per_beam in cases:
+        tid = ctx.load_tables(w.materials, w.physics)
+        pid = ctx.load_phantom(w.phantom)
+        shape = w.phantom.shape
+        row = {}
+        ref = None
+        for sort in (0, 1):
+            tuning = {"chunk": 1 << 22, "pass_items": 1 << 23, "energy_sort": sort}
+            for i in range(args.warmup):
+                ctx.run_beams(pid, tid, srcs, counts, 100 + i, shape=shape, per_beam=per_beam, tuning=tuning,
+                              out="torch")
+            acc = Acc()
+            sync()
+            t0 = time.perf_counter()
+            for k in range(reps):
+                r = ctx.run_beams(pid, tid, srcs, counts, 1000 + k, shape=shape, per_beam=per_beam, tuning=tuning,
+                                  out="torch")
+                acc.add(r[4])
+            sync()
+            el = (time.perf_counter() - t0) / reps
+            acc_all.merge(acc)
+            if ref is None:
+                ref = r[2]
+            else:
+                identical &= bool(torch_equal(ref, r[2]))
+            key = "sorted" if sort else "unsorted"
+            row[key] = {"ms_per_step": el * 1e3, "electron_pass_ms": acc.t[1] / reps * 1e3,
+                        "photon_pass_ms": acc.t[0] / reps * 1e3}
+            print("%-30s %-8s %7.1f ms/step  e-pass %6.1f ms  photon pass %6.1f ms" %
+                  (name, key, el * 1e3, acc.t[1] / reps * 1e3, acc.t[0] / reps * 1e3), file=sys.stderr, flush=True)
+            del r
+            torch.cuda.empty_cache()
+        row["speedup"] = row["unsorted"]["ms_per_step"] / row["sorted"]["ms_per_step"]
+        rows[name] = row
+        ctx.release(pid)
+        ctx.release(tid)
+    total = sum(int(sum(c[3])) for c in cases)
+    t_sorted = sum(r["sorted"]["ms_per_step"] for r in rows.values())
+    out = {
+        "metric": "histories/s with energy regrouping before every pass (vs without)",
+        "value": total / (t_sorted * 1e-3),
+        "unit": "histories/s",
+        "n_gpus": 1,
+        "steps": reps,
+        "warmup": args.warmup,
+        "ms_per_step": t_sorted,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "batched form, chunk 2^22, pass 2^23: 15 MeV e (5.2e6) + photons (6.5e7) on 64^3 water; "
+                        "triangular 2-10-18 MeV e (5e6) + photons (5e7) on 64^3 water; 256 beamlets 1-20 MeV on a "
+                        "200x200x160 ellipsoid phantom; one step = the three jobs with regrouping",
+        },
+        "cases": rows,
+        "doses_bit_identical": identical,
+        "roofline": roofline(acc_all, "regroup"),
+        "ledger_residual_lsb": acc_all.resid,
+    }
+    ctx.close()
+    return out
+
+
 def torch_equal(a, b):
     import torch
     return torch.equal(a, b)
@@ -511,7 +599,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("water", "beamlets", "geometries"), default="water")
+    ap.add_argument("--workload", choices=("water", "beamlets", "geometries", "regroup"), default="water")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form leg")
     ap.add_argument("--serve-requests", type=int, default=200)
@@ -554,8 +642,10 @@ def main():
             out["cpu_baseline"] = cpu_baseline()
     elif args.workload == "beamlets":
         out = bench_beamlets(args, G, E, I)
-    else:
+    elif args.workload == "geometries":
         out = bench_geometries(args, G, E, I)
+    else:
+        out = bench_regroup(args, G, E, I)
     print(json.dumps(out), flush=True)
 
 

@@ -150,11 +150,17 @@ typedef struct {
  *     2 x rounds_per_check rounds and the host reads the particle counts
  *     once per replay (1..1024, default 4);
  *   refill_lanes: idle lanes of a wavefront (1..64, default 4) before they
- *     take new particles from the wavefront's range.
+ *     take new particles from the wavefront's range;
+ *   energy_sort: > 0 regroups every pass's particles by energy first
+ *     (highest first; a counting sort on log-energy buckets into a spare
+ *     buffer of pass_items particles), the grouping of similar energies that
+ *     Sec. IV.B proposes for polyenergetic beams (default 0: off: on MI355X
+ *     the sort costs more than the passes gain).
  * No tuning changes any result: the dose is bit-identical for every choice. */
 typedef struct {
   int events_per_visit, secondaries_per_visit, chunk, wg_size;
   int pass_items, wave_items, rounds_per_check, refill_lanes;
+  int energy_sort;
 } gmc_tuning;
 
 /* Transport n_histories histories of one beam (the plain form: one beam per

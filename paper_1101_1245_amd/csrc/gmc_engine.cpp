@@ -58,6 +58,19 @@ int ensure_queues(Workspace* w, uint32_t cap) {
   return GMC_OK;
 }
 
+// The regrouping buffer (one pass's items) and the sort's counters, which
+// start at zero.
+int ensure_sorted(Workspace* w, uint32_t cap) {
+  if (!w->d_sort) WS_TRY(w, hipMalloc(&w->d_sort, 2 * kSortBuckets * sizeof(uint32_t)));
+  WS_TRY(w, hipMemsetAsync(w->d_sort, 0, 2 * kSortBuckets * sizeof(uint32_t), w->stream));
+  if (w->sorted_cap >= cap) return GMC_OK;
+  free_queue(w->sorted);
+  w->sorted_cap = 0;
+  WS_TRY(w, alloc_queue(w->sorted, cap, Q_FIELDS));
+  w->sorted_cap = cap;
+  return GMC_OK;
+}
+
 int ensure_staging(Workspace* w, uint32_t slots) {
   if (w->stg_cap >= slots) return GMC_OK;
   if ((uint64_t)slots * kStgFields >= (1ull << 32)) return wfail(w, GMC_EOVERFLOW, "staging queue too large");
@@ -152,8 +165,9 @@ void ws_free(Workspace* w) {
   for (auto& t : w->qbuf)
     for (auto& b : t) free_queue(b);
   for (auto& b : w->stg) free_queue(b);
-  w->cap = w->stg_cap = 0;
-  for (void* p : {(void*)w->d_ctl, (void*)w->d_ctr, (void*)w->d_beams,
+  free_queue(w->sorted);
+  w->cap = w->stg_cap = w->sorted_cap = 0;
+  for (void* p : {(void*)w->d_ctl, (void*)w->d_ctr, (void*)w->d_beams, (void*)w->d_sort,
                   (void*)w->d_sources, (void*)w->d_start, (void*)w->d_beam_of, (void*)w->d_nk})
     if (p) (void)hipFree(p);
   for (void* p : {(void*)w->h_ctl, (void*)w->h_ctr, (void*)w->h_nk})
@@ -164,6 +178,7 @@ void ws_free(Workspace* w) {
   w->d_beams = nullptr;
   w->d_sources = nullptr;
   w->d_start = w->d_beam_of = nullptr;
+  w->d_sort = nullptr;
   w->d_nk = w->h_nk = nullptr;
   w->beams_cap = 0;
   for (hipEvent_t e : {w->ev0, w->ev1, w->kev0, w->kev1, w->ev_ctl})
@@ -177,7 +192,7 @@ void ws_free(Workspace* w) {
 }
 
 size_t ws_device_bytes(const Workspace& w) {
-  return sizeof(uint32_t) * ((size_t)Q_FIELDS * 4ull * w.cap + (size_t)kStgFields * 2ull * w.stg_cap) +
+  return sizeof(uint32_t) * ((size_t)Q_FIELDS * (4ull * w.cap + w.sorted_cap) + (size_t)kStgFields * 2ull * w.stg_cap) +
          w.tally_elems * sizeof(unsigned long long) + 2 * w.out_elems * sizeof(double) +
          w.beams_cap * (sizeof(DevBeam) + sizeof(DevSource) + 4 * sizeof(uint32_t));
 }
@@ -222,7 +237,7 @@ int ws_ensure_beams(Workspace* w, size_t n) {
 
 // ---------------------------------------------------------------- settings
 Tune resolve_tuning(const gmc_tuning* t) {
-  Tune r{64, 4, 1 << 21, 0, 1 << 22, 64, 4, 4};
+  Tune r{64, 4, 1 << 21, 0, 1 << 22, 64, 4, 4, 0};
   if (t) {
     // an electron parked at a hard event keeps its visit's event count in 16 bits
     if (t->events_per_visit > 0) r.events = std::min(t->events_per_visit, 1 << 15);
@@ -238,6 +253,7 @@ Tune resolve_tuning(const gmc_tuning* t) {
     }
     if (t->rounds_per_check > 0) r.rounds = std::min(t->rounds_per_check, 1024);
     if (t->refill_lanes > 0) r.refill = std::min(t->refill_lanes, 64);
+    if (t->energy_sort > 0) r.sort = 1;
   }
   return r;
 }
@@ -253,6 +269,7 @@ gmc_tuning default_tuning() {
   t.wave_items = d.wave_items;
   t.rounds_per_check = d.rounds;
   t.refill_lanes = d.refill;
+  t.energy_sort = d.sort;
   return t;
 }
 
@@ -476,6 +493,19 @@ int enqueue_pass(Engine& E, int type, hipEvent_t t0, hipEvent_t t1, bool capturi
   WS_TRY(w, launch_plan_pass(pa, w->stream));
   PassArgs a = E.proto;
   a.work = w->qbuf[type][wi].q;
+  a.carry_src = a.work;
+  if (E.tu.sort) {
+    // the pass's items, regrouped by energy into the spare buffer; the
+    // carry-over stays where it is
+    SortArgs sa;
+    sa.src = a.work;
+    sa.dst = w->sorted.q;
+    sa.n = &w->d_ctl->plan[type].m;
+    sa.hist = w->d_sort;
+    sa.cursor = w->d_sort + kSortBuckets;
+    WS_TRY(w, launch_sort(sa, kSortGrid, w->stream));
+    a.work = w->sorted.q;
+  }
   a.plan = w->d_ctl->plan + type;
   a.stg_same = w->stg[0].q;
   a.stg_other = w->stg[1].q;
@@ -562,6 +592,10 @@ int engine_setup(Workspace* w, Engine& E, const Job& J, const Tune& tu) {
   w->cap_soft = soft;
   rc = ensure_staging(w, stg);
   if (rc) return rc;
+  if (tu.sort) {
+    rc = ensure_sorted(w, (uint32_t)tu.pass_items);   // a pass's items
+    if (rc) return rc;
+  }
   for (int t = 0; t < 2; ++t) {
     E.bud_same[t] = t == 0 ? 1u : (uint32_t)tu.secondaries + 1u;
     E.bud_other[t] = (uint32_t)tu.secondaries;

@@ -50,6 +50,7 @@ struct QueueBuf {
 constexpr uint32_t kMinSoftCap = 1u << 23;
 constexpr uint32_t kMaxSoftCap = 1u << 25;
 constexpr uint32_t kMaxWaves = 1u << 15;
+constexpr int kSortGrid = 2048;              // workgroups of the regrouping kernels
 constexpr double kAutotuneBudgetS = 10.0;   // default wall-clock budget of one tuning
 constexpr double kTuneTrials = 24.0;        // about how many candidates one tuning runs
 constexpr uint64_t kTuneMinSample = 1ull << 25;   // 8 chunks of the largest candidate
@@ -85,6 +86,9 @@ struct Workspace {
   int acc[2] = {0, 0};          // buffer of each type that accumulates
   QueueBuf stg[2];              // staging: [0] same type, [1] other type
   uint32_t stg_cap = 0;
+  QueueBuf sorted;              // a work buffer regrouped by energy (when sorting)
+  uint32_t sorted_cap = 0;
+  uint32_t* d_sort = nullptr;   // [2][kSortBuckets]: bucket counts, bucket cursors
   Control* d_ctl = nullptr;
   Control* h_ctl = nullptr;     // pinned host copy
   unsigned long long* d_ctr = nullptr;   // [C_COUNT][kCtrSlots]
@@ -133,6 +137,7 @@ int ws_ensure_beams(Workspace* w, size_t n);
 // Engine knobs (gmc_tuning with defaults filled in).
 struct Tune {
   int events, secondaries, chunk, block, pass_items, wave_items, rounds, refill;
+  int sort;   // 1: energy regrouping before every pass
 };
 Tune resolve_tuning(const gmc_tuning* t);
 gmc_tuning default_tuning();

@@ -156,7 +156,8 @@ struct PassArgs {
   DevPhantom ph;
   DevTables tab;
   DevCuts cut;
-  DevQueue work;
+  DevQueue work;           // items 0..m-1 of the pass
+  DevQueue carry_src;      // items m..n-1, carried over (the work buffer, or the unsorted one)
   const PassPlan* plan;
   DevQueue stg_same;       // survivors and same-type secondaries
   DevQueue stg_other;      // other-type secondaries
@@ -204,6 +205,21 @@ struct AdmitArgs {
   uint32_t nvox;
 };
 
+// Energy regrouping of a work queue before its pass (the grouping of
+// particles of similar energy that Sec. IV.B proposes against the divergence
+// of polyenergetic beams): a counting sort on log-energy buckets, four per
+// octave of the 2^-27 MeV units, highest energy first, so that the lanes of a
+// chunk hold particles of similar energy and every wavefront takes its
+// longest-lived particles first.  Order within a bucket is whatever the
+// atomics give: no result depends on queue order.
+constexpr int kSortBuckets = 128;
+struct SortArgs {
+  DevQueue src, dst;            // dst: room for n entries
+  const uint32_t* n;            // entries to regroup: the first n of src (the pass's m)
+  uint32_t* hist;               // [kSortBuckets] counts; zero before and after a sort
+  uint32_t* cursor;             // [kSortBuckets] next free slot of each bucket in dst
+};
+
 struct FinalizeArgs {
   const unsigned long long* tally;  // [nsum][K][nvox] (the nsum tallies are added)
   uint32_t nsum;
@@ -232,6 +248,7 @@ hipError_t launch_table_eval(const DevTables& t, int which, int mat, const float
                              hipStream_t s);
 hipError_t launch_first_events(const PassArgs& a, const DevSource& src, uint32_t h0, uint32_t count, float* xyz,
                                uint32_t* nused, hipStream_t s);
+hipError_t launch_sort(const SortArgs& a, int grid, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
 int max_resident_blocks(int kernel, int block, size_t lds);
 

@@ -323,7 +323,7 @@ __device__ __forceinline__ void append_outputs(const PassArgs& a, const PassPlan
   __shared__ uint32_t s_base[2];
   const uint32_t carry = P.n - P.m;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < carry; i += gridDim.x * blockDim.x)
-    copy_entry(a.dst_same, i, a.work, P.m + i, a.ctr);
+    copy_entry(a.dst_same, i, a.carry_src, P.m + i, a.ctr);
   const uint32_t wl = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const uint32_t n0 = min(gs.used, gs.cap), n1 = min(go.used, go.cap);
   if (lane_id() == 0) {
@@ -994,6 +994,70 @@ __global__ void k_plan_pass(PlanArgs a) {
   *a.plan = P;
 }
 
+// ------------------------------------------------------ energy regrouping
+// Sort key: bucket 4 log2(e) + the two bits below the leading one, reversed
+// so that the highest energies come first; zero-energy entries go last.
+__device__ __forceinline__ uint32_t sort_key(uint32_t e) {
+  if (e == 0u) return kSortBuckets - 1u;
+  const uint32_t lg = 31u - (uint32_t)__clz(e);
+  const uint32_t sub = lg >= 2u ? (e >> (lg - 2u)) & 3u : (e << (2u - lg)) & 3u;
+  return (uint32_t)(kSortBuckets - 1) - min((lg << 2) | sub, (uint32_t)(kSortBuckets - 2));
+}
+
+// Bucket counts of all entries (grid-stride, one LDS histogram per workgroup).
+__global__ void __launch_bounds__(256) k_sort_count(SortArgs a) {
+  __shared__ uint32_t h[kSortBuckets];
+  for (int b = threadIdx.x; b < kSortBuckets; b += blockDim.x) h[b] = 0u;
+  __syncthreads();
+  const uint32_t n = *a.n;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    atomicAdd(&h[sort_key(qf(a.src, Q_E, i))], 1u);
+  __syncthreads();
+  for (int b = threadIdx.x; b < kSortBuckets; b += blockDim.x)
+    if (h[b]) atomicAdd(a.hist + b, h[b]);
+}
+
+// Bucket starts (exclusive prefix sum in key order); the counts are cleared
+// for the next sort.  One workgroup of kSortBuckets threads.
+__global__ void __launch_bounds__(kSortBuckets) k_sort_offsets(SortArgs a) {
+  __shared__ uint32_t c[kSortBuckets];
+  const int b = threadIdx.x;
+  c[b] = a.hist[b];
+  __syncthreads();
+  uint32_t start = 0u;
+  for (int j = 0; j < b; ++j) start += c[j];
+  a.cursor[b] = start;
+  a.hist[b] = 0u;
+}
+
+// Every entry to its bucket: each workgroup counts a tile of entries in LDS,
+// reserves room per bucket with one atomic each, and writes its entries
+// there (the queue count is unchanged).
+constexpr uint32_t kSortTile = 2048;
+__global__ void __launch_bounds__(256) k_sort_scatter(SortArgs a) {
+  __shared__ uint32_t h[kSortBuckets];
+  __shared__ uint32_t base[kSortBuckets];
+  const uint32_t n = *a.n;
+  for (uint32_t t0 = blockIdx.x * kSortTile; t0 < n; t0 += gridDim.x * kSortTile) {
+    const uint32_t t1 = min(t0 + kSortTile, n);
+    for (int b = threadIdx.x; b < kSortBuckets; b += blockDim.x) h[b] = 0u;
+    __syncthreads();
+    for (uint32_t i = t0 + threadIdx.x; i < t1; i += blockDim.x) atomicAdd(&h[sort_key(qf(a.src, Q_E, i))], 1u);
+    __syncthreads();
+    for (int b = threadIdx.x; b < kSortBuckets; b += blockDim.x) {
+      base[b] = h[b] ? atomicAdd(a.cursor + b, h[b]) : 0u;
+      h[b] = 0u;
+    }
+    __syncthreads();
+    for (uint32_t i = t0 + threadIdx.x; i < t1; i += blockDim.x) {
+      const uint32_t key = sort_key(qf(a.src, Q_E, i));
+      const uint32_t slot = base[key] + atomicAdd(&h[key], 1u);
+      for (int f = 0; f < Q_FIELDS; ++f) qf(a.dst, f, slot) = qf(a.src, f, i);
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 // Tables, majorant, (screening table,) beam table.
 size_t photon_lds_bytes(int n_mat) {
@@ -1017,6 +1081,13 @@ static hipError_t lds_limits() {
     return r;
   }();
   return e;
+}
+
+hipError_t launch_sort(const SortArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_sort_count, dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_sort_offsets, dim3(1), dim3(kSortBuckets), 0, s, a);
+  hipLaunchKernelGGL(k_sort_scatter, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_plan_pass(const PlanArgs& a, hipStream_t s) {

@@ -131,6 +131,7 @@ def test_tuning_replay_and_output_kind_invariance(ctx, small_job, loaded, batche
         {"chunk": 3001, "pass_items": 4096, "wave_items": 256, "rounds_per_check": 1, "events_per_visit": 5,
          "secondaries_per_visit": 2, "wg_size": 128, "refill_lanes": 64},
         {"rounds_per_check": 9, "chunk": 20000, "wave_items": 64, "refill_lanes": 17},
+        {"energy_sort": 1, "chunk": 5000, "pass_items": 20000},
     ]
     for tu in tunings:
         pb2, ps2, d2, s2, st2 = ctx.run_beams(pid, tid, j.sources, j.counts, j.seed, shape=j.phantom.shape,
