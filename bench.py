@@ -64,8 +64,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # on a 1 GiB device copy (fetched bytes x2.0, written x1.0).  Valid only for the kernel and engine sources they
 # were measured on (their digest); per launch they are multiplied by this
 # run's work per launch.
-TRAFFIC = {"sources_sha256": "ca8c86f4ab97f7980a673d41b2dce80f9da0f29a78e6bbe7cfe48190aadb5f88",
-           "k_electron_pass": 59.76}
+TRAFFIC = {"sources_sha256": "6b1b0f0693456b490e4f6e3b12d7816451c7a58071a3fbd97e29bb39ced3a95a",
+           "k_electron_pass": 58.93}
 MEASURED_SOURCES = ("paper_1101_1245_amd/csrc/gmc_kernels.hip",
                     "paper_1101_1245_amd/csrc/gmc_device.hpp",
                     "paper_1101_1245_amd/csrc/gmc_internal.hpp",
@@ -88,7 +88,7 @@ def cpu_baseline():
     from paper_1101_1245_amd import inputs as I
     we = I.water_15mev(I.ELECTRON)
     wg = I.water_15mev(I.PHOTON)
-    ne, ng = 20000, 80000
+    ne, ng = 70000, 280000
     t0 = time.perf_counter()
     O.run(we.materials, we.phantom, we.source, we.physics, we.seed, ne, batches=False)
     t1 = time.perf_counter()
