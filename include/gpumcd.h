@@ -135,14 +135,14 @@ typedef struct {
  *   secondaries_per_visit: secondaries a particle may create per visit
  *     (2..64, default 4);
  *   chunk: primaries admitted per admission step while a particle type's
- *     array holds fewer (default 2^21, at most 2^24);
+ *     array holds fewer (default 2^22, at most 2^24);
  *   wg_size: threads per workgroup of the pass kernels (64..1024, multiple
  *     of 64; default: per pass kernel, the smallest of 256, 512 and 1024 that
  *     keeps the most wavefronts resident -- each workgroup stages its own
  *     copy of the tables in LDS, so with several materials larger workgroups
  *     keep more wavefronts per compute unit);
  *   pass_items: most particles one pass launch transports (1024..2^23,
- *     default 2^22); the rest is carried to the next pass;
+ *     default 2^23); the rest is carried to the next pass;
  *   wave_items: particles per chunk when a pass deals its particles to the
  *     wavefronts round-robin (64..1024, rounded down to a power of two;
  *     default 64);

@@ -237,7 +237,7 @@ int ws_ensure_beams(Workspace* w, size_t n) {
 
 // ---------------------------------------------------------------- settings
 Tune resolve_tuning(const gmc_tuning* t) {
-  Tune r{64, 4, 1 << 21, 0, 1 << 22, 64, 4, 4, 0};
+  Tune r{64, 4, 1 << 22, 0, 1 << 23, 64, 4, 4, 0};
   if (t) {
     // an electron parked at a hard event keeps its visit's event count in 16 bits
     if (t->events_per_visit > 0) r.events = std::min(t->events_per_visit, 1 << 15);
