@@ -863,10 +863,29 @@ static void ctx_free(ctx_t* c) {
   free(c->mats); free(c->tmp); free(c->touched); free(c->stack);
 }
 
+/* Tabulated spectrum: a histogram (weight w_j spread evenly over
+ * [e_j, e_j+1)), sampled by inverting its piecewise-linear CDF with one
+ * uniform.  C_j = (w_0 + ... + w_j-1) / W, summed left to right, C_n = 1;
+ * u falls in the bin with C_j <= u < C_j+1. */
+static double sample_tabulated(const orc_source* src, double u) {
+  const int n = src->tab_n;
+  double total = 0.0;
+  for (int j = 0; j < n; ++j) total += src->tab_w[j];
+  double s = 0.0;   /* w_0 + ... + w_j-1 */
+  for (int j = 0; j < n; ++j) {
+    const double c0 = s / total;
+    s += src->tab_w[j];
+    const double c1 = (j == n - 1) ? 1.0 : s / total;
+    if (u < c1 && c1 > c0)
+      return src->tab_e[j] + (u - c0) / (c1 - c0) * (src->tab_e[j + 1] - src->tab_e[j]);
+  }
+  return src->tab_e[n];
+}
+
 /* Source (Sec. II.C.2, initParticle): a parallel beam along +z entering at
- * z = 0, position uniform over the field rectangle, energy monoenergetic or
- * triangular (inverse CDF).  Consumes the first block (four words) of the
- * history's root stream; transport continues from word 4. */
+ * z = 0, position uniform over the field rectangle, energy monoenergetic,
+ * triangular (inverse CDF) or tabulated.  Consumes the first block (four
+ * words) of the history's root stream; transport continues from word 4. */
 static void sample_source(const orc_source* src, const uint32_t key[2], uint32_t hist, part_t* p) {
   stream_t s; stream_init(&s, key, hist, 0, 0);
   double u0 = next_u(&s), u1 = next_u(&s), u2 = next_u(&s);
@@ -880,6 +899,8 @@ static void sample_source(const orc_source* src, const uint32_t key[2], uint32_t
     double a = src->e_lo, m = src->e_mode, b = src->e_hi;
     double fc = (m - a) / (b - a);
     e = (u2 < fc) ? a + sqrt(u2 * (b - a) * (m - a)) : b - sqrt((1.0 - u2) * (b - a) * (b - m));
+  } else if (src->spectrum == 2) {
+    e = sample_tabulated(src, u2);
   }
   p->e = e;
   p->path = 0;
@@ -893,7 +914,29 @@ static int check_source(const orc_source* src) {
   if (src->spectrum == 1)
     return (src->e_lo > 0 && src->e_lo <= src->e_mode && src->e_mode <= src->e_hi &&
             src->e_lo < src->e_hi && src->e_hi <= 30.0) ? 0 : -1;
+  if (src->spectrum == 2) {
+    if (!src->tab_e || !src->tab_w || src->tab_n < 1 || src->tab_n > 4096) return -1;
+    if (!(src->tab_e[0] > 0.0 && src->tab_e[src->tab_n] <= 30.0)) return -1;
+    double total = 0.0;
+    for (int j = 0; j < src->tab_n; ++j) {
+      if (!(src->tab_e[j + 1] > src->tab_e[j]) || !(src->tab_w[j] >= 0.0) || !isfinite(src->tab_w[j])) return -1;
+      total += src->tab_w[j];
+    }
+    return (total > 0.0 && isfinite(total)) ? 0 : -1;
+  }
   return -1;
+}
+
+int orc_sample_source(const orc_source* src, uint64_t seed, uint64_t h_begin, uint64_t h_end, double* out) {
+  if (check_source(src)) return -1;
+  uint32_t key[2]; make_key(seed, src->beam_id, key);
+  for (uint64_t h = h_begin; h < h_end; ++h) {
+    part_t p;
+    sample_source(src, key, (uint32_t)h, &p);
+    double* o = out + 3 * (h - h_begin);
+    o[0] = p.x[0]; o[1] = p.x[1]; o[2] = p.e;
+  }
+  return 0;
 }
 
 int orc_run(const orc_material* mats, int n_mat, const orc_phantom* ph,

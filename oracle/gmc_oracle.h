@@ -32,10 +32,13 @@ typedef struct {
 
 typedef struct {
   int particle;            /* 0 photon, 1 electron */
-  int spectrum;            /* 0 monoenergetic, 1 triangular */
+  int spectrum;            /* 0 monoenergetic, 1 triangular, 2 tabulated (histogram) */
   double e, e_lo, e_mode, e_hi;
   double cx, cy, wx, wy;   /* field centre and full widths at z = 0, direction +z */
   uint32_t beam_id;        /* enters the RNG key */
+  const double* tab_e;     /* tabulated: tab_n + 1 increasing bin edges, MeV */
+  const double* tab_w;     /* tabulated: tab_n bin weights (>= 0, not all zero) */
+  int tab_n;
 } orc_source;
 
 typedef struct {
@@ -88,6 +91,10 @@ int orc_run(const orc_material* mats, int n_mat, const orc_phantom* ph,
             const orc_source* src, const orc_physics* phys, uint64_t seed,
             uint64_t h_begin, uint64_t h_end, uint64_t n_total,
             double* e1, double* e2, double* eb, orc_stats* st);
+
+/* Primaries of histories [h_begin, h_end): x, y and kinetic energy (MeV)
+ * into out[3 * i .. 3 * i + 2].  Returns 0, or -1 for an invalid source. */
+int orc_sample_source(const orc_source* src, uint64_t seed, uint64_t h_begin, uint64_t h_end, double* out);
 
 /* Per-history first real photon interaction (test mode 1 semantics):
  * writes x,y,z of the first real interaction (NaN if escaped) and the

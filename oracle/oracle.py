@@ -59,7 +59,8 @@ class _Source(C.Structure):
     _fields_ = [("particle", C.c_int), ("spectrum", C.c_int),
                 ("e", C.c_double), ("e_lo", C.c_double), ("e_mode", C.c_double), ("e_hi", C.c_double),
                 ("cx", C.c_double), ("cy", C.c_double), ("wx", C.c_double), ("wy", C.c_double),
-                ("beam_id", C.c_uint32)]
+                ("beam_id", C.c_uint32), ("tab_e", C.POINTER(C.c_double)), ("tab_w", C.POINTER(C.c_double)),
+                ("tab_n", C.c_int)]
 
 
 class _Physics(C.Structure):
@@ -105,6 +106,7 @@ def lib():
         L.orc_run.argtypes = [C.POINTER(_Material), C.c_int, C.POINTER(_Phantom), C.POINTER(_Source),
                               C.POINTER(_Physics), C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64,
                               dp, dp, dp, C.POINTER(_Stats)]
+        L.orc_sample_source.argtypes = [C.POINTER(_Source), C.c_uint64, C.c_uint64, C.c_uint64, dp]
         L.orc_first_events.argtypes = [C.POINTER(_Material), C.c_int, C.POINTER(_Phantom), C.POINTER(_Source),
                                        C.POINTER(_Physics), C.c_uint64, C.c_uint64, C.c_uint64, dp, u32p]
         _lib = L
@@ -133,9 +135,27 @@ def _phantom(ph):
 
 
 def _source(src):
-    return _Source(int(src.particle), int(src.spectrum), float(src.e), float(src.e_lo), float(src.e_mode),
-                   float(src.e_hi), float(src.cx), float(src.cy), float(src.wx), float(src.wy),
-                   int(src.beam_id))
+    s = _Source(int(src.particle), int(src.spectrum), float(src.e), float(src.e_lo), float(src.e_mode),
+                float(src.e_hi), float(src.cx), float(src.cy), float(src.wx), float(src.wy),
+                int(src.beam_id))
+    tab_e, tab_w = getattr(src, "tab_e", None), getattr(src, "tab_w", None)
+    if tab_e is not None and tab_w is not None:
+        e = np.ascontiguousarray(tab_e, dtype=np.float64)
+        w = np.ascontiguousarray(tab_w, dtype=np.float64)
+        s.tab_e, s.tab_w, s.tab_n = _ptr(e, C.c_double), _ptr(w, C.c_double), int(w.size)
+        s._keep = (e, w)   # the arrays live as long as the structure
+    return s
+
+
+def sample_source(source, seed: int, h_begin: int, h_end: int) -> np.ndarray:
+    """Primaries of histories [h_begin, h_end): rows (x, y, kinetic energy)."""
+    src = _source(source)
+    out = np.zeros((h_end - h_begin, 3))
+    rc = lib().orc_sample_source(C.byref(src), C.c_uint64(seed), C.c_uint64(h_begin), C.c_uint64(h_end),
+                                 _ptr(out, C.c_double))
+    if rc != 0:
+        raise ValueError("invalid source")
+    return out
 
 
 def _physics(phys):

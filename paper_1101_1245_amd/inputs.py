@@ -14,12 +14,12 @@ generated from a numpy ``default_rng`` seed.
 from __future__ import annotations
 
 from dataclasses import dataclass, field, replace
-from typing import List, Sequence, Tuple
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
 PHOTON, ELECTRON = 0, 1
-MONO, TRIANGULAR = 0, 1
+MONO, TRIANGULAR, TABULATED = 0, 1, 2
 
 
 @dataclass(frozen=True)
@@ -71,6 +71,8 @@ class Source:
     wx: float = 1.0
     wy: float = 1.0
     beam_id: int = 0
+    tab_e: Optional[np.ndarray] = None   # TABULATED: tab_n + 1 increasing bin edges (MeV)
+    tab_w: Optional[np.ndarray] = None   # TABULATED: tab_n bin weights
 
 
 @dataclass
