@@ -47,7 +47,7 @@ enum {
 
 enum { GMC_HOST = 0, GMC_DEVICE = 1 };          /* pointer kinds */
 enum { GMC_PHOTON = 0, GMC_ELECTRON = 1 };
-enum { GMC_MONO = 0, GMC_TRIANGULAR = 1 };
+enum { GMC_MONO = 0, GMC_TRIANGULAR = 1, GMC_TABULATED = 2 };
 
 typedef struct gmc_context gmc_context;
 
@@ -97,15 +97,23 @@ int gmc_release(gmc_context* ctx, int32_t id);
 
 /* Parallel beam along +z entering at z = 0 (Sec. II.C.2, initParticle):
  * position uniform over the field of full widths (wx, wy) centred at
- * (cx, cy); energy monoenergetic (e_mev) or triangular on
- * [e_lo, e_hi] with mode e_mode (inverse CDF).  beam_id enters the random
- * stream key, so beamlets with different ids draw independent streams. */
+ * (cx, cy); energy monoenergetic (e_mev), triangular on [e_lo, e_hi] with
+ * mode e_mode (inverse CDF), or tabulated: a histogram of tab_n bins (1..4096)
+ * with increasing edges tab_e[0..tab_n] in (0, 30] MeV and weights
+ * tab_w[0..tab_n-1] (>= 0, finite, not all zero), each bin's weight spread
+ * evenly over the bin, sampled by inverting the piecewise-linear CDF.  The
+ * tables are host memory, read during the call (copied by gmc_submit); they
+ * are ignored by the other spectra.  beam_id enters the random stream key, so
+ * beamlets with different ids draw independent streams. */
 typedef struct {
   int particle;
   int spectrum;
   double e_mev, e_lo, e_mode, e_hi;
   double cx_cm, cy_cm, wx_cm, wy_cm;
   uint32_t beam_id;
+  const double* tab_e;
+  const double* tab_w;
+  int tab_n;
 } gmc_source;
 
 /* Per-run statistics.  Energies in MeV; the integer ledger residual (in units

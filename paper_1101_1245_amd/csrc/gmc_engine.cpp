@@ -167,7 +167,7 @@ void ws_free(Workspace* w) {
   for (auto& b : w->stg) free_queue(b);
   free_queue(w->sorted);
   w->cap = w->stg_cap = w->sorted_cap = 0;
-  for (void* p : {(void*)w->d_ctl, (void*)w->d_ctr, (void*)w->d_beams, (void*)w->d_sort,
+  for (void* p : {(void*)w->d_ctl, (void*)w->d_ctr, (void*)w->d_beams, (void*)w->d_sort, (void*)w->d_tab,
                   (void*)w->d_sources, (void*)w->d_start, (void*)w->d_beam_of, (void*)w->d_nk})
     if (p) (void)hipFree(p);
   for (void* p : {(void*)w->h_ctl, (void*)w->h_ctr, (void*)w->h_nk})
@@ -179,6 +179,8 @@ void ws_free(Workspace* w) {
   w->d_sources = nullptr;
   w->d_start = w->d_beam_of = nullptr;
   w->d_sort = nullptr;
+  w->d_tab = nullptr;
+  w->tab_cap = 0;
   w->d_nk = w->h_nk = nullptr;
   w->beams_cap = 0;
   for (hipEvent_t e : {w->ev0, w->ev1, w->kev0, w->kev1, w->ev_ctl})
@@ -194,7 +196,7 @@ void ws_free(Workspace* w) {
 size_t ws_device_bytes(const Workspace& w) {
   return sizeof(uint32_t) * ((size_t)Q_FIELDS * (4ull * w.cap + w.sorted_cap) + (size_t)kStgFields * 2ull * w.stg_cap) +
          w.tally_elems * sizeof(unsigned long long) + 2 * w.out_elems * sizeof(double) +
-         w.beams_cap * (sizeof(DevBeam) + sizeof(DevSource) + 4 * sizeof(uint32_t));
+         w.beams_cap * (sizeof(DevBeam) + sizeof(DevSource) + 4 * sizeof(uint32_t)) + w.tab_cap * sizeof(double);
 }
 
 int ws_ensure_tally(Workspace* w, size_t elems) {
@@ -312,6 +314,17 @@ int check_source(std::string* err, const gmc_source* s) {
   } else if (s->spectrum == GMC_TRIANGULAR) {
     if (!(s->e_lo > 0.0 && s->e_lo <= s->e_mode && s->e_mode <= s->e_hi && s->e_lo < s->e_hi && s->e_hi <= 30.0))
       return bad("triangular spectrum needs 0 < lo <= mode <= hi <= 30, lo < hi");
+  } else if (s->spectrum == GMC_TABULATED) {
+    if (!s->tab_e || !s->tab_w || s->tab_n < 1 || s->tab_n > 4096)
+      return bad("tabulated spectrum needs 1..4096 bins and both tables");
+    if (!(s->tab_e[0] > 0.0 && s->tab_e[s->tab_n] <= 30.0)) return bad("tabulated spectrum must lie in (0, 30] MeV");
+    double total = 0.0;
+    for (int j = 0; j < s->tab_n; ++j) {
+      if (!(s->tab_e[j + 1] > s->tab_e[j])) return bad("tabulated spectrum edges must increase");
+      if (!(s->tab_w[j] >= 0.0 && std::isfinite(s->tab_w[j]))) return bad("tabulated spectrum weights must be >= 0");
+      total += s->tab_w[j];
+    }
+    if (!(total > 0.0 && std::isfinite(total))) return bad("tabulated spectrum weights sum to zero");
   } else {
     return bad("bad spectrum kind");
   }
@@ -322,6 +335,40 @@ int check_source(std::string* err, const gmc_source* s) {
 }
 
 uint32_t mev_to_lsb(double e) { return (uint32_t)std::llround(e * 134217728.0); }
+
+double source_emax(const gmc_source& s) {
+  if (s.spectrum == GMC_TRIANGULAR) return s.e_hi;
+  if (s.spectrum == GMC_TABULATED) return s.tab_e[s.tab_n];
+  return s.e_mev;
+}
+
+double source_emean(const gmc_source& s) {
+  if (s.spectrum == GMC_TRIANGULAR) return (s.e_lo + s.e_mode + s.e_hi) / 3.0;
+  if (s.spectrum == GMC_TABULATED) {
+    double m = 0.0, w = 0.0;
+    for (int j = 0; j < s.tab_n; ++j) {
+      m += s.tab_w[j] * 0.5 * (s.tab_e[j] + s.tab_e[j + 1]);
+      w += s.tab_w[j];
+    }
+    return m / w;
+  }
+  return s.e_mev;
+}
+
+// The normalised CDF is summed left to right and divided by the total, with
+// C_n set to exactly 1, so that a uniform below 1 always finds a bin.
+void tabulated_cdf(const gmc_source& s, std::vector<double>* out) {
+  const int n = s.tab_n;
+  double total = 0.0;
+  for (int j = 0; j < n; ++j) total += s.tab_w[j];
+  out->insert(out->end(), s.tab_e, s.tab_e + n + 1);
+  double sum = 0.0;
+  out->push_back(0.0);
+  for (int j = 0; j < n; ++j) {
+    sum += s.tab_w[j];
+    out->push_back(j == n - 1 ? 1.0 : sum / total);
+  }
+}
 
 DevPhantom dev_phantom(const PhantomObj& p) {
   DevPhantom d;
@@ -361,6 +408,8 @@ DevSource dev_source(const gmc_source& s) {
   d.cy = (float)s.cy_cm;
   d.wx = (float)s.wx_cm;
   d.wy = (float)s.wy_cm;
+  d.tab = nullptr;   // set where the job's tables are uploaded
+  d.tab_n = s.spectrum == GMC_TABULATED ? (uint32_t)s.tab_n : 0u;
   return d;
 }
 
@@ -433,6 +482,8 @@ void build_job(Job* J, Workspace* w, const PhantomObj& P, const TablesObj& T, co
     }
     J->beams.push_back(db);
     J->sources.push_back(dev_source(srcs[b]));
+    J->tab_off.push_back(J->tab.size());
+    if (srcs[b].spectrum == GMC_TABULATED) tabulated_cdf(srcs[b], &J->tab);
     const int t = srcs[b].particle;
     J->beam_of[t].push_back((uint32_t)b);
     J->start[t].push_back(J->start[t].back() + (uint32_t)n_hist[b]);
@@ -607,7 +658,20 @@ int engine_setup(Workspace* w, Engine& E, const Job& J, const Tune& tu) {
   rc = ws_ensure_beams(w, nb);
   if (rc) return rc;
   WS_TRY(w, hipMemcpy(w->d_beams, J.beams.data(), nb * sizeof(DevBeam), hipMemcpyHostToDevice));
-  WS_TRY(w, hipMemcpy(w->d_sources, J.sources.data(), nb * sizeof(DevSource), hipMemcpyHostToDevice));
+  std::vector<DevSource> srcs = J.sources;
+  if (!J.tab.empty()) {
+    if (w->tab_cap < J.tab.size()) {
+      if (w->d_tab) (void)hipFree(w->d_tab);
+      w->d_tab = nullptr;
+      w->tab_cap = 0;
+      WS_TRY(w, hipMalloc(&w->d_tab, J.tab.size() * sizeof(double)));
+      w->tab_cap = J.tab.size();
+    }
+    WS_TRY(w, hipMemcpy(w->d_tab, J.tab.data(), J.tab.size() * sizeof(double), hipMemcpyHostToDevice));
+    for (size_t b = 0; b < nb; ++b)
+      if (srcs[b].spectrum == GMC_TABULATED) srcs[b].tab = w->d_tab + J.tab_off[b];
+  }
+  WS_TRY(w, hipMemcpy(w->d_sources, srcs.data(), nb * sizeof(DevSource), hipMemcpyHostToDevice));
   for (int t = 0; t < 2; ++t) {
     WS_TRY(w, hipMemcpy(w->d_start + t * (w->beams_cap + 1), J.start[t].data(), J.start[t].size() * sizeof(uint32_t),
                         hipMemcpyHostToDevice));
@@ -896,7 +960,7 @@ int run_job_ws(gmc_context* c, Workspace* w, int32_t phantom_id, int32_t tables_
     if (n_hist[b] >= (1ull << 32)) return wfail(w, GMC_EINVAL, "histories must be < 2^32");
     n_total += n_hist[b];
     n_min = std::min<uint64_t>(n_min, n_hist[b]);
-    const double e_max = srcs[b].spectrum == GMC_MONO ? srcs[b].e_mev : srcs[b].e_hi;
+    const double e_max = source_emax(srcs[b]);
     e_sum += (double)n_hist[b] * (e_max * 134217728.0 + 1.0);
   }
   if (n_total < K) return wfail(w, GMC_EINVAL, "need at least n_batches histories");
@@ -1006,7 +1070,7 @@ std::vector<int> job_class(const PhantomObj& P, const TablesObj& T, const gmc_so
   for (int b = 0; b < n_beams; ++b) {
     const double w = (double)n_hist[b];
     n += w;
-    e += w * (srcs[b].spectrum == GMC_MONO ? srcs[b].e_mev : srcs[b].e_mode);
+    e += w * source_emean(srcs[b]);
     fe += srcs[b].particle == GMC_ELECTRON ? w : 0.0;
     area += w * srcs[b].wx_cm * srcs[b].wy_cm;
   }

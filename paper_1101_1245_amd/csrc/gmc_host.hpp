@@ -97,6 +97,8 @@ struct Workspace {
   size_t tally_elems = 0;
   DevBeam* d_beams = nullptr;
   DevSource* d_sources = nullptr;
+  double* d_tab = nullptr;      // the job's tabulated spectra
+  size_t tab_cap = 0;
   uint32_t* d_start = nullptr;   // [2][beams_cap + 1]
   uint32_t* d_beam_of = nullptr;   // [2][beams_cap]
   size_t beams_cap = 0;
@@ -146,6 +148,11 @@ gmc_tuning default_tuning();
 void queue_sizes(Workspace* w, const Tune& tu, int n_mat, uint32_t* cap, uint32_t* cap_soft, uint32_t* stg);
 
 int check_source(std::string* err, const gmc_source* s);
+// Highest and mean kinetic energy of a (checked) source's spectrum, MeV.
+double source_emax(const gmc_source& s);
+double source_emean(const gmc_source& s);
+// Edges then the normalised CDF at them (C_0 = 0, C_n = 1) of a tabulated spectrum.
+void tabulated_cdf(const gmc_source& s, std::vector<double>* out);
 uint32_t mev_to_lsb(double e);
 DevPhantom dev_phantom(const PhantomObj& p);
 DevCuts dev_cuts(const TablesObj& t);
@@ -161,6 +168,8 @@ struct Job {
   MajObj maj;
   std::vector<DevBeam> beams;
   std::vector<DevSource> sources;
+  std::vector<double> tab;            // tabulated spectra: per such beam, edges then normalised CDF
+  std::vector<size_t> tab_off;        // per beam: offset in tab (tabulated beams only)
   std::vector<uint32_t> start[2], beam_of[2];
   uint32_t total[2] = {0, 0};
 };

@@ -107,6 +107,8 @@ struct DevSource {
   uint32_t e_lsb;               // monoenergetic energy
   float e_lo, e_mode, e_hi;     // triangular spectrum
   float cx, cy, wx, wy;
+  const double* tab;            // tabulated: bin edges [tab_n + 1], then the normalised CDF at them [tab_n + 1]
+  uint32_t tab_n;
 };
 
 // Run counters (energy ledger in 2^-27 MeV units, event counts).  Each counter

@@ -23,9 +23,24 @@ using namespace dev;
 
 // ------------------------------------------------------------------ source
 // Primary of history h (Sec. II.C.2, initParticle): parallel beam along +z at
-// z = 0, position uniform over the field, energy monoenergetic or triangular.
-// Uses the first block (words 0-3) of the history's root stream.
+// z = 0, position uniform over the field, energy monoenergetic, triangular or
+// tabulated.  Uses the first block (words 0-3) of the history's root stream.
 struct Primary { float x, y; uint32_t e; };
+
+// Tabulated spectrum (a histogram): the bin j with C_j <= u < C_j+1 of the
+// normalised CDF C at the edges (C_0 = 0, C_n = 1), found by bisection for
+// the first edge above u, and the linear inverse inside it, in FP64.
+__device__ __forceinline__ uint32_t sample_tabulated(const double* tab, uint32_t n, double u) {
+  const double* edge = tab;
+  const double* cdf = tab + n + 1;
+  uint32_t lo = 0u, hi = n;   // cdf[lo] <= u < cdf[hi]
+  while (hi - lo > 1u) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (cdf[mid] <= u) lo = mid; else hi = mid;
+  }
+  const double e = edge[lo] + (u - cdf[lo]) / (cdf[lo + 1] - cdf[lo]) * (edge[lo + 1] - edge[lo]);
+  return (uint32_t)__double2uint_rn(e * 134217728.0);
+}
 
 __device__ __forceinline__ Primary sample_primary(const DevSource& a, const DevBeam& b, uint32_t h) {
   const Block blk = philox(0u, 0u, 0u, h, b.key0, b.key1);
@@ -38,6 +53,8 @@ __device__ __forceinline__ Primary sample_primary(const DevSource& a, const DevB
     const float fc = (md - lo) / (hi - lo);
     const float e = (u2 < fc) ? lo + sqrtf(u2 * (hi - lo) * (md - lo)) : hi - sqrtf((1.0f - u2) * (hi - lo) * (hi - md));
     p.e = to_lsb(e);
+  } else if (a.spectrum == 2) {
+    p.e = sample_tabulated(a.tab, a.tab_n, (double)u2);
   } else {
     p.e = a.e_lsb;
   }

@@ -300,10 +300,18 @@ int gmc_first_events(gmc_context* c, int32_t phantom_id, int32_t tables_id, cons
   a.cut = dev_cuts(*tp);
   a.beams = w->d_beams;
   a.n_beams = 1;
-  const DevSource ds = dev_source(*src);
+  DevSource ds = dev_source(*src);
   float* dx = nullptr;
   uint32_t* dn = nullptr;
+  double* dt = nullptr;
   hipError_t e = hipMemcpy(w->d_beams, &beam, sizeof(beam), hipMemcpyHostToDevice);
+  if (e == hipSuccess && src->spectrum == GMC_TABULATED) {
+    std::vector<double> tab;
+    tabulated_cdf(*src, &tab);
+    e = hipMalloc(&dt, tab.size() * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(dt, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
+    ds.tab = dt;
+  }
   if (e == hipSuccess) e = hipMalloc(&dx, (size_t)n * 3 * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&dn, (size_t)n * sizeof(uint32_t));
   if (e == hipSuccess) e = launch_first_events(a, ds, h_begin, n, dx, dn, w->stream);
@@ -314,6 +322,7 @@ int gmc_first_events(gmc_context* c, int32_t phantom_id, int32_t tables_id, cons
   if (e == hipSuccess) e = hipStreamSynchronize(w->stream);
   if (dx) (void)hipFree(dx);
   if (dn) (void)hipFree(dn);
+  if (dt) (void)hipFree(dt);
   if (e != hipSuccess) return cfail(c, GMC_EDEVICE, hipGetErrorString(e));
   return GMC_OK;
 }

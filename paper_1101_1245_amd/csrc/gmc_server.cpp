@@ -30,6 +30,7 @@ struct Request {
   uint64_t ticket = 0;
   int32_t pid = 0, tid = 0;
   gmc_source src{};
+  std::vector<double> tab_e, tab_w;   // a tabulated spectrum's tables (src points at them)
   uint64_t n = 0, seed = 0;
   size_t nvox = 0;
   uint32_t K = 0;
@@ -366,7 +367,7 @@ int gmc_submit(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_
     r->K = (uint32_t)T.phys.n_batches;
     if (n_hist < r->K || n_hist >= (1ull << 32))
       return cfail(c, GMC_EINVAL, "histories must be in [n_batches, 2^32)");
-    const double e_max = src->spectrum == GMC_MONO ? src->e_mev : src->e_hi;
+    const double e_max = source_emax(*src);
     if ((double)n_hist * (e_max * 134217728.0 + 1.0) >= 9.2e18)
       return cfail(c, GMC_EOVERFLOW, "histories x energy would overflow the 64-bit tallies");
     r->nvox = P.nvox();
@@ -379,6 +380,12 @@ int gmc_submit(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_
   r->pid = phantom_id;
   r->tid = tables_id;
   r->src = *src;
+  if (src->spectrum == GMC_TABULATED) {
+    r->tab_e.assign(src->tab_e, src->tab_e + src->tab_n + 1);
+    r->tab_w.assign(src->tab_w, src->tab_w + src->tab_n);
+    r->src.tab_e = r->tab_e.data();
+    r->src.tab_w = r->tab_w.data();
+  }
   r->n = n_hist;
   r->seed = seed;
   r->t_submit = Clock::now();

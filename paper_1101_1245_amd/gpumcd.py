@@ -46,7 +46,8 @@ class gmc_physics(C.Structure):
 class gmc_source(C.Structure):
     _fields_ = [("particle", C.c_int), ("spectrum", C.c_int), ("e_mev", C.c_double), ("e_lo", C.c_double),
                 ("e_mode", C.c_double), ("e_hi", C.c_double), ("cx_cm", C.c_double), ("cy_cm", C.c_double),
-                ("wx_cm", C.c_double), ("wy_cm", C.c_double), ("beam_id", C.c_uint32)]
+                ("wx_cm", C.c_double), ("wy_cm", C.c_double), ("beam_id", C.c_uint32),
+                ("tab_e", C.POINTER(C.c_double)), ("tab_w", C.POINTER(C.c_double)), ("tab_n", C.c_int)]
 
 
 class gmc_run_stats(C.Structure):
@@ -146,9 +147,20 @@ def lib():
     return L
 
 
-def _src(s) -> gmc_source:
-    return gmc_source(int(s.particle), int(s.spectrum), float(s.e), float(s.e_lo), float(s.e_mode), float(s.e_hi),
-                      float(s.cx), float(s.cy), float(s.wx), float(s.wy), int(s.beam_id))
+def _src(s, keep: list) -> gmc_source:
+    """The C source of `s`; a tabulated spectrum's tables go into `keep`,
+    which the caller holds until the call that reads them has returned."""
+    out = gmc_source(int(s.particle), int(s.spectrum), float(s.e), float(s.e_lo), float(s.e_mode), float(s.e_hi),
+                     float(s.cx), float(s.cy), float(s.wx), float(s.wy), int(s.beam_id))
+    tab_e, tab_w = getattr(s, "tab_e", None), getattr(s, "tab_w", None)
+    if tab_e is not None and tab_w is not None:
+        e = np.ascontiguousarray(tab_e, dtype=np.float64)
+        w = np.ascontiguousarray(tab_w, dtype=np.float64)
+        keep.append((e, w))
+        out.tab_e = e.ctypes.data_as(C.POINTER(C.c_double))
+        out.tab_w = w.ctypes.data_as(C.POINTER(C.c_double))
+        out.tab_n = int(w.size)
+    return out
 
 
 def _phys(p) -> gmc_physics:
@@ -238,7 +250,8 @@ class Context:
         out="numpy": host arrays; out="torch": float64 tensors on the context's
         GPU written directly by the finalize kernel."""
         st = gmc_run_stats()
-        src = _src(source)
+        keep = []
+        src = _src(source, keep)
         tun = _tuning(tuning)
         tun_p = C.byref(tun) if tun is not None else None
         if shape is None:
@@ -270,7 +283,8 @@ class Context:
         if nb != len(n_hist):
             raise ValueError("one history count per source")
         st = gmc_run_stats()
-        srcs = (gmc_source * nb)(*[_src(s) for s in sources])
+        keep = []
+        srcs = (gmc_source * nb)(*[_src(s, keep) for s in sources])
         counts = (C.c_uint64 * nb)(*[int(n) for n in n_hist])
         tun = _tuning(tuning)
         tun_p = C.byref(tun) if tun is not None else None
@@ -302,7 +316,8 @@ class Context:
     def autotune(self, phantom_id: int, tables_id: int, sources, n_hist, budget_s: float = 0.0):
         """The autotuner's choice for this job (cached per job class): (tuning dict, report dict)."""
         nb = len(sources)
-        srcs = (gmc_source * nb)(*[_src(s) for s in sources])
+        keep = []
+        srcs = (gmc_source * nb)(*[_src(s, keep) for s in sources])
         counts = (C.c_uint64 * nb)(*[int(n) for n in n_hist])
         tun = gmc_tuning()
         rep = gmc_autotune_report()
@@ -325,7 +340,8 @@ class Context:
         return {f: getattr(st, f) for f, _ in gmc_server_status_t._fields_}
 
     def submit(self, phantom_id: int, tables_id: int, source, n_hist: int, seed: int) -> int:
-        src = _src(source)
+        keep = []
+        src = _src(source, keep)
         t = C.c_uint64()
         self._check(self._L.gmc_submit(self._h, phantom_id, tables_id, C.byref(src), int(n_hist), int(seed),
                                        C.byref(t)))
@@ -372,7 +388,8 @@ class Context:
         n = h_end - h_begin
         xyz = np.zeros(3 * n, np.float32)
         nu = np.zeros(n, np.uint32)
-        src = _src(source)
+        keep = []
+        src = _src(source, keep)
         self._check(self._L.gmc_first_events(self._h, phantom_id, tables_id, C.byref(src), seed, h_begin, h_end,
                                              xyz.ctypes.data_as(C.POINTER(C.c_float)),
                                              nu.ctypes.data_as(C.POINTER(C.c_uint32))))
