@@ -32,6 +32,10 @@ geometries (water, lung box, tissue-lung-bone slabs; Table IV), and on the lung
 box the base, compaction (N = 4, 16, 64), pool, combined and default
 settings (Table VI; A_comp is the best N).
 
+``--workload atomics``: the library's 64-bit atomic-add microbenchmark (the
+tally path's second roof), random addresses into 0.26 MB-1 GiB arrays and hot
+sets of 1-4096 words.
+
 ``--workload regroup``: energy regrouping before every pass against none, in
 the batched form (monoenergetic water beams, triangular-spectrum beams,
 beamlets).
@@ -64,8 +68,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # on a 1 GiB device copy (fetched bytes x2.0, written x1.0).  Valid only for the kernel and engine sources they
 # were measured on (their digest); per launch they are multiplied by this
 # run's work per launch.
-TRAFFIC = {"sources_sha256": "6b1b0f0693456b490e4f6e3b12d7816451c7a58071a3fbd97e29bb39ced3a95a",
-           "k_electron_pass": 58.93}
+TRAFFIC = {"sources_sha256": "2f32007071bc667b36779c44bd60bde78a0feac839da933c1f89a88a660418df",
+           "k_electron_pass": 57.81}
 MEASURED_SOURCES = ("paper_1101_1245_amd/csrc/gmc_kernels.hip",
                     "paper_1101_1245_amd/csrc/gmc_device.hpp",
                     "paper_1101_1245_amd/csrc/gmc_internal.hpp",
@@ -516,6 +520,42 @@ def bench_regroup(args, G, E, I):
     return out
 
 
+def bench_atomics(args, G):
+    """The tally path's second roof: 64-bit atomic additions per second into
+    arrays from L2 size to HBM size at hashed addresses, and into hot sets of
+    1, 64 and 4096 words (the library's own microbenchmark kernel)."""
+    ctx = G.Context(0)
+    sizes = {}
+    for lg in (15, 18, 21, 23, 25, 27):
+        rate = max(ctx.atomic_rate(lg) for _ in range(max(args.steps, 1)))
+        sizes["%.3g MB" % ((1 << lg) * 8 / 1e6)] = rate
+        print("random atomics into %8.3g MB: %.3e /s" % ((1 << lg) * 8 / 1e6, rate), file=sys.stderr, flush=True)
+    hot = {}
+    for h in (1, 64, 4096):
+        hot[str(h)] = max(ctx.atomic_rate(15, h) for _ in range(max(args.steps, 1)))
+        print("hot set of %4d words: %.3e /s" % (h, hot[str(h)]), file=sys.stderr, flush=True)
+    ctx.close()
+    big = sizes["%.3g MB" % ((1 << 27) * 8 / 1e6)]
+    return {
+        "metric": "64-bit atomic additions/s at hashed addresses of a 1 GiB array",
+        "value": big,
+        "unit": "additions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": (1 << 26) / big * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "2^20 lanes x 64 atomic adds of 1 into uint64 arrays of 2^15..2^27 words at hashed "
+                               "addresses, and into hot sets of 1 / 64 / 4096 words; best of --steps launches"},
+        "random_by_array_size": sizes,
+        "hot_set": hot,
+    }
+
+
 def torch_equal(a, b):
     import torch
     return torch.equal(a, b)
@@ -599,7 +639,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("water", "beamlets", "geometries", "regroup"), default="water")
+    ap.add_argument("--workload", choices=("water", "beamlets", "geometries", "regroup", "atomics"), default="water")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form leg")
     ap.add_argument("--serve-requests", type=int, default=200)
@@ -644,8 +684,10 @@ def main():
         out = bench_beamlets(args, G, E, I)
     elif args.workload == "geometries":
         out = bench_geometries(args, G, E, I)
-    else:
+    elif args.workload == "regroup":
         out = bench_regroup(args, G, E, I)
+    else:
+        out = bench_atomics(args, G)
     print(json.dumps(out), flush=True)
 
 

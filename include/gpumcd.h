@@ -312,6 +312,15 @@ int gmc_table_eval(gmc_context* ctx, int32_t tables_id, int which, int mat, cons
 int gmc_first_events(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const gmc_source* src,
                      uint64_t seed, uint32_t h_begin, uint32_t h_end, float* out_xyz, uint32_t* out_nused);
 
+/* Measure the device's 64-bit atomic-add rate, the second roof of the
+ * tally path: 2^20 lanes each add 1 to 64 words of an array of
+ * 2^log2_words uint64 words (10..27), at hashed addresses (hot = 0) or on
+ * word t mod hot of the first hot words (hot a power of two, at most the
+ * array's size), with the instruction the tallies use; timed with HIP events
+ * after a warm-up launch.  *adds_per_s receives the additions per second.
+ * The array is allocated and freed by the call. */
+int gmc_atomic_rate(gmc_context* ctx, int log2_words, int hot, double* adds_per_s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -251,6 +251,8 @@ hipError_t launch_table_eval(const DevTables& t, int which, int mat, const float
 hipError_t launch_first_events(const PassArgs& a, const DevSource& src, uint32_t h0, uint32_t count, float* xyz,
                                uint32_t* nused, hipStream_t s);
 hipError_t launch_sort(const SortArgs& a, int grid, hipStream_t s);
+constexpr uint64_t kAtomicRateAdds = 4096ull * 256ull * 64ull;   // additions per microbenchmark launch
+hipError_t launch_atomic_rate(unsigned long long* a, uint32_t mask, uint32_t hot, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
 int max_resident_blocks(int kernel, int block, size_t lds);
 

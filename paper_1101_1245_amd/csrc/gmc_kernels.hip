@@ -1172,6 +1172,34 @@ hipError_t launch_first_events(const PassArgs& a, const DevSource& src, uint32_t
   return hipGetLastError();
 }
 
+// Atomic-rate microbenchmark: lane t adds 1 to 64 words of a + (0..mask),
+// at hashed addresses (a 32-bit xorshift-multiply finaliser), or (hot > 0)
+// to word t mod hot, through the same global atomic as the tallies.
+constexpr int kAtomicPerLane = 64;
+constexpr int kAtomicBlocks = 4096;
+static_assert(kAtomicRateAdds == (uint64_t)kAtomicBlocks * 256u * kAtomicPerLane, "additions per launch");
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+
+__global__ void __launch_bounds__(256) k_atomic_rate(unsigned long long* a, uint32_t mask, uint32_t hot) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int j = 0; j < kAtomicPerLane; ++j) {
+    const uint32_t i = hot ? (t & (hot - 1u)) : (mix32(t * 977u + (uint32_t)j * 131071u) & mask);
+    tally_add(a + i, 1ull);
+  }
+}
+
+hipError_t launch_atomic_rate(unsigned long long* a, uint32_t mask, uint32_t hot, hipStream_t s) {
+  hipLaunchKernelGGL(k_atomic_rate, dim3(kAtomicBlocks), dim3(256), 0, s, a, mask, hot);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s) {
   if (n == 0) return hipSuccess;
   size_t blocks = (n + 255) / 256;

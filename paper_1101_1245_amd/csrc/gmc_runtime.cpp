@@ -210,6 +210,36 @@ int gmc_autotune(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gm
                   report);
 }
 
+int gmc_atomic_rate(gmc_context* c, int log2_words, int hot, double* adds_per_s) {
+  if (!c) return GMC_EINVAL;
+  if (!adds_per_s) return cfail(c, GMC_EINVAL, "output pointer is NULL");
+  if (log2_words < 10 || log2_words > 27) return cfail(c, GMC_EINVAL, "log2_words must be in [10, 27]");
+  const uint64_t words = 1ull << log2_words;
+  if (hot < 0 || (hot > 0 && ((hot & (hot - 1)) != 0 || (uint64_t)hot > words)))
+    return cfail(c, GMC_EINVAL, "hot must be 0 or a power of two no larger than the array");
+  (void)hipSetDevice(c->device);
+  const hipStream_t s = c->ws.stream;
+  unsigned long long* d = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float ms = 0.0f;
+  hipError_t e = hipMalloc(&d, words * sizeof(unsigned long long));
+  if (e == hipSuccess) e = launch_fill_u64(d, words, 0ull, s);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = launch_atomic_rate(d, (uint32_t)(words - 1), (uint32_t)hot, s);   // warm-up
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  if (e == hipSuccess) e = launch_atomic_rate(d, (uint32_t)(words - 1), (uint32_t)hot, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (d) (void)hipFree(d);
+  if (e != hipSuccess) return cfail(c, GMC_EDEVICE, hipGetErrorString(e));
+  *adds_per_s = (double)kAtomicRateAdds / (ms * 1e-3);
+  return GMC_OK;
+}
+
 int gmc_rng_words(gmc_context* c, uint64_t seed, uint32_t beam, uint32_t hist, uint64_t path, uint32_t n0, int count,
                   uint32_t* out) {
   if (!c) return GMC_EINVAL;

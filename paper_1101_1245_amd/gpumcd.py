@@ -141,6 +141,7 @@ def lib():
     L.gmc_rng_words.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint32, C.c_int,
                                 C.POINTER(C.c_uint32)]
     L.gmc_table_eval.argtypes = [vp, C.c_int32, C.c_int, C.c_int, dp, C.c_int, dp]
+    L.gmc_atomic_rate.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_double)]
     L.gmc_first_events.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(gmc_source), C.c_uint64, C.c_uint32,
                                    C.c_uint32, C.POINTER(C.c_float), C.POINTER(C.c_uint32)]
     _lib = L
@@ -383,6 +384,13 @@ class Context:
         self._check(self._L.gmc_table_eval(self._h, tables_id, which, mat, e.ctypes.data_as(C.POINTER(C.c_double)),
                                            e.size, out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
+
+    def atomic_rate(self, log2_words: int, hot: int = 0) -> float:
+        """Measured 64-bit atomic additions per second into 2^log2_words words
+        (hashed addresses, or hot > 0: t mod hot)."""
+        r = C.c_double()
+        self._check(self._L.gmc_atomic_rate(self._h, int(log2_words), int(hot), C.byref(r)))
+        return r.value
 
     def first_events(self, phantom_id: int, tables_id: int, source, seed: int, h_begin: int, h_end: int):
         n = h_end - h_begin

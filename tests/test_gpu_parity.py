@@ -287,3 +287,15 @@ def test_device_outputs_and_errors(ctx, G):
     finally:
         ctx.release(pid)
         ctx.release(tid)
+
+
+def test_atomic_rate_microbenchmark(ctx, G):
+    """The atomic-add microbenchmark runs in bounds and tells a single hot
+    word (all lanes serialised on one address) from hashed addresses."""
+    spread = ctx.atomic_rate(20)
+    one = ctx.atomic_rate(12, 1)
+    assert spread > 1e9 and one > 0 and spread > 10 * one, (spread, one)
+    for bad in ((9, 0), (28, 0), (12, 3), (10, 2048), (12, -1)):
+        with pytest.raises(G.GpumcdError) as e:
+            ctx.atomic_rate(*bad)
+        assert e.value.code == G.GMC_EINVAL
