@@ -86,8 +86,21 @@ def measured_traffic(kernel):
     return TRAFFIC.get(kernel) if h.hexdigest() == TRAFFIC["sources_sha256"] else None
 
 
-def cpu_baseline():
-    """The FP64 oracle, single-threaded, on a bounded sample of the same beams."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(n1=None):
+    """The FP64 oracle, single-threaded, on a bounded sample of the same beams;
+    with n1 (histories per beam at 1%), the time the oracle would take to reach
+    1% on both beams at the sampled per-beam rates."""
     from oracle import oracle as O
     from paper_1101_1245_amd import inputs as I
     we = I.water_15mev(I.ELECTRON)
@@ -98,9 +111,12 @@ def cpu_baseline():
     t1 = time.perf_counter()
     O.run(wg.materials, wg.phantom, wg.source, wg.physics, wg.seed, ng, batches=False)
     t2 = time.perf_counter()
-    return {"value": (ne + ng) / (t2 - t0), "unit": "histories/s", "cores": 1, "kind": "oracle",
-            "sample": "%d electrons (%.1f s) + %d photons (%.1f s), 15 MeV, 64^3 water, one host core (%s)" %
-                      (ne, t1 - t0, ng, t2 - t1, platform.processor() or platform.machine())}
+    out = {"value": (ne + ng) / (t2 - t0), "unit": "histories/s", "cores": 1, "kind": "oracle",
+           "sample": "%d electrons (%.1f s) + %d photons (%.1f s), 15 MeV, 64^3 water, one host core of %d (%s)" %
+                     (ne, t1 - t0, ng, t2 - t1, os.cpu_count() or 0, cpu_model())}
+    if n1:
+        out["time_to_1pct_s"] = n1["electron"] * (t1 - t0) / ne + n1["photon"] * (t2 - t1) / ng
+    return out
 
 
 class Acc:
@@ -199,6 +215,7 @@ def bench_water(args, G, E, I):
 
     legs = {}
     last = {}
+    t_beam = {"electron": 0.0, "photon": 0.0}   # device time per beam, plain leg
     for leg, fn in (("plain", plain), ("batched", batched)):
         acc = Acc()
         sync()
@@ -206,8 +223,9 @@ def bench_water(args, G, E, I):
         for k in range(args.steps):
             r = fn(1000 + k)
             if leg == "plain":
-                for _, _, st in r:
+                for (_, _, st), key in zip(r, ("electron", "photon")):
                     acc.add(st)
+                    t_beam[key] += st["t_device_s"] / args.steps
             else:
                 acc.add(r[4])
             last[leg] = r
@@ -224,6 +242,15 @@ def bench_water(args, G, E, I):
     pb, ps = last["batched"][0], last["batched"][1]
     same = all(bool((pb[i] == last["plain"][i][0]).all()) and bool((ps[i] == last["plain"][i][1]).all())
                for i in range(2))
+
+    # the paper's timings include the transfer of the results: the plain leg
+    # once more with dose and sigma copied to host memory
+    sync()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        for w, key in ((we, "electron"), (wg, "photon")):
+            ctx.run_beam(pid, tid, w.source, n1[key], 1000 + k, shape=shape, out="numpy")
+    el_h = time.perf_counter() - t0
 
     acc_b, el_b = legs["batched"]
     acc_p, el_p = legs["plain"]
@@ -255,6 +282,10 @@ def bench_water(args, G, E, I):
         "plain": {"value": acc_p.hist / el_p, "ms_per_step": el_p / args.steps * 1e3},
         "batched_over_plain": (acc_b.hist / el_b) / (acc_p.hist / el_p),
         "batched_equals_plain_per_beam": same,
+        "plain_host_outputs": {"value": acc_p.hist / el_h, "ms_per_step": el_h / args.steps * 1e3,
+                               "note": "plain leg with dose and sigma copied to host memory in the timed region"},
+        "efficiency_per_s": {key: 1.0 / (s_final[key] ** 2 * t_beam[key]) for key in ("electron", "photon")},
+        "efficiency_note": "epsilon = 1 / (s^2 T) (Eq. 11) per beam, T its plain-form device time",
     }
     ctx.close()
     return out, both
@@ -381,6 +412,15 @@ def bench_geometries(args, G, E, I):
                   file=sys.stderr, flush=True)
         table_iv[gname] = row
 
+    # the other fixed-count set-ups: 1 MeV photons on 32^3 water (1e5) and
+    # 6 MeV photons on the 128^3 slab phantom (4e7)
+    fixed = {}
+    for w in (I.small_photon_water(), I.slab_6mev()):
+        el, _, _ = timed(w, None)
+        fixed[w.name] = {"histories": w.n_hist, "s": el, "histories_per_s": w.n_hist / el}
+        print("fixed count %-24s %9.2f ms  (%.3e histories/s)" % (w.name, el * 1e3, w.n_hist / el),
+              file=sys.stderr, flush=True)
+
     table_vi = {}
     identical = True
     settings = list(I.ABLATION_TUNINGS.items()) + [("default", None)]
@@ -427,6 +467,7 @@ def bench_geometries(args, G, E, I):
             "ablation": "lung box, tunings " + json.dumps(I.ABLATION_TUNINGS),
         },
         "table_iv_s": table_iv,
+        "fixed_count": fixed,
         "table_vi": table_vi,
         "ablation_doses_bit_identical": identical,
         "roofline": roofline(acc_all, "geometries"),
@@ -679,7 +720,8 @@ def main():
             out["served"]["electron_pass_ms_mean_overlapped"] = acc_s.t[1] / max(acc_s.n[1], 1) * 1e3
             out["ledger_residual_lsb"] |= acc_s.resid
         if not args.no_cpu_baseline:
-            out["cpu_baseline"] = cpu_baseline()
+            out["cpu_baseline"] = cpu_baseline({"electron": out["config"]["n_electrons"],
+                                                "photon": out["config"]["n_photons"]})
     elif args.workload == "beamlets":
         out = bench_beamlets(args, G, E, I)
     elif args.workload == "geometries":
