@@ -131,6 +131,8 @@ typedef struct {
   int64_t ledger_residual_lsb;
   double t_photon_pass_s, t_electron_pass_s;
   uint64_t n_photon_launches, n_electron_launches;
+  double s_rel;   /* Eq. 12: mean sigma/D over voxels with D > 0.2 D_max of the
+                     (combined) dose; NaN when sigma was not requested */
 } gmc_run_stats;
 
 /* Optional tuning of the engine.  A field <= 0 selects its default; a NULL

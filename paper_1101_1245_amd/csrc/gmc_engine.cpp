@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 
 #include "gmc_host.hpp"
 
@@ -140,6 +141,8 @@ int ws_init(Workspace* w, int device, hipStream_t stream) {
   WS_TRY(w, hipMalloc(&w->d_ctr, C_COUNT * kCtrSlots * sizeof(unsigned long long)));
   WS_TRY(w, hipHostMalloc(&w->h_ctr, C_COUNT * kCtrSlots * sizeof(unsigned long long), hipHostMallocDefault));
   WS_TRY(w, hipMalloc(&w->d_nk, kMaxBatches * sizeof(double)));
+  WS_TRY(w, hipMalloc(&w->d_srel, (3 * kRelBlocks + 1) * sizeof(double)));
+  WS_TRY(w, hipHostMalloc(&w->h_srel, sizeof(double), hipHostMallocDefault));
   WS_TRY(w, hipHostMalloc(&w->h_nk, kMaxBatches * sizeof(double), hipHostMallocDefault));
   WS_TRY(w, hipEventCreate(&w->ev0));
   WS_TRY(w, hipEventCreate(&w->ev1));
@@ -170,7 +173,7 @@ void ws_free(Workspace* w) {
   for (void* p : {(void*)w->d_ctl, (void*)w->d_ctr, (void*)w->d_beams, (void*)w->d_sort, (void*)w->d_tab,
                   (void*)w->d_sources, (void*)w->d_start, (void*)w->d_beam_of, (void*)w->d_nk})
     if (p) (void)hipFree(p);
-  for (void* p : {(void*)w->h_ctl, (void*)w->h_ctr, (void*)w->h_nk})
+  for (void* p : {(void*)w->h_ctl, (void*)w->h_ctr, (void*)w->h_nk, (void*)w->h_srel})
     if (p) (void)hipHostFree(p);
   w->d_ctl = nullptr;
   w->h_ctl = nullptr;
@@ -181,6 +184,9 @@ void ws_free(Workspace* w) {
   w->d_sort = nullptr;
   w->d_tab = nullptr;
   w->tab_cap = 0;
+  if (w->d_srel) (void)hipFree(w->d_srel);
+  w->d_srel = nullptr;
+  w->h_srel = nullptr;
   w->d_nk = w->h_nk = nullptr;
   w->beams_cap = 0;
   for (hipEvent_t e : {w->ev0, w->ev1, w->kev0, w->kev1, w->ev_ctl})
@@ -850,6 +856,15 @@ int finalize(Workspace* w, const PhantomObj& P, const unsigned long long* tally,
   fa.sigma = d_sigma;
   fa.ctr = ledger ? w->d_ctr : nullptr;
   WS_TRY(w, launch_finalize(fa, w->stream));
+  // the job's s (Eq. 12) with its combined result, read with the counters
+  if (ledger) {
+    w->h_srel[0] = std::numeric_limits<double>::quiet_NaN();
+    if (d_sigma) {
+      WS_TRY(w, launch_rel_uncertainty(d_dose, d_sigma, (uint32_t)P.nvox(), w->d_srel, w->stream));
+      WS_TRY(w, hipMemcpyAsync(w->h_srel, w->d_srel + 3 * kRelBlocks, sizeof(double), hipMemcpyDeviceToHost,
+                               w->stream));
+    }
+  }
   // nk is caller memory that may go away on return
   if (sync) WS_TRY(w, hipStreamSynchronize(w->stream));
   return GMC_OK;
@@ -881,6 +896,7 @@ int stats_from_counters(Workspace* w, const unsigned long long* slots, gmc_run_s
     stats->t_electron_pass_s = w->t_pass[1];
     stats->n_photon_launches = w->n_pass[0];
     stats->n_electron_launches = w->n_pass[1];
+    stats->s_rel = w->h_srel[0];
   }
   if (ctr[C_OVERFLOW]) return wfail(w, GMC_EINTERNAL, "queue overflow detected on the device");
   if (resid != 0) return wfail(w, GMC_EINTERNAL, "energy ledger does not close: residual " + std::to_string(resid));

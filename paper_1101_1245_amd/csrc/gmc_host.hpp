@@ -103,6 +103,8 @@ struct Workspace {
   uint32_t* d_beam_of = nullptr;   // [2][beams_cap]
   size_t beams_cap = 0;
   double* d_nk = nullptr;
+  double* d_srel = nullptr;     // [3 kRelBlocks + 1] work of the s reduction, s last
+  double* h_srel = nullptr;     // pinned copy of s
   double* h_nk = nullptr;       // pinned batch sizes for the finalize
   double* d_dose = nullptr;
   double* d_sigma = nullptr;

@@ -252,6 +252,11 @@ hipError_t launch_first_events(const PassArgs& a, const DevSource& src, uint32_t
                                uint32_t* nused, hipStream_t s);
 hipError_t launch_sort(const SortArgs& a, int grid, hipStream_t s);
 constexpr uint64_t kAtomicRateAdds = 4096ull * 256ull * 64ull;   // additions per microbenchmark launch
+// Eq. 12's s of a dose and sigma array: mean sigma/D over voxels with
+// D > 0.2 D_max, by fixed-order reductions (the same inputs give the same
+// bits).  work holds kRelBlocks block maxima, sums and counts, then s.
+constexpr int kRelBlocks = 256;
+hipError_t launch_rel_uncertainty(const double* dose, const double* sigma, uint32_t nvox, double* work, hipStream_t s);
 hipError_t launch_atomic_rate(unsigned long long* a, uint32_t mask, uint32_t hot, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
 int max_resident_blocks(int kernel, int block, size_t lds);

@@ -904,6 +904,55 @@ __global__ void __launch_bounds__(256) k_finalize(FinalizeArgs a) {
   if (lane_id() == 0 && t && a.ctr) ctr_add(a.ctr, C_E_DEP, t);
 }
 
+// Eq. 12's s: block maxima of D, then per-block sums of sigma/D and counts
+// over D > 0.2 D_max, then their totals; every sum in a fixed order.
+__device__ __forceinline__ double block_reduce(double v, bool take_max) {
+  __shared__ double r[256];
+  r[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) r[threadIdx.x] = take_max ? fmax(r[threadIdx.x], r[threadIdx.x + h])
+                                                       : r[threadIdx.x] + r[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double out = r[0];
+  __syncthreads();
+  return out;
+}
+
+__global__ void __launch_bounds__(256) k_rel_max(const double* dose, uint32_t nvox, double* work) {
+  double m = 0.0;
+  for (uint32_t v = blockIdx.x * 256u + threadIdx.x; v < nvox; v += gridDim.x * 256u) m = fmax(m, dose[v]);
+  m = block_reduce(m, true);
+  if (threadIdx.x == 0) work[blockIdx.x] = m;
+}
+
+__global__ void __launch_bounds__(256) k_rel_sum(const double* dose, const double* sigma, uint32_t nvox, double* work) {
+  double m = 0.0;
+  for (int b = 0; b < kRelBlocks; ++b) m = fmax(m, work[b]);
+  const double cut = 0.2 * m;
+  double s = 0.0, c = 0.0;
+  for (uint32_t v = blockIdx.x * 256u + threadIdx.x; v < nvox; v += gridDim.x * 256u) {
+    const double d = dose[v];
+    if (d > cut) {
+      s += sigma[v] / d;
+      c += 1.0;
+    }
+  }
+  s = block_reduce(s, false);
+  c = block_reduce(c, false);
+  if (threadIdx.x == 0) {
+    work[kRelBlocks + blockIdx.x] = s;
+    work[2 * kRelBlocks + blockIdx.x] = c;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_rel_final(double* work) {
+  const double s = block_reduce(work[kRelBlocks + threadIdx.x], false);
+  const double c = block_reduce(work[2 * kRelBlocks + threadIdx.x], false);
+  if (threadIdx.x == 0) work[3 * kRelBlocks] = c > 0.0 ? s / c : __longlong_as_double(0x7ff8000000000000ll);
+}
+
 // ------------------------------------------------------------------ checks
 __global__ void k_rng_words(uint32_t key0, uint32_t key1, uint32_t hist, uint32_t plo, uint32_t phi, uint32_t n0,
                             int count, uint32_t* out) {
@@ -1143,6 +1192,15 @@ hipError_t launch_electron_pass(const PassArgs& a, int grid, int block, hipStrea
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s) {
   const int grid = (int)((a.nvox + 255) / 256);
   hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rel_uncertainty(const double* dose, const double* sigma, uint32_t nvox, double* work,
+                                  hipStream_t s) {
+  static_assert(kRelBlocks == 256, "k_rel_final reduces one block of 256 partials");
+  hipLaunchKernelGGL(k_rel_max, dim3(kRelBlocks), dim3(256), 0, s, dose, nvox, work);
+  hipLaunchKernelGGL(k_rel_sum, dim3(kRelBlocks), dim3(256), 0, s, dose, sigma, nvox, work);
+  hipLaunchKernelGGL(k_rel_final, dim3(1), dim3(256), 0, s, work);
   return hipGetLastError();
 }
 

@@ -58,7 +58,7 @@ class gmc_run_stats(C.Structure):
                 ("n_majorant_violations", C.c_uint64), ("n_passes", C.c_uint64),
                 ("ledger_residual_lsb", C.c_int64), ("t_photon_pass_s", C.c_double),
                 ("t_electron_pass_s", C.c_double), ("n_photon_launches", C.c_uint64),
-                ("n_electron_launches", C.c_uint64)]
+                ("n_electron_launches", C.c_uint64), ("s_rel", C.c_double)]
 
 
 class gmc_tuning(C.Structure):

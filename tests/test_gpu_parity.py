@@ -299,3 +299,26 @@ def test_atomic_rate_microbenchmark(ctx, G):
         with pytest.raises(G.GpumcdError) as e:
             ctx.atomic_rate(*bad)
         assert e.value.code == G.GMC_EINVAL
+
+
+def test_run_stats_uncertainty_s(ctx, G):
+    """The run statistics carry s of Eq. 12 for the combined dose, reduced on
+    the device in a fixed order: it equals the host's value of the returned
+    dose and sigma, repeats bit for bit, and is NaN when sigma is not
+    requested."""
+    w = I.small_photon_water(n_hist=200_000)
+    tid = ctx.load_tables(w.materials, w.physics)
+    pid = ctx.load_phantom(w.phantom)
+    try:
+        d, s, st = ctx.run_beam(pid, tid, w.source, w.n_hist, 3, shape=w.phantom.shape)
+        _, _, st2 = ctx.run_beam(pid, tid, w.source, w.n_hist, 3, shape=w.phantom.shape)
+        _, _, st3 = ctx.run_beam(pid, tid, w.source, w.n_hist, 3, shape=w.phantom.shape, sigma=False)
+        pb, ps, db, sb, stb = ctx.run_beams(pid, tid, [w.source, w.source], [w.n_hist, w.n_hist // 2], 3,
+                                            shape=w.phantom.shape, per_beam=True, per_beam_sigma=True)
+    finally:
+        ctx.release(pid)
+        ctx.release(tid)
+    assert st["s_rel"] == pytest.approx(E.uncertainty_s(d, s), rel=1e-12)
+    assert st2["s_rel"] == st["s_rel"]
+    assert np.isnan(st3["s_rel"])
+    assert stb["s_rel"] == pytest.approx(E.uncertainty_s(db, sb), rel=1e-12)

@@ -62,8 +62,9 @@ def test_results_equal_alone(ctx, stream):
         ctx.server_stop()
     for (d, s, st), r in zip(res, reqs):
         assert st["ledger_residual_lsb"] == 0 and st["n_majorant_violations"] == 0
-        da, sa, _ = ctx.run_beam(pids[r.phantom], tid, r.source, r.n_hist, r.seed, shape=pool[r.phantom].shape)
+        da, sa, sta = ctx.run_beam(pids[r.phantom], tid, r.source, r.n_hist, r.seed, shape=pool[r.phantom].shape)
         assert np.array_equal(d, da) and np.array_equal(s, sa), r
+        assert st["s_rel"] == sta["s_rel"] or (np.isnan(st["s_rel"]) and np.isnan(sta["s_rel"])), r
     # overlap: some request started before an earlier one finished
     starts = [st["t_queue_s"] for _, _, st in res]
     ends = [st["t_latency_s"] for _, _, st in res]
