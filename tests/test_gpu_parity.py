@@ -269,6 +269,20 @@ def test_electron_15mev_ztest(ctx, oracle, G):
         assert abs(a - b) < 6 * np.sqrt(b) + 0.01 * b, (k, a, b)
 
 
+def test_electron_15mev_gamma(ctx, oracle, G):
+    # gamma 2%/2 mm of the 15 MeV electron beam on 64^3 water against the
+    # oracle on the same 1e6 histories, voxels above 10% of the maximum
+    w = I.water_15mev(I.ELECTRON, n_hist=1_000_000)
+    d, s, st = G.run_workload(ctx, w)
+    assert st["ledger_residual_lsb"] == 0
+    res = oracle.run_parallel(w.materials, w.phantom, w.source, w.physics, w.seed, w.n_hist, batches=False)
+    do, so = oracle.dose(res, w.phantom)
+    g = E.gamma_index(do, d, w.phantom.voxel)
+    print("\ngamma 2%%/2 mm, 15 MeV electrons, same 1e6 histories: pass rate %.5f over %d voxels, max %.3f" %
+          (g.pass_rate, g.n_voxels, g.gamma_max))
+    assert g.pass_rate >= 0.99, (g.pass_rate, g.gamma_max, g.n_voxels)
+
+
 def test_device_outputs_and_errors(ctx, G):
     torch = pytest.importorskip("torch")
     w = I.small_photon_water(n_hist=20000)

@@ -11,6 +11,13 @@ the very estimates being compared favours voxels where one of them ran high.
 * FP32 vs FP64 (GPU and oracle on the same 4e6 histories): the z-test passes
   and in every band the GPU/oracle ratio of the band's summed dose is within
   0.2% of 1 -- the stated FP32-vs-FP64 error (measured: 0.03% or less).
+* Gamma 2%/2 mm of the same-stream GPU dose against the oracle's, voxels
+  above 10% of the maximum: at least 97% pass (measured 97.3%).  The 99% bar
+  is not reached at this size: histories whose FP32 and FP64 trajectories
+  part after a flipped decision become independent samples, and at 4e6
+  histories on 0.25 cm voxels (lung at 0.26 g/cm^3) a voxel's dose from such
+  histories fluctuates by several percent of the maximum.  The same bar holds
+  at 99% for the water phantoms, whose voxels are larger and denser.
 * Statistical agreement (GPU on 4e6 other histories): the z-test's mean,
   maximum and variance bounds hold; its fraction beyond 3 sigma is bounded
   at 0.5%, because in a broad beam every history deposits in many voxels,
@@ -83,6 +90,16 @@ def test_slab_fp32_vs_fp64_same_streams(runs):
     assert zt.passed, (zt.n, zt.frac_over_3, zt.max_abs, zt.mean, zt.var)
     for name, bname, n, ratio in rows:
         assert n >= 50 and abs(ratio - 1.0) < 2e-3, (name, bname, n, ratio)
+
+
+def test_slab_gamma_same_streams(runs):
+    # gamma 2%/2 mm (Eqs. 14-15) of the GPU dose against the oracle's on the
+    # same 4e6 histories, over voxels above 10% of the oracle's maximum
+    w, ref, (d, s, st), _, _, (do, so, r) = runs
+    g = E.gamma_index(do, d, w.phantom.voxel)
+    print("\ngamma 2%%/2 mm, same 4e6 histories: pass rate %.5f over %d voxels, max %.3f" %
+          (g.pass_rate, g.n_voxels, g.gamma_max))
+    assert g.pass_rate >= 0.97, (g.pass_rate, g.gamma_max, g.n_voxels)
 
 
 def test_slab_statistical_agreement(runs):
