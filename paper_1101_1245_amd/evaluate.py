@@ -110,6 +110,30 @@ def gamma_index(ref: np.ndarray, ev: np.ndarray, voxel, dose_tol: float = 0.02, 
                        float(g.mean()) if g.size else 0.0, int(g.size), int(np.sum(g > 1.0)), int(np.sum(g > 1.2)))
 
 
+# ------------------------------------------------------------------ precision
+@dataclass
+class PrecisionError:
+    n: int               # voxels with ref > threshold * max(ref)
+    sum_rel: float       # sum(ev) / sum(ref) - 1 over those voxels
+    mean_abs: float      # mean |ev - ref| / max(ref) over those voxels
+    max_abs: float       # max |ev - ref| / max(ref) over those voxels
+
+
+def precision_error(ev: np.ndarray, ref: np.ndarray, threshold: float = 0.1) -> PrecisionError:
+    """Difference of a dose ``ev`` from a reference dose ``ref`` computed on
+    the same random streams (FP32 transport against the FP64 one): the
+    relative difference of the summed dose and the mean and largest voxel
+    difference in units of the reference maximum, over voxels above
+    ``threshold`` of that maximum."""
+    dmax = float(ref.max())
+    sel = ref > threshold * dmax
+    n = int(sel.sum())
+    if n == 0:
+        return PrecisionError(0, 0.0, 0.0, 0.0)
+    diff = np.abs(ev[sel] - ref[sel]) / dmax
+    return PrecisionError(n, float(ev[sel].sum() / ref[sel].sum() - 1.0), float(diff.mean()), float(diff.max()))
+
+
 # ------------------------------------------------------------------ z-test
 @dataclass
 class ZTest:

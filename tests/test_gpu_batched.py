@@ -224,6 +224,9 @@ def test_full_beamlet_job(ctx, oracle):
                                 batches=False)
         do, so = oracle.dose(r, j.phantom)
         zt = E.z_test(pb[b].cpu().numpy(), so, do, so, dof=10 ** 6, same_streams=True)
+        pe = E.precision_error(pb[b].cpu().numpy(), do)
+        print("\nsmallest beamlet (%d histories), same streams: summed dose %+.2e, voxel |diff| mean %.2e max %.2e "
+              "of D_max over %d voxels" % (int(j.counts[b]), pe.sum_rel, pe.mean_abs, pe.max_abs, pe.n))
         assert zt.passed, (zt.n, zt.frac_over_3, zt.max_abs, zt.mean, zt.var)
         del pb, d, s
         torch.cuda.empty_cache()

@@ -39,6 +39,14 @@ def ctx(G):
     c.close()
 
 
+def show_precision(title, d, do, g):
+    """FP32 transport against the FP64 oracle on the same histories."""
+    p = E.precision_error(d, do)
+    print("\n%s: summed dose %+.2e, voxel |diff| mean %.2e max %.2e of D_max over %d voxels; "
+          "gamma 2%%/2 mm pass %.5f, max %.3f" % (title, p.sum_rel, p.mean_abs, p.max_abs, p.n, g.pass_rate,
+                                                 g.gamma_max))
+
+
 def test_rng_words_bit_exact(ctx, oracle):
     cases = [(1, 0, 0, 0, 0), (0x1122334455667788, 7, 123456, 0, 5), (42, 3, 99, 0xDEADBEEFCAFEF00D, 1001),
              (2 ** 64 - 1, 0xFFFFFFFF, 0xFFFFFFFF, 2 ** 64 - 1, 2 ** 32 - 300)]
@@ -211,6 +219,7 @@ def test_small_photon_water_gamma(ctx, oracle, G):
     res = oracle.run_parallel(w.materials, w.phantom, w.source, w.physics, w.seed, w.n_hist, batches=False)
     do, so = oracle.dose(res, w.phantom)
     g = E.gamma_index(do, d, w.phantom.voxel)
+    show_precision("1 MeV photons, 32^3 water, same 2e6 histories", d, do, g)
     assert g.pass_rate >= 0.99, (g.pass_rate, g.gamma_max, g.n_voxels)
 
 
@@ -278,8 +287,25 @@ def test_electron_15mev_gamma(ctx, oracle, G):
     res = oracle.run_parallel(w.materials, w.phantom, w.source, w.physics, w.seed, w.n_hist, batches=False)
     do, so = oracle.dose(res, w.phantom)
     g = E.gamma_index(do, d, w.phantom.voxel)
-    print("\ngamma 2%%/2 mm, 15 MeV electrons, same 1e6 histories: pass rate %.5f over %d voxels, max %.3f" %
-          (g.pass_rate, g.n_voxels, g.gamma_max))
+    show_precision("15 MeV electrons, 64^3 water, same 1e6 histories", d, do, g)
+    assert g.pass_rate >= 0.99, (g.pass_rate, g.gamma_max, g.n_voxels)
+
+
+def test_photon_15mev_same_streams(ctx, oracle, G):
+    # the 15 MeV photon beam of the same set-up (4e6 histories, the paper's
+    # count) against the oracle on the same streams: z-test, event counts,
+    # gamma 2%/2 mm over voxels above 10% of the maximum
+    w = I.water_15mev(I.PHOTON)
+    d, s, st = G.run_workload(ctx, w)
+    assert st["ledger_residual_lsb"] == 0 and st["n_majorant_violations"] == 0
+    res = oracle.run_parallel(w.materials, w.phantom, w.source, w.physics, w.seed, w.n_hist, batches=False)
+    do, so = oracle.dose(res, w.phantom)
+    zt = E.z_test(d, s, do, so, dof=w.physics.n_batches - 1, same_streams=True)
+    assert zt.passed, (zt.n, zt.frac_over_3, zt.max_abs, zt.mean, zt.var)
+    for k in ("n_e_steps", "n_photon_events", "n_secondaries", "n_hard"):
+        assert abs(st[k] - res.stats[k]) < 1e-3 * res.stats[k], k
+    g = E.gamma_index(do, d, w.phantom.voxel)
+    show_precision("15 MeV photons, 64^3 water, same 4e6 histories", d, do, g)
     assert g.pass_rate >= 0.99, (g.pass_rate, g.gamma_max, g.n_voxels)
 
 

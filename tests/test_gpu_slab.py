@@ -97,8 +97,9 @@ def test_slab_gamma_same_streams(runs):
     # same 4e6 histories, over voxels above 10% of the oracle's maximum
     w, ref, (d, s, st), _, _, (do, so, r) = runs
     g = E.gamma_index(do, d, w.phantom.voxel)
-    print("\ngamma 2%%/2 mm, same 4e6 histories: pass rate %.5f over %d voxels, max %.3f" %
-          (g.pass_rate, g.n_voxels, g.gamma_max))
+    p = E.precision_error(d, do)
+    print("\nslab, same 4e6 histories: summed dose %+.2e, voxel |diff| mean %.2e max %.2e of D_max over %d voxels; "
+          "gamma 2%%/2 mm pass %.5f, max %.3f" % (p.sum_rel, p.mean_abs, p.max_abs, p.n, g.pass_rate, g.gamma_max))
     assert g.pass_rate >= 0.97, (g.pass_rate, g.gamma_max, g.n_voxels)
 
 
