@@ -21,6 +21,21 @@ constexpr float kInf = __builtin_huge_valf();
 constexpr float kMaxLsbF = 4294967040.0f;           // largest float below 2^32
 // Multiple scattering is drawn isotropically at or above this first moment.
 constexpr float kG1Iso = 0.9999f;
+constexpr float kLn2 = 0.693147180559945309f;
+constexpr float kLog2e = 1.44269504088896341f;
+
+// ---------------------------------------------------------------- fast FP32 forms
+// Reciprocal, quotient, natural log and exponential of the transport as the
+// hardware's v_rcp_f32, v_log_f32 (log2) and v_exp_f32 (exp2), each within
+// about 1 ulp, and at most one multiply.  The general forms add range scaling
+// for operands beyond 2^96 and an extended-precision ln 2 product; no operand
+// here comes near such ranges (denormals are flushed, uniforms lie in
+// [2^-24, 1), energies in [1 keV, 32 MeV], lengths and cross sections far
+// inside), so those steps would only cost instructions.
+__device__ __forceinline__ float frcp(float b) { return __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ float fln(float x) { return __builtin_amdgcn_logf(x) * kLn2; }
+__device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
 
 // ---------------------------------------------------------------- Philox4x32-10
 struct Block { uint32_t w0, w1, w2, w3; };
@@ -150,12 +165,12 @@ __device__ __forceinline__ bool electron_voxel(const DevPhantom& P, float x, flo
 __device__ __forceinline__ float dist_boundary(const DevPhantom& P, float x, float y, float z, float u, float v,
                                                float w, int ix, int iy, int iz) {
   float t = kInf;
-  if (u > 0.0f) t = fminf(t, ((float)(ix + 1) * P.dx - x) / u);
-  else if (u < 0.0f) t = fminf(t, ((float)ix * P.dx - x) / u);
-  if (v > 0.0f) t = fminf(t, ((float)(iy + 1) * P.dy - y) / v);
-  else if (v < 0.0f) t = fminf(t, ((float)iy * P.dy - y) / v);
-  if (w > 0.0f) t = fminf(t, ((float)(iz + 1) * P.dz - z) / w);
-  else if (w < 0.0f) t = fminf(t, ((float)iz * P.dz - z) / w);
+  if (u > 0.0f) t = fminf(t, fdiv((float)(ix + 1) * P.dx - x, u));
+  else if (u < 0.0f) t = fminf(t, fdiv((float)ix * P.dx - x, u));
+  if (v > 0.0f) t = fminf(t, fdiv((float)(iy + 1) * P.dy - y, v));
+  else if (v < 0.0f) t = fminf(t, fdiv((float)iy * P.dy - y, v));
+  if (w > 0.0f) t = fminf(t, fdiv((float)(iz + 1) * P.dz - z, w));
+  else if (w < 0.0f) t = fminf(t, fdiv((float)iz * P.dz - z, w));
   return fmaxf(t, 0.0f);
 }
 
@@ -170,7 +185,7 @@ __device__ __forceinline__ void rotate_cs(float& u, float& v, float& w, float co
   float nu, nv, nw;
   if (rho2 > 1e-20f) {
     const float r = sqrtf(rho2);
-    const float ir = 1.0f / r;
+    const float ir = frcp(r);
     nu = u * cost + sint * (u * w * cp - v * sp) * ir;
     nv = v * cost + sint * (v * w * cp + u * sp) * ir;
     nw = w * cost - r * sint * cp;
@@ -205,15 +220,15 @@ __device__ __forceinline__ uint32_t to_lsb(float mev) {
 // 1/eps with weight ln(1/eps0) and eps with weight (1 - eps0^2)/2, accepted
 // with 1 - eps sin^2/(1 + eps^2).  Three uniforms per trial.
 __device__ __forceinline__ void sample_kn(float k, Stream& s, float& eps, float& cost) {
-  const float eps0 = 1.0f / (1.0f + 2.0f * k);
-  const float a1 = __logf(1.0f + 2.0f * k);
+  const float eps0 = frcp(1.0f + 2.0f * k);
+  const float a1 = fln(1.0f + 2.0f * k);
   const float a2 = 0.5f * (1.0f - eps0 * eps0);
   for (;;) {
     const float u1 = s.uniform(), u2 = s.uniform(), u3 = s.uniform();
-    const float e = (u1 * (a1 + a2) < a1) ? __expf(-a1 * u2) : sqrtf(eps0 * eps0 + (1.0f - eps0 * eps0) * u2);
-    const float t = (1.0f - e) / (k * e);
+    const float e = (u1 * (a1 + a2) < a1) ? fexp(-a1 * u2) : sqrtf(eps0 * eps0 + (1.0f - eps0 * eps0) * u2);
+    const float t = fdiv(1.0f - e, k * e);
     const float sin2 = t * (2.0f - t);
-    const float g = 1.0f - e * sin2 / (1.0f + e * e);
+    const float g = 1.0f - fdiv(e * sin2, 1.0f + e * e);
     if (u3 <= g) { eps = e; cost = 1.0f - t; return; }
   }
 }
@@ -223,15 +238,15 @@ __device__ __forceinline__ void sample_kn(float k, Stream& s, float& eps, float&
 // (2 - nu)(1/(A+nu) + B)/(2/A + 2 max(B, 0)).  Two uniforms per trial.
 __device__ __forceinline__ float sample_sauter(float t, Stream& s) {
   const float g = 1.0f + t / kMc2;
-  const float beta = sqrtf(t * (t + 2.0f * kMc2)) / (t + kMc2);
-  const float a = 1.0f / (g * g * beta * (1.0f + beta));
+  const float beta = fdiv(sqrtf(t * (t + 2.0f * kMc2)), t + kMc2);
+  const float a = frcp(g * g * beta * (1.0f + beta));
   const float b = 0.5f * beta * g * (g - 1.0f) * (g - 2.0f);
-  const float mx = 2.0f / a + 2.0f * fmaxf(b, 0.0f);
+  const float mx = fdiv(2.0f, a) + 2.0f * fmaxf(b, 0.0f);
   for (;;) {
     const float u1 = s.uniform(), u2 = s.uniform();
-    const float q = 2.0f * sqrtf(u1) / (a + 2.0f);
-    const float nu = q * a / (1.0f - q);
-    const float f = (2.0f - nu) * (1.0f / (a + nu) + b);
+    const float q = fdiv(2.0f * sqrtf(u1), a + 2.0f);
+    const float nu = fdiv(q * a, 1.0f - q);
+    const float f = (2.0f - nu) * (frcp(a + nu) + b);
     if (u2 * mx <= f) return 1.0f - nu;
   }
 }
@@ -239,24 +254,24 @@ __device__ __forceinline__ float sample_sauter(float t, Stream& s) {
 // Pair electron polar cosine from (1 - beta cos)^-2 by inversion.
 __device__ __forceinline__ float pair_cos(float t, float u) {
   const float g = 1.0f + t / kMc2;
-  const float beta = sqrtf(t * (t + 2.0f * kMc2)) / (t + kMc2);
-  const float omb = 1.0f / (g * g * (1.0f + beta));
-  return (2.0f * u - 1.0f + beta) / (omb + 2.0f * beta * u);
+  const float beta = fdiv(sqrtf(t * (t + 2.0f * kMc2)), t + kMc2);
+  const float omb = frcp(g * g * (1.0f + beta));
+  return fdiv(2.0f * u - 1.0f + beta, omb + 2.0f * beta * u);
 }
 
 // Moller energy fraction in [kcut/T, 1/2] (Sec. II.B.1): 1/eps^2 and flat
 // components, accepted with h(eps)/(1 + 5 eps^2).  Three uniforms per trial.
 __device__ __forceinline__ float sample_moller(float t, float kcut, Stream& s) {
   const float tau = t / kMc2, g = tau + 1.0f;
-  const float e0 = kcut / t;
-  const float r2 = (tau / g) * (tau / g);
-  const float c = (2.0f * tau + 1.0f) / (g * g);
-  const float ie0 = 1.0f / e0;
+  const float e0 = fdiv(kcut, t);
+  const float r2 = fdiv(tau, g) * fdiv(tau, g);
+  const float c = fdiv(2.0f * tau + 1.0f, g * g);
+  const float ie0 = frcp(e0);
   const float w1 = ie0 - 2.0f, w2 = 5.0f * (0.5f - e0);
   for (;;) {
     const float u1 = s.uniform(), u2 = s.uniform(), u3 = s.uniform();
-    const float eps = (u1 * (w1 + w2) < w1) ? 1.0f / (ie0 - u2 * (ie0 - 2.0f)) : e0 + u2 * (0.5f - e0);
-    const float q = eps / (1.0f - eps);
+    const float eps = (u1 * (w1 + w2) < w1) ? frcp(ie0 - u2 * (ie0 - 2.0f)) : e0 + u2 * (0.5f - e0);
+    const float q = fdiv(eps, 1.0f - eps);
     const float h = 1.0f + q * q + r2 * eps * eps - c * q;
     if (u3 * (1.0f + 5.0f * eps * eps) <= h) return eps;
   }
@@ -266,11 +281,11 @@ __device__ __forceinline__ float sample_moller(float t, float kcut, Stream& s) {
 // accepted with (4/3 - 4y/3 + y^2)/(4/3), y = k/E.  Two uniforms per trial.
 __device__ __forceinline__ float sample_brems(float t, float kc, Stream& s) {
   const float e = t + kMc2;
-  const float lr = __logf(t / kc);
+  const float lr = fln(fdiv(t, kc));
   for (;;) {
     const float u1 = s.uniform(), u2 = s.uniform();
-    const float k = kc * __expf(u1 * lr);
-    const float y = k / e;
+    const float k = kc * fexp(u1 * lr);
+    const float y = fdiv(k, e);
     if (u2 * (4.0f / 3.0f) <= 4.0f / 3.0f - (4.0f / 3.0f) * y + y * y) return k;
   }
 }
@@ -278,11 +293,11 @@ __device__ __forceinline__ float sample_brems(float t, float kc, Stream& s) {
 // Screening parameter A of the step's screened-Rutherford angular shape for a
 // first moment G1 (Sec. II.B.2), from the table of ln A at logit(G1).
 __device__ __forceinline__ float screening_A(const DevTables& T, const float* ms, float g1) {
-  const float y = __logf(g1 / (1.0f - g1));
+  const float y = fln(fdiv(g1, 1.0f - g1));
   const float f = (y - T.ms_y0) * T.ms_inv_dy;
   const int i = min(max((int)floorf(f), 0), kNms - 2);
   const float t = f - (float)i;     // outside [0, 1] extrapolates the end segment
-  return __expf(fmaf(t, ms[i + 1] - ms[i], ms[i]));
+  return fexp(fmaf(t, ms[i + 1] - ms[i], ms[i]));
 }
 
 // Polar cosine of one condensed step: w = 1 - cos = 2 A u / (1 + A - u).
@@ -295,7 +310,7 @@ __device__ __forceinline__ float wentzel_om(const DevTables& T, const float* ms,
   if (!(g1 > 0.0f)) return 0.0f;
   if (g1 >= kG1Iso) return 2.0f * u;
   const float a = screening_A(T, ms, g1);
-  return 2.0f * a * u / ((1.0f - u) + a);
+  return fdiv(2.0f * a * u, (1.0f - u) + a);
 }
 
 // ---------------------------------------------------------------- wave helpers

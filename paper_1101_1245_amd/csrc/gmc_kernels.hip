@@ -298,7 +298,7 @@ __device__ __forceinline__ int photon_flight(Lane& L, const PassArgs& a, const f
   const TPos p = tpos(a.tab, ef);
   const float muh = majg[p.i];
   if (!(muh > 0.0f)) return PH_ESCAPE;
-  const float d = -__logf(L.s.uniform()) / muh;
+  const float d = fdiv(-fln(L.s.uniform()), muh);
   L.x = fmaf(d, L.u, L.x);
   L.y = fmaf(d, L.v, L.y);
   L.z = fmaf(d, L.w, L.z);
@@ -601,8 +601,8 @@ __device__ __forceinline__ bool hard_event(Lane& L, const PassArgs& a, const flo
     const uint32_t wl = min(to_lsb(eps * t1f), L.e);
     const uint32_t tp = L.e - wl;
     const float wf = (float)wl * kLsbF, tpf = (float)tp * kLsbF;
-    const float cd = sqrtf(wf * (t1f + 2.0f * kMc2) / (t1f * (wf + 2.0f * kMc2)));
-    const float cpp = sqrtf(tpf * (t1f + 2.0f * kMc2) / (t1f * (tpf + 2.0f * kMc2)));
+    const float cd = sqrtf(fdiv(wf * (t1f + 2.0f * kMc2), t1f * (wf + 2.0f * kMc2)));
+    const float cpp = sqrtf(fdiv(tpf * (t1f + 2.0f * kMc2), t1f * (tpf + 2.0f * kMc2)));
     const float phi = kTwoPi * L.s.uniform();
     c0.u = L.u; c0.v = L.v; c0.w = L.w;
     rotate(c0.u, c0.v, c0.w, cd, phi);
@@ -622,7 +622,7 @@ __device__ __forceinline__ bool hard_event(Lane& L, const PassArgs& a, const flo
     const float phi = kTwoPi * L.s.uniform();
     const uint32_t kl = min(to_lsb(k), L.e);
     c0.u = L.u; c0.v = L.v; c0.w = L.w;
-    rotate(c0.u, c0.v, c0.w, __cosf(kMc2 / (t1f + kMc2)), phi);
+    rotate(c0.u, c0.v, c0.w, __cosf(fdiv(kMc2, t1f + kMc2)), phi);
     if (kl >= a.cut.pcut_lsb) {
       c0.e = kl;
       child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
@@ -767,9 +767,9 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
           const TPos p0 = tpos(a.tab, tf);
           sh = maje[p0.i];
           const float uh = L.s.uniform();
-          const float ehard = (a.cut.mode == 2 || !(sh > 0.0f)) ? kInf : -__logf(uh) / sh;
+          const float ehard = (a.cut.mode == 2 || !(sh > 0.0f)) ? kInf : fdiv(-fln(uh), sh);
           const float dv = fmaxf(dist_boundary(a.ph, L.x, L.y, L.z, L.u, L.v, L.w, ix, iy, iz), a.ph.skin);
-          const float emax = (a.cut.esmax_gcm2 > 0.0f && rho0 > 0.0f) ? a.cut.esmax_gcm2 / rho0 : kInf;
+          const float emax = (a.cut.esmax_gcm2 > 0.0f && rho0 > 0.0f) ? fdiv(a.cut.esmax_gcm2, rho0) : kInf;
           float es = dv;
           bool hard = false;
           if (emax < es) es = emax;
@@ -797,7 +797,7 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
               const float il = (wz & 1u) ? lerp_w(smem, base0, tpos(a.tab, t1f)) : t0.w;
               const float xx = es * rho0 * il;
               // G1 = 1 - exp(-x), by its series where the subtraction would cancel
-              const float g1 = xx < 1e-3f ? xx * (1.0f - 0.5f * xx * (1.0f - xx * (1.0f / 3.0f))) : 1.0f - __expf(-xx);
+              const float g1 = xx < 1e-3f ? xx * (1.0f - 0.5f * xx * (1.0f - xx * (1.0f / 3.0f))) : 1.0f - fexp(-xx);
               rotate_om(L.u, L.v, L.w, wentzel_om(a.tab, ms, g1, ua), kTwoPi * uphi);
             }
             deposit_later(L, pend, v0, dl);
