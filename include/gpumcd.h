@@ -165,12 +165,21 @@ typedef struct {
  *     (highest first; a counting sort on log-energy buckets into a spare
  *     buffer of pass_items particles), the grouping of similar energies that
  *     Sec. IV.B proposes for polyenergetic beams (default 0: off: on MI355X
- *     the sort costs more than the passes gain).
+ *     the sort costs more than the passes gain);
+ *   tail_lanes: once a wavefront has taken every particle of its share of a
+ *     pass (and, in the electron pass, no parked electron waits), the
+ *     particles still on its lanes are requeued for the next pass after
+ *     their next event whenever at most tail_lanes lanes hold one, instead
+ *     of the wavefront running on for its last few particles; only while
+ *     primaries remain to be admitted (a next pass of each type follows
+ *     anyway; the last passes of a job finish in place) and for shares of at
+ *     least 256 particles (0: default, 64 in the electron pass and 32 in the
+ *     photon pass; 1..64 both passes; -1 off).
  * No tuning changes any result: the dose is bit-identical for every choice. */
 typedef struct {
   int events_per_visit, secondaries_per_visit, chunk, wg_size;
   int pass_items, wave_items, rounds_per_check, refill_lanes;
-  int energy_sort;
+  int energy_sort, tail_lanes;
 } gmc_tuning;
 
 /* Transport n_histories histories of one beam (the plain form: one beam per

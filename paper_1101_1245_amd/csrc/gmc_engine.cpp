@@ -245,7 +245,7 @@ int ws_ensure_beams(Workspace* w, size_t n) {
 
 // ---------------------------------------------------------------- settings
 Tune resolve_tuning(const gmc_tuning* t) {
-  Tune r{64, 4, 1 << 22, 0, 1 << 23, 64, 4, 4, 0};
+  Tune r{64, 4, 1 << 22, 0, 1 << 23, 64, 4, 4, 0, 32, 64};
   if (t) {
     // an electron parked at a hard event keeps its visit's event count in 16 bits
     if (t->events_per_visit > 0) r.events = std::min(t->events_per_visit, 1 << 15);
@@ -262,6 +262,8 @@ Tune resolve_tuning(const gmc_tuning* t) {
     if (t->rounds_per_check > 0) r.rounds = std::min(t->rounds_per_check, 1024);
     if (t->refill_lanes > 0) r.refill = std::min(t->refill_lanes, 64);
     if (t->energy_sort > 0) r.sort = 1;
+    if (t->tail_lanes < 0) r.tail_g = r.tail_e = 0;
+    if (t->tail_lanes > 0) r.tail_g = r.tail_e = std::min(t->tail_lanes, 64);
   }
   return r;
 }
@@ -278,6 +280,7 @@ gmc_tuning default_tuning() {
   t.rounds_per_check = d.rounds;
   t.refill_lanes = d.refill;
   t.energy_sort = d.sort;
+  t.tail_lanes = 0;   // the per-pass defaults
   return t;
 }
 
@@ -547,6 +550,7 @@ int enqueue_pass(Engine& E, int type, hipEvent_t t0, hipEvent_t t1, bool capturi
   pa.bud_same = E.bud_same[type];
   pa.bud_other = E.bud_other[type];
   pa.park_slots = 1u;   // one parked entry per particle: electrons at hard events, photons at absorption
+  pa.sched = w->d_ctl->sched;
   WS_TRY(w, launch_plan_pass(pa, w->stream));
   PassArgs a = E.proto;
   a.work = w->qbuf[type][wi].q;
@@ -570,6 +574,8 @@ int enqueue_pass(Engine& E, int type, hipEvent_t t0, hipEvent_t t1, bool capturi
   a.dst_other = w->qbuf[other][w->acc[other]].q;
   a.cnt_same = count_ptr(w, type, ni);
   a.cnt_other = count_ptr(w, other, w->acc[other]);
+  a.tail_lanes = type == 0 ? E.tu.tail_g : E.tu.tail_e;
+  a.tail_min = kTailMinItems;
   WS_TRY(w, record_event(w->stream, t0, capturing));
   hipError_t e = type == 0 ? launch_photon_pass(a, (int)E.blocks[0], E.block[0], w->stream)
                            : launch_electron_pass(a, (int)E.blocks[1], E.block[1], w->stream);

@@ -57,6 +57,8 @@ constexpr uint64_t kTuneMinSample = 1ull << 25;   // 8 chunks of the largest can
 // Idle lanes of an electron-pass wavefront, its range done, that take back
 // parked electrons together (their hard events then run on that many lanes).
 constexpr int kResumeLanes = 32;
+// Smallest share of a pass (particles per wavefront) whose tail is requeued.
+constexpr uint32_t kTailMinItems = 256u;
 
 // Device control block of a workspace: queue counts [type][buffer],
 // admission cursor and histories per type, the last pass plans and
@@ -141,7 +143,8 @@ int ws_ensure_beams(Workspace* w, size_t n);
 // Engine knobs (gmc_tuning with defaults filled in).
 struct Tune {
   int events, secondaries, chunk, block, pass_items, wave_items, rounds, refill;
-  int sort;   // 1: energy regrouping before every pass
+  int sort;            // 1: energy regrouping before every pass
+  int tail_g, tail_e;  // tail requeue lanes of the photon / electron pass (0: off)
 };
 Tune resolve_tuning(const gmc_tuning* t);
 gmc_tuning default_tuning();

@@ -128,6 +128,7 @@ constexpr int kCtrSlots = 256;
 // Particles m..n-1 are carried over to the next buffer.
 struct PassPlan {
   uint32_t n, m, per_wave, seg_same, seg_other, chunk_log2;
+  uint32_t admitting;   // primaries remain to be admitted: more passes of both types follow
 };
 
 struct PlanArgs {
@@ -142,6 +143,7 @@ struct PlanArgs {
   uint32_t chunk_log2;          // items per chunk dealt to a wavefront: 2^chunk_log2 (>= 64)
   uint32_t bud_same, bud_other; // per-visit output budgets per particle
   uint32_t park_slots;          // same-type staging slots per particle for parked electrons
+  const uint32_t* sched;        // admission cursors [2] and totals [2]
 };
 
 // A pass kernel's work: each wave of the grid owns its chunks of the work
@@ -174,6 +176,8 @@ struct PassArgs {
   int max_secondaries;
   int refill_lanes;          // idle lanes (1..64) that trigger a refill
   int resume_lanes;          // idle lanes (1..64) that take back parked electrons
+  int tail_lanes;            // requeue the lanes' particles once the share is done and at most this many remain
+  uint32_t tail_min;         // ... for shares of at least this many particles
 };
 
 // Admission of primaries of one particle type.  The histories of all beams of

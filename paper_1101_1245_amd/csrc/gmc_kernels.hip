@@ -470,6 +470,12 @@ __global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
     Child c0, c1;
     bool surv = false, park = false;
     int kind = PH_ESCAPE;
+    // tail of the share: with the range empty and few lanes still busy, a
+    // photon that lives on after this event is requeued (while primaries
+    // remain to be admitted)
+    bool tail = false;
+    if (a.tail_lanes > 0 && P.admitting && range.next >= range.end && range.end >= a.tail_min)
+      tail = (uint32_t)__popcll(__ballot(have)) <= (uint32_t)a.tail_lanes;
     if (have) {
       int v0 = 0;
       kind = photon_flight(L, a, smem, majg, v0, c_viol);
@@ -518,7 +524,7 @@ __global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
       c_sec += nchild;
       if (have) {
         ++events;
-        if (events >= a.max_events || pushes + 2 > a.max_secondaries) {
+        if (tail || events >= a.max_events || pushes + 2 > a.max_secondaries) {
           surv = true;
           have = false;
         }
@@ -740,7 +746,14 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
     }
     bool surv = false, park = false;
     float sh = 0.0f;
-    if (have && (events >= a.max_events || pushes + 1 > a.max_secondaries)) {
+    // tail of the share: with the range and the stack empty and few lanes
+    // still busy, an electron that has stepped in this visit is requeued
+    // rather than holding the wavefront for its last few particles -- while
+    // primaries remain to be admitted, when a next pass comes anyway
+    bool tail = false;
+    if (a.tail_lanes > 0 && P.admitting && range.next >= range.end && npark == 0 && range.end >= a.tail_min)
+      tail = (uint32_t)__popcll(__ballot(have)) <= (uint32_t)a.tail_lanes;
+    if (have && ((tail && events > 0) || events >= a.max_events || pushes + 1 > a.max_secondaries)) {
       // visit budget spent (after a hard event): requeued
       surv = true;
       have = false;
@@ -1057,6 +1070,7 @@ __global__ void k_plan_pass(PlanArgs a) {
   P.chunk_log2 = a.chunk_log2;
   P.seg_same = q * (a.bud_same + a.park_slots);
   P.seg_other = q * a.bud_other;
+  P.admitting = (a.sched[0] < a.sched[2] || a.sched[1] < a.sched[3]) ? 1u : 0u;
   *a.plan = P;
 }
 

@@ -64,7 +64,8 @@ class gmc_run_stats(C.Structure):
 class gmc_tuning(C.Structure):
     _fields_ = [("events_per_visit", C.c_int), ("secondaries_per_visit", C.c_int), ("chunk", C.c_int),
                 ("wg_size", C.c_int), ("pass_items", C.c_int), ("wave_items", C.c_int),
-                ("rounds_per_check", C.c_int), ("refill_lanes", C.c_int), ("energy_sort", C.c_int)]
+                ("rounds_per_check", C.c_int), ("refill_lanes", C.c_int), ("energy_sort", C.c_int),
+                ("tail_lanes", C.c_int)]
 
 
 class gmc_autotune_report(C.Structure):

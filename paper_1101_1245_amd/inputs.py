@@ -234,7 +234,8 @@ def tissue_lung_bone(particle: int, n_hist: int = None, tissue_density: float = 
 # creates more is requeued); hard-event and absorption parking are part of
 # every pass.
 def _ablation(events: int, refill: int) -> dict:
-    return {"events_per_visit": events, "secondaries_per_visit": 16, "refill_lanes": refill}
+    # the paper's two techniques alone: no requeue at the tail of a share
+    return {"events_per_visit": events, "secondaries_per_visit": 16, "refill_lanes": refill, "tail_lanes": -1}
 
 
 ABLATION_TUNINGS = {

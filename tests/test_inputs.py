@@ -121,6 +121,8 @@ def test_divergence_settings_are_valid_tunings():
     assert set(I.ABLATION_TUNINGS) == {"base", "compaction_n4", "compaction_n16", "compaction_n64", "pool", "both"}
     for t in I.ABLATION_TUNINGS.values():
         assert set(t) <= fields and 1 <= t["events_per_visit"] <= 1 << 15 and 1 <= t["refill_lanes"] <= 64
+    # the paper's techniques alone: no requeue at the tail of a share
+    assert all(t["tail_lanes"] == -1 for t in I.ABLATION_TUNINGS.values())
     # base: no requeue cadence and whole-wavefront refills; pool: per-lane refills
     assert I.ABLATION_TUNINGS["base"]["refill_lanes"] == 64 and I.ABLATION_TUNINGS["pool"]["refill_lanes"] == 1
     for n in (4, 16, 64):
