@@ -68,8 +68,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # on a 1 GiB device copy (fetched bytes x2.0, written x1.0).  Valid only for the kernel and engine sources they
 # were measured on (their digest); per launch they are multiplied by this
 # run's work per launch.
-TRAFFIC = {"sources_sha256": "b562d01ea33cecb22ec01ed321c4a6ba69c3b27ca48be292058b9f26e5a2aac9",
-           "k_electron_pass": 57.98}
+TRAFFIC = {"sources_sha256": "106fdc841f0c35867690145c5a47ef83891ed23b1a17958aabc7dd466152e64a",
+           "k_electron_pass": 57.88}
 MEASURED_SOURCES = ("paper_1101_1245_amd/csrc/gmc_kernels.hip",
                     "paper_1101_1245_amd/csrc/gmc_device.hpp",
                     "paper_1101_1245_amd/csrc/gmc_internal.hpp",
