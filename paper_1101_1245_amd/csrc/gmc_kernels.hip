@@ -754,7 +754,7 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
     if (a.tail_lanes > 0 && P.admitting && range.next >= range.end && npark == 0 && range.end >= a.tail_min)
       tail = (uint32_t)__popcll(__ballot(have)) <= (uint32_t)a.tail_lanes;
     if (have && ((tail && events > 0) || events >= a.max_events || pushes + 1 > a.max_secondaries)) {
-      // visit budget spent (after a hard event): requeued
+      // tail of the share, or visit budget spent (after a hard event): requeued
       surv = true;
       have = false;
     }
