@@ -47,6 +47,11 @@
 /* [reading] multiple scattering is taken as isotropic at or above this G1. */
 #define G1_ISO 0.9999
 
+/* [reading] the electron voxel skin as a fraction of the smallest voxel width
+ * (1e-4); tests may change it to show that the dose does not depend on it. */
+static double g_skin_fraction = 1e-4;
+void orc_set_skin_fraction(double f) { if (f > 0.0 && f < 0.5) g_skin_fraction = f; }
+
 /* ------------------------------------------------------------------ */
 /* Philox4x32-10 and Philox4x64-10 (Salmon et al., SC'11).            */
 void orc_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
@@ -466,6 +471,100 @@ int orc_sample(int which, double p1, double p2, uint64_t seed, int count, double
 }
 
 /* ------------------------------------------------------------------ */
+/* Event kinematics.  Each takes the incoming particle's energy and direction,
+ * draws from its stream in a fixed order and returns the outgoing particles;
+ * the transport below calls exactly these, and orc_event exposes them to the
+ * tests, which check them against the conservation laws they must obey.    */
+
+/* Compton (Sec. II.A): scattered photon (e1, d1) and recoil electron (t, dt);
+ * the electron's direction is that of the momentum the photon gave up,
+ * E d - E1 d1 (units of MeV/c), so momentum is conserved exactly and
+ * |E d - E1 d1| = sqrt(t (t + 2 mc^2)) is the Compton relation. */
+static void compton_event(double e, const double d[3], stream_t* s, double* e1, double d1[3], double* t,
+                          double dt[3]) {
+  double eps, cost;
+  sample_kn(e / MC2, s, &eps, &cost);
+  double phi = TWOPI * next_u(s);
+  rotate(d, cost, phi, d1);
+  *e1 = eps * e;
+  *t = e - *e1;
+  double pe[3] = { e * d[0] - *e1 * d1[0], e * d[1] - *e1 * d1[1], e * d[2] - *e1 * d1[2] };
+  double n2 = pe[0] * pe[0] + pe[1] * pe[1] + pe[2] * pe[2];
+  double inv = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+  dt[0] = pe[0] * inv; dt[1] = pe[1] * inv; dt[2] = pe[2] * inv;
+}
+
+/* Photoelectric (Sec. II.A): one electron with the whole photon energy
+ * (binding neglected) in the Sauter direction. */
+static void photo_event(double e, const double d[3], stream_t* s, double de[3]) {
+  double cost = sample_sauter(e, s);
+  double phi = TWOPI * next_u(s);
+  rotate(d, cost, phi, de);
+}
+
+/* [reading] pair production without positron transport (Sec. II.A): two
+ * electrons share e - 2 mc^2 uniformly, each at its own (1 - beta cos)^-2
+ * angle, at opposite azimuths. */
+static void pair_event(double e, const double d[3], stream_t* s, double* t1, double d1[3], double* t2,
+                       double d2[3]) {
+  double avail = e - 2.0 * MC2;
+  *t1 = next_u(s) * avail;
+  *t2 = avail - *t1;
+  double c1 = pair_cos(*t1, next_u(s));
+  double c2 = pair_cos(*t2, next_u(s));
+  double phi = TWOPI * next_u(s);
+  rotate(d, c1, phi, d1);
+  rotate(d, c2, phi + PI, d2);
+}
+
+/* Moller (Sec. II.B.1): binary collision of an electron of kinetic energy t
+ * with a free electron at rest; the delta ray (w, dd) and the primary
+ * (t - w, dp) leave at the two-body angles cos^2 = T'(T + 2 mc^2) /
+ * (T (T' + 2 mc^2)) of each outgoing kinetic energy T', at opposite
+ * azimuths, so that their momenta add up to the incoming one. */
+static void moller_event(double t, const double d[3], double kcut, stream_t* s, double* w, double dd[3],
+                         double* tp, double dp[3]) {
+  double eps = sample_moller(t, kcut, s);
+  *w = eps * t;
+  *tp = t - *w;
+  double cd = sqrt(*w * (t + 2.0 * MC2) / (t * (*w + 2.0 * MC2)));
+  double cpp = sqrt(*tp * (t + 2.0 * MC2) / (t * (*tp + 2.0 * MC2)));
+  double phi = TWOPI * next_u(s);
+  rotate(d, cd, phi, dd);
+  rotate(d, cpp, phi + PI, dp);
+}
+
+/* [reading] bremsstrahlung (Sec. II.B.1): photon energy k from the
+ * complete-screening spectrum, emitted at the polar angle mc^2 / E (E the
+ * electron's total energy) with a uniform azimuth; the electron keeps its
+ * direction and loses k. */
+static void brems_event(double t, const double d[3], double kc, stream_t* s, double* k, double dg[3]) {
+  *k = sample_brems(t, kc, s);
+  double phi = TWOPI * next_u(s);
+  rotate(d, cos(MC2 / (t + MC2)), phi, dg);
+}
+
+int orc_event(int which, double e, double p2, const double d[3], uint64_t seed, int count, double* out) {
+  uint32_t key[2]; make_key(seed, 0, key);
+  for (int i = 0; i < count; ++i) {
+    stream_t s; stream_init(&s, key, (uint32_t)i, 0, 0);
+    double* o = out + 8 * (size_t)i;
+    double ea = 0.0, eb = 0.0, da[3] = { 0, 0, 0 }, db[3] = { 0, 0, 0 };
+    switch (which) {
+      case 0: compton_event(e, d, &s, &ea, da, &eb, db); break;
+      case 1: ea = e; photo_event(e, d, &s, da); break;
+      case 2: if (e <= 2.0 * MC2) return -1; pair_event(e, d, &s, &ea, da, &eb, db); break;
+      case 3: if (e <= 2.0 * p2) return -1; moller_event(e, d, p2, &s, &ea, da, &eb, db); break;
+      case 4: if (e <= p2) return -1; brems_event(e, d, p2, &s, &ea, da); eb = e - ea; memcpy(db, d, sizeof db); break;
+      default: return -1;
+    }
+    o[0] = ea; o[1] = da[0]; o[2] = da[1]; o[3] = da[2];
+    o[4] = eb; o[5] = db[0]; o[6] = db[1]; o[7] = db[2];
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* Majorants for the Woodcock scheme (Eq. 3; Sec. II.B.3 for electrons).
  * [reading] mu_hat is piecewise constant per grid bin: 1.001 times the largest
  * rho_max(m) mu_m at either bin edge over the materials present.  Sigma_hat is
@@ -559,6 +658,9 @@ typedef struct {
   double first_xyz[3];
   uint32_t first_n;
   int first_hit;
+  /* path-limited electron tracks (test modes 3 and 4) */
+  double path_left;
+  int track_done;
 } ctx_t;
 
 static int inside(const ctx_t* c, const double* x) {
@@ -693,44 +795,26 @@ static void photon_run(ctx_t* c, part_t* p) {
     }
     if (c->mode == 1) { deposit(c, v, e); return; }
     if (r < mc) {
-      /* Compton: scattered photon and a recoil electron whose direction
-       * follows from momentum conservation. */
-      double eps, cost;
-      sample_kn(e / MC2, &s, &eps, &cost);
-      double phi = TWOPI * next_u(&s);
-      double d1[3]; rotate(p->d, cost, phi, d1);
-      double e1 = eps * e, t = e - e1;
-      if (t >= c->ecut) {
-        double pe[3] = { e * p->d[0] - e1 * d1[0], e * p->d[1] - e1 * d1[1], e * p->d[2] - e1 * d1[2] };
-        double inv = 1.0 / sqrt(pe[0] * pe[0] + pe[1] * pe[1] + pe[2] * pe[2]);
-        pe[0] *= inv; pe[1] *= inv; pe[2] *= inv;
-        spawn(c, 1, p->x, pe, t, orc_child_path(p->path, s.n, 0), v);
-      } else {
-        deposit(c, v, t);
-      }
+      /* Compton: scattered photon and a recoil electron. */
+      double e1, t, d1[3], dt[3];
+      compton_event(e, p->d, &s, &e1, d1, &t, dt);
+      if (t >= c->ecut) spawn(c, 1, p->x, dt, t, orc_child_path(p->path, s.n, 0), v);
+      else deposit(c, v, t);
       memcpy(p->d, d1, sizeof d1);
       p->e = e1;
       if (e1 < c->pcut) { deposit(c, v, e1); return; }
     } else if (r < mc + mp) {
-      /* Photoelectric: one electron with the full photon energy (binding
-       * neglected), Sauter direction. */
-      double cost = sample_sauter(e, &s);
-      double phi = TWOPI * next_u(&s);
-      double de[3]; rotate(p->d, cost, phi, de);
+      /* Photoelectric: one electron with the full photon energy. */
+      double de[3];
+      photo_event(e, p->d, &s, de);
       spawn(c, 1, p->x, de, e, orc_child_path(p->path, s.n, 0), v);
       return;
     } else {
-      /* Pair: two electrons, uniform energy split, opposite azimuths; the
-       * rest energy 2 mc^2 leaves the ledger as a sink (no positrons). */
+      /* Pair: two electrons; the rest energy 2 mc^2 leaves the ledger as a
+       * sink (no positrons). */
+      double t1, t2, d1[3], d2[3];
+      pair_event(e, p->d, &s, &t1, d1, &t2, d2);
       double avail = e - 2.0 * MC2;
-      double t1 = next_u(&s) * avail;
-      double t2 = avail - t1;
-      double c1 = pair_cos(t1, next_u(&s));
-      double c2 = pair_cos(t2, next_u(&s));
-      double phi = TWOPI * next_u(&s);
-      double d1[3], d2[3];
-      rotate(p->d, c1, phi, d1);
-      rotate(p->d, c2, phi + PI, d2);
       kadd(&c->e_sink, e - avail);
       spawn(c, 1, p->x, d1, t1, orc_child_path(p->path, s.n, 0), v);
       spawn(c, 1, p->x, d2, t2, orc_child_path(p->path, s.n, 1), v);
@@ -751,6 +835,9 @@ static void photon_run(ctx_t* c, part_t* p) {
  * Sigma(end)/Sigma_hat and split into Moller or bremsstrahlung. */
 static void electron_run(ctx_t* c, part_t* p) {
   stream_t s; stream_init(&s, c->key, c->hist, p->path, p->n);
+  /* test modes: 2 straight-ahead CSDA (no hard events, no deflection);
+   * 3 CSDA loss and deflection without hard events; 4 deflection only */
+  const int no_hard = c->mode >= 2, no_ms = c->mode == 2, no_loss = c->mode == 4;
   for (;;) {
     stream_align(&s);
     double t = p->e;
@@ -763,7 +850,7 @@ static void electron_run(ctx_t* c, part_t* p) {
     c->st.n_e_steps++;
     double sh = c->sig_hat[ebin(t)];
     double uh = next_u(&s);
-    double ehard = (c->mode == 2 || !(sh > 0.0)) ? INFINITY : -log(uh) / sh;
+    double ehard = (no_hard || !(sh > 0.0)) ? INFINITY : -log(uh) / sh;
     double dv = dist_boundary(c, p->x, p->d, ix, iy, iz);
     if (dv < c->skin) dv = c->skin;
     double emax = (c->esmax > 0.0 && rho0 > 0.0) ? c->esmax / rho0 : INFINITY;
@@ -771,10 +858,11 @@ static void electron_run(ctx_t* c, part_t* p) {
     int hard = 0;
     if (emax < es) es = emax;
     if (ehard < es) { es = ehard; hard = 1; }
+    if (c->path_left < es) es = c->path_left;   /* a path-limited test track (never hard: modes 3, 4) */
     double l0 = rho0 * l_total(m0, t, c->kcut, c->kc);
     double tm = t - 0.5 * es * l0;
     if (tm < EMIN) tm = EMIN;
-    double de = es * rho0 * l_total(m0, tm, c->kcut, c->kc);
+    double de = no_loss ? 0.0 : es * rho0 * l_total(m0, tm, c->kcut, c->kc);
     /* one word gives the hinge fraction (its top 24 bits) and the fair coin of
      * the deflection energy (its lowest bit, which the uniform does not use) */
     uint32_t wz = stream_word(&s);
@@ -784,7 +872,9 @@ static void electron_run(ctx_t* c, part_t* p) {
     if (t1 < c->ecut) { deposit(c, v0, t); return; }
     double tms = (wz & 1u) ? t1 : t;
     double ua = next_u(&s), uphi = next_u(&s);
-    if (c->mode != 2) {
+    if (!no_ms) {
+      /* Sec. II.B.2: the first moment of the deflection over the step,
+       * G1 = 1 - exp(-e_s / lambda_1), lambda_1 at the chosen energy */
       double g1 = -expm1(-es * rho0 * inv_lambda1(m0, tms));
       double cost = wentzel_cos(g1, ua);
       double nd[3]; rotate(p->d, cost, TWOPI * uphi, nd);
@@ -793,6 +883,13 @@ static void electron_run(ctx_t* c, part_t* p) {
     deposit(c, v0, de);
     p->e = t1;
     move(p, (1.0 - zeta) * es);
+    if (c->path_left < INFINITY) {
+      c->path_left -= es;
+      if (c->path_left <= 1e-12 * es) {
+        c->track_done = 1;
+        return;
+      }
+    }
     int jx, jy, jz;
     size_t v1;
     if (!electron_voxel(c, p->x, p->d, &jx, &jy, &jz, &v1)) { escape(c, t1); return; }
@@ -805,27 +902,17 @@ static void electron_run(ctx_t* c, part_t* p) {
     if (sm + sb > sh) c->st.n_majorant_violations++;
     double r = ur * sh;
     if (r < sm) {
-      /* Moller: binary collision with a free electron at rest. */
       c->st.n_hard++;
-      double eps = sample_moller(t1, c->kcut, &s);
-      double w = eps * t1, tp = t1 - w;
-      double cd = sqrt(w * (t1 + 2.0 * MC2) / (t1 * (w + 2.0 * MC2)));
-      double cpp = sqrt(tp * (t1 + 2.0 * MC2) / (t1 * (tp + 2.0 * MC2)));
-      double phi = TWOPI * next_u(&s);
-      double dd[3], dp[3];
-      rotate(p->d, cd, phi, dd);
-      rotate(p->d, cpp, phi + PI, dp);
+      double w, tp, dd[3], dp[3];
+      moller_event(t1, p->d, c->kcut, &s, &w, dd, &tp, dp);
       spawn(c, 1, p->x, dd, w, orc_child_path(p->path, s.n, 0), v1);
       memcpy(p->d, dp, sizeof dp);
       p->e = tp;
       if (tp < c->ecut) { deposit(c, v1, tp); return; }
     } else if (r < sm + sb) {
-      /* Bremsstrahlung: electron direction unchanged, photon at
-       * theta = mc^2 / E (E total energy of the incoming electron). */
       c->st.n_hard++;
-      double k = sample_brems(t1, c->kc, &s);
-      double phi = TWOPI * next_u(&s);
-      double dg[3]; rotate(p->d, cos(MC2 / (t1 + MC2)), phi, dg);
+      double k, dg[3];
+      brems_event(t1, p->d, c->kc, &s, &k, dg);
       spawn(c, 0, p->x, dg, k, orc_child_path(p->path, s.n, 0), v1);
       p->e = t1 - k;
       if (p->e < c->ecut) { deposit(c, v1, p->e); return; }
@@ -852,7 +939,8 @@ static int ctx_setup(ctx_t* c, const orc_material* mats, int n_mat, const orc_ph
   c->lx = ph->nx * ph->dx; c->ly = ph->ny * ph->dy; c->lz = ph->nz * ph->dz;
   double dmin = ph->dx < ph->dy ? ph->dx : ph->dy;
   if (ph->dz < dmin) dmin = ph->dz;
-  c->skin = 1e-4 * dmin;
+  c->skin = g_skin_fraction * dmin;
+  c->path_left = INFINITY;
   make_key(seed, beam, c->key);
   if (build_majorants(c->mats, n_mat, ph, c->kcut, c->kc, c->mu_hat, c->sig_hat)) return -2;
   c->tmp = (double*)calloc(nv, sizeof(double));
@@ -945,7 +1033,10 @@ int orc_run(const orc_material* mats, int n_mat, const orc_phantom* ph,
             double* e1, double* e2, double* eb, orc_stats* st) {
   if (check_source(src)) return -1;
   if (h_end < h_begin || h_end > n_total || n_total > 0xFFFFFFFFull) return -1;
-  int nb = phys && phys->n_batches > 0 ? phys->n_batches : 1;
+  /* mode 4 (deflection without energy loss) only ends an electron at the
+   * phantom's surface; it serves path-limited tracks alone */
+  if (!phys || phys->test_mode < 0 || phys->test_mode > 3) return -1;
+  int nb = phys->n_batches > 0 ? phys->n_batches : 1;
   ctx_t c;
   int rc = ctx_setup(&c, mats, n_mat, ph, phys, seed, src->beam_id);
   if (rc) { ctx_free(&c); return rc; }
@@ -1023,4 +1114,33 @@ int orc_majorants(const orc_material* mats, int n_mat, const orc_phantom* ph,
   int rc = build_majorants(m, n_mat, ph, kcut, kc, mu_hat, sigma_hat);
   free(m);
   return rc;
+}
+
+int orc_electron_tracks(const orc_material* mats, int n_mat, const orc_phantom* ph,
+                        const orc_source* src, const orc_physics* phys, uint64_t seed,
+                        uint64_t h_begin, uint64_t h_end, double path_cm, double z_start, double* out) {
+  if (check_source(src) || src->particle != 1) return -1;
+  if (!phys || (phys->test_mode != 3 && phys->test_mode != 4) || !(path_cm > 0.0)) return -1;
+  ctx_t c;
+  int rc = ctx_setup(&c, mats, n_mat, ph, phys, seed, src->beam_id);
+  if (rc) { ctx_free(&c); return rc; }
+  for (uint64_t h = h_begin; h < h_end; ++h) {
+    double* o = out + 5 * (h - h_begin);
+    c.hist = (uint32_t)h;
+    part_t p;
+    sample_source(src, c.key, c.hist, &p);
+    p.x[2] = z_start;
+    c.path_left = path_cm;
+    c.track_done = 0;
+    if (inside(&c, p.x) && p.e >= c.ecut) electron_run(&c, &p);
+    if (c.track_done) {
+      o[0] = p.d[0]; o[1] = p.d[1]; o[2] = p.d[2]; o[3] = p.e; o[4] = p.x[2];
+    } else {
+      o[0] = o[1] = o[2] = o[3] = o[4] = NAN;
+    }
+    for (size_t i = 0; i < c.n_touched; ++i) c.tmp[c.touched[i]] = 0.0;
+    c.n_touched = 0;
+  }
+  ctx_free(&c);
+  return 0;
 }

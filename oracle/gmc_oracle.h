@@ -46,7 +46,10 @@ typedef struct {
   double kcut, kc;         /* Moller and bremsstrahlung thresholds (<=0 -> ecut, pcut) */
   double esmax_gcm2;       /* user step bound in g/cm^2 (<=0 -> none) */
   int n_batches;           /* K for the batch variance estimate */
-  int test_mode;           /* 0 full, 1 photon first collision, 2 electron CSDA straight-ahead */
+  int test_mode;           /* 0 full, 1 photon first collision, 2 electron CSDA straight-ahead,
+                              3 electron CSDA loss and deflection without hard events,
+                              4 electron deflection only (no energy loss, no hard events;
+                              path-limited tracks only) */
 } orc_physics;
 
 typedef struct {
@@ -102,6 +105,29 @@ int orc_sample_source(const orc_source* src, uint64_t seed, uint64_t h_begin, ui
 int orc_first_events(const orc_material* mats, int n_mat, const orc_phantom* ph,
                      const orc_source* src, const orc_physics* phys, uint64_t seed,
                      uint64_t h_begin, uint64_t h_end, double* xyz, uint32_t* n_used);
+
+/* Outgoing particles of one event, `count` samples on the streams
+ * (seed, 0, hist i, path 0) of an incoming particle of energy e (MeV) moving
+ * along d.  which: 0 Compton (photon, recoil electron), 1 photoelectric
+ * (electron), 2 pair (two electrons), 3 Moller (p2 = kcut: delta ray, primary),
+ * 4 bremsstrahlung (p2 = kc: photon, electron).  out[8 i .. 8 i + 7] =
+ * E_a, d_a, E_b, d_b (unused entries zero).  Returns -1 below the event's
+ * threshold or for an unknown kind. */
+int orc_event(int which, double e, double p2, const double d[3], uint64_t seed, int count, double* out);
+
+/* Path-limited tracks of the primary electrons of histories [h_begin, h_end)
+ * in test mode 3 or 4, started at depth z_start (instead of the phantom's
+ * entrance face) along +z: each stops after path_cm of path (its last step
+ * shortened to fit).  out[5 i .. 5 i + 4] = final direction, kinetic energy and
+ * depth z, or NaN if the electron left the phantom or fell below the cutoff
+ * first. */
+int orc_electron_tracks(const orc_material* mats, int n_mat, const orc_phantom* ph,
+                        const orc_source* src, const orc_physics* phys, uint64_t seed,
+                        uint64_t h_begin, uint64_t h_end, double path_cm, double z_start, double* out);
+
+/* The electron voxel skin as a fraction of the smallest voxel width (default
+ * 1e-4; values outside (0, 0.5) are ignored).  Process-wide. */
+void orc_set_skin_fraction(double f);
 
 #ifdef __cplusplus
 }

@@ -80,6 +80,7 @@ _lib = None
 XS = {"mu_C": 0, "mu_pe": 1, "mu_pair": 2, "S_col": 3, "Sigma_M": 4, "E_M_hard": 5, "L_col": 6,
       "Sigma_B": 7, "L_rad": 8, "S_rad": 9, "L": 10, "inv_lambda1": 11, "eta": 12}
 SAMPLERS = {"kn": 0, "sauter": 1, "pair": 2, "moller": 3, "brems": 4, "wentzel": 5}
+EVENTS = {"compton": 0, "photo": 1, "pair": 2, "moller": 3, "brems": 4}
 
 
 def lib():
@@ -109,6 +110,12 @@ def lib():
         L.orc_sample_source.argtypes = [C.POINTER(_Source), C.c_uint64, C.c_uint64, C.c_uint64, dp]
         L.orc_first_events.argtypes = [C.POINTER(_Material), C.c_int, C.POINTER(_Phantom), C.POINTER(_Source),
                                        C.POINTER(_Physics), C.c_uint64, C.c_uint64, C.c_uint64, dp, u32p]
+        L.orc_event.argtypes = [C.c_int, C.c_double, C.c_double, dp, C.c_uint64, C.c_int, dp]
+        L.orc_electron_tracks.argtypes = [C.POINTER(_Material), C.c_int, C.POINTER(_Phantom), C.POINTER(_Source),
+                                          C.POINTER(_Physics), C.c_uint64, C.c_uint64, C.c_uint64, C.c_double, C.c_double,
+                                          dp]
+        L.orc_set_skin_fraction.argtypes = [C.c_double]
+        L.orc_set_skin_fraction.restype = None
         _lib = L
     return _lib
 
@@ -206,6 +213,44 @@ def sample(which: str, p1: float, p2: float = 0.0, seed: int = 1, count: int = 1
     rc = lib().orc_sample(SAMPLERS[which], p1, p2, seed, count, _ptr(out, C.c_double), _ptr(out2, C.c_double))
     assert rc == 0
     return (out, out2) if which == "kn" else out
+
+
+def event(which: str, e: float, p2: float = 0.0, direction=(0.0, 0.0, 1.0), seed: int = 1, count: int = 10000):
+    """Outgoing particles of `count` events of kind `which` (compton, photo,
+    pair, moller with p2 = kcut, brems with p2 = kc) for an incoming particle
+    of energy e along `direction`, each on its own stream: rows (E_a, d_a,
+    E_b, d_b) as returned by the transport's own event routine."""
+    d = np.ascontiguousarray(direction, dtype=np.float64)
+    out = np.zeros((count, 8))
+    rc = lib().orc_event(EVENTS[which], e, p2, _ptr(d, C.c_double), seed, count, _ptr(out, C.c_double))
+    if rc != 0:
+        raise ValueError("event below threshold or unknown")
+    return out
+
+
+def electron_tracks(materials, phantom, source, physics, seed: int, h_begin: int, h_end: int, path_cm: float,
+                    z_start: float = 0.0):
+    """Primary electrons of histories [h_begin, h_end) in test mode 3 or 4,
+    started at depth z_start along +z and stopped after path_cm of path: rows
+    (u, v, w, T, z), NaN where the electron left the phantom or fell below
+    the cutoff first."""
+    n = h_end - h_begin
+    out = np.zeros((n, 5))
+    mats = _materials(materials)
+    ph, keep = _phantom(phantom)
+    src = _source(source)
+    phy = _physics(physics)
+    rc = lib().orc_electron_tracks(mats, len(materials), C.byref(ph), C.byref(src), C.byref(phy), seed, h_begin,
+                                   h_end, path_cm, z_start, _ptr(out, C.c_double))
+    if rc != 0:
+        raise ValueError("oracle rejected the input (code %d)" % rc)
+    return out
+
+
+def set_skin_fraction(f: float) -> None:
+    """The electron voxel skin as a fraction of the smallest voxel width
+    (default 1e-4), for this process and the workers it forks later."""
+    lib().orc_set_skin_fraction(float(f))
 
 
 def ms_screening_A(g1: float) -> float:

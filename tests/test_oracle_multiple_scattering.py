@@ -1,0 +1,123 @@
+"""Transport-level pins of the oracle's multiple scattering (Sec. II.B.2-3).
+
+The deflection of a condensed step is drawn from a screened-Rutherford shape
+whose first moment is G1 = 1 - exp(-s rho / lambda_1) (lambda_1 per unit
+density, at the energy the step's coin picks).  Two properties fix how the
+transport applies it, independently of the sampler tests:
+
+* **Addition theorem.**  With energy loss and hard events off (test mode 4),
+  the deflections of successive steps are independent rotations, symmetric
+  about the current direction, so after a total path s the mean cosine to the
+  initial direction is prod_i exp(-s_i rho / lambda_1) = exp(-s rho / lambda_1)
+  exactly, for any way the path is split into steps (by e_s-max, by voxel
+  boundaries, by the random hinges).  A deflection applied with the wrong
+  density, path or rotation fails it; azimuths that are not uniform show as a
+  lateral drift or unequal lateral spreads.
+* **Deflection energy.**  With CSDA loss on and hard events off (test mode 3),
+  a single step of length s from T0 to T1 turns the electron by an angle
+  whose mean cosine is [exp(-s rho/lambda_1(T0)) + exp(-s rho/lambda_1(T1))]/2:
+  the fair coin of Sec. II.B.3 picks the energy before or after the loss.
+  Taking only T0 or only T1 would move the mean by many standard errors.
+
+lambda_1 comes from the oracle's closed form, which test_oracle_xs pins
+against the quadrature of the screened-Rutherford cross section.  A third
+test shows that the electron voxel skin (a reading: points a hair short of a
+face count as beyond it) leaves the dose unchanged within statistics.
+"""
+import numpy as np
+import pytest
+
+from paper_1101_1245_amd import evaluate as E
+from paper_1101_1245_amd.inputs import BONE, ELECTRON, LUNG, WATER, Phantom, Physics, Source, centred, homogeneous, z_slabs
+
+
+def inv_l1(oracle, m, t):
+    return float(oracle.xs(m, "inv_lambda1", [t])[0])
+
+
+def box(n, voxel, density, mat=0):
+    return homogeneous((n, n, n), voxel, mat, density)
+
+
+@pytest.mark.parametrize("mat,rho,t,path", [(WATER, 1.0, 5.0, 3.0), (LUNG, 0.26, 5.0, 10.0), (BONE, 1.85, 15.0, 5.0)])
+@pytest.mark.parametrize("split", [1, 4, 16])
+def test_mean_cosine_addition_theorem(oracle, mat, rho, t, path, split):
+    ph = box(40, 1.0, rho)   # 40 cm: a track started at its centre cannot leave within the path
+    src = centred(ph, Source(ELECTRON, e=t, wx=0.0, wy=0.0))
+    phys = Physics(ecut=0.2, pcut=0.01, esmax_gcm2=rho * path / split, test_mode=4)
+    n = 20000
+    out = oracle.electron_tracks((mat,), ph, src, phys, seed=21 + split, h_begin=0, h_end=n, path_cm=path,
+                                 z_start=20.0)
+    assert np.all(np.isfinite(out)), "a track left the phantom"
+    assert np.all(out[:, 3] == t)                       # no energy loss in this mode
+    w = out[:, 2]
+    want = np.exp(-path * rho * inv_l1(oracle, mat, t))
+    assert 0.3 < want < 0.8
+    se = w.std() / np.sqrt(n)
+    assert abs(w.mean() - want) < 4 * se, (w.mean(), want, se)
+    # azimuths uniform: no lateral drift, the same spread along x and y
+    for c in (0, 1):
+        assert abs(out[:, c].mean()) < 4 * out[:, c].std() / np.sqrt(n), c
+    u2, v2 = out[:, 0] ** 2, out[:, 1] ** 2
+    assert abs(u2.mean() - v2.mean()) < 4 * np.sqrt((u2.var() + v2.var()) / n)
+
+
+@pytest.mark.parametrize("mat,rho,t0,path", [(WATER, 1.0, 1.0, 0.15), (BONE, 1.85, 5.0, 0.6), (LUNG, 0.26, 2.0, 2.0)])
+def test_single_step_deflection_energy(oracle, mat, rho, t0, path):
+    ph = Phantom(np.full((1, 1, 1), rho, np.float32), np.zeros((1, 1, 1), np.uint8), (60.0, 60.0, 60.0))
+    src = centred(ph, Source(ELECTRON, e=t0, wx=0.0, wy=0.0))
+    phys = Physics(ecut=0.2, pcut=0.01, esmax_gcm2=rho * path, test_mode=3)
+    n = 40000
+    out = oracle.electron_tracks((mat,), ph, src, phys, seed=33, h_begin=0, h_end=n, path_cm=path,
+                                 z_start=30.0)
+    assert np.all(np.isfinite(out))
+    t1 = out[0, 3]
+    assert np.all(out[:, 3] == t1) and 0.2 < t1 < t0      # the loss of one step is deterministic
+    a0 = np.exp(-path * rho * inv_l1(oracle, mat, t0))
+    a1 = np.exp(-path * rho * inv_l1(oracle, mat, t1))
+    w = out[:, 2]
+    se = w.std() / np.sqrt(n)
+    assert abs(w.mean() - 0.5 * (a0 + a1)) < 4 * se, (w.mean(), a0, a1, se)
+    assert abs(a0 - a1) > 12 * se                        # either energy alone would fail
+
+
+def test_tracks_refuse_other_modes(oracle):
+    ph = box(4, 1.0, 1.0)
+    src = centred(ph, Source(ELECTRON, e=1.0))
+    with pytest.raises(ValueError):
+        oracle.electron_tracks((WATER,), ph, src, Physics(test_mode=0), 1, 0, 10, 1.0)
+    with pytest.raises(ValueError):
+        oracle.run((WATER,), ph, src, Physics(test_mode=4), 1, 10)
+
+
+def test_voxel_skin_does_not_change_the_dose(oracle):
+    # 6 MeV electrons through water / bone / lung slabs on 0.25 cm voxels:
+    # the same histories with the skin at 1e-4 and at 1e-6 of a voxel width.
+    # Trajectories part where a step's voxel differs, so the two estimates
+    # are correlated but not equal.  The dose per voxel must agree within
+    # statistics (same-stream z-test), and so must the energy deposited in
+    # each slab: a paired t-test on the differences of the 32 batches' slab
+    # sums (batch k holds the histories h = k mod 32 of both runs).
+    mats = (WATER, BONE, LUNG)
+    ph = z_slabs((24, 24, 64), 0.25, [(3.0, 0, 1.0), (5.0, 1, 1.85), (12.0, 2, 0.26), (16.0, 0, 1.0)])
+    src = centred(ph, Source(ELECTRON, e=6.0, wx=3.0, wy=3.0))
+    phys = Physics(ecut=0.2, pcut=0.01, n_batches=32)
+    n = 16000
+    try:
+        oracle.set_skin_fraction(1e-6)
+        b = oracle.run(mats, ph, src, phys, seed=41, n_hist=n)
+    finally:
+        oracle.set_skin_fraction(1e-4)
+    a = oracle.run(mats, ph, src, phys, seed=41, n_hist=n)
+    assert a.stats["e_in"] == b.stats["e_in"]
+    da, sa = oracle.dose(a, ph)
+    db, sb = oracle.dose(b, ph)
+    zt = E.z_test(da, sa, db, sb, dof=n - 1, same_streams=True)
+    assert zt.passed, (zt.n, zt.frac_over_3, zt.max_abs, zt.mean, zt.var)
+    for z0, z1 in ((0, 12), (12, 20), (20, 48), (48, 64)):
+        diff = a.eb[:, z0:z1].sum(axis=(1, 2, 3)) - b.eb[:, z0:z1].sum(axis=(1, 2, 3))
+        t = diff.mean() / (diff.std(ddof=1) / np.sqrt(diff.size))
+        assert abs(t) < 4.0, (z0, z1, t)
+    # what the skin is for: without it a step's end point, left a hair short
+    # of the face it heads for, starts another step in the same voxel
+    assert b.stats["n_e_steps"] > a.stats["n_e_steps"]
