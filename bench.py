@@ -123,8 +123,8 @@ class Acc:
     """Sums of pass-kernel times and work units over runs."""
 
     def __init__(self):
-        self.t = [0.0, 0.0]      # photon, electron pass seconds
-        self.n = [0, 0]          # launches
+        self.t = [0.0, 0.0, 0.0]  # photon pass, electron pass, persistent round kernel seconds
+        self.n = [0, 0, 0]        # launches
         self.steps = 0
         self.events = 0
         self.resid = 0
@@ -135,13 +135,15 @@ class Acc:
         self.t[1] += st["t_electron_pass_s"]
         self.n[0] += st["n_photon_launches"]
         self.n[1] += st["n_electron_launches"]
+        self.t[2] += st["t_round_s"]
+        self.n[2] += st["n_round_launches"]
         self.steps += st["n_e_steps"]
         self.events += st["n_photon_events"]
         self.resid |= st["ledger_residual_lsb"]
         self.hist += st["n_hist"]
 
     def merge(self, o):
-        for i in range(2):
+        for i in range(3):
             self.t[i] += o.t[i]
             self.n[i] += o.n[i]
         self.steps += o.steps
@@ -153,7 +155,11 @@ class Acc:
 def roofline(acc, workload="water"):
     """Dominant pass kernel (most device time), its average launch duration and
     algorithmic lane-ops per launch against the VALU lane-op peak."""
-    if acc.t[1] >= acc.t[0]:
+    if acc.t[2] > max(acc.t[0], acc.t[1]):
+        # persistent round kernels: both particle types in each launch
+        name, t, n = "k_round", acc.t[2], acc.n[2]
+        ops = acc.steps * OPS_PER_E_STEP + acc.events * OPS_PER_PH_EVENT
+    elif acc.t[1] >= acc.t[0]:
         name, t, n, ops = "k_electron_pass", acc.t[1], acc.n[1], acc.steps * OPS_PER_E_STEP
     else:
         name, t, n, ops = "k_photon_pass", acc.t[0], acc.n[0], acc.events * OPS_PER_PH_EVENT
@@ -162,11 +168,11 @@ def roofline(acc, workload="water"):
     achieved = ops / n / avg / 1e12 if avg > 0 else 0.0
     peak = PEAK_LANE_OPS / 1e12
     per_unit = measured_traffic(name) if workload == "water" else None
-    units = (acc.steps if name == "k_electron_pass" else acc.events) / n
+    units = (acc.steps if name != "k_photon_pass" else acc.events) / n
     traffic = per_unit * units if per_unit else None
     out = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": peak, "unit": "TOP/s",
            "frac": achieved / peak, "traffic": traffic, "avg_launch_ms": avg * 1e3, "launches": n,
-           "share_of_pass_time": t / max(acc.t[0] + acc.t[1], 1e-30)}
+           "share_of_pass_time": t / max(acc.t[0] + acc.t[1] + acc.t[2], 1e-30)}
     if traffic:
         out["traffic_unit"] = "HBM bytes per launch (%.2f per unit of work x %.3g units)" % (per_unit, units)
         out["hbm_GBps"] = traffic / avg / 1e9
@@ -654,9 +660,31 @@ def bench_serve(args, G, I):
         th.join()
     finally:
         ctx.server_stop()
+    acc_stream, acc = acc, Acc()      # the closed loop below is not part of the stream's kernel statistics
     lat = np.array([st["t_latency_s"] for st in stats])
     queue = np.array([st["t_queue_s"] for st in stats])
     hist = sum(r.n_hist for r in reqs)
+
+    # the same requests as a closed loop (all submitted at once) and through
+    # the plain form one after another: throughput of the two forms on
+    # identical work
+    ctx.server_start(max_slots=args.serve_slots)
+    try:
+        sync()
+        t0 = time.perf_counter()
+        tickets = [ctx.submit(pids[r.phantom], tid, r.source, r.n_hist, 20_000 + r.seed) for r in reqs]
+        drain(tickets, reqs)
+        el_closed = time.perf_counter() - t0
+    finally:
+        ctx.server_stop()
+    acc_plain = Acc()
+    sync()
+    t0 = time.perf_counter()
+    for r in reqs:
+        _, _, st = ctx.run_beam(pids[r.phantom], tid, r.source, r.n_hist, 20_000 + r.seed, sigma=True, out="torch")
+        acc_plain.add(st)
+    sync()
+    el_plain = time.perf_counter() - t0
     for p in pids:
         ctx.release(p)
     ctx.close()
@@ -666,13 +694,21 @@ def bench_serve(args, G, I):
         "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
         "mean_latency_s": float(lat.mean()), "p99_queue_s": float(np.percentile(queue, 99)),
         "histories_per_s": hist / el, "histories": hist, "elapsed_s": el,
+        "closed_loop": {"histories_per_s": hist / el_closed, "elapsed_s": el_closed,
+                        "note": "all requests submitted at once to the server"},
+        "plain_sequential": {"histories_per_s": hist / el_plain, "elapsed_s": el_plain,
+                             "note": "the same requests through gmc_run_beam one after another, outputs on the "
+                                     "device"},
+        "closed_loop_over_plain": el_plain / el_closed,
         "workload": "Poisson stream of %d requests (seed 13) at 0.7 x closed-loop capacity: cubic ellipsoid "
                     "phantoms 32^3-256^3 at 0.25-0.5 cm (pool of %d), photons:electrons 3:1, 1-20 MeV mono or "
                     "2-10-18 MeV triangular, 1-10 cm fields, 1e5-1e8 histories" % (len(reqs), len(pool)),
     }
+    print("served closed loop %.3e histories/s, plain one after another %.3e histories/s (x%.2f)" %
+          (hist / el_closed, hist / el_plain, el_plain / el_closed), file=sys.stderr, flush=True)
     print("served: p50 %.3f s p99 %.3f s, %.3e histories/s at %.2f req/s" %
           (out["p50_latency_s"], out["p99_latency_s"], out["histories_per_s"], rate), file=sys.stderr, flush=True)
-    return out, acc
+    return out, acc_stream
 
 
 def main():
@@ -683,6 +719,9 @@ def main():
     ap.add_argument("--workload", choices=("water", "beamlets", "geometries", "regroup", "atomics"), default="water")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form leg")
+    ap.add_argument("--no-beamlets", action="store_true", help="skip the 256-beamlet leg of the default workload")
+    ap.add_argument("--beamlet-steps", type=int, default=3,
+                    help="timed steps of the 256-beamlet leg of the default workload (each ~0.8 s)")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
@@ -714,6 +753,15 @@ def main():
         # stretches every kernel's duration
         out["roofline"] = roofline(acc)
         out["ledger_residual_lsb"] = acc.resid
+        if not args.no_beamlets:
+            import copy
+            bargs = copy.copy(args)
+            bargs.steps, bargs.warmup = max(1, args.beamlet_steps), 1
+            bl = bench_beamlets(bargs, G, E, I)
+            out["beamlets"] = {k: bl[k] for k in ("value", "unit", "steps", "ms_per_step", "plain",
+                                                   "batched_over_plain", "roofline", "ledger_residual_lsb")}
+            out["beamlets"]["workload"] = bl["config"]["workload"]
+            out["ledger_residual_lsb"] |= bl["ledger_residual_lsb"]
         if not args.no_serve:
             out["served"], acc_s = bench_serve(args, G, I)
             out["served"]["electron_pass_launches"] = acc_s.n[1]

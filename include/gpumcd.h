@@ -71,11 +71,18 @@ typedef struct { double z_over_a, z_eff, i_ev; } gmc_material;
  * Eq. 4 in g/cm^2 (<= 0: none).  n_batches is K of the batch uncertainty
  * estimate (default 32 when <= 0).  test_mode: 0 full transport; 1 photons
  * deposit their energy at their first real interaction; 2 electrons move in
- * straight lines with CSDA loss only (no hard events, no deflection). */
+ * straight lines with CSDA loss only (no hard events, no deflection).
+ * majorant_margin scales the Woodcock majorants of Eq. 3 (photons) and of
+ * the hard-event distance (electrons, Sec. II.B.3) over the largest
+ * attenuation they bound (<= 0: 1.001; accepted in [0.01, 100]).  Below 1 the
+ * majorant undercuts the real coefficient somewhere: the transport still runs
+ * and every such event is counted in n_majorant_violations (the dose is then
+ * biased; values below 1 exist to exercise that count). */
 typedef struct {
   double ecut_mev, pcut_mev, kcut_mev, kc_mev, esmax_gcm2;
   int n_batches;
   int test_mode;
+  double majorant_margin;
 } gmc_physics;
 
 /* Build the FP32 log-energy tables (cross sections, restricted stopping
@@ -104,7 +111,16 @@ int gmc_release(gmc_context* ctx, int32_t id);
  * evenly over the bin, sampled by inverting the piecewise-linear CDF.  The
  * tables are host memory, read during the call (copied by gmc_submit); they
  * are ignored by the other spectra.  beam_id enters the random stream key, so
- * beamlets with different ids draw independent streams. */
+ * beamlets with different ids draw independent streams.
+ * first_history numbers the beam's histories: a run of n histories
+ * transports histories first_history .. first_history + n - 1, drawing their
+ * random streams and falling into their batches (history h in batch
+ * h mod n_batches) exactly as those histories of one larger run do
+ * (first_history + n must stay below 2^32).  Shards of a beam run with
+ * consecutive ranges -- on one GPU after another or on several GPUs -- thus
+ * produce integer tallies whose sum is bit for bit the tally of the whole
+ * run (gmc_run_beam_tally, gmc_finalize_tally).  0 for an ordinary run;
+ * gmc_first_events takes explicit history numbers and ignores it. */
 typedef struct {
   int particle;
   int spectrum;
@@ -114,6 +130,7 @@ typedef struct {
   const double* tab_e;
   const double* tab_w;
   int tab_n;
+  uint64_t first_history;
 } gmc_source;
 
 /* Per-run statistics.  Energies in MeV; the integer ledger residual (in units
@@ -133,6 +150,8 @@ typedef struct {
   uint64_t n_photon_launches, n_electron_launches;
   double s_rel;   /* Eq. 12: mean sigma/D over voxels with D > 0.2 D_max of the
                      (combined) dose; NaN when sigma was not requested */
+  double t_round_s;            /* summed durations of the persistent round kernels */
+  uint64_t n_round_launches;   /* (tuning persistent), bracketed like the passes */
 } gmc_run_stats;
 
 /* Optional tuning of the engine.  A field <= 0 selects its default; a NULL
@@ -174,12 +193,34 @@ typedef struct {
  *     primaries remain to be admitted (a next pass of each type follows
  *     anyway; the last passes of a job finish in place) and for shares of at
  *     least 256 particles (0: default, 64 in the electron pass and 32 in the
- *     photon pass; 1..64 both passes; -1 off).
- * No tuning changes any result: the dose is bit-identical for every choice. */
+ *     photon pass; 1..64 both passes; -1 off);
+ *   queue_items: particles that admission and the other type's outputs may
+ *     put in a type's queue (its soft capacity; 64..2^25, default 8 x chunk,
+ *     at least 2^23).  A queue too small for the per-visit output budget
+ *     leaves neither pass able to move: such a job ends with GMC_EOVERFLOW
+ *     ("both particle queues are too full") instead of running forever;
+ *   persistent: > 0 runs each round as one persistent kernel instead of an
+ *     electron pass and a photon pass: its wavefronts claim chunks of
+ *     wave_items particles from a device work queue -- the round's
+ *     electrons first, then its photons (the round's new primaries come last
+ *     in each queue) -- from counters spread over eight partitions of each
+ *     queue, each wavefront up to a cap (an even share plus one chunk) that
+ *     bounds its staging, and no wavefront waits for another; every
+ *     workgroup holds both table blocks in LDS, so jobs with more than four
+ *     materials run the passes instead (default 0; energy_sort is ignored
+ *     with it);
+ *   aggregate: the electron pass sums, at the end of each loop iteration,
+ *     the tally additions of the wavefront's lanes that go to one address
+ *     and adds the sum with one atomic (1 on, -1 off; 0, the default: on
+ *     where every beam's own tally is a single slice -- per-beam doses of a
+ *     batched job too large for per-beam batches -- whose pencil beams send
+ *     many lanes to one address).
+ * No tuning changes any result: the dose is bit-identical for every choice
+ * that lets the job finish. */
 typedef struct {
   int events_per_visit, secondaries_per_visit, chunk, wg_size;
   int pass_items, wave_items, rounds_per_check, refill_lanes;
-  int energy_sort, tail_lanes;
+  int energy_sort, tail_lanes, queue_items, persistent, aggregate;
 } gmc_tuning;
 
 /* Transport n_histories histories of one beam (the plain form: one beam per
@@ -191,6 +232,37 @@ typedef struct {
 int gmc_run_beam(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const gmc_source* src,
                  uint64_t n_histories, uint64_t seed, double* dose_gy_per_hist, double* sigma_gy_per_hist,
                  int out_ptr_kind, const gmc_tuning* tuning, gmc_run_stats* stats);
+
+/* The plain form's run of gmc_run_beam, returning the raw integer batch
+ * tallies instead of the dose: tally[k * nvox + v] is the energy deposited in
+ * voxel v by the histories of batch k (history h of the run, numbered from
+ * src->first_history, in batch h mod n_batches), in units of 2^-27 MeV,
+ * n_batches * nx*ny*nz uint64 values in host or device memory per
+ * out_ptr_kind.  Tallies of runs over disjoint history ranges add up (as
+ * integers, in any order) to the tally of one run over their union: the
+ * exchange format of a beam sharded across GPUs (Sec. II.C.3's multi-GPU
+ * scheme, one reduction of integer sums).  stats as for gmc_run_beam (s_rel
+ * NaN). */
+int gmc_run_beam_tally(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const gmc_source* src,
+                       uint64_t n_histories, uint64_t seed, uint64_t* tally, int out_ptr_kind,
+                       const gmc_tuning* tuning, gmc_run_stats* stats);
+
+/* Dose per history and batch uncertainty (Sec. II.D: D = sum_k T_k / N in
+ * Gy; sigma^2 = sum_k n_k^2 (m_k - m)^2 / (N^2 (K - 1)/K), Eq. 13 over K
+ * batches) of integer batch tallies laid out as gmc_run_beam_tally writes
+ * them, covering histories [h_begin, h_end) of a beam (N = h_end - h_begin,
+ * at least n_batches; n_k the histories of batch k in that range), on the
+ * phantom's voxels.  tally is host or device memory per tally_ptr_kind,
+ * dose and sigma (sigma may be NULL) per out_ptr_kind; *s_rel (may be NULL)
+ * receives s of Eq. 12 (NaN without sigma).  Equal tallies and ranges give
+ * bit-identical results to gmc_run_beam's finalize. */
+int gmc_finalize_tally(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const uint64_t* tally,
+                       int tally_ptr_kind, uint64_t h_begin, uint64_t h_end, double* dose, double* sigma,
+                       int out_ptr_kind, double* s_rel);
+
+/* Grid size of a loaded phantom: the number of doubles every dose and sigma
+ * output of a run on it holds is nx*ny*nz. */
+int gmc_phantom_dims(gmc_context* ctx, int32_t phantom_id, int* nx, int* ny, int* nz);
 
 /* Transport several beams in one job (the batched form): primaries of every
  * beam are admitted into the shared per-type particle arrays as space frees

@@ -100,7 +100,8 @@ int resident_blocks(Workspace* w, int kernel, int block, int n_mat) {
   const std::vector<int> key{kernel, block, n_mat};
   auto it = w->resident.find(key);
   if (it != w->resident.end()) return it->second;
-  const size_t lds = kernel == 0 ? photon_lds_bytes(n_mat) : electron_lds_bytes(n_mat);
+  const size_t lds = kernel == 0 ? photon_lds_bytes(n_mat)
+                     : kernel == 1 ? electron_lds_bytes(n_mat) : round_lds_bytes(n_mat);
   const int r = max_resident_blocks(kernel, block, lds);
   w->resident[key] = r;
   return r;
@@ -245,7 +246,7 @@ int ws_ensure_beams(Workspace* w, size_t n) {
 
 // ---------------------------------------------------------------- settings
 Tune resolve_tuning(const gmc_tuning* t) {
-  Tune r{64, 4, 1 << 22, 0, 1 << 23, 64, 4, 4, 0, 32, 64};
+  Tune r{64, 4, 1 << 22, 0, 1 << 23, 64, 4, 4, 0, 32, 64, 0, 0, 0};
   if (t) {
     // an electron parked at a hard event keeps its visit's event count in 16 bits
     if (t->events_per_visit > 0) r.events = std::min(t->events_per_visit, 1 << 15);
@@ -264,6 +265,9 @@ Tune resolve_tuning(const gmc_tuning* t) {
     if (t->energy_sort > 0) r.sort = 1;
     if (t->tail_lanes < 0) r.tail_g = r.tail_e = 0;
     if (t->tail_lanes > 0) r.tail_g = r.tail_e = std::min(t->tail_lanes, 64);
+    if (t->queue_items > 0) r.queue = (int)std::min<uint32_t>(std::max(t->queue_items, 64), kMaxSoftCap);
+    if (t->persistent > 0) r.persistent = 1;
+    r.aggregate = t->aggregate > 0 ? 1 : (t->aggregate < 0 ? -1 : 0);
   }
   return r;
 }
@@ -281,6 +285,9 @@ gmc_tuning default_tuning() {
   t.refill_lanes = d.refill;
   t.energy_sort = d.sort;
   t.tail_lanes = 0;   // the per-pass defaults
+  t.queue_items = 0;
+  t.persistent = d.persistent;
+  t.aggregate = d.aggregate;
   return t;
 }
 
@@ -292,7 +299,9 @@ gmc_tuning default_tuning() {
 // the other type feeding it).  Staging: every wavefront of the pass grid
 // gets segments for its largest share of a pass times the per-visit budget.
 void queue_sizes(Workspace* w, const Tune& tu, int n_mat, uint32_t* cap, uint32_t* cap_soft, uint32_t* stg) {
-  const uint64_t soft = std::max<uint64_t>(kMinSoftCap, std::min<uint64_t>(8ull * (uint64_t)tu.chunk, kMaxSoftCap));
+  const uint64_t soft = tu.queue > 0 ? (uint64_t)tu.queue
+                                     : std::max<uint64_t>(kMinSoftCap, std::min<uint64_t>(8ull * (uint64_t)tu.chunk,
+                                                                                          kMaxSoftCap));
   *cap_soft = (uint32_t)soft;
   *cap = (uint32_t)(soft + (uint64_t)tu.secondaries * (uint64_t)tu.pass_items);
   uint32_t s = 0;
@@ -308,8 +317,23 @@ void queue_sizes(Workspace* w, const Tune& tu, int n_mat, uint32_t* cap, uint32_
     const uint32_t qmax = (chunks + waves - 1) / waves * cs;
     s = std::max<uint32_t>(s, waves * qmax * bud);
   }
+  if (uses_round(tu, n_mat)) {
+    // round kernel: per wavefront an electron segment (electron phase
+    // survivors, secondaries and parked stack, photon phase electrons) and
+    // a photon segment (bremsstrahlung, photon survivors and parked stack),
+    // for claim caps of an even share of chunks plus one
+    const uint32_t waves = pass_waves(w, 2, pass_block(w, 2, tu.block, n_mat), n_mat);
+    const uint64_t cs = (uint64_t)tu.wave_items;
+    const uint64_t cap = (((uint64_t)tu.pass_items + cs - 1u) / cs + waves - 1u) / waves * cs + cs;
+    const uint64_t sec = (uint64_t)tu.secondaries;
+    const uint64_t seg = std::max(cap * (sec + 2u) + cap * sec, cap * sec + 2u * cap);
+    // beyond 32-bit slot indices the staging check refuses the job (GMC_EOVERFLOW)
+    s = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(s, (uint64_t)waves * seg), 0xFFFFFFFFull);
+  }
   *stg = s;
 }
+
+bool uses_round(const Tune& tu, int n_mat) { return tu.persistent > 0 && n_mat <= kMaxRoundMat; }
 
 int check_source(std::string* err, const gmc_source* s) {
   auto bad = [&](const char* m) {
@@ -419,6 +443,7 @@ DevSource dev_source(const gmc_source& s) {
   d.wy = (float)s.wy_cm;
   d.tab = nullptr;   // set where the job's tables are uploaded
   d.tab_n = s.spectrum == GMC_TABULATED ? (uint32_t)s.tab_n : 0u;
+  d.h0 = (uint32_t)s.first_history;
   return d;
 }
 
@@ -444,7 +469,7 @@ int get_majorants(gmc_context* c, int32_t pid, int32_t tid, const PhantomObj& p,
     return GMC_OK;
   }
   std::vector<float> g(kNE), e(kNE);
-  build_majorants(t.host, p.rho_max.data(), g.data(), e.data());
+  build_majorants(t.host, p.rho_max.data(), t.margin, g.data(), e.data());
   MajObj m;
   hipError_t he = hipMalloc(&m.d_g, kNE * sizeof(float));
   if (he == hipSuccess) he = hipMalloc(&m.d_e, kNE * sizeof(float));
@@ -584,6 +609,60 @@ int enqueue_pass(Engine& E, int type, hipEvent_t t0, hipEvent_t t1, bool capturi
   return GMC_OK;
 }
 
+// Enqueue the round plan and the persistent round kernel over both types'
+// accumulating buffers, which become the work buffers (each type's other
+// buffer accumulates from then on), bracketed by t0 / t1.
+int enqueue_round(Engine& E, hipEvent_t t0, hipEvent_t t1, bool capturing) {
+  Workspace* w = E.w;
+  int wi[2], ni[2];
+  for (int t = 0; t < 2; ++t) {
+    wi[t] = w->acc[t];
+    w->acc[t] ^= 1;
+    ni[t] = w->acc[t];
+  }
+  uint32_t lg = 0;
+  while ((1u << lg) < (uint32_t)E.tu.wave_items) ++lg;
+  RoundPlanArgs pa;
+  for (int t = 0; t < 2; ++t) {
+    pa.n_work[t] = count_ptr(w, t, wi[t]);
+    pa.n_new[t] = count_ptr(w, t, ni[t]);
+  }
+  pa.plan = w->d_ctl->plan;
+  pa.claims = w->d_ctl->claim;
+  pa.claim_ctr = &w->d_ctl->claim_ctr[0][0];
+  pa.cap = w->cap;
+  pa.cap_soft = w->cap_soft;
+  pa.max_items = (uint32_t)E.tu.pass_items;
+  pa.waves = E.round_waves;
+  pa.chunk_log2 = lg;
+  pa.sec = (uint32_t)E.tu.secondaries;
+  pa.sched = w->d_ctl->sched;
+  WS_TRY(w, launch_plan_round(pa, w->stream));
+  RoundArgs r;
+  r.g = E.proto;
+  r.e = E.proto;
+  r.g.work = r.g.carry_src = w->qbuf[0][wi[0]].q;
+  r.e.work = r.e.carry_src = w->qbuf[1][wi[1]].q;
+  r.g.plan = w->d_ctl->plan + 0;
+  r.e.plan = w->d_ctl->plan + 1;
+  r.e.stg_same = r.g.stg_other = w->stg[0].q;   // electron outputs
+  r.g.stg_same = r.e.stg_other = w->stg[1].q;   // photon outputs
+  r.g.dst_same = r.e.dst_other = w->qbuf[0][ni[0]].q;
+  r.e.dst_same = r.g.dst_other = w->qbuf[1][ni[1]].q;
+  r.g.cnt_same = r.e.cnt_other = count_ptr(w, 0, ni[0]);
+  r.e.cnt_same = r.g.cnt_other = count_ptr(w, 1, ni[1]);
+  r.g.tail_lanes = E.tu.tail_g;
+  r.e.tail_lanes = E.tu.tail_e;
+  r.g.tail_min = r.e.tail_min = kTailMinItems;
+  r.claims = w->d_ctl->claim;
+  r.claim_ctr = &w->d_ctl->claim_ctr[0][0];
+  WS_TRY(w, record_event(w->stream, t0, capturing));
+  const hipError_t e = launch_round(r, (int)E.round_blocks, E.round_block, w->stream);
+  if (e != hipSuccess) return wfail(w, GMC_EDEVICE, std::string("round launch: ") + hipGetErrorString(e));
+  WS_TRY(w, record_event(w->stream, t1, capturing));
+  return GMC_OK;
+}
+
 int enqueue_admission(Engine& E) {
   Workspace* w = E.w;
   AdmitPlanArgs ap;
@@ -710,6 +789,9 @@ int engine_setup(Workspace* w, Engine& E, const Job& J, const Tune& tu) {
   E.proto.max_secondaries = tu.secondaries;
   E.proto.refill_lanes = tu.refill;
   E.proto.resume_lanes = kResumeLanes;
+  bool single = true;   // every beam's own tally is one slice
+  for (const DevBeam& b : J.beams) single &= b.a.K == 1u;
+  E.proto.agg_a = tu.aggregate > 0 || (tu.aggregate == 0 && single) ? 1 : 0;
   for (int t = 0; t < 2; ++t) {
     AdmitArgs& a = E.adm[t];
     a = AdmitArgs{};
@@ -724,8 +806,16 @@ int engine_setup(Workspace* w, Engine& E, const Job& J, const Tune& tu) {
     a.ctr = w->d_ctr;
     a.nvox = (uint32_t)J.P->nvox();
   }
-  w->t_pass[0] = w->t_pass[1] = 0.0;
-  w->n_pass[0] = w->n_pass[1] = 0;
+  E.round = uses_round(tu, n_mat);
+  if (E.round) {
+    E.round_block = pass_block(w, 2, tu.block, n_mat);
+    E.round_waves = pass_waves(w, 2, E.round_block, n_mat);
+    E.round_blocks = E.round_waves / ((uint32_t)E.round_block / 64u);
+  }
+  for (int k = 0; k < 3; ++k) {
+    w->t_pass[k] = 0.0;
+    w->n_pass[k] = 0;
+  }
   return GMC_OK;
 }
 
@@ -737,6 +827,27 @@ int engine_setup(Workspace* w, Engine& E, const Job& J, const Tune& tu) {
 int engine_run_plain(Engine& E, uint64_t* rounds) {
   Workspace* w = E.w;
   const Control& st = *w->h_ctl;
+  if (E.round) {
+    // one persistent kernel per round; the control block is read after each
+    bool moved = true;
+    for (;;) {
+      int rc = enqueue_admission(E);
+      if (rc) return rc;
+      rc = read_control(w);
+      if (rc) return rc;
+      if (*rounds > 0) rc = add_pass_time(w, 2, w->kev0, w->kev1);
+      if (rc) return rc;
+      if (st.done()) break;
+      if (*rounds > 0 && st.adm[0].count == 0 && st.adm[1].count == 0 && !moved) return stuck(w);
+      ++*rounds;
+      rc = enqueue_round(E, w->kev0, w->kev1, false);
+      if (rc) return rc;
+      rc = read_control(w);
+      if (rc) return rc;
+      moved = st.plan[0].m > 0 || st.plan[1].m > 0;
+    }
+    return GMC_OK;
+  }
   bool e_prog = true, g_ran = false;
   for (;;) {
     int rc = enqueue_admission(E);
@@ -782,6 +893,10 @@ int engine_capture(Engine& E, hipGraphExec_t* exec, int* rounds_per_replay) {
   WS_TRY(w, hipStreamBeginCapture(w->stream, hipStreamCaptureModeThreadLocal));
   for (int r = 0; r < nr && rc == GMC_OK; ++r) {
     rc = enqueue_admission(E);
+    if (E.round) {
+      if (rc == GMC_OK) rc = enqueue_round(E, w->gev[4 * r], w->gev[4 * r + 1], true);
+      continue;
+    }
     if (rc == GMC_OK) rc = enqueue_pass(E, 1, w->gev[4 * r + 2], w->gev[4 * r + 3], true);
     if (rc == GMC_OK) rc = enqueue_pass(E, 0, w->gev[4 * r], w->gev[4 * r + 1], true);
   }
@@ -801,8 +916,12 @@ int engine_capture(Engine& E, hipGraphExec_t* exec, int* rounds_per_replay) {
 int after_replay(Engine& E, int nr, bool* done) {
   Workspace* w = E.w;
   int rc = check_control(w);
-  // pair i brackets the pass of type i & 1 in round i / 2
-  for (int i = 0; i < 2 * nr && rc == GMC_OK; ++i) rc = add_pass_time(w, i & 1, w->gev[2 * i], w->gev[2 * i + 1]);
+  // pair i brackets the pass of type i & 1 in round i / 2 (the round kernel: pair 2 r)
+  if (E.round) {
+    for (int r = 0; r < nr && rc == GMC_OK; ++r) rc = add_pass_time(w, 2, w->gev[4 * r], w->gev[4 * r + 1]);
+  } else {
+    for (int i = 0; i < 2 * nr && rc == GMC_OK; ++i) rc = add_pass_time(w, i & 1, w->gev[2 * i], w->gev[2 * i + 1]);
+  }
   if (rc) return rc;
   const Control& st = *w->h_ctl;
   *done = st.done();
@@ -834,9 +953,10 @@ int engine_run_graph(Engine& E, uint64_t* rounds) {
 }
 
 // ------------------------------------------------------------------ finalize
-void add_batch_sizes(std::vector<double>& nk, uint64_t n, uint32_t K) {
+void add_batch_sizes(std::vector<double>& nk, uint64_t h0, uint64_t n, uint32_t K) {
   nk.resize(K, 0.0);
-  for (uint32_t k = 0; k < K; ++k) nk[k] += (double)((n + K - 1 - k) / K);
+  // #{h < m : h mod K = k} = (m + K - 1 - k) / K, differenced over [h0, h0 + n)
+  for (uint32_t k = 0; k < K; ++k) nk[k] += (double)((h0 + n + K - 1 - k) / K - (h0 + K - 1 - k) / K);
 }
 
 int finalize(Workspace* w, const PhantomObj& P, const unsigned long long* tally, uint32_t nsum, size_t stride,
@@ -902,6 +1022,8 @@ int stats_from_counters(Workspace* w, const unsigned long long* slots, gmc_run_s
     stats->t_electron_pass_s = w->t_pass[1];
     stats->n_photon_launches = w->n_pass[0];
     stats->n_electron_launches = w->n_pass[1];
+    stats->t_round_s = w->t_pass[2];
+    stats->n_round_launches = w->n_pass[2];
     stats->s_rel = w->h_srel[0];
   }
   if (ctr[C_OVERFLOW]) return wfail(w, GMC_EINTERNAL, "queue overflow detected on the device");
@@ -954,7 +1076,7 @@ struct StreamSwap {
 int run_job_ws(gmc_context* c, Workspace* w, int32_t phantom_id, int32_t tables_id, const gmc_source* srcs,
                const uint64_t* n_hist, int n_beams, uint64_t seed, double* const* dose_per_beam,
                double* const* sigma_per_beam, double* dose, double* sigma, int out_kind, const gmc_tuning* tuning,
-               gmc_run_stats* stats, bool batched) {
+               gmc_run_stats* stats, bool batched, uint64_t* tally_out, int tally_kind) {
   const auto t_start = std::chrono::steady_clock::now();
   const PhantomObj* pp = nullptr;
   const TablesObj* tp = nullptr;
@@ -969,8 +1091,10 @@ int run_job_ws(gmc_context* c, Workspace* w, int32_t phantom_id, int32_t tables_
   const PhantomObj& P = *pp;
   const TablesObj& T = *tp;
   if (n_beams < 1 || n_beams > (1 << 20) || !srcs || !n_hist) return wfail(w, GMC_EINVAL, "need 1 .. 2^20 beams");
-  if (!dose) return wfail(w, GMC_EINVAL, "dose output is NULL");
+  if (!dose && !tally_out) return wfail(w, GMC_EINVAL, "dose output is NULL");
   if (out_kind != GMC_HOST && out_kind != GMC_DEVICE) return wfail(w, GMC_EINVAL, "bad out_ptr_kind");
+  if (tally_out && (batched || n_beams != 1 || (tally_kind != GMC_HOST && tally_kind != GMC_DEVICE)))
+    return wfail(w, GMC_EINVAL, "raw tallies are returned for one beam in the plain form, to host or device memory");
   if (P.max_mat >= T.host.n_mat) return wfail(w, GMC_EINVAL, "phantom uses a material index beyond the tables");
   const uint32_t K = (uint32_t)T.phys.n_batches;
   uint64_t n_total = 0, n_min = ~0ull;
@@ -980,6 +1104,9 @@ int run_job_ws(gmc_context* c, Workspace* w, int32_t phantom_id, int32_t tables_
     if (rc) return rc;
     if (n_hist[b] == 0) return wfail(w, GMC_EINVAL, "every beam needs at least one history");
     if (n_hist[b] >= (1ull << 32)) return wfail(w, GMC_EINVAL, "histories must be < 2^32");
+    // history numbers and their batch index (off + h, off < n_total) stay within 32 bits
+    if (srcs[b].first_history + n_hist[b] + n_total >= (1ull << 32))
+      return wfail(w, GMC_EINVAL, "first_history + histories must stay below 2^32");
     n_total += n_hist[b];
     n_min = std::min<uint64_t>(n_min, n_hist[b]);
     const double e_max = source_emax(srcs[b]);
@@ -1031,12 +1158,16 @@ int run_job_ws(gmc_context* c, Workspace* w, int32_t phantom_id, int32_t tables_
 
   // combined result (and the ledger's deposited total)
   std::vector<double> nk;
-  if (mode == kBeamBatched) {
-    for (int b = 0; b < n_beams; ++b) add_batch_sizes(nk, n_hist[b], K);
-  } else {
-    add_batch_sizes(nk, n_total, K);
+  {
+    // beam b's history h (numbered from its first history) is in combined
+    // batch (off_b + h) mod K, off_b its offset in the combined tally
+    uint64_t off = 0;
+    for (int b = 0; b < n_beams; ++b) {
+      add_batch_sizes(nk, (mode == kBeamBatched ? 0 : off) + srcs[b].first_history, n_hist[b], K);
+      off += n_hist[b];
+    }
   }
-  double* d_out = out_kind == GMC_DEVICE ? dose : w->d_dose;
+  double* d_out = out_kind == GMC_DEVICE && dose ? dose : w->d_dose;
   double* s_out = sigma ? (out_kind == GMC_DEVICE ? sigma : w->d_sigma) : nullptr;
   rc = mode == kBeamBatched
            ? finalize(w, P, w->d_tally, (uint32_t)NB, nvox * K, K, nk, n_total, d_out, s_out, true, true)
@@ -1047,6 +1178,9 @@ int run_job_ws(gmc_context* c, Workspace* w, int32_t phantom_id, int32_t tables_
     if (rc == GMC_OK && sigma) rc = copy_out(w, sigma, w->d_sigma, nvox);
     if (rc) return rc;
   }
+  if (tally_out)
+    WS_TRY(w, hipMemcpyAsync(tally_out, w->d_tally, nvox * K * sizeof(unsigned long long),
+                             tally_kind == GMC_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, w->stream));
   // per-beam results
   if (mode != kCombined) {
     for (int b = 0; b < n_beams; ++b) {
@@ -1060,7 +1194,7 @@ int run_job_ws(gmc_context* c, Workspace* w, int32_t phantom_id, int32_t tables_
       const unsigned long long* tb =
           w->d_tally + (mode == kBeamBatched ? nvox * K * (size_t)b : nvox * ((size_t)K + (size_t)b));
       std::vector<double> nkb;
-      add_batch_sizes(nkb, n_hist[b], kb);
+      add_batch_sizes(nkb, srcs[b].first_history, n_hist[b], kb);
       rc = finalize(w, P, tb, 1u, 0u, kb, nkb, n_hist[b], dd, ds, false, true);
       if (rc) return rc;
       if (out_kind == GMC_HOST) {
@@ -1078,9 +1212,10 @@ int run_job_ws(gmc_context* c, Workspace* w, int32_t phantom_id, int32_t tables_
 
 int run_job(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_source* srcs, const uint64_t* n_hist,
             int n_beams, uint64_t seed, double* const* dose_per_beam, double* const* sigma_per_beam, double* dose,
-            double* sigma, int out_kind, const gmc_tuning* tuning, gmc_run_stats* stats, bool batched) {
+            double* sigma, int out_kind, const gmc_tuning* tuning, gmc_run_stats* stats, bool batched,
+            uint64_t* tally_out, int tally_kind) {
   const int rc = run_job_ws(c, &c->ws, phantom_id, tables_id, srcs, n_hist, n_beams, seed, dose_per_beam,
-                            sigma_per_beam, dose, sigma, out_kind, tuning, stats, batched);
+                            sigma_per_beam, dose, sigma, out_kind, tuning, stats, batched, tally_out, tally_kind);
   if (rc) c->err = c->ws.err;
   return rc;
 }
@@ -1220,7 +1355,8 @@ int autotune(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_so
       if (d.twin) cand.*(d.twin) = 2 * v;
       double t = 0.0;
       rc = trial(cand, &t);
-      if (rc) return rc;
+      if (rc == GMC_EDEVICE) return rc;   // the device itself failed: stop
+      if (rc) continue;                   // a candidate the job cannot run with (memory, queues): rejected
       if (t < 0.98 * t_best) {
         t_best = t;
         best = cand;

@@ -22,6 +22,7 @@ namespace gmc {
 struct TablesObj {
   gmc_physics phys{};
   double kcut = 0, kc = 0;
+  double margin = 1.001;         // majorant safety factor
   HostTables host;
   float4* d_ph = nullptr;
   float4* d_el = nullptr;
@@ -68,6 +69,8 @@ struct Control {
   uint32_t sched[4];            // cursor[2], total[2]
   PassPlan plan[2];
   AdmitPlan adm[2];
+  ClaimType claim[2];           // the round kernel's work queue per type
+  uint32_t claim_ctr[2][kClaimParts];
   bool done() const {
     return sched[0] == sched[2] && sched[1] == sched[3] && counts[0] == 0 && counts[1] == 0 && counts[2] == 0 &&
            counts[3] == 0;
@@ -116,8 +119,8 @@ struct Workspace {
   hipEvent_t kev0 = nullptr, kev1 = nullptr;   // around a pass launch (plain form)
   hipEvent_t ev_ctl = nullptr;                 // after a control-block copy
   std::vector<hipEvent_t> gev;                 // pairs around the passes of a captured graph
-  double t_pass[2] = {0.0, 0.0};               // summed pass durations, s
-  uint64_t n_pass[2] = {0, 0};
+  double t_pass[3] = {0.0, 0.0, 0.0};          // summed photon pass, electron pass, round kernel durations, s
+  uint64_t n_pass[3] = {0, 0, 0};
 };
 
 int wfail(Workspace* w, int code, const std::string& msg);
@@ -145,12 +148,17 @@ struct Tune {
   int events, secondaries, chunk, block, pass_items, wave_items, rounds, refill;
   int sort;            // 1: energy regrouping before every pass
   int tail_g, tail_e;  // tail requeue lanes of the photon / electron pass (0: off)
+  int queue;           // soft queue capacity (0: from the chunk)
+  int persistent;      // 1: one persistent round kernel per round
+  int aggregate;       // 1 on, -1 off, 0 where every beam's tally a is a single slice
 };
 Tune resolve_tuning(const gmc_tuning* t);
 gmc_tuning default_tuning();
 
 // Queue capacity (allocated and soft) and staging slots the engine uses for a tuning.
 void queue_sizes(Workspace* w, const Tune& tu, int n_mat, uint32_t* cap, uint32_t* cap_soft, uint32_t* stg);
+// Whether a tuning runs rounds as the persistent kernel for n_mat materials.
+bool uses_round(const Tune& tu, int n_mat);
 
 int check_source(std::string* err, const gmc_source* s);
 // Highest and mean kinetic energy of a (checked) source's spectrum, MeV.
@@ -205,6 +213,9 @@ uint32_t pass_waves(Workspace* w, int kernel, int block, int n_mat);
 struct Engine {
   Workspace* w = nullptr;
   Tune tu{};
+  bool round = false;             // rounds as one persistent kernel (tu.persistent and the tables fit)
+  int round_block = 0;            // its workgroup size, grid, wavefronts
+  uint32_t round_blocks = 0, round_waves = 0;
   int block[2] = {0, 0};          // workgroup size of each pass kernel
   PassArgs proto{};
   AdmitArgs adm[2]{};
@@ -231,8 +242,8 @@ int enqueue_control_copy(Workspace* w);
 // returns GMC_EOVERFLOW).
 int after_replay(Engine& E, int rounds_per_replay, bool* done);
 
-// Histories per batch for interleaved batches: n_k += #{h < n : h mod K = k}.
-void add_batch_sizes(std::vector<double>& nk, uint64_t n, uint32_t K);
+// Histories per batch for interleaved batches: n_k += #{h in [h0, h0 + n) : h mod K = k}.
+void add_batch_sizes(std::vector<double>& nk, uint64_t h0, uint64_t n, uint32_t K);
 // Dose and sigma of `nsum` tallies ([K][nvox] each, `stride` apart, added).
 // With sync false the batch sizes go through the pinned w->h_nk and the
 // call does not wait (one finalize in flight per workspace).
@@ -275,9 +286,12 @@ int cfail(gmc_context* c, int code, const std::string& msg);
 int get_majorants(gmc_context* c, int32_t pid, int32_t tid, const PhantomObj& p, const TablesObj& t, MajObj* out,
                   std::string* err);
 // Blocking run of a job in the context's workspace (the plain and batched forms).
+// tally_out (single-beam plain runs): the raw [K][nvox] batch tallies are
+// copied there too (host or device per tally_kind); dose may then be NULL.
 int run_job(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_source* srcs, const uint64_t* n_hist,
             int n_beams, uint64_t seed, double* const* dose_per_beam, double* const* sigma_per_beam, double* dose,
-            double* sigma, int out_kind, const gmc_tuning* tuning, gmc_run_stats* stats, bool batched);
+            double* sigma, int out_kind, const gmc_tuning* tuning, gmc_run_stats* stats, bool batched,
+            uint64_t* tally_out = nullptr, int tally_kind = GMC_HOST);
 // per_beam: tune the job as run with per-beam outputs (their tally layout),
 // a job class of its own.
 int autotune(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_source* srcs, const uint64_t* n_hist,

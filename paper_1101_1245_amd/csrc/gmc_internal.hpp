@@ -109,6 +109,7 @@ struct DevSource {
   float cx, cy, wx, wy;
   const double* tab;            // tabulated: bin edges [tab_n + 1], then the normalised CDF at them [tab_n + 1]
   uint32_t tab_n;
+  uint32_t h0;                  // number of the beam's first history (its stream and batch)
 };
 
 // Run counters (energy ledger in 2^-27 MeV units, event counts).  Each counter
@@ -129,6 +130,15 @@ constexpr int kCtrSlots = 256;
 struct PassPlan {
   uint32_t n, m, per_wave, seg_same, seg_other, chunk_log2;
   uint32_t admitting;   // primaries remain to be admitted: more passes of both types follow
+};
+
+// The device work queue of the persistent round kernel, per particle type:
+// the round's m items split into kClaimParts contiguous partitions (chunk
+// counters of their own), and the most items one wavefront may claim.
+constexpr int kClaimParts = 8;
+struct ClaimType {
+  uint32_t cap;
+  uint32_t start[kClaimParts + 1];
 };
 
 struct PlanArgs {
@@ -178,6 +188,37 @@ struct PassArgs {
   int resume_lanes;          // idle lanes (1..64) that take back parked electrons
   int tail_lanes;            // requeue the lanes' particles once the share is done and at most this many remain
   uint32_t tail_min;         // ... for shares of at least this many particles
+  int agg_a;                 // electron pass: tally-a additions of a loop iteration aggregated per address
+};
+
+// The persistent round kernel: one launch per round transports the
+// electrons and then the photons of the round's work queues, every
+// wavefront claiming chunks of items from the device work queue (ClaimType
+// per type, with its counters) instead of a fixed share.  g and e are the
+// photon and electron halves as pass arguments: each reads its own work
+// queue and plan; electron outputs go to staging queue 0 (e.stg_same,
+// g.stg_other) and photon outputs to staging queue 1.
+struct RoundArgs {
+  PassArgs g, e;
+  const ClaimType* claims;      // [2] photon, electron
+  uint32_t* claim_ctr;          // [2][kClaimParts] chunk counters (cleared by the plan)
+};
+
+// Sizes of a round: both types' plans as k_plan_pass would make them in
+// sequence (electrons first; the photons transported in the round are those
+// queued at its start), the per-wavefront claim caps and segments.
+struct RoundPlanArgs {
+  uint32_t* n_work[2];          // counts of the work buffers (read, then cleared)
+  uint32_t* n_new[2];           // counts of the new accumulating buffers: set to the carry-overs
+  PassPlan* plan;               // [2]
+  ClaimType* claims;            // [2]
+  uint32_t* claim_ctr;          // [2][kClaimParts]
+  uint32_t cap, cap_soft;       // allocated and soft queue capacity
+  uint32_t max_items;           // most particles of a type per round
+  uint32_t waves;               // wavefronts of the round grid
+  uint32_t chunk_log2;          // items per claimed chunk: 2^chunk_log2
+  uint32_t sec;                 // secondaries per visit
+  const uint32_t* sched;        // admission cursors [2] and totals [2]
 };
 
 // Admission of primaries of one particle type.  The histories of all beams of
@@ -244,6 +285,10 @@ size_t photon_lds_bytes(int n_mat);
 size_t electron_lds_bytes(int n_mat);
 hipError_t launch_plan_pass(const PlanArgs& a, hipStream_t s);
 hipError_t launch_photon_pass(const PassArgs& a, int grid, int block, hipStream_t s);
+size_t round_lds_bytes(int n_mat);
+constexpr int kMaxRoundMat = 4;        // both table blocks of more materials do not fit in LDS
+hipError_t launch_plan_round(const RoundPlanArgs& a, hipStream_t s);
+hipError_t launch_round(const RoundArgs& a, int grid, int block, hipStream_t s);
 hipError_t launch_electron_pass(const PassArgs& a, int grid, int block, hipStream_t s);
 hipError_t launch_admit_plan(const AdmitPlanArgs& a, hipStream_t s);
 hipError_t launch_admit(const AdmitArgs& a, uint32_t max_count, hipStream_t s);
@@ -263,6 +308,7 @@ constexpr int kRelBlocks = 256;
 hipError_t launch_rel_uncertainty(const double* dose, const double* sigma, uint32_t nvox, double* work, hipStream_t s);
 hipError_t launch_atomic_rate(unsigned long long* a, uint32_t mask, uint32_t hot, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
+// kernel: 0 photon pass, 1 electron pass, 2 round kernel
 int max_resident_blocks(int kernel, int block, size_t lds);
 
 }  // namespace gmc

@@ -116,12 +116,13 @@ __global__ void __launch_bounds__(256) k_admit(AdmitArgs a) {
     j = lo;
   }
   const uint32_t beam = valid ? a.beam_of[j] : 0u;
-  const uint32_t h = valid ? g - a.start[j] : 0u;
+  uint32_t h = 0u;   // history number: the beam's first history plus its index in the beam
   Primary p{0.0f, 0.0f, 0u};
   int particle = 0;
   if (valid) {
     const DevSource src = a.sources[beam];
     particle = src.particle;
+    h = g - a.start[j] + src.h0;
     p = sample_primary(src, a.beams[beam], h);
   }
   const bool in = valid && inside(a.ph, p.x, p.y, 0.0f);
@@ -206,7 +207,17 @@ struct Child { float u, v, w; uint32_t e, plo, phi; };
 // lives differ widely; contiguous shares left many wavefronts idle while a
 // few finished theirs.  Loads stay coalesced within a chunk.  [next, end) is
 // the wave-uniform cursor over the wavefront's own items, numbered 0..end-1.
-struct WaveRange { uint32_t next, end, wave, waves, lg; };
+struct WaveRange {
+  uint32_t next, end, wave, waves, lg;
+  // every item of the share has been handed to a lane
+  __device__ __forceinline__ bool done() { return next >= end; }
+  // items in the share (the tail requeue applies to large shares only)
+  __device__ __forceinline__ uint32_t size() const { return end; }
+  // work-queue index of the wavefront's item j
+  __device__ __forceinline__ uint32_t item(uint32_t j) const {
+    return (((j >> lg) * waves + wave) << lg) + (j & ((1u << lg) - 1u));
+  }
+};
 
 __device__ __forceinline__ WaveRange wave_range(const PassPlan& P, uint32_t wave, uint32_t waves) {
   const uint32_t lg = P.chunk_log2;
@@ -220,23 +231,78 @@ __device__ __forceinline__ WaveRange wave_range(const PassPlan& P, uint32_t wave
   return r;
 }
 
-// Work-queue index of the wavefront's item j.
-__device__ __forceinline__ uint32_t range_item(const WaveRange& r, uint32_t j) {
-  return (((j >> r.lg) * r.waves + r.wave) << r.lg) + (j & ((1u << r.lg) - 1u));
+// A wavefront's work in the persistent round kernel: chunks of 2^lg
+// consecutive work-queue items claimed one at a time from a device work
+// queue.  The m items of a type are split into kClaimParts contiguous
+// partitions, each with its own chunk counter, so claims spread over
+// kClaimParts addresses instead of one hot word; a wavefront claims from the
+// partition of its workgroup's slot first and moves on to the next one when
+// that is empty.  It never claims more than `cap` items in all (the bound its
+// staging segments were sized for); the caps add up to more than m, so every
+// item is claimed by some wavefront.  No wavefront waits for another: a claim
+// is one atomic addition, and an empty partition is skipped.  [next, end)
+// are queue indices of the current chunk's items not yet handed out.
+struct ClaimRange {
+  uint32_t next, end;
+  uint32_t taken, cap;        // items claimed so far, most it may claim
+  uint32_t part, left;        // partition claimed from, partitions not yet found empty
+  uint32_t lg;
+  const ClaimType* T;
+  uint32_t* ctr;              // [kClaimParts] chunk counters of this type
+
+  __device__ __forceinline__ void claim() {
+    while (left > 0u && taken + (1u << lg) <= cap) {
+      uint32_t c = 0u;
+      if (lane_id() == 0u) c = atomicAdd(ctr + part, 1u);
+      c = __shfl(c, 0);
+      const uint32_t lo = T->start[part], hi = T->start[part + 1];
+      const uint64_t first = (uint64_t)lo + ((uint64_t)c << lg);
+      if (first < hi) {
+        next = (uint32_t)first;
+        end = (uint32_t)min<uint64_t>(first + (1u << lg), hi);
+        taken += end - next;
+        return;
+      }
+      part = part + 1u == (uint32_t)kClaimParts ? 0u : part + 1u;
+      --left;
+    }
+  }
+  // wave-uniform: claims the next chunk when the current one is used up
+  __device__ __forceinline__ bool done() {
+    if (next < end) return false;
+    claim();
+    return next >= end;
+  }
+  __device__ __forceinline__ uint32_t size() const { return taken; }
+  __device__ __forceinline__ uint32_t item(uint32_t j) const { return j; }
+};
+
+__device__ __forceinline__ ClaimRange claim_range(const ClaimType& T, uint32_t* ctr, uint32_t lg, uint32_t slot) {
+  ClaimRange r;
+  r.next = r.end = 0u;
+  r.taken = 0u;
+  r.cap = T.cap;
+  r.part = slot % (uint32_t)kClaimParts;
+  r.left = (uint32_t)kClaimParts;
+  r.lg = lg;
+  r.T = &T;
+  r.ctr = ctr;
+  return r;
 }
 
 // Lanes without a particle take the next items of the range, in lane order,
 // once at least a.refill_lanes of them are idle (one refill then pays the
 // load latency for many lanes; with every lane idle it always proceeds).
 // Entries with zero energy (primaries settled by the source) are skipped.
-__device__ __forceinline__ void refill(Lane& L, bool& have, int& events, int& pushes, WaveRange& r,
-                                       const PassArgs& a, const DevBeam* lbeams, uint32_t nvox) {
+template <class R>
+__device__ __forceinline__ void refill(Lane& L, bool& have, int& events, int& pushes, R& r, const PassArgs& a,
+                                       const DevBeam* lbeams, uint32_t nvox) {
   const unsigned long long need = __ballot(!have);
-  if (need == 0 || r.next >= r.end || __popcll(need) < a.refill_lanes) return;
+  if (need == 0 || __popcll(need) < a.refill_lanes || r.done()) return;
   if (!have) {
     const uint32_t it = r.next + (uint32_t)__popcll(need & lanes_below());
     if (it < r.end) {
-      load_lane(L, a.work, range_item(r, it), a, lbeams, nvox);
+      load_lane(L, a.work, r.item(it), a, lbeams, nvox);
       have = L.e != 0;
       events = 0;
       pushes = 0;
@@ -271,19 +337,56 @@ struct Pending {
   uint32_t e = 0;
 };
 
-__device__ __forceinline__ void flush(const Lane& L, Pending& p) {
-  if (p.e) deposit(L, p.v, p.e);
+// A finished pending deposit whose tally-a addition waits for the end of the
+// loop iteration, where the wavefront adds it aggregated (agg_a): lanes whose
+// additions go to the same address are summed and their leader adds the sum
+// with one atomic.  That pays where many lanes add to one address -- a
+// single-slice tally of a pencil beam, all of whose histories deposit on the
+// beam's axis -- and is left off where the batch slices already spread the
+// addresses.
+struct Deferred {
+  unsigned long long* addr = nullptr;
+  uint32_t e = 0;
+};
+
+__device__ __forceinline__ void flush(const Lane& L, Pending& p, Deferred& d, bool agg) {
+  if (p.e) {
+    if (!agg) {
+      deposit(L, p.v, p.e);
+    } else {
+      if (L.tb) tally_add(L.tb + p.v, (unsigned long long)p.e);
+      if (d.e) tally_add(d.addr, (unsigned long long)d.e);   // a second one in the same iteration
+      d.addr = L.ta + p.v;
+      d.e = p.e;
+    }
+  }
   p.e = 0;
   p.v = -1;
 }
 
-__device__ __forceinline__ void deposit_later(const Lane& L, Pending& p, int v, uint32_t e) {
+__device__ __forceinline__ void deposit_later(const Lane& L, Pending& p, int v, uint32_t e, Deferred& d, bool agg) {
   if (!e) return;
   if (v != p.v) {
-    flush(L, p);
+    flush(L, p, d, agg);
     p.v = v;
   }
   p.e += e;
+}
+
+// End of a loop iteration (all lanes): the deferred additions, those to the
+// first deferring lane's address summed into one atomic, the others each
+// their own (one round: addresses that differ cost no extra rounds).
+__device__ __forceinline__ void commit_deferred(Deferred& d) {
+  const bool want = d.e != 0u;
+  const unsigned long long m = __ballot(want);
+  if (m == 0ull) return;
+  const int leader = __ffsll((long long)m) - 1;
+  const unsigned long long la = __shfl((unsigned long long)d.addr, leader);
+  const bool same = want && (unsigned long long)d.addr == la;
+  const unsigned long long sum = wave_sum(same ? (unsigned long long)d.e : 0ull);
+  if ((int)lane_id() == leader) tally_add(d.addr, sum);
+  else if (want && !same) tally_add(d.addr, (unsigned long long)d.e);
+  d.e = 0u;
 }
 
 // One photon flight and interaction decision (Sec. II.A, Eqs. 1-3): free path
@@ -435,27 +538,38 @@ __device__ __forceinline__ void push_electrons(const Lane& L, const PassArgs& a,
 // in the same order either way.  Segment bound: each photon of the range
 // leaves at most one survivor and is parked at most once, within per_wave x 2
 // slots.
-__global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
-  extern __shared__ float4 smem[];
-  const int nt = a.tab.n_mat * kNE;
-  for (int i = threadIdx.x; i < nt; i += blockDim.x) smem[i] = a.tab.ph[i];
-  float* majg = reinterpret_cast<float*>(smem + nt);
-  for (int i = threadIdx.x; i < kNE; i += blockDim.x) majg[i] = a.tab.maj_g[i];
-  DevBeam* lbeams = reinterpret_cast<DevBeam*>(majg + kNE);
-  if (a.n_beams <= kLdsBeams)
-    for (int i = threadIdx.x; i < a.n_beams; i += blockDim.x) lbeams[i] = a.beams[i];
-  __syncthreads();
+// Run counters a wavefront accumulates over its loop, added to the run's
+// counters once at the end of the kernel.
+struct WaveTotals {
+  unsigned long long esc = 0, sink = 0;
+  uint32_t ev = 0, fict = 0, viol = 0, sec = 0, steps = 0, hard = 0;
+};
 
-  const uint32_t nvox = (uint32_t)(a.ph.nx * a.ph.ny * a.ph.nz);
-  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const PassPlan P = *a.plan;
-  WaveRange range = wave_range(P, wave, (gridDim.x * blockDim.x) >> 6);
-  WaveSeg gsame{wave * P.seg_same, P.seg_same, 0u}, gother{wave * P.seg_other, P.seg_other, 0u};
+__device__ __forceinline__ void add_totals(const WaveTotals& t, unsigned long long* ctr) {
+  const unsigned long long s_esc = wave_sum(t.esc), s_sink = wave_sum(t.sink);
+  const unsigned long long s_ev = wave_sum(t.ev), s_fict = wave_sum(t.fict), s_viol = wave_sum(t.viol),
+                           s_sec = wave_sum(t.sec), s_steps = wave_sum(t.steps), s_hard = wave_sum(t.hard);
+  if (lane_id() == 0) {
+    if (s_esc) ctr_add(ctr, C_E_ESC, s_esc);
+    if (s_sink) ctr_add(ctr, C_E_SINK, s_sink);
+    if (s_ev) ctr_add(ctr, C_PH_EVENTS, s_ev);
+    if (s_fict) ctr_add(ctr, C_FICT, s_fict);
+    if (s_viol) ctr_add(ctr, C_VIOL, s_viol);
+    if (s_sec) ctr_add(ctr, C_SEC, s_sec);
+    if (s_steps) ctr_add(ctr, C_E_STEPS, s_steps);
+    if (s_hard) ctr_add(ctr, C_HARD, s_hard);
+  }
+}
+
+// The photon transport of one wavefront over its range: photon tables in
+// LDS at tab (per material) and majg (majorant), the beam table at lbeams.
+template <class R>
+__device__ void photon_loop(const PassArgs& a, uint32_t admitting, R& range, WaveSeg& gsame, WaveSeg& gother,
+                            const float4* tab, const float* majg, const DevBeam* lbeams, uint32_t nvox,
+                            WaveTotals& tot) {
   Lane L;
   bool have = false;
   int events = 0, pushes = 0;
-  unsigned long long acc_esc = 0, acc_sink = 0;
-  uint32_t c_ev = 0, c_fict = 0, c_viol = 0, c_sec = 0;
   uint32_t npark = 0;   // parked absorptions on the stack, wave-uniform
 
   for (;;) {
@@ -463,7 +577,7 @@ __global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
     // a refill may bring only zero-energy entries: the wavefront goes on
     // until its range is done
     if (!__any(have)) {
-      if (range.next >= range.end) break;
+      if (range.done()) break;
       continue;
     }
     int nchild = 0;
@@ -474,17 +588,17 @@ __global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
     // photon that lives on after this event is requeued (while primaries
     // remain to be admitted)
     bool tail = false;
-    if (a.tail_lanes > 0 && P.admitting && range.next >= range.end && range.end >= a.tail_min)
+    if (a.tail_lanes > 0 && admitting && range.done() && range.size() >= a.tail_min)
       tail = (uint32_t)__popcll(__ballot(have)) <= (uint32_t)a.tail_lanes;
     if (have) {
       int v0 = 0;
-      kind = photon_flight(L, a, smem, majg, v0, c_viol);
-      ++c_ev;
+      kind = photon_flight(L, a, tab, majg, v0, tot.viol);
+      ++tot.ev;
       if (kind == PH_ESCAPE) {
-        acc_esc += L.e;
+        tot.esc += L.e;
         have = false;
       } else if (kind == PH_FICT) {
-        ++c_fict;
+        ++tot.fict;
       } else if (a.cut.mode == 1) {
         deposit(L, v0, L.e);
         have = false;
@@ -521,7 +635,7 @@ __global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
         have = false;
       }
       pushes += nchild;
-      c_sec += nchild;
+      tot.sec += nchild;
       if (have) {
         ++events;
         if (tail || events >= a.max_events || pushes + 2 > a.max_secondaries) {
@@ -562,23 +676,33 @@ __global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
       const int kind = (int)qf(a.stg_same, Q_AUX, slot);
       int ix, iy, iz;
       const int v0 = voxel(a.ph, L.x, L.y, L.z, ix, iy, iz);
-      absorb_photon(L, a, kind, v0, c0, c1, nchild, acc_sink);
-      c_sec += nchild;
+      absorb_photon(L, a, kind, v0, c0, c1, nchild, tot.sink);
+      tot.sec += nchild;
     }
     push_electrons(L, a, gother, nchild, c0, c1);
   }
+}
+
+__global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
+  extern __shared__ float4 smem[];
+  const int nt = a.tab.n_mat * kNE;
+  for (int i = threadIdx.x; i < nt; i += blockDim.x) smem[i] = a.tab.ph[i];
+  float* majg = reinterpret_cast<float*>(smem + nt);
+  for (int i = threadIdx.x; i < kNE; i += blockDim.x) majg[i] = a.tab.maj_g[i];
+  DevBeam* lbeams = reinterpret_cast<DevBeam*>(majg + kNE);
+  if (a.n_beams <= kLdsBeams)
+    for (int i = threadIdx.x; i < a.n_beams; i += blockDim.x) lbeams[i] = a.beams[i];
+  __syncthreads();
+
+  const uint32_t nvox = (uint32_t)(a.ph.nx * a.ph.ny * a.ph.nz);
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const PassPlan P = *a.plan;
+  WaveRange range = wave_range(P, wave, (gridDim.x * blockDim.x) >> 6);
+  WaveSeg gsame{wave * P.seg_same, P.seg_same, 0u}, gother{wave * P.seg_other, P.seg_other, 0u};
+  WaveTotals tot;
+  photon_loop(a, P.admitting, range, gsame, gother, smem, majg, lbeams, nvox, tot);
   append_outputs(a, P, gsame, gother);
-  const unsigned long long s_esc = wave_sum(acc_esc), s_sink = wave_sum(acc_sink);
-  const unsigned long long s_ev = wave_sum(c_ev), s_fict = wave_sum(c_fict), s_viol = wave_sum(c_viol),
-                           s_sec = wave_sum(c_sec);
-  if (lane_id() == 0) {
-    if (s_esc) ctr_add(a.ctr, C_E_ESC, s_esc);
-    if (s_sink) ctr_add(a.ctr, C_E_SINK, s_sink);
-    if (s_ev) ctr_add(a.ctr, C_PH_EVENTS, s_ev);
-    if (s_fict) ctr_add(a.ctr, C_FICT, s_fict);
-    if (s_viol) ctr_add(a.ctr, C_VIOL, s_viol);
-    if (s_sec) ctr_add(a.ctr, C_SEC, s_sec);
-  }
+  add_totals(tot, a.ctr);
 }
 
 // ---------------------------------------------------------- electron pass
@@ -665,31 +789,19 @@ __device__ __forceinline__ bool hard_event(Lane& L, const PassArgs& a, const flo
 // max_secondaries secondaries and one survivor at the bottom, and is parked
 // at most once at a time, so a segment of per_wave x (max_secondaries + 2)
 // slots holds bottom and stack without overlap.
-__global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
-  extern __shared__ float4 smem[];
-  const int nt = a.tab.n_mat * kNE;
-  for (int i = threadIdx.x; i < nt; i += blockDim.x) smem[i] = a.tab.el[i];
-  float* maje = reinterpret_cast<float*>(smem + nt);
-  float* ms = maje + kNE;
-  for (int i = threadIdx.x; i < kNE; i += blockDim.x) maje[i] = a.tab.maj_e[i];
-  for (int i = threadIdx.x; i < kNms; i += blockDim.x) ms[i] = a.tab.ms[i];
-  DevBeam* lbeams = reinterpret_cast<DevBeam*>(ms + kNms);
-  if (a.n_beams <= kLdsBeams)
-    for (int i = threadIdx.x; i < a.n_beams; i += blockDim.x) lbeams[i] = a.beams[i];
-  __syncthreads();
-
-  const uint32_t nvox = (uint32_t)(a.ph.nx * a.ph.ny * a.ph.nz);
-  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const PassPlan P = *a.plan;
-  WaveRange range = wave_range(P, wave, (gridDim.x * blockDim.x) >> 6);
-  WaveSeg gsame{wave * P.seg_same, P.seg_same, 0u}, gother{wave * P.seg_other, P.seg_other, 0u};
+// The electron transport of one wavefront over its range: electron tables
+// in LDS at tab (per material), maje (hard-event majorant) and ms (screening),
+// the beam table at lbeams.
+template <class R>
+__device__ void electron_loop(const PassArgs& a, uint32_t admitting, R& range, WaveSeg& gsame, WaveSeg& gother,
+                              const float4* tab, const float* maje, const float* ms, const DevBeam* lbeams,
+                              uint32_t nvox, WaveTotals& tot) {
   Lane L;
   Pending pend;
+  Deferred dfr;
   bool have = false;
   int events = 0, pushes = 0;
   uint32_t npark = 0;   // parked electrons on the stack, wave-uniform
-  unsigned long long acc_esc = 0;
-  uint32_t c_steps = 0, c_hard = 0, c_viol = 0, c_sec = 0;
   const float emin = a.cut.emin;
 
   for (;;) {
@@ -697,7 +809,7 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
     // range done: idle lanes take back parked electrons, newest first
     bool hd = false;
     float hsh = 0.0f;
-    if (npark && range.next >= range.end) {
+    if (npark && range.done()) {
       const unsigned long long need = __ballot(!have);
       const uint32_t nn = (uint32_t)__popcll(need);
       if (nn >= (uint32_t)a.resume_lanes || nn == 64u) {
@@ -721,7 +833,7 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
       }
     }
     if (!__any(have || hd)) {
-      if (range.next >= range.end) break;
+      if (range.done()) break;
       continue;
     }
     if (__any(hd)) {
@@ -730,11 +842,11 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
       if (hd) {
         int jx, jy, jz, v1;
         if (electron_voxel(a.ph, L.x, L.y, L.z, L.u, L.v, L.w, jx, jy, jz, v1)) {   // inside when it was parked
-          have = hard_event(L, a, smem, hsh, v1, c0, ctype, c_hard, c_viol);
+          have = hard_event(L, a, tab, hsh, v1, c0, ctype, tot.hard, tot.viol);
         } else {
-          acc_esc += L.e;
+          tot.esc += L.e;
         }
-        if (ctype >= 0) { ++pushes; ++c_sec; }
+        if (ctype >= 0) { ++pushes; ++tot.sec; }
       }
       // delta rays to the electron staging segment, photons to the photon one
       const WaveSeg::Slots se = gsame.append(ctype == 1, false);
@@ -751,7 +863,7 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
     // rather than holding the wavefront for its last few particles -- while
     // primaries remain to be admitted, when a next pass comes anyway
     bool tail = false;
-    if (a.tail_lanes > 0 && P.admitting && range.next >= range.end && npark == 0 && range.end >= a.tail_min)
+    if (a.tail_lanes > 0 && admitting && npark == 0 && range.done() && range.size() >= a.tail_min)
       tail = (uint32_t)__popcll(__ballot(have)) <= (uint32_t)a.tail_lanes;
     if (have && ((tail && events > 0) || events >= a.max_events || pushes + 1 > a.max_secondaries)) {
       // tail of the share, or visit budget spent (after a hard event): requeued
@@ -760,22 +872,22 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
     }
     // a resumed electron that ended at its hard event, or is requeued, adds
     // the pending deposit it brought back (idle lanes hold none)
-    if (!have) flush(L, pend);
+    if (!have) flush(L, pend, dfr, a.agg_a);
     if (have) {
       L.s.align();
       int ix, iy, iz, v0;
       if (!electron_voxel(a.ph, L.x, L.y, L.z, L.u, L.v, L.w, ix, iy, iz, v0)) {
-        acc_esc += L.e;
+        tot.esc += L.e;
         have = false;
       } else {
         const uint2 vx = a.ph.vox[v0];
         const float rho0 = __uint_as_float(vx.x);
         const int base0 = (int)vx.y * kNE;
         if (L.e < a.cut.ecut_lsb) {
-          deposit_later(L, pend, v0, L.e);
+          deposit_later(L, pend, v0, L.e, dfr, a.agg_a);
           have = false;
         } else {
-          ++c_steps;
+          ++tot.steps;
           const float tf = (float)L.e * kLsbF;
           const TPos p0 = tpos(a.tab, tf);
           sh = maje[p0.i];
@@ -787,10 +899,10 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
           bool hard = false;
           if (emax < es) es = emax;
           if (ehard < es) { es = ehard; hard = true; }
-          const float4 t0 = lerp4(smem, base0, p0);
+          const float4 t0 = lerp4(tab, base0, p0);
           const float l0 = rho0 * t0.x;
           const float tm = fmaxf(tf - 0.5f * es * l0, emin);
-          const float de = es * rho0 * lerp_x(smem, base0, tpos(a.tab, tm));
+          const float de = es * rho0 * lerp_x(tab, base0, tpos(a.tab, tm));
           // the hinge word: fraction zeta from its top bits, deflection-energy coin from bit 0
           const uint32_t wz = L.s.word();
           const float zeta = to_uniform(wz);
@@ -800,20 +912,20 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
           L.z = fmaf(s1, L.w, L.z);
           const uint32_t dl = to_lsb(de);
           if (dl >= L.e || L.e - dl < a.cut.ecut_lsb) {
-            deposit_later(L, pend, v0, L.e);
+            deposit_later(L, pend, v0, L.e, dfr, a.agg_a);
             have = false;
           } else {
             const uint32_t e1 = L.e - dl;
             const float t1f = (float)e1 * kLsbF;
             const float ua = L.s.uniform(), uphi = L.s.uniform();
             if (a.cut.mode != 2) {
-              const float il = (wz & 1u) ? lerp_w(smem, base0, tpos(a.tab, t1f)) : t0.w;
+              const float il = (wz & 1u) ? lerp_w(tab, base0, tpos(a.tab, t1f)) : t0.w;
               const float xx = es * rho0 * il;
               // G1 = 1 - exp(-x), by its series where the subtraction would cancel
               const float g1 = xx < 1e-3f ? xx * (1.0f - 0.5f * xx * (1.0f - xx * (1.0f / 3.0f))) : 1.0f - fexp(-xx);
               rotate_om(L.u, L.v, L.w, wentzel_om(a.tab, ms, g1, ua), kTwoPi * uphi);
             }
-            deposit_later(L, pend, v0, dl);
+            deposit_later(L, pend, v0, dl, dfr, a.agg_a);
             L.e = e1;
             const float s2 = (1.0f - zeta) * es;
             L.x = fmaf(s2, L.u, L.x);
@@ -821,7 +933,7 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
             L.z = fmaf(s2, L.w, L.z);
             int jx, jy, jz, v1;
             if (!electron_voxel(a.ph, L.x, L.y, L.z, L.u, L.v, L.w, jx, jy, jz, v1)) {
-              acc_esc += L.e;
+              tot.esc += L.e;
               have = false;
             } else if (hard) {
               park = true;
@@ -840,7 +952,7 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
       // before the lane takes another particle; a parked electron keeps its
       // pending deposit (pencil beams concentrate deposits on few voxels,
       // where every extra atomic costs)
-      if (!have && !park) flush(L, pend);
+      if (!have && !park) flush(L, pend, dfr, a.agg_a);
     }
     {
       // survivors to the bottom of the electron staging segment, parked electrons onto its stack
@@ -859,25 +971,118 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
           pend = Pending{};
         } else {
           ctr_add(a.ctr, C_OVERFLOW, 1ull);
-          flush(L, pend);
+          flush(L, pend, dfr, a.agg_a);
         }
       }
       npark += (uint32_t)__popcll(pm);
       // a lane that reads a parked entry may not be the lane that wrote it
       if (pm) __threadfence_block();
     }
+    if (a.agg_a) commit_deferred(dfr);
   }
+}
+
+__global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
+  extern __shared__ float4 smem[];
+  const int nt = a.tab.n_mat * kNE;
+  for (int i = threadIdx.x; i < nt; i += blockDim.x) smem[i] = a.tab.el[i];
+  float* maje = reinterpret_cast<float*>(smem + nt);
+  float* ms = maje + kNE;
+  for (int i = threadIdx.x; i < kNE; i += blockDim.x) maje[i] = a.tab.maj_e[i];
+  for (int i = threadIdx.x; i < kNms; i += blockDim.x) ms[i] = a.tab.ms[i];
+  DevBeam* lbeams = reinterpret_cast<DevBeam*>(ms + kNms);
+  if (a.n_beams <= kLdsBeams)
+    for (int i = threadIdx.x; i < a.n_beams; i += blockDim.x) lbeams[i] = a.beams[i];
+  __syncthreads();
+
+  const uint32_t nvox = (uint32_t)(a.ph.nx * a.ph.ny * a.ph.nz);
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const PassPlan P = *a.plan;
+  WaveRange range = wave_range(P, wave, (gridDim.x * blockDim.x) >> 6);
+  WaveSeg gsame{wave * P.seg_same, P.seg_same, 0u}, gother{wave * P.seg_other, P.seg_other, 0u};
+  WaveTotals tot;
+  electron_loop(a, P.admitting, range, gsame, gother, smem, maje, ms, lbeams, nvox, tot);
   append_outputs(a, P, gsame, gother);
-  const unsigned long long s_esc = wave_sum(acc_esc);
-  const unsigned long long s_steps = wave_sum(c_steps), s_hard = wave_sum(c_hard), s_viol = wave_sum(c_viol),
-                           s_sec = wave_sum(c_sec);
+  add_totals(tot, a.ctr);
+}
+
+// ------------------------------------------------------------ round kernel
+// End of a round kernel's workgroup: both types' carried-over particles to
+// the front of their new queues, then one atomic per type reserves room for
+// the workgroup's staged outputs of that type and each wavefront copies its
+// segments.
+__device__ __forceinline__ void append_round(const RoundArgs& r, const PassPlan& Pe, const PassPlan& Pg,
+                                             const WaveSeg& se, const WaveSeg& sg) {
+  __shared__ uint32_t s_used[2][16];
+  __shared__ uint32_t s_base[2];
+  const uint32_t ce = Pe.n - Pe.m, cg = Pg.n - Pg.m;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ce; i += gridDim.x * blockDim.x)
+    copy_entry(r.e.dst_same, i, r.e.carry_src, Pe.m + i, r.e.ctr);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cg; i += gridDim.x * blockDim.x)
+    copy_entry(r.g.dst_same, i, r.g.carry_src, Pg.m + i, r.g.ctr);
+  const uint32_t wl = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const uint32_t n0 = min(se.used, se.cap), n1 = min(sg.used, sg.cap);
   if (lane_id() == 0) {
-    if (s_esc) ctr_add(a.ctr, C_E_ESC, s_esc);
-    if (s_steps) ctr_add(a.ctr, C_E_STEPS, s_steps);
-    if (s_hard) ctr_add(a.ctr, C_HARD, s_hard);
-    if (s_viol) ctr_add(a.ctr, C_VIOL, s_viol);
-    if (s_sec) ctr_add(a.ctr, C_SEC, s_sec);
+    s_used[0][wl] = n0;
+    s_used[1][wl] = n1;
   }
+  __syncthreads();
+  if (threadIdx.x < 2u) {
+    uint32_t tot = 0;
+    for (uint32_t w = 0; w < nw; ++w) tot += s_used[threadIdx.x][w];
+    s_base[threadIdx.x] = tot ? atomicAdd(threadIdx.x == 0 ? r.e.cnt_same : r.g.cnt_same, tot) : 0u;
+  }
+  __syncthreads();
+  uint32_t o0 = s_base[0], o1 = s_base[1];
+  for (uint32_t w = 0; w < wl; ++w) {
+    o0 += s_used[0][w];
+    o1 += s_used[1][w];
+  }
+  for (uint32_t i = lane_id(); i < n0; i += 64u) copy_entry(r.e.dst_same, o0 + i, r.e.stg_same, se.base + i, r.e.ctr);
+  for (uint32_t i = lane_id(); i < n1; i += 64u) copy_entry(r.g.dst_same, o1 + i, r.g.stg_same, sg.base + i, r.g.ctr);
+}
+
+// The persistent round kernel (the batched form's pool of persistent
+// wavefronts, Sec. II.C.3): every workgroup stages both table blocks, and
+// each wavefront claims chunks of the round's electrons from the device work
+// queue until none is left (or its cap is reached), finishes its electrons
+// and their parked hard events, then claims photons the same way.  The
+// electron and photon loops are those of the pass kernels; only where their
+// items come from differs.  Electron outputs of both phases go to the
+// wavefront's electron segment, photon outputs to its photon segment.
+__global__ void __launch_bounds__(1024) k_round(RoundArgs r) {
+  extern __shared__ float4 smem[];
+  const int nt = r.e.tab.n_mat * kNE;
+  float4* tg = smem;
+  float4* te = smem + nt;
+  float* majg = reinterpret_cast<float*>(te + nt);
+  float* maje = majg + kNE;
+  float* ms = maje + kNE;
+  DevBeam* lbeams = reinterpret_cast<DevBeam*>(ms + kNms);
+  for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+    tg[i] = r.g.tab.ph[i];
+    te[i] = r.e.tab.el[i];
+  }
+  for (int i = threadIdx.x; i < kNE; i += blockDim.x) {
+    majg[i] = r.g.tab.maj_g[i];
+    maje[i] = r.e.tab.maj_e[i];
+  }
+  for (int i = threadIdx.x; i < kNms; i += blockDim.x) ms[i] = r.e.tab.ms[i];
+  if (r.e.n_beams <= kLdsBeams)
+    for (int i = threadIdx.x; i < r.e.n_beams; i += blockDim.x) lbeams[i] = r.e.beams[i];
+  __syncthreads();
+
+  const uint32_t nvox = (uint32_t)(r.e.ph.nx * r.e.ph.ny * r.e.ph.nz);
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const PassPlan Pg = *r.g.plan, Pe = *r.e.plan;
+  WaveSeg se{wave * Pe.seg_same, Pe.seg_same, 0u}, sg{wave * Pg.seg_same, Pg.seg_same, 0u};
+  WaveTotals tot;
+  ClaimRange re = claim_range(r.claims[1], r.claim_ctr + kClaimParts, Pe.chunk_log2, blockIdx.x);
+  electron_loop(r.e, Pe.admitting, re, se, sg, te, maje, ms, lbeams, nvox, tot);
+  ClaimRange rg = claim_range(r.claims[0], r.claim_ctr, Pg.chunk_log2, blockIdx.x);
+  photon_loop(r.g, Pg.admitting, rg, sg, se, tg, majg, lbeams, nvox, tot);
+  append_round(r, Pe, Pg, se, sg);
+  add_totals(tot, r.e.ctr);
 }
 
 // ---------------------------------------------------------------- finalize
@@ -1074,6 +1279,64 @@ __global__ void k_plan_pass(PlanArgs a) {
   *a.plan = P;
 }
 
+// Sizes of a round (one lane): the electrons' share first, bounded like an
+// electron pass (own outputs within the allocated capacity, photons within
+// the soft one), then the photons queued at the round's start, bounded so
+// that the electrons they create keep the electron queue within the soft
+// capacity; the claim caps (an even share of chunks plus one) and the
+// segments those caps need; the claim counters are cleared.
+__global__ void k_plan_round(RoundPlanArgs a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const uint32_t ne = *a.n_work[1], ng = *a.n_work[0];
+  const uint64_t s = a.sec;
+  uint64_t me = ne < a.max_items ? ne : a.max_items;
+  if (s > 0) {
+    const uint64_t l1 = ne < a.cap ? (uint64_t)(a.cap - ne) / s : 0u;
+    const uint64_t l2 = ng < a.cap_soft ? (uint64_t)(a.cap_soft - ng) / s : 0u;
+    if (me > l1) me = l1;
+    if (me > l2) me = l2;
+  }
+  uint64_t mg = ng < a.max_items ? ng : a.max_items;
+  if (s > 0) {
+    const uint64_t held = (uint64_t)ne + me * s;   // most the electron queue holds after the electron phase
+    const uint64_t l3 = held < a.cap_soft ? ((uint64_t)a.cap_soft - held) / s : 0u;
+    if (mg > l3) mg = l3;
+  }
+  const uint32_t ch = 1u << a.chunk_log2;
+  const uint32_t ms[2] = {(uint32_t)mg, (uint32_t)me};
+  const uint32_t ns[2] = {ng, ne};
+  uint32_t caps[2];
+  for (int t = 0; t < 2; ++t) {
+    const uint64_t chunks = ((uint64_t)ms[t] + ch - 1u) >> a.chunk_log2;
+    caps[t] = (uint32_t)(((chunks + a.waves - 1u) / a.waves + 1u) << a.chunk_log2);
+    ClaimType c;
+    c.cap = caps[t];
+    for (int p = 0; p <= kClaimParts; ++p) c.start[p] = (uint32_t)((uint64_t)ms[t] * (uint64_t)p / kClaimParts);
+    a.claims[t] = c;
+    for (int p = 0; p < kClaimParts; ++p) a.claim_ctr[t * kClaimParts + p] = 0u;
+    *a.n_work[t] = 0u;
+    *a.n_new[t] = ns[t] - ms[t];
+  }
+  const uint32_t admitting = (a.sched[0] < a.sched[2] || a.sched[1] < a.sched[3]) ? 1u : 0u;
+  // electron outputs: survivors, secondaries and the parked stack of the
+  // electron phase, the photon phase's electrons; photon outputs:
+  // bremsstrahlung of the electron phase, survivors and the parked stack of
+  // the photon phase
+  const uint64_t seg_e = (uint64_t)caps[1] * (s + 2u) + (uint64_t)caps[0] * s;
+  const uint64_t seg_g = (uint64_t)caps[1] * s + 2ull * caps[0];
+  for (int t = 0; t < 2; ++t) {
+    PassPlan P;
+    P.n = ns[t];
+    P.m = ms[t];
+    P.per_wave = caps[t];
+    P.chunk_log2 = a.chunk_log2;
+    P.seg_same = (uint32_t)(t == 1 ? seg_e : seg_g);
+    P.seg_other = (uint32_t)(t == 1 ? seg_g : seg_e);
+    P.admitting = admitting;
+    a.plan[t] = P;
+  }
+}
+
 // ------------------------------------------------------ energy regrouping
 // Sort key: bucket 4 log2(e) + the two bits below the leading one, reversed
 // so that the highest energies come first; zero-energy entries go last.
@@ -1148,6 +1411,12 @@ size_t electron_lds_bytes(int n_mat) {
          kLdsBeams * sizeof(DevBeam);
 }
 
+// Both table blocks and the beam table.
+size_t round_lds_bytes(int n_mat) {
+  return 2 * (size_t)n_mat * kNE * sizeof(float4) + 2 * kNE * sizeof(float) + kNms * sizeof(float) +
+         kLdsBeams * sizeof(DevBeam);
+}
+
 // The pass kernels' dynamic-LDS limit is raised once, to what the largest
 // table set needs (occupancy follows the size each launch asks for), so that
 // launches -- also those recorded into a graph -- set no attributes.
@@ -1158,6 +1427,9 @@ static hipError_t lds_limits() {
     if (r == hipSuccess)
       r = hipFuncSetAttribute((const void*)k_electron_pass, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)electron_lds_bytes(kMaxMat));
+    if (r == hipSuccess)
+      r = hipFuncSetAttribute((const void*)k_round, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)round_lds_bytes(kMaxRoundMat));
     return r;
   }();
   return e;
@@ -1192,6 +1464,20 @@ hipError_t launch_photon_pass(const PassArgs& a, int grid, int block, hipStream_
   const hipError_t e = lds_limits();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_photon_pass, dim3(grid), dim3(block), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_round(const RoundPlanArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_plan_round, dim3(1), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_round(const RoundArgs& a, int grid, int block, hipStream_t s) {
+  if (a.e.tab.n_mat > kMaxRoundMat) return hipErrorInvalidValue;
+  const size_t lds = round_lds_bytes(a.e.tab.n_mat);
+  const hipError_t e = lds_limits();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_round, dim3(grid), dim3(block), lds, s, a);
   return hipGetLastError();
 }
 
@@ -1282,7 +1568,8 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v
 
 int max_resident_blocks(int kernel, int block, size_t lds) {
   int per_cu = 0;
-  const void* fn = kernel == 0 ? (const void*)k_photon_pass : (const void*)k_electron_pass;
+  const void* fn = kernel == 0 ? (const void*)k_photon_pass
+                   : kernel == 1 ? (const void*)k_electron_pass : (const void*)k_round;
   (void)lds_limits();
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess || per_cu <= 0) per_cu = 1;
   int dev = 0, cus = 0;

@@ -65,12 +65,15 @@ int gmc_load_tables(gmc_context* c, const gmc_material* mats, int n_mat, const g
     return cfail(c, GMC_EINVAL, "cutoffs must lie in [0.002, 30) MeV (electrons) and [0.001, 30) MeV (photons)");
   if (phys->test_mode < 0 || phys->test_mode > 2) return cfail(c, GMC_EINVAL, "test_mode must be 0, 1 or 2");
   if (phys->n_batches > kMaxBatches) return cfail(c, GMC_EINVAL, "n_batches must be <= 1024");
+  if (phys->majorant_margin > 0 && !(phys->majorant_margin >= 0.01 && phys->majorant_margin <= 100.0))
+    return cfail(c, GMC_EINVAL, "majorant_margin must lie in [0.01, 100] (or <= 0 for the default)");
   (void)hipSetDevice(c->device);
   auto t = std::make_unique<TablesObj>();
   t->phys = *phys;
   if (t->phys.n_batches <= 0) t->phys.n_batches = 32;
   t->kcut = phys->kcut_mev > 0 ? phys->kcut_mev : phys->ecut_mev;
   t->kc = phys->kc_mev > 0 ? phys->kc_mev : phys->pcut_mev;
+  if (phys->majorant_margin > 0) t->margin = phys->majorant_margin;
   if (!(t->kcut >= kEmin && t->kc >= kEmin)) return cfail(c, GMC_EINVAL, "kcut and kc must be >= 0.001 MeV");
   build_tables(mats, n_mat, t->kcut, t->kc, &t->host);
   const size_t nb = (size_t)n_mat * kNE * sizeof(float4);
@@ -185,6 +188,75 @@ int gmc_run_beam(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gm
   if (!src) return cfail(c, GMC_EINVAL, "source is NULL");
   return run_job(c, phantom_id, tables_id, src, &n_hist, 1, seed, nullptr, nullptr, dose, sigma, out_kind, tuning,
                  stats, false);
+}
+
+int gmc_run_beam_tally(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_source* src, uint64_t n_hist,
+                       uint64_t seed, uint64_t* tally, int out_kind, const gmc_tuning* tuning, gmc_run_stats* stats) {
+  if (!c) return GMC_EINVAL;
+  if (!src) return cfail(c, GMC_EINVAL, "source is NULL");
+  if (!tally) return cfail(c, GMC_EINVAL, "tally output is NULL");
+  return run_job(c, phantom_id, tables_id, src, &n_hist, 1, seed, nullptr, nullptr, nullptr, nullptr, GMC_DEVICE,
+                 tuning, stats, false, tally, out_kind);
+}
+
+int gmc_finalize_tally(gmc_context* c, int32_t phantom_id, int32_t tables_id, const uint64_t* tally, int tally_kind,
+                       uint64_t h_begin, uint64_t h_end, double* dose, double* sigma, int out_kind, double* s_rel) {
+  if (!c) return GMC_EINVAL;
+  const PhantomObj* pp = nullptr;
+  const TablesObj* tp = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto pi = c->phantoms.find(phantom_id);
+    auto ti = c->tables.find(tables_id);
+    if (pi != c->phantoms.end()) pp = pi->second.get();
+    if (ti != c->tables.end()) tp = ti->second.get();
+  }
+  if (!pp || !tp) return cfail(c, GMC_ENOTFOUND, "unknown phantom or tables id");
+  if (!tally || !dose) return cfail(c, GMC_EINVAL, "tally or dose is NULL");
+  if ((tally_kind != GMC_HOST && tally_kind != GMC_DEVICE) || (out_kind != GMC_HOST && out_kind != GMC_DEVICE))
+    return cfail(c, GMC_EINVAL, "bad pointer kind");
+  const uint32_t K = (uint32_t)tp->phys.n_batches;
+  if (h_end <= h_begin || h_end > (1ull << 32) || h_end - h_begin < K)
+    return cfail(c, GMC_EINVAL, "the history range must hold at least n_batches histories below 2^32");
+  (void)hipSetDevice(c->device);
+  Workspace* w = &c->ws;
+  const size_t nvox = pp->nvox();
+  int rc = ws_ensure_out(w, nvox);
+  if (rc) return cfail(c, rc, w->err);
+  const unsigned long long* d_tally = reinterpret_cast<const unsigned long long*>(tally);
+  if (tally_kind == GMC_HOST) {
+    rc = ws_ensure_tally(w, nvox * K);
+    if (rc) return cfail(c, rc, w->err);
+    if (hipMemcpyAsync(w->d_tally, tally, nvox * K * sizeof(unsigned long long), hipMemcpyHostToDevice,
+                       w->stream) != hipSuccess)
+      return cfail(c, GMC_EDEVICE, "copy of the tallies to the device failed");
+    d_tally = w->d_tally;
+  }
+  std::vector<double> nk;
+  add_batch_sizes(nk, h_begin, h_end - h_begin, K);
+  double* dd = out_kind == GMC_DEVICE ? dose : w->d_dose;
+  double* ds = sigma ? (out_kind == GMC_DEVICE ? sigma : w->d_sigma) : nullptr;
+  rc = finalize(w, *pp, d_tally, 1u, 0u, K, nk, h_end - h_begin, dd, ds, true, true);
+  if (rc) return cfail(c, rc, w->err);
+  if (out_kind == GMC_HOST) {
+    hipError_t e = hipMemcpy(dose, w->d_dose, nvox * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && sigma) e = hipMemcpy(sigma, w->d_sigma, nvox * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return cfail(c, GMC_EDEVICE, std::string("result copy: ") + hipGetErrorString(e));
+  }
+  if (s_rel) *s_rel = w->h_srel[0];
+  return GMC_OK;
+}
+
+int gmc_phantom_dims(gmc_context* c, int32_t phantom_id, int* nx, int* ny, int* nz) {
+  if (!c) return GMC_EINVAL;
+  if (!nx || !ny || !nz) return cfail(c, GMC_EINVAL, "NULL output");
+  std::lock_guard<std::mutex> lk(c->mu);
+  auto pi = c->phantoms.find(phantom_id);
+  if (pi == c->phantoms.end()) return cfail(c, GMC_ENOTFOUND, "unknown phantom id " + std::to_string(phantom_id));
+  *nx = pi->second->nx;
+  *ny = pi->second->ny;
+  *nz = pi->second->nz;
+  return GMC_OK;
 }
 
 int gmc_run_beams(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_source* srcs,

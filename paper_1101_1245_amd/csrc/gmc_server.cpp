@@ -161,7 +161,7 @@ int finish(Slot& sl) {
   Workspace* w = &sl.w;
   const Request& r = *sl.req;
   std::vector<double> nk;
-  add_batch_sizes(nk, r.n, r.K);
+  add_batch_sizes(nk, r.src.first_history, r.n, r.K);
   int rc = finalize(w, *sl.P, w->d_tally, 1u, 0u, r.K, nk, r.n, w->d_dose, w->d_sigma, true, false);
   if (rc) return rc;
   WS_TRY(w, hipMemcpyAsync(sl.h_dose, w->d_dose, r.nvox * sizeof(double), hipMemcpyDeviceToHost, w->stream));
@@ -367,6 +367,8 @@ int gmc_submit(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_
     r->K = (uint32_t)T.phys.n_batches;
     if (n_hist < r->K || n_hist >= (1ull << 32))
       return cfail(c, GMC_EINVAL, "histories must be in [n_batches, 2^32)");
+    if (src->first_history + n_hist >= (1ull << 32))
+      return cfail(c, GMC_EINVAL, "first_history + histories must stay below 2^32");
     const double e_max = source_emax(*src);
     if ((double)n_hist * (e_max * 134217728.0 + 1.0) >= 9.2e18)
       return cfail(c, GMC_EOVERFLOW, "histories x energy would overflow the 64-bit tallies");

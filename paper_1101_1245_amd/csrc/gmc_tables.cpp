@@ -28,7 +28,6 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kPhotoConst = 1.9522732685184204e-31;  // cm^2
 constexpr double kPairConst = 2.0;
 constexpr double kTfRadius = 0.885;   // Thomas-Fermi radius in units of a0 Z^-1/3
-constexpr double kMargin = 1.001;     // majorant safety factor
 
 struct Kin {
   double t, tau, gam, beta2, pc, beta;
@@ -200,7 +199,7 @@ void build_tables(const gmc_material* mats, int n_mat, double kcut, double kc, H
   }
 }
 
-void build_majorants(const HostTables& t, const double* rho_max, float* maj_g, float* maj_e) {
+void build_majorants(const HostTables& t, const double* rho_max, double margin, float* maj_g, float* maj_e) {
   double running = 0.0;
   for (int i = 0; i < kNE - 1; ++i) {
     double mu = 0.0, sg = 0.0;
@@ -213,8 +212,8 @@ void build_majorants(const HostTables& t, const double* rho_max, float* maj_g, f
       sg = std::max(sg, r * std::max((double)c.y + (double)c.z, (double)d.y + (double)d.z));
     }
     running = std::max(running, sg);
-    maj_g[i] = (float)(kMargin * mu);
-    maj_e[i] = (float)(kMargin * running);
+    maj_g[i] = (float)(margin * mu);
+    maj_e[i] = (float)(margin * running);
   }
   maj_g[kNE - 1] = maj_g[kNE - 2];
   maj_e[kNE - 1] = maj_e[kNE - 2];

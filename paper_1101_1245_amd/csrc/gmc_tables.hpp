@@ -20,9 +20,9 @@ struct HostTables {
 void build_tables(const gmc_material* mats, int n_mat, double kcut, double kc, HostTables* out);
 
 // Majorants per grid bin for a phantom whose densest voxel of material m has
-// density rho_max[m] (0 when absent): photon mu_hat from the total attenuation
-// and electron Sigma_hat from the hard-event cross section, the latter as a
-// running maximum over lower bins.
-void build_majorants(const HostTables& t, const double* rho_max, float* maj_g, float* maj_e);
+// density rho_max[m] (0 when absent): `margin` times the photon total
+// attenuation and the electron hard-event cross section at either bin edge,
+// the latter as a running maximum over lower bins.
+void build_majorants(const HostTables& t, const double* rho_max, double margin, float* maj_g, float* maj_e);
 
 }  // namespace gmc

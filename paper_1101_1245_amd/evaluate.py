@@ -150,18 +150,62 @@ class ZTest:
     passed: bool
 
 
+LSB_MEV = 2.0 ** -27
+MEV_TO_J = 1.602176634e-13
+
+
+def batch_doses(batch_energy, rho, voxel, n_hist_total: int, h0: int = 0):
+    """Per-batch dose per history D_k[v] (Gy) and the batch sizes n_k from
+    batch energy sums (MeV; history h in batch h mod K), for histories
+    [h0, h0 + N)."""
+    e = np.asarray(batch_energy, dtype=np.float64)
+    K = e.shape[0]
+    h = np.arange(h0, h0 + n_hist_total, dtype=np.int64)
+    nk = np.bincount(h % K, minlength=K).astype(np.float64)
+    rho = np.asarray(rho, dtype=np.float64)
+    vol = float(np.prod(voxel))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        conv = np.where(rho > 0, MEV_TO_J / (rho * vol * 1e-3), 0.0)
+    return e / nk.reshape((K,) + (1,) * (e.ndim - 1)) * conv, nk
+
+
+def weighted_sum_se(dk, nk, w):
+    """Standard error of sum_v w_v D_v, D = sum_k n_k D_k / N, from the spread
+    of the K batch values Y_k = sum_v w_v D_k,v (the batch estimator of Eq.
+    13): var = sum_k n_k^2 (Y_k - Y)^2 / (N^2 (K - 1)/K).  It carries every
+    covariance between voxels that share histories."""
+    K = dk.shape[0]
+    y = np.array([np.sum(w * dk[k]) for k in range(K)])
+    n = nk.sum()
+    m = np.sum(nk * y) / n
+    return math.sqrt(np.sum(nk * nk * (y - m) ** 2) / (n * n * (K - 1) / K))
+
+
 def z_test(d_a, s_a, d_b, s_b, ref_for_mask=None, threshold: float = 0.1, dof: int = 31,
-           same_streams: bool = False) -> ZTest:
+           same_streams: bool = False, dof_b: float = None, batches=None) -> ZTest:
     """Voxel-by-voxel agreement of two Monte Carlo estimates.
 
     Over voxels with ref > threshold * max(ref) (ref defaults to d_b),
     z = (d_a - d_b)/sqrt(s_a^2 + s_b^2).  A literal "every voxel within 3
-    sigma" fails 0.27% of voxels by chance, so the test asks: the fraction
-    with |z| > 3 is at most 0.27% + 3 sqrt(0.0027/n); max |z| is below the
-    two-sided Bonferroni bound at alpha = 1e-3 over n voxels using a Student
-    t with ``dof`` degrees of freedom (the batch estimate of sigma); |mean z|
-    <= 4/sqrt(n); and var z lies within (dof/(dof-2)) (1 +- 4 sqrt(2/n)) and
-    at least [0.6, 1.6].
+    sigma" fails voxels by chance, so the test asks:
+
+    * the fraction with |z| > 3 is at most p + 3 sqrt(p/n), p the expected
+      fraction: the mean over the voxels of P(|t_nu| > 3), nu each voxel's
+      Welch-Satterthwaite degrees of freedom (``dof`` for s_a, a batch
+      estimate; ``dof_b`` for s_b, None for a history-by-history estimate,
+      whose degrees of freedom are practically infinite) -- with an
+      estimated sigma z has heavier tails than a normal variate, and
+      P(|t_31| > 3) = 0.53% against 0.27%;
+    * max |z| below the two-sided Bonferroni bound at alpha = 1e-3 over the n
+      voxels, for the smallest nu;
+    * |mean z| <= 3/sqrt(n) -- or, with ``batches`` = ((Dk_a, nk_a), (Dk_b,
+      nk_b)) the per-batch doses of both estimates (independent runs), within
+      t(K - 1) at the 3-sigma level of its own standard error: mean z is the
+      weighted sum sum_v (d_a - d_b)_v / (n sigma_v) of dose differences,
+      whose batch spread includes the correlation of voxels that share
+      histories (a photon history deposits in many voxels), which 3/sqrt(n)
+      -- the bound for independent voxels -- leaves out;
+    * var z in [0.8, 1.25].
 
     With ``same_streams`` the two runs drew the same random streams, so their
     estimates are positively correlated and z has a variance below one
@@ -170,19 +214,38 @@ def z_test(d_a, s_a, d_b, s_b, ref_for_mask=None, threshold: float = 0.1, dof: i
     """
     ref = d_b if ref_for_mask is None else ref_for_mask
     sel = ref > threshold * ref.max()
-    den = np.sqrt(s_a[sel] ** 2 + s_b[sel] ** 2)
+    va, vb = s_a[sel] ** 2, s_b[sel] ** 2
+    den = np.sqrt(va + vb)
     den = np.where(den > 0, den, np.inf)
     z = (d_a[sel] - d_b[sel]) / den
     n = int(z.size)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        tail_b = vb * vb / dof_b if dof_b else 0.0
+        nu = np.where(va > 0, (va + vb) ** 2 / (va * va / dof + tail_b), np.inf)
+    nu = np.clip(np.nan_to_num(nu, nan=1e9, posinf=1e9), dof, 1e9)
+    p3 = float(np.mean(2.0 * stats.t.sf(3.0, nu))) if n else 0.0027
     frac = float(np.mean(np.abs(z) > 3.0)) if n else 0.0
-    frac_lim = 0.0027 + 3.0 * math.sqrt(0.0027 / max(n, 1))
-    max_lim = float(stats.t.isf(1e-3 / (2.0 * max(n, 1)), dof))
+    frac_lim = p3 + 3.0 * math.sqrt(p3 / max(n, 1))
+    max_lim = float(stats.t.isf(1e-3 / (2.0 * max(n, 1)), float(nu.min()) if n else dof))
     mean = float(np.mean(z)) if n else 0.0
-    mean_lim = 4.0 / math.sqrt(max(n, 1))
+    mean_lim = 3.0 / math.sqrt(max(n, 1))
+    if batches is not None and n:
+        (dka, nka), (dkb, nkb) = batches
+        w = np.zeros(np.shape(d_a))
+        w[sel] = 1.0 / (n * den)
+        se = math.hypot(weighted_sum_se(dka, nka, w), weighted_sum_se(dkb, nkb, w))
+        kk = min(dka.shape[0], dkb.shape[0]) - 1
+        mean_lim = float(stats.t.isf(0.00135, kk)) * se
     var = float(np.var(z)) if n else 1.0
-    tv = dof / (dof - 2.0)
-    half = 4.0 * math.sqrt(2.0 / max(n, 1))
-    vr = (0.0 if same_streams else min(0.6, tv * (1 - half)), max(1.6, tv * (1 + half)))
+    vr = (0.0 if same_streams else 0.8, 1.25)
     ok = n > 0 and frac <= frac_lim and float(np.max(np.abs(z))) <= max_lim and abs(mean) <= mean_lim \
         and vr[0] <= var <= vr[1]
     return ZTest(n, z, frac, frac_lim, float(np.max(np.abs(z))) if n else 0.0, max_lim, mean, mean_lim, var, vr, ok)
+
+
+def describe(zt: ZTest) -> str:
+    """One line with the z-test's statistics and their bounds."""
+    return ("n %d, frac |z|>3 %.5f (<= %.5f), max |z| %.2f (<= %.2f), mean z %+.4f (<= %.4f), var z %.3f in "
+            "[%.2f, %.2f] -> %s" % (zt.n, zt.frac_over_3, zt.frac_limit, zt.max_abs, zt.max_limit, zt.mean,
+                                     zt.mean_limit, zt.var, zt.var_range[0], zt.var_range[1],
+                                     "pass" if zt.passed else "FAIL"))

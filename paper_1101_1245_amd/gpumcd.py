@@ -40,14 +40,15 @@ class gmc_material(C.Structure):
 class gmc_physics(C.Structure):
     _fields_ = [("ecut_mev", C.c_double), ("pcut_mev", C.c_double), ("kcut_mev", C.c_double),
                 ("kc_mev", C.c_double), ("esmax_gcm2", C.c_double), ("n_batches", C.c_int),
-                ("test_mode", C.c_int)]
+                ("test_mode", C.c_int), ("majorant_margin", C.c_double)]
 
 
 class gmc_source(C.Structure):
     _fields_ = [("particle", C.c_int), ("spectrum", C.c_int), ("e_mev", C.c_double), ("e_lo", C.c_double),
                 ("e_mode", C.c_double), ("e_hi", C.c_double), ("cx_cm", C.c_double), ("cy_cm", C.c_double),
                 ("wx_cm", C.c_double), ("wy_cm", C.c_double), ("beam_id", C.c_uint32),
-                ("tab_e", C.POINTER(C.c_double)), ("tab_w", C.POINTER(C.c_double)), ("tab_n", C.c_int)]
+                ("tab_e", C.POINTER(C.c_double)), ("tab_w", C.POINTER(C.c_double)), ("tab_n", C.c_int),
+                ("first_history", C.c_uint64)]
 
 
 class gmc_run_stats(C.Structure):
@@ -58,14 +59,16 @@ class gmc_run_stats(C.Structure):
                 ("n_majorant_violations", C.c_uint64), ("n_passes", C.c_uint64),
                 ("ledger_residual_lsb", C.c_int64), ("t_photon_pass_s", C.c_double),
                 ("t_electron_pass_s", C.c_double), ("n_photon_launches", C.c_uint64),
-                ("n_electron_launches", C.c_uint64), ("s_rel", C.c_double)]
+                ("n_electron_launches", C.c_uint64), ("s_rel", C.c_double), ("t_round_s", C.c_double),
+                ("n_round_launches", C.c_uint64)]
 
 
 class gmc_tuning(C.Structure):
     _fields_ = [("events_per_visit", C.c_int), ("secondaries_per_visit", C.c_int), ("chunk", C.c_int),
                 ("wg_size", C.c_int), ("pass_items", C.c_int), ("wave_items", C.c_int),
                 ("rounds_per_check", C.c_int), ("refill_lanes", C.c_int), ("energy_sort", C.c_int),
-                ("tail_lanes", C.c_int)]
+                ("tail_lanes", C.c_int), ("queue_items", C.c_int), ("persistent", C.c_int),
+                ("aggregate", C.c_int)]
 
 
 class gmc_autotune_report(C.Structure):
@@ -145,6 +148,11 @@ def lib():
     L.gmc_atomic_rate.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_double)]
     L.gmc_first_events.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(gmc_source), C.c_uint64, C.c_uint32,
                                    C.c_uint32, C.POINTER(C.c_float), C.POINTER(C.c_uint32)]
+    L.gmc_run_beam_tally.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(gmc_source), C.c_uint64, C.c_uint64, vp,
+                                     C.c_int, C.POINTER(gmc_tuning), C.POINTER(gmc_run_stats)]
+    L.gmc_finalize_tally.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_int, C.c_uint64, C.c_uint64, vp, vp, C.c_int,
+                                     C.POINTER(C.c_double)]
+    L.gmc_phantom_dims.argtypes = [vp, C.c_int32, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
     _lib = L
     return L
 
@@ -154,6 +162,7 @@ def _src(s, keep: list) -> gmc_source:
     which the caller holds until the call that reads them has returned."""
     out = gmc_source(int(s.particle), int(s.spectrum), float(s.e), float(s.e_lo), float(s.e_mode), float(s.e_hi),
                      float(s.cx), float(s.cy), float(s.wx), float(s.wy), int(s.beam_id))
+    out.first_history = int(getattr(s, "first_history", 0))
     tab_e, tab_w = getattr(s, "tab_e", None), getattr(s, "tab_w", None)
     if tab_e is not None and tab_w is not None:
         e = np.ascontiguousarray(tab_e, dtype=np.float64)
@@ -167,7 +176,7 @@ def _src(s, keep: list) -> gmc_source:
 
 def _phys(p) -> gmc_physics:
     return gmc_physics(float(p.ecut), float(p.pcut), float(p.kcut), float(p.kc), float(p.esmax_gcm2),
-                       int(p.n_batches), int(p.test_mode))
+                       int(p.n_batches), int(p.test_mode), float(getattr(p, "majorant_margin", 0.0)))
 
 
 def _tuning(t) -> Optional[gmc_tuning]:
@@ -200,6 +209,8 @@ class Context:
             raise GpumcdError(rc, "gmc_create failed (no HIP device %d?)" % device)
         self._h = h
         self._L = L
+        self._tickets = {}   # ticket -> phantom id, for the output shape of gmc_poll
+        self._nbatch = {}    # tables id -> n_batches
 
     def close(self):
         if getattr(self, "_h", None):
@@ -229,6 +240,7 @@ class Context:
         tid = C.c_int32()
         ph = _phys(physics)
         self._check(self._L.gmc_load_tables(self._h, arr, len(materials), C.byref(ph), C.byref(tid)))
+        self._nbatch[tid.value] = int(physics.n_batches) if int(physics.n_batches) > 0 else 32
         return tid.value
 
     def load_phantom(self, phantom) -> int:
@@ -244,6 +256,20 @@ class Context:
     def release(self, handle: int):
         self._check(self._L.gmc_release(self._h, handle))
 
+    def phantom_shape(self, phantom_id: int):
+        """(nz, ny, nx) of a loaded phantom: the shape of every dose output on it."""
+        nx, ny, nz = C.c_int(), C.c_int(), C.c_int()
+        self._check(self._L.gmc_phantom_dims(self._h, phantom_id, C.byref(nx), C.byref(ny), C.byref(nz)))
+        return (nz.value, ny.value, nx.value)
+
+    def _out_shape(self, phantom_id: int, shape):
+        """The phantom's (nz, ny, nx); a given shape must hold exactly its voxels
+        (the library writes nx*ny*nz doubles into every output)."""
+        real = self.phantom_shape(phantom_id)
+        if shape is not None and int(np.prod(shape)) != int(np.prod(real)):
+            raise ValueError("output shape %s does not match the phantom's %s" % (tuple(shape), real))
+        return tuple(shape) if shape is not None else real
+
     # --------------------------------------------------------------- runs
     def run_beam(self, phantom_id: int, tables_id: int, source, n_hist: int, seed: int, shape=None,
                  tuning=None, sigma: bool = True, out: str = "numpy"):
@@ -256,8 +282,7 @@ class Context:
         src = _src(source, keep)
         tun = _tuning(tuning)
         tun_p = C.byref(tun) if tun is not None else None
-        if shape is None:
-            raise ValueError("shape (nz, ny, nx) is required")
+        shape = self._out_shape(phantom_id, shape)
         n = int(np.prod(shape))
         if out == "torch":
             import torch
@@ -279,8 +304,7 @@ class Context:
         """Batched form: several beams in one job.  Returns (per_beam_dose or
         None, per_beam_sigma or None, combined_dose, combined_sigma or None,
         stats); per-beam arrays have shape (n_beams, nz, ny, nx)."""
-        if shape is None:
-            raise ValueError("shape (nz, ny, nx) is required")
+        shape = self._out_shape(phantom_id, shape)
         nb = len(sources)
         if nb != len(n_hist):
             raise ValueError("one history count per source")
@@ -315,6 +339,54 @@ class Context:
         per = (nb,) + tuple(shape)
         return rs(pb, per), rs(ps, per), rs(d, tuple(shape)), rs(s, tuple(shape)), stats_dict(st)
 
+    def run_beam_tally(self, phantom_id: int, tables_id: int, source, n_hist: int, seed: int, tuning=None,
+                       out: str = "numpy"):
+        """Raw integer batch tallies (uint64, 2^-27 MeV units, shape (K, nz, ny,
+        nx)) of a plain run, and its statistics; K is the tables' n_batches."""
+        st = gmc_run_stats()
+        keep = []
+        src = _src(source, keep)
+        tun = _tuning(tuning)
+        shape = self.phantom_shape(phantom_id)
+        n = int(np.prod(shape))
+        K = self._batches(tables_id)
+        if out == "torch":
+            import torch
+            t = torch.empty(K * n, dtype=torch.int64, device="cuda")
+            ptr, kind = t.data_ptr(), GMC_DEVICE
+        else:
+            t = np.empty(K * n, np.uint64)
+            ptr, kind = t.ctypes.data, GMC_HOST
+        self._check(self._L.gmc_run_beam_tally(self._h, phantom_id, tables_id, C.byref(src), int(n_hist), int(seed),
+                                               ptr, kind, C.byref(tun) if tun is not None else None, C.byref(st)))
+        return t.reshape((K,) + shape), stats_dict(st)
+
+    def finalize_tally(self, phantom_id: int, tables_id: int, tally, h_begin: int, h_end: int, sigma: bool = True):
+        """Dose and sigma (host arrays) and s of Eq. 12 of batch tallies covering
+        histories [h_begin, h_end): a numpy uint64 array or a torch int64
+        tensor on the GPU, shape (K, nz, ny, nx)."""
+        shape = self.phantom_shape(phantom_id)
+        n = int(np.prod(shape))
+        if hasattr(tally, "data_ptr"):
+            if tally.numel() != self._batches(tables_id) * n or not tally.is_contiguous():
+                raise ValueError("tally must be a contiguous (K, nz, ny, nx) tensor")
+            tp, tk = tally.data_ptr(), GMC_DEVICE
+        else:
+            tally = np.ascontiguousarray(tally, dtype=np.uint64)
+            if tally.size != self._batches(tables_id) * n:
+                raise ValueError("tally must hold (K, nz, ny, nx) values")
+            tp, tk = tally.ctypes.data, GMC_HOST
+        d = np.empty(n, np.float64)
+        s = np.empty(n, np.float64) if sigma else None
+        srel = C.c_double()
+        self._check(self._L.gmc_finalize_tally(self._h, phantom_id, tables_id, tp, tk, int(h_begin), int(h_end),
+                                               d.ctypes.data, s.ctypes.data if s is not None else None, GMC_HOST,
+                                               C.byref(srel)))
+        return d.reshape(shape), (s.reshape(shape) if s is not None else None), srel.value
+
+    def _batches(self, tables_id: int) -> int:
+        return self._nbatch[tables_id]
+
     def autotune(self, phantom_id: int, tables_id: int, sources, n_hist, budget_s: float = 0.0):
         """The autotuner's choice for this job (cached per job class): (tuning dict, report dict)."""
         nb = len(sources)
@@ -347,11 +419,17 @@ class Context:
         t = C.c_uint64()
         self._check(self._L.gmc_submit(self._h, phantom_id, tables_id, C.byref(src), int(n_hist), int(seed),
                                        C.byref(t)))
+        self._tickets[t.value] = phantom_id
         return t.value
 
-    def poll(self, ticket: int, shape, wait: bool = True, sigma: bool = True, out: str = "numpy"):
+    def poll(self, ticket: int, shape=None, wait: bool = True, sigma: bool = True, out: str = "numpy"):
         """(done, dose, sigma, stats); dose/sigma None while not done.  A
-        finished ticket is retired by the call that returns it."""
+        finished ticket is retired by the call that returns it.  shape
+        defaults to the request's phantom's and must hold as many voxels."""
+        if ticket in self._tickets:
+            shape = self._out_shape(self._tickets[ticket], shape)
+        elif shape is None:
+            raise ValueError("unknown ticket %d: give the output shape" % ticket)
         n = int(np.prod(shape))
         if out == "torch":
             import torch
@@ -368,6 +446,7 @@ class Context:
                                      C.byref(st)))
         if not done.value:
             return False, None, None, None
+        self._tickets.pop(ticket, None)
         stats = {"t_queue_s": st.t_queue_s, "t_run_s": st.t_run_s, "t_latency_s": st.t_latency_s}
         stats.update(stats_dict(st.run))
         return True, d.reshape(*shape), (s.reshape(*shape) if s is not None else None), stats

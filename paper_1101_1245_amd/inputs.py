@@ -73,6 +73,7 @@ class Source:
     beam_id: int = 0
     tab_e: Optional[np.ndarray] = None   # TABULATED: tab_n + 1 increasing bin edges (MeV)
     tab_w: Optional[np.ndarray] = None   # TABULATED: tab_n bin weights
+    first_history: int = 0               # number of the first history (a shard of a larger run)
 
 
 @dataclass
@@ -85,6 +86,7 @@ class Physics:
     esmax_gcm2: float = 0.0    # <= 0: no user step bound
     n_batches: int = 32
     test_mode: int = 0         # 0 full, 1 photon first collision, 2 electron CSDA straight-ahead
+    majorant_margin: float = 0.0   # <= 0: the default 1.001
 
 
 # ------------------------------------------------------------------ phantoms

@@ -88,3 +88,67 @@ def test_z_test_gaussian_and_offset():
     assert zt.passed and zt.n == mu.size
     bad = E.z_test(da + 2.5, sa, db, sb, dof=10 ** 6)           # 5 combined sigma
     assert not bad.passed and bad.frac_over_3 > 0.9
+
+
+def test_z_test_batch_sigma_tails_and_mean_offset():
+    # sigma of one estimate from K = 32 batches (31 degrees of freedom), the
+    # other known: |z| > 3 occurs more often than for a normal variate, and
+    # the t-adjusted bounds accept it; a 0.1 sigma offset of every voxel is a
+    # mean z far beyond 3/sqrt(n)
+    rng = np.random.default_rng(12)
+    n, K = 40000, 32
+    batches = rng.standard_normal((K, n))
+    da = batches.mean(axis=0)
+    sa = batches.std(axis=0, ddof=1) / math.sqrt(K)
+    sb = np.full(n, 1.0 / math.sqrt(K))
+    db = sb * rng.standard_normal(n)
+    zt = E.z_test(da, sa, db, sb, ref_for_mask=np.ones(n), dof=K - 1)
+    assert zt.passed, E.describe(zt)
+    assert zt.frac_limit > 0.0027
+    off = E.z_test(da + 0.1 * np.sqrt(sa ** 2 + sb ** 2), sa, db, sb, ref_for_mask=np.ones(n), dof=K - 1)
+    assert not off.passed and abs(off.mean) > off.mean_limit
+    # same streams: a variance far below one is accepted, above 1.25 is not
+    same = E.z_test(da, sa, da + 0.01 * sa, sa, ref_for_mask=np.ones(n), dof=K - 1, same_streams=True)
+    assert same.passed and same.var < 0.01
+    wide = E.z_test(da, sa / 1.3, db, sb / 1.3, ref_for_mask=np.ones(n), dof=K - 1)
+    assert not wide.passed and wide.var > 1.25
+
+
+def test_z_test_mean_bound_with_correlated_voxels():
+    # Every batch of an estimate shifts all voxels together by a common
+    # amount (as one history deposits in many voxels): mean z then scatters
+    # far more than 1/sqrt(n) between independent runs.  The bound from the
+    # batches' own spread accepts such runs and still rejects a real offset.
+    rng = np.random.default_rng(21)
+    n, K, trials = 3000, 32, 40
+    strict_fail = batch_fail = 0
+    for _ in range(trials):
+        runs = []
+        for _ in range(2):
+            b = 10.0 + 0.2 * rng.standard_normal((K, 1)) + rng.standard_normal((K, n))
+            nk = np.full(K, 100.0)
+            d = b.mean(axis=0)
+            s = b.std(axis=0, ddof=1) / math.sqrt(K)
+            runs.append((d, s, (b, nk)))
+        (da, sa, ba), (db, sb, bb) = runs
+        mask = np.ones(n)
+        strict_fail += not E.z_test(da, sa, db, sb, ref_for_mask=mask, dof=K - 1).passed
+        batch_fail += not E.z_test(da, sa, db, sb, ref_for_mask=mask, dof=K - 1, batches=(ba, bb)).passed
+    assert strict_fail > trials // 2 and batch_fail <= 2, (strict_fail, batch_fail)
+    (da, sa, ba), (db, sb, bb) = runs
+    off = E.z_test(da + 0.25, sa, db, sb, ref_for_mask=np.ones(n), dof=K - 1,
+                   batches=((ba[0] + 0.25, ba[1]), bb))
+    assert not off.passed and abs(off.mean) > off.mean_limit
+
+
+def test_batch_doses_match_the_dose():
+    rng = np.random.default_rng(4)
+    K, N = 8, 1003
+    e = rng.random((K, 3, 4, 5))
+    rho = np.full((3, 4, 5), 1.5)
+    dk, nk = E.batch_doses(e, rho, (0.5, 0.5, 0.5), N, h0=5)
+    assert nk.sum() == N and nk.max() - nk.min() <= 1
+    assert nk[5 % K] == np.ceil(N / K)                      # the first history (5) is in batch 5
+    d = (nk[:, None, None, None] * dk).sum(axis=0) / N
+    want = e.sum(axis=0) / N * E.MEV_TO_J / (1.5 * 0.125 * 1e-3)
+    assert np.allclose(d, want, rtol=1e-13)

@@ -161,7 +161,8 @@ def test_combined_matches_oracle(small_job, batched, oracle):
     comb = types.SimpleNamespace(e1=e1, e2=e2, n_hist=int(j.counts.sum()))
     do, so = oracle.dose(comb, j.phantom)
     zt = E.z_test(d, s, do, so, dof=j.physics.n_batches - 1, same_streams=True)
-    assert zt.passed, (zt.n, zt.frac_over_3, zt.max_abs, zt.mean, zt.var)
+    print("\n" + E.describe(zt))
+    assert zt.passed, E.describe(zt)
     assert st["e_in_mev"] == pytest.approx(stats["e_in"], rel=1e-6)
     for k in ("n_e_steps", "n_photon_events", "n_secondaries"):
         a, b = st[k], stats[k]
@@ -227,7 +228,8 @@ def test_full_beamlet_job(ctx, oracle):
         pe = E.precision_error(pb[b].cpu().numpy(), do)
         print("\nsmallest beamlet (%d histories), same streams: summed dose %+.2e, voxel |diff| mean %.2e max %.2e "
               "of D_max over %d voxels" % (int(j.counts[b]), pe.sum_rel, pe.mean_abs, pe.max_abs, pe.n))
-        assert zt.passed, (zt.n, zt.frac_over_3, zt.max_abs, zt.mean, zt.var)
+        print("\n" + E.describe(zt))
+        assert zt.passed, E.describe(zt)
         del pb, d, s
         torch.cuda.empty_cache()
     finally:

@@ -9,11 +9,16 @@ Bars:
   run one after another;
 * a request whose footprint can never fit is refused (GMC_EBUSY), ids held by
   queued requests cannot be released, and bad requests are rejected at
-  submission.
+  submission;
+* served requests of the request stream's kind -- an ellipsoid phantom with
+  four materials, triangular 2-10-18 MeV photon and electron beams --
+  submitted together with others agree with the FP64 oracle: per-voxel
+  z-tests on the same and on independent streams, event counts.
 """
 import numpy as np
 import pytest
 
+from paper_1101_1245_amd import evaluate as E
 from paper_1101_1245_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -115,3 +120,51 @@ def test_bad_requests_and_device_output(ctx, G, stream):
         ctx.server_stop()
     da, sa, _ = ctx.run_beam(pids[r.phantom], tid, r.source, r.n_hist, r.seed, shape=pool[r.phantom].shape)
     assert np.array_equal(d.cpu().numpy(), da) and np.array_equal(s.cpu().numpy(), sa)
+
+
+def test_served_triangular_requests_match_oracle(ctx, oracle, batched_run):
+    from conftest import oracle_batches
+    ph = I.ellipsoids(40, 0.4, seed=23)
+    phys = I.serving_physics()
+    reqs = [(I.centred(ph, I.Source(I.PHOTON, I.TRIANGULAR, 10.0, e_lo=2.0, e_mode=10.0, e_hi=18.0, wx=6.0, wy=6.0,
+                                    beam_id=3)), 1_000_000, 7),
+            (I.centred(ph, I.Source(I.ELECTRON, I.TRIANGULAR, 10.0, e_lo=2.0, e_mode=10.0, e_hi=18.0, wx=4.0,
+                                    wy=4.0, beam_id=4)), 200_000, 8),
+            (I.centred(ph, I.Source(I.PHOTON, I.MONO, 12.0, wx=3.0, wy=3.0, beam_id=5)), 300_000, 9)]
+    tid = ctx.load_tables(I.DEFAULT_MATERIALS, phys)
+    pid = ctx.load_phantom(ph)
+    try:
+        ctx.server_start(max_slots=3)
+        try:
+            tickets = [ctx.submit(pid, tid, src, n, seed) for src, n, seed in reqs]
+            out = [ctx.poll(t, ph.shape, wait=True) for t in tickets]
+        finally:
+            ctx.server_stop()
+        masks = [ctx.run_beam(pid, tid, src, n, 101, shape=ph.shape)[0] for src, n, _ in reqs[:2]]
+        # the same requests through the raw-tally entry points: the batches for the mean bound
+        batches = []
+        for (src, n, seed), (_, d, s, _) in zip(reqs[:2], out[:2]):
+            db, sb, _, bg = batched_run(ctx, pid, tid, src, n, seed, ph)
+            assert np.array_equal(db, d) and np.array_equal(sb, s)
+            batches.append(bg)
+    finally:
+        ctx.release(pid)
+        ctx.release(tid)
+    for (src, n, seed), (done, d, s, st), ref, bg in zip(reqs[:2], out[:2], masks, batches):
+        assert done and st["ledger_residual_lsb"] == 0 and st["n_majorant_violations"] == 0
+        res = oracle.run_parallel(I.DEFAULT_MATERIALS, ph, src, phys, seed, n, batches=False)
+        assert st["e_in_mev"] == pytest.approx(res.stats["e_in"], rel=1e-6)
+        do, so = oracle.dose(res, ph)
+        zt = E.z_test(d, s, do, so, ref_for_mask=ref, dof=phys.n_batches - 1, same_streams=True)
+        p = E.precision_error(d, do)
+        print("\nserved triangular %s, same %d histories: z-test %s; summed dose %+.2e, voxel |diff| max %.2e of "
+              "D_max" % ("electrons" if src.particle else "photons", n, E.describe(zt), p.sum_rel, p.max_abs))
+        assert zt.passed, E.describe(zt)
+        for k in ("n_e_steps", "n_photon_events", "n_secondaries"):
+            assert abs(st[k] - res.stats[k]) < 2e-3 * res.stats[k] + 10, (k, st[k], res.stats[k])
+        r2 = oracle.run_parallel(I.DEFAULT_MATERIALS, ph, src, phys, seed + 100, n)
+        do2, so2 = oracle.dose(r2, ph)
+        zi = E.z_test(d, s, do2, so2, ref_for_mask=ref, dof=phys.n_batches - 1,
+                      batches=(bg, oracle_batches(r2, ph, n)))
+        print("served triangular, independent: z-test %s" % E.describe(zi))
+        assert zi.passed, E.describe(zi)

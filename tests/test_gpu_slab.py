@@ -1,35 +1,26 @@
 """GPU: the heterogeneous slab phantom against the FP64 oracle.
 
 128^3 voxels of 0.25 cm: water 0-3 cm, bone (1.85 g/cm^3) 3-5 cm, lung
-(0.26 g/cm^3) 5-12 cm, water beyond; 6 MeV photons, 10 x 10 cm field; the
-oracle runs 4e6 histories.
+(0.26 g/cm^3) 5-12 cm, water beyond; 6 MeV photons, 10 x 10 cm field, the
+full 4e7 histories on both sides (the oracle over the host cores, in worker
+processes over disjoint history ranges).
 
 Voxel masks and dose bands (each slab x dose above 50% and 10-50% of the
 maximum) come from a separate GPU run with its own seed: choosing voxels by
 the very estimates being compared favours voxels where one of them ran high.
 
-* FP32 vs FP64 (GPU and oracle on the same 4e6 histories): the z-test passes
-  and in every band the GPU/oracle ratio of the band's summed dose is within
-  0.2% of 1 -- the stated FP32-vs-FP64 error (measured: 0.03% or less).
-* Gamma 2%/2 mm of the same-stream GPU dose against the oracle's, voxels
-  above 10% of the maximum: at least 97% pass (measured 97.3%).  The 99% bar
-  is not reached at this size: histories whose FP32 and FP64 trajectories
-  part after a flipped decision become independent samples, and at 4e6
-  histories on 0.25 cm voxels (lung at 0.26 g/cm^3) a voxel's dose from such
-  histories fluctuates by several percent of the maximum.  The same bar holds
-  at 99% for the water phantoms, whose voxels are larger and denser.
-* Statistical agreement (GPU on 4e6 other histories): the z-test's mean,
-  maximum and variance bounds hold; its fraction beyond 3 sigma is bounded
-  at 0.5%, because in a broad beam every history deposits in many voxels,
-  which widens the spread of that fraction beyond the independent-voxel
-  bound.  (Estimates of unequal history counts are not compared voxel by
-  voxel: with few events per voxel the smaller run's sigma is correlated
-  with its dose, which biases the mean z away from 0.)
-* Full size (GPU 4e7 histories): the integer ledger closes, no majorant is
-  violated, events per history match the oracle's within 0.5%, and every
-  band's summed dose is within 3% of the oracle's (whose 4e6-history band
-  sums fluctuate by 1-2%).
-Per-band figures are printed with -s.
+* FP32 vs FP64 (GPU and oracle on the same 4e7 histories): the z-test passes,
+  event counts agree within 1e-3, and in every band the GPU/oracle ratio of
+  the band's summed dose is within 0.1% of 1 -- the stated FP32-vs-FP64
+  error, printed per band with -s.
+* Gamma 2%/2 mm (Eqs. 14-15) of the same-stream GPU dose against the
+  oracle's, voxels above 10% of the maximum: at least 99% pass.  Histories
+  whose FP32 and FP64 trajectories part after a flipped decision become
+  independent samples; at 4e7 histories their voxel-to-voxel noise is well
+  inside the 2% criterion.
+* Statistical agreement (GPU on 4e7 other histories): the z-test with the
+  t-adjusted bounds of the evaluation module.
+* The integer ledger closes and no majorant is violated.
 """
 import numpy as np
 import pytest
@@ -59,67 +50,62 @@ def band_ratios(d, do, ref, voxel):
 
 
 def show(title, rows, zt):
-    print("\n%s: z-test n %d, frac |z|>3 %.5f, max |z| %.2f, mean z %+.4f, var z %.3f" %
-          (title, zt.n, zt.frac_over_3, zt.max_abs, zt.mean, zt.var))
+    print("\n%s: z-test %s" % (title, E.describe(zt)))
     for name, bname, n, ratio in rows:
         print("  %-15s %-7s %7d voxels  sum ratio %.5f" % (name, bname, n, ratio))
+
+
+N_FULL = 40_000_000
 
 
 @pytest.fixture(scope="module")
 def runs(oracle):
     from paper_1101_1245_amd import gpumcd as G
     w = I.slab_6mev()
+    assert w.n_hist == N_FULL
     with G.Context(0) as ctx:
         ref, _, _ = G.run_workload(ctx, w, seed=101)                       # masks and bands only
-        same = G.run_workload(ctx, w, n_hist=4_000_000, seed=2)
-        other = G.run_workload(ctx, w, n_hist=4_000_000, seed=5)
         full = G.run_workload(ctx, w, seed=1)
-    r = oracle.run_parallel(w.materials, w.phantom, w.source, w.physics, 2, 4_000_000, batches=False)
+        other = G.run_workload(ctx, w, seed=5)
+    print("\nslab: GPU runs done; oracle on %d histories" % N_FULL, flush=True)
+    r = oracle.run_parallel(w.materials, w.phantom, w.source, w.physics, 1, N_FULL, batches=False)
     do, so = oracle.dose(r, w.phantom)
-    return w, ref, same, other, full, (do, so, r)
+    return w, ref, full, other, (do, so, r)
 
 
+@pytest.mark.timeout(900)
 def test_slab_fp32_vs_fp64_same_streams(runs):
-    w, ref, (d, s, st), _, _, (do, so, r) = runs
+    w, ref, (d, s, st), _, (do, so, r) = runs
     assert st["ledger_residual_lsb"] == 0 and st["n_majorant_violations"] == 0
+    assert st["n_hist"] == N_FULL
     for k in ("n_photon_events", "n_e_steps", "n_hard", "n_secondaries"):
         assert abs(st[k] - r.stats[k]) < 1e-3 * r.stats[k], k      # the same trajectories, up to FP32 flips
     zt = E.z_test(d, s, do, so, ref_for_mask=ref, dof=w.physics.n_batches - 1, same_streams=True)
     rows = band_ratios(d, do, ref, w.phantom.voxel[2])
-    show("same 4e6 histories (FP32 - FP64)", rows, zt)
-    assert zt.passed, (zt.n, zt.frac_over_3, zt.max_abs, zt.mean, zt.var)
+    show("same 4e7 histories (FP32 - FP64)", rows, zt)
+    assert zt.passed, E.describe(zt)
     for name, bname, n, ratio in rows:
-        assert n >= 50 and abs(ratio - 1.0) < 2e-3, (name, bname, n, ratio)
+        assert n >= 50 and abs(ratio - 1.0) < 1e-3, (name, bname, n, ratio)
 
 
+@pytest.mark.timeout(900)
 def test_slab_gamma_same_streams(runs):
     # gamma 2%/2 mm (Eqs. 14-15) of the GPU dose against the oracle's on the
-    # same 4e6 histories, over voxels above 10% of the oracle's maximum
-    w, ref, (d, s, st), _, _, (do, so, r) = runs
+    # same 4e7 histories, over voxels above 10% of the oracle's maximum
+    w, ref, (d, s, st), _, (do, so, r) = runs
     g = E.gamma_index(do, d, w.phantom.voxel)
     p = E.precision_error(d, do)
-    print("\nslab, same 4e6 histories: summed dose %+.2e, voxel |diff| mean %.2e max %.2e of D_max over %d voxels; "
+    print("\nslab, same 4e7 histories: summed dose %+.2e, voxel |diff| mean %.2e max %.2e of D_max over %d voxels; "
           "gamma 2%%/2 mm pass %.5f, max %.3f" % (p.sum_rel, p.mean_abs, p.max_abs, p.n, g.pass_rate, g.gamma_max))
-    assert g.pass_rate >= 0.97, (g.pass_rate, g.gamma_max, g.n_voxels)
+    assert g.pass_rate >= 0.99, (g.pass_rate, g.gamma_max, g.n_voxels)
 
 
+@pytest.mark.timeout(900)
 def test_slab_statistical_agreement(runs):
-    w, ref, _, (d, s, st), _, (do, so, r) = runs
-    zt = E.z_test(d, s, do, so, ref_for_mask=ref, dof=w.physics.n_batches - 1)
-    show("independent 4e6 histories", band_ratios(d, do, ref, w.phantom.voxel[2]), zt)
-    assert zt.frac_over_3 <= 0.005 and zt.max_abs <= zt.max_limit, (zt.frac_over_3, zt.max_abs)
-    assert abs(zt.mean) <= zt.mean_limit and zt.var_range[0] <= zt.var <= zt.var_range[1], (zt.mean, zt.var)
-
-
-def test_slab_full_size(runs):
-    w, ref, _, _, (d, s, st), (do, so, r) = runs
+    w, ref, _, (d, s, st), (do, so, r) = runs
     assert st["ledger_residual_lsb"] == 0 and st["n_majorant_violations"] == 0
-    assert st["n_hist"] == 40_000_000
-    for k in ("n_photon_events", "n_e_steps", "n_secondaries"):
-        per_gpu, per_orc = st[k] / 4e7, r.stats[k] / 4e6
-        assert abs(per_gpu / per_orc - 1.0) < 5e-3, (k, per_gpu, per_orc)
     zt = E.z_test(d, s, do, so, ref_for_mask=ref, dof=w.physics.n_batches - 1)
-    rows = band_ratios(d, do, ref, w.phantom.voxel[2])
-    show("4e7 GPU histories vs 4e6 oracle histories", rows, zt)
-    for name, bname, n, ratio in rows:
-        assert abs(ratio - 1.0) < 0.03, (name, bname, n, ratio)
+    show("independent 4e7 histories", band_ratios(d, do, ref, w.phantom.voxel[2]), zt)
+    assert zt.passed, E.describe(zt)
+    for k in ("n_photon_events", "n_e_steps", "n_secondaries"):
+        assert abs(st[k] / r.stats[k] - 1.0) < 2e-3, (k, st[k], r.stats[k])

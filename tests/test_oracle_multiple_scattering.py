@@ -113,7 +113,7 @@ def test_voxel_skin_does_not_change_the_dose(oracle):
     da, sa = oracle.dose(a, ph)
     db, sb = oracle.dose(b, ph)
     zt = E.z_test(da, sa, db, sb, dof=n - 1, same_streams=True)
-    assert zt.passed, (zt.n, zt.frac_over_3, zt.max_abs, zt.mean, zt.var)
+    assert zt.passed, E.describe(zt)
     for z0, z1 in ((0, 12), (12, 20), (20, 48), (48, 64)):
         diff = a.eb[:, z0:z1].sum(axis=(1, 2, 3)) - b.eb[:, z0:z1].sum(axis=(1, 2, 3))
         t = diff.mean() / (diff.std(ddof=1) / np.sqrt(diff.size))
