@@ -177,6 +177,13 @@ def roofline(acc, workload="water"):
         out["traffic_unit"] = "HBM bytes per launch (%.2f per unit of work x %.3g units)" % (per_unit, units)
         out["hbm_GBps"] = traffic / avg / 1e9
         out["hbm_frac"] = traffic / avg / 8.0e12
+    # the other pass kernel against the same peak
+    for other, i, work, per in (("k_photon_pass", 0, acc.events, OPS_PER_PH_EVENT),
+                                ("k_electron_pass", 1, acc.steps, OPS_PER_E_STEP)):
+        if other != name and acc.n[i] > 0 and acc.t[i] > 0:
+            a = work * per / acc.t[i] / 1e12
+            out[other] = {"achieved": a, "frac": a / peak, "avg_launch_ms": acc.t[i] / acc.n[i] * 1e3,
+                          "launches": acc.n[i], "ops_per_unit": per}
     return out
 
 
@@ -213,7 +220,7 @@ def bench_water(args, G, E, I):
 
     def batched(seed):
         return ctx.run_beams(pid, tid, srcs, counts, seed, shape=shape, per_beam=True, per_beam_sigma=True,
-                             out="torch")
+                             tuning=args.tuning, out="torch")
 
     for i in range(args.warmup):
         plain(100 + i)
@@ -283,6 +290,7 @@ def bench_water(args, G, E, I):
             "n_electrons": n1["electron"], "n_photons": n1["photon"],
             "s_pilot": s_pilot, "s_timed": s_final,
             "tallies": "int64 fixed point, 32 batches",
+            "batched_tuning": args.tuning if args.tuning is not None else "autotuned",
             "outputs": "device memory (no PCIe in the timed region)",
         },
         "plain": {"value": acc_p.hist / el_p, "ms_per_step": el_p / args.steps * 1e3},
@@ -317,7 +325,7 @@ def bench_beamlets(args, G, E, I):
     def batched(seed):
         acc = Acc()
         pb, _, d, s, st = ctx.run_beams(pid, tid, j.sources, j.counts, seed, shape=shape, per_beam=True,
-                                        out="torch")
+                                        tuning=args.tuning, out="torch")
         acc.add(st)
         del pb, d, s
         return acc
@@ -361,6 +369,7 @@ def bench_beamlets(args, G, E, I):
                         "each (%d in total), 200x200x160 ellipsoid phantom at 0.25 cm, ECUT 0.7 / PCUT 0.01 MeV; "
                         "value = one gmc_run_beams job with per-beamlet doses" % total,
             "beamlets": len(j.sources), "histories": total,
+            "batched_tuning": args.tuning if args.tuning is not None else "autotuned",
             "outputs": "device memory (no PCIe in the timed region)",
         },
         "plain": {"value": acc_p.hist / el_p, "ms_per_step": el_p / args.steps * 1e3},
@@ -728,6 +737,9 @@ def main():
                     help="first run one device-to-device copy of MIB MiB: a kernel of known traffic that "
                          "hardware byte counters can be scaled by")
     ap.add_argument("--target", type=float, default=0.01, help="statistical uncertainty s of Eq. 12")
+    ap.add_argument("--tuning", type=json.loads, default=None, metavar="JSON",
+                    help="tuning of the batched legs (water, beamlets) as a JSON object of gmc_tuning fields, "
+                         "e.g. '{\"persistent\": 1}'; default: the autotuner's choice")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the per-GPU transport is what is measured; how it would shard "
