@@ -260,6 +260,23 @@ int gmc_finalize_tally(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, 
                        int tally_ptr_kind, uint64_t h_begin, uint64_t h_end, double* dose, double* sigma,
                        int out_ptr_kind, double* s_rel);
 
+/* gmc_finalize_tally for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments and results as gmc_finalize_tally with device
+ * pointers: tally (n_batches * nx*ny*nz uint64, layout as gmc_run_beam_tally
+ * writes it), dose and sigma (nx*ny*nz doubles each; sigma may be NULL) are
+ * device memory, s_rel (may be NULL; NaN without sigma) host memory.  Equal
+ * tallies and ranges give bit-identical dose, sigma and s to
+ * gmc_finalize_tally.  The call allocates nothing: its work memory (the
+ * histories per batch and the partial sums of s, at most 1024 batches,
+ * 14.3 KB) is one array of the library's device code per GPU, held until
+ * the process ends; n_batches above 1024 is refused with GMC_EINVAL.  Every
+ * call on a GPU shares that GPU's array, so calls that overlap on one GPU
+ * (other threads, other contexts) race and must not be made.  Runs on the
+ * context stream and returns when the results are complete. */
+int gmc_finalize_tally_noalloc(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const uint64_t* tally,
+                               uint64_t h_begin, uint64_t h_end, double* dose, double* sigma, double* s_rel);
+
 /* Grid size of a loaded phantom: the number of doubles every dose and sigma
  * output of a run on it holds is nx*ny*nz. */
 int gmc_phantom_dims(gmc_context* ctx, int32_t phantom_id, int* nx, int* ny, int* nz);

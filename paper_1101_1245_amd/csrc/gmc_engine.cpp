@@ -959,6 +959,8 @@ void add_batch_sizes(std::vector<double>& nk, uint64_t h0, uint64_t n, uint32_t 
   for (uint32_t k = 0; k < K; ++k) nk[k] += (double)((h0 + n + K - 1 - k) / K - (h0 + K - 1 - k) / K);
 }
 
+double dose_per_lsb(const PhantomObj& P) { return kLsbMeV * 1.602176634e-13 / (P.dx * P.dy * P.dz * 1e-3); }
+
 int finalize(Workspace* w, const PhantomObj& P, const unsigned long long* tally, uint32_t nsum, size_t stride,
              uint32_t K, const std::vector<double>& nk, uint64_t n, double* d_dose, double* d_sigma, bool ledger,
              bool sync) {
@@ -977,7 +979,7 @@ int finalize(Workspace* w, const PhantomObj& P, const unsigned long long* tally,
   fa.nvox = (uint32_t)P.nvox();
   fa.K = K;
   fa.n_total = (double)n;
-  fa.conv = kLsbMeV * 1.602176634e-13 / (P.dx * P.dy * P.dz * 1e-3);
+  fa.conv = dose_per_lsb(P);
   fa.dose = d_dose;
   fa.sigma = d_sigma;
   fa.ctr = ledger ? w->d_ctr : nullptr;

@@ -244,6 +244,8 @@ int after_replay(Engine& E, int rounds_per_replay, bool* done);
 
 // Histories per batch for interleaved batches: n_k += #{h in [h0, h0 + n) : h mod K = k}.
 void add_batch_sizes(std::vector<double>& nk, uint64_t h0, uint64_t n, uint32_t K);
+// Gy per tally unit (2^-27 MeV) per unit density of a voxel of P.
+double dose_per_lsb(const PhantomObj& P);
 // Dose and sigma of `nsum` tallies ([K][nvox] each, `stride` apart, added).
 // With sync false the batch sizes go through the pinned w->h_nk and the
 // call does not wait (one finalize in flight per workspace).

@@ -311,4 +311,18 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v
 // kernel: 0 photon pass, 1 electron pass, 2 round kernel
 int max_resident_blocks(int kernel, int block, size_t lds);
 
+// Work memory of the allocation-free finalize: a file-scope device array of
+// the kernels' source, one copy per device, never freed.  It holds the
+// histories per batch (kMaxBatches doubles) and then the s reduction's work
+// (3 kRelBlocks + 1 doubles).
+constexpr size_t kScratchDoubles = (size_t)kMaxBatches + 3 * (size_t)kRelBlocks + 1;
+constexpr int kScratchDevices = 64;
+// Resolve the array's address on `device` (which must be current): done once
+// per device, at context creation.
+hipError_t scratch_resolve(int device);
+// Its address on `device` (nullptr before scratch_resolve succeeded there).
+double* scratch_address(int device);
+// nk[k] = histories of [h0, h0 + n) in batch k (h mod K), k < K.
+hipError_t launch_batch_sizes(double* nk, uint64_t h0, uint64_t n, uint32_t K, hipStream_t s);
+
 }  // namespace gmc

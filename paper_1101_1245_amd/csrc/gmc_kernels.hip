@@ -16,6 +16,8 @@
 // Deposits are uint64 fixed-point atomics, so the dose is an exact integer
 // sum independent of thread order.  Cross-section and stopping-power tables
 // are staged in LDS by every workgroup.
+#include <mutex>
+
 #include "gmc_device.hpp"
 
 namespace gmc {
@@ -1563,6 +1565,47 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v
   size_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ allocation-free finalize
+// The work memory of gmc_finalize_tally_noalloc lives here instead of in
+// memory the library allocates.  Host code never uses the array's name as an
+// address: it takes the device address hipGetSymbolAddress returns for the
+// current device, once per device, and passes that to the kernels.
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+static std::mutex g_scratch_mu;
+static double* g_scratch_addr[kScratchDevices] = {};
+
+hipError_t scratch_resolve(int device) {
+  if (device < 0 || device >= kScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_addr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch_addr[device] = static_cast<double*>(p);
+  return hipSuccess;
+}
+
+double* scratch_address(int device) {
+  if (device < 0 || device >= kScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_addr[device];
+}
+
+// #{h in [h0, h0 + n) : h mod K = k}, from #{h < m : h mod K = k} = (m + K - 1 - k) / K.
+__global__ void k_batch_sizes(double* nk, unsigned long long h0, unsigned long long n, uint32_t K) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < K) nk[k] = (double)((h0 + n + K - 1 - k) / K - (h0 + K - 1 - k) / K);
+}
+
+hipError_t launch_batch_sizes(double* nk, uint64_t h0, uint64_t n, uint32_t K, hipStream_t s) {
+  if (K == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_sizes, dim3((K + 255u) / 256u), dim3(256), 0, s, nk, (unsigned long long)h0,
+                     (unsigned long long)n, K);
   return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 
 #include "gmc_host.hpp"
 
@@ -18,6 +19,8 @@ int gmc_create(int device, void* hip_stream, gmc_context** out) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return GMC_EDEVICE;
   if (hipSetDevice(device) != hipSuccess) return GMC_EDEVICE;
+  // The allocation-free entry points' work memory: its address on this device.
+  if (scratch_resolve(device) != hipSuccess) return GMC_EDEVICE;
   auto* c = new gmc_context();
   c->device = device;
   if (ws_init(&c->ws, device, static_cast<hipStream_t>(hip_stream)) != GMC_OK ||
@@ -243,6 +246,60 @@ int gmc_finalize_tally(gmc_context* c, int32_t phantom_id, int32_t tables_id, co
     if (e == hipSuccess && sigma) e = hipMemcpy(sigma, w->d_sigma, nvox * sizeof(double), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return cfail(c, GMC_EDEVICE, std::string("result copy: ") + hipGetErrorString(e));
   }
+  if (s_rel) *s_rel = w->h_srel[0];
+  return GMC_OK;
+}
+
+int gmc_finalize_tally_noalloc(gmc_context* c, int32_t phantom_id, int32_t tables_id, const uint64_t* tally,
+                               uint64_t h_begin, uint64_t h_end, double* dose, double* sigma, double* s_rel) {
+  if (!c) return GMC_EINVAL;
+  const PhantomObj* pp = nullptr;
+  const TablesObj* tp = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto pi = c->phantoms.find(phantom_id);
+    auto ti = c->tables.find(tables_id);
+    if (pi != c->phantoms.end()) pp = pi->second.get();
+    if (ti != c->tables.end()) tp = ti->second.get();
+  }
+  if (!pp || !tp) return cfail(c, GMC_ENOTFOUND, "unknown phantom or tables id");
+  if (!tally || !dose) return cfail(c, GMC_EINVAL, "tally or dose is NULL");
+  const uint32_t K = (uint32_t)tp->phys.n_batches;
+  if (K > (uint32_t)kMaxBatches)
+    return cfail(c, GMC_EINVAL, "n_batches above the " + std::to_string(kMaxBatches) +
+                                    " batches the allocation-free work area holds");
+  if (h_end <= h_begin || h_end > (1ull << 32) || h_end - h_begin < K)
+    return cfail(c, GMC_EINVAL, "the history range must hold at least n_batches histories below 2^32");
+  if (pp->nvox() > 0xffffffffull) return cfail(c, GMC_EINVAL, "phantom too large");
+  (void)hipSetDevice(c->device);
+  double* work = scratch_address(c->device);
+  if (!work) return cfail(c, GMC_EDEVICE, "the allocation-free work area has no address on this device");
+  Workspace* w = &c->ws;
+  double* nk = work;                    // [K] histories per batch
+  double* rel = work + kMaxBatches;     // [3 kRelBlocks + 1] s reduction, s last
+  hipError_t e = launch_batch_sizes(nk, h_begin, h_end - h_begin, K, w->stream);
+  FinalizeArgs fa;
+  fa.tally = reinterpret_cast<const unsigned long long*>(tally);
+  fa.nsum = 1u;
+  fa.sum_stride = 0u;
+  fa.vox = pp->d_vox;
+  fa.nk = nk;
+  fa.nvox = (uint32_t)pp->nvox();
+  fa.K = K;
+  fa.n_total = (double)(h_end - h_begin);
+  fa.conv = dose_per_lsb(*pp);
+  fa.dose = dose;
+  fa.sigma = sigma;
+  fa.ctr = nullptr;
+  if (e == hipSuccess) e = launch_finalize(fa, w->stream);
+  w->h_srel[0] = std::numeric_limits<double>::quiet_NaN();
+  if (e == hipSuccess && sigma && s_rel) {
+    e = launch_rel_uncertainty(dose, sigma, (uint32_t)pp->nvox(), rel, w->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(w->h_srel, rel + 3 * kRelBlocks, sizeof(double), hipMemcpyDeviceToHost, w->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(w->stream);
+  if (e != hipSuccess) return cfail(c, GMC_EDEVICE, std::string("allocation-free finalize: ") + hipGetErrorString(e));
   if (s_rel) *s_rel = w->h_srel[0];
   return GMC_OK;
 }

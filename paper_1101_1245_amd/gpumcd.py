@@ -152,6 +152,8 @@ def lib():
                                      C.c_int, C.POINTER(gmc_tuning), C.POINTER(gmc_run_stats)]
     L.gmc_finalize_tally.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_int, C.c_uint64, C.c_uint64, vp, vp, C.c_int,
                                      C.POINTER(C.c_double)]
+    L.gmc_finalize_tally_noalloc.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_uint64, C.c_uint64, vp, vp,
+                                             C.POINTER(C.c_double)]
     L.gmc_phantom_dims.argtypes = [vp, C.c_int32, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
     _lib = L
     return L
@@ -383,6 +385,26 @@ class Context:
                                                d.ctypes.data, s.ctypes.data if s is not None else None, GMC_HOST,
                                                C.byref(srel)))
         return d.reshape(shape), (s.reshape(shape) if s is not None else None), srel.value
+
+    def finalize_tally_noalloc(self, phantom_id: int, tables_id: int, tally, h_begin: int, h_end: int, dose,
+                               sigma=None, want_s: bool = True):
+        """gmc_finalize_tally_noalloc: tally, dose and sigma are contiguous torch
+        tensors on the GPU ((K, nz, ny, nx) int64, (nz, ny, nx) float64);
+        writes dose and sigma in place and returns s of Eq. 12 (NaN without
+        sigma or when not wanted)."""
+        shape = self.phantom_shape(phantom_id)
+        n = int(np.prod(shape))
+        if tally.numel() != self._batches(tables_id) * n or not tally.is_contiguous():
+            raise ValueError("tally must be a contiguous (K, nz, ny, nx) tensor")
+        for t in (dose, sigma):
+            if t is not None and (t.numel() != n or not t.is_contiguous()):
+                raise ValueError("dose and sigma must be contiguous tensors of nx*ny*nz values")
+        srel = C.c_double(float("nan"))
+        self._check(self._L.gmc_finalize_tally_noalloc(self._h, phantom_id, tables_id, tally.data_ptr(),
+                                                       int(h_begin), int(h_end), dose.data_ptr(),
+                                                       sigma.data_ptr() if sigma is not None else None,
+                                                       C.byref(srel) if want_s else None))
+        return srel.value
 
     def _batches(self, tables_id: int) -> int:
         return self._nbatch[tables_id]
