@@ -628,10 +628,10 @@ def bench_serve(args, G, I):
     pids = [ctx.load_phantom(p) for p in pool]
     acc = Acc()
 
-    def drain(tickets, sub):
+    def drain(tickets, sub, out_kind="torch"):
         out = []
         for t, r in zip(tickets, sub):
-            _, _, _, st = ctx.poll(t, pool[r.phantom].shape, wait=True, sigma=True)
+            _, _, _, st = ctx.poll(t, pool[r.phantom].shape, wait=True, sigma=True, out=out_kind)
             acc.add(st)
             out.append(st)
         return out
@@ -676,24 +676,31 @@ def bench_serve(args, G, I):
 
     # the same requests as a closed loop (all submitted at once) and through
     # the plain form one after another: throughput of the two forms on
-    # identical work
-    ctx.server_start(max_slots=args.serve_slots)
-    try:
+    # identical work, with the outputs in device memory and in host memory
+    def closed_loop(out_kind):
+        ctx.server_start(max_slots=args.serve_slots)
+        try:
+            sync()
+            t0 = time.perf_counter()
+            tickets = [ctx.submit(pids[r.phantom], tid, r.source, r.n_hist, 20_000 + r.seed) for r in reqs]
+            drain(tickets, reqs, out_kind)
+            sync()
+            return time.perf_counter() - t0
+        finally:
+            ctx.server_stop()
+
+    def plain_sequential(out_kind):
         sync()
         t0 = time.perf_counter()
-        tickets = [ctx.submit(pids[r.phantom], tid, r.source, r.n_hist, 20_000 + r.seed) for r in reqs]
-        drain(tickets, reqs)
-        el_closed = time.perf_counter() - t0
-    finally:
-        ctx.server_stop()
-    acc_plain = Acc()
-    sync()
-    t0 = time.perf_counter()
-    for r in reqs:
-        _, _, st = ctx.run_beam(pids[r.phantom], tid, r.source, r.n_hist, 20_000 + r.seed, sigma=True, out="torch")
-        acc_plain.add(st)
-    sync()
-    el_plain = time.perf_counter() - t0
+        for r in reqs:
+            ctx.run_beam(pids[r.phantom], tid, r.source, r.n_hist, 20_000 + r.seed, sigma=True, out=out_kind)
+        sync()
+        return time.perf_counter() - t0
+
+    el_closed = closed_loop("torch")
+    el_plain = plain_sequential("torch")
+    el_closed_h = closed_loop("numpy")
+    el_plain_h = plain_sequential("numpy")
     for p in pids:
         ctx.release(p)
     ctx.close()
@@ -704,17 +711,22 @@ def bench_serve(args, G, I):
         "mean_latency_s": float(lat.mean()), "p99_queue_s": float(np.percentile(queue, 99)),
         "histories_per_s": hist / el, "histories": hist, "elapsed_s": el,
         "closed_loop": {"histories_per_s": hist / el_closed, "elapsed_s": el_closed,
-                        "note": "all requests submitted at once to the server"},
+                        "note": "all requests submitted at once to the server, results polled into device memory"},
         "plain_sequential": {"histories_per_s": hist / el_plain, "elapsed_s": el_plain,
                              "note": "the same requests through gmc_run_beam one after another, outputs on the "
                                      "device"},
         "closed_loop_over_plain": el_plain / el_closed,
+        "host_outputs": {"closed_loop_histories_per_s": hist / el_closed_h,
+                         "plain_sequential_histories_per_s": hist / el_plain_h,
+                         "closed_loop_over_plain": el_plain_h / el_closed_h,
+                         "note": "both legs again with dose and sigma delivered to host memory (numpy)"},
         "workload": "Poisson stream of %d requests (seed 13) at 0.7 x closed-loop capacity: cubic ellipsoid "
                     "phantoms 32^3-256^3 at 0.25-0.5 cm (pool of %d), photons:electrons 3:1, 1-20 MeV mono or "
                     "2-10-18 MeV triangular, 1-10 cm fields, 1e5-1e8 histories" % (len(reqs), len(pool)),
     }
-    print("served closed loop %.3e histories/s, plain one after another %.3e histories/s (x%.2f)" %
-          (hist / el_closed, hist / el_plain, el_plain / el_closed), file=sys.stderr, flush=True)
+    print("served closed loop %.3e histories/s, plain one after another %.3e histories/s (x%.2f); host outputs "
+          "%.3e vs %.3e (x%.2f)" % (hist / el_closed, hist / el_plain, el_plain / el_closed, hist / el_closed_h,
+                                    hist / el_plain_h, el_plain_h / el_closed_h), file=sys.stderr, flush=True)
     print("served: p50 %.3f s p99 %.3f s, %.3e histories/s at %.2f req/s" %
           (out["p50_latency_s"], out["p99_latency_s"], out["histories_per_s"], rate), file=sys.stderr, flush=True)
     return out, acc_stream

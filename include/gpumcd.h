@@ -356,8 +356,12 @@ int gmc_autotune(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const 
  * batched form's engine on one beam with the autotuner's cached choice for
  * its class (defaults when none), so its dose and sigma are bit-identical
  * to gmc_run_beam's for the same phantom, tables, source, histories and
- * seed, whatever else runs beside it.  Results stay in host memory until
- * polled. */
+ * seed, whatever else runs beside it.  A finished request's dose and sigma
+ * stay in device memory (a pool of result buffers the server reuses) until
+ * gmc_poll copies them out -- device to device, or device to host -- in one
+ * copy; results waiting to be polled count against hbm_budget_bytes, and
+ * when a request could not start otherwise, the oldest of them moves to host
+ * memory instead. */
 typedef struct {
   size_t hbm_budget_bytes;    /* device memory the slots may hold; 0: 3/4 of the free memory */
   int max_slots;              /* requests on the device at once, 1..16 (0: 4) */
@@ -388,7 +392,8 @@ int gmc_submit(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const gm
 int gmc_poll(gmc_context* ctx, uint64_t ticket, int wait, int* done, double* dose, double* sigma,
              int out_ptr_kind, gmc_request_stats* stats);
 /* Finish every queued and running request, then stop the thread and free
- * the slots; finished tickets stay pollable. */
+ * the slots; finished tickets stay pollable (their results move to host
+ * memory). */
 int gmc_server_stop(gmc_context* ctx);
 int gmc_server_status(gmc_context* ctx, gmc_server_status_t* status);
 

@@ -116,10 +116,11 @@ uint32_t pass_waves(Workspace* w, int kernel, int block, int n_mat) {
 }
 
 int pass_block(Workspace* w, int kernel, int requested, int n_mat) {
-  if (requested > 0) return requested;
+  if (requested > 0) return kernel == 2 ? std::min(requested, kRoundMaxBlock) : requested;
   int best = 256;
   uint32_t best_waves = 0;
   for (int b : {256, 512, 1024}) {
+    if (kernel == 2 && b > kRoundMaxBlock) continue;
     const uint32_t waves = pass_waves(w, kernel, b, n_mat);
     if (waves > best_waves) {
       best_waves = waves;

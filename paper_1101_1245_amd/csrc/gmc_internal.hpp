@@ -311,6 +311,12 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v
 // kernel: 0 photon pass, 1 electron pass, 2 round kernel
 int max_resident_blocks(int kernel, int block, size_t lds);
 
+// Largest workgroup of the round kernel: it holds the electron and the photon
+// loop, whose registers together exceed what a 1024-thread workgroup leaves
+// each lane (128), so it is bounded at 512 threads (up to 256 registers)
+// rather than spill.
+constexpr int kRoundMaxBlock = 512;
+
 // Work memory of the allocation-free finalize: a file-scope device array of
 // the kernels' source, one copy per device, never freed.  It holds the
 // histories per batch (kMaxBatches doubles) and then the s reduction's work

@@ -1052,7 +1052,7 @@ __device__ __forceinline__ void append_round(const RoundArgs& r, const PassPlan&
 // electron and photon loops are those of the pass kernels; only where their
 // items come from differs.  Electron outputs of both phases go to the
 // wavefront's electron segment, photon outputs to its photon segment.
-__global__ void __launch_bounds__(1024) k_round(RoundArgs r) {
+__global__ void __launch_bounds__(kRoundMaxBlock) k_round(RoundArgs r) {
   extern __shared__ float4 smem[];
   const int nt = r.e.tab.n_mat * kNE;
   float4* tg = smem;

@@ -9,8 +9,11 @@
 // the slot's control block through an event it polls, so requests that
 // arrive while others run start at once and their kernels overlap on the
 // device.  Phantoms and tables stay resident in the context; a request only
-// references them.  A finished request's dose and sigma are copied to host
-// memory kept until gmc_poll hands them out.
+// references them.  A finished request's dose and sigma are finalized into a
+// device buffer of the server's result pool and stay there until gmc_poll
+// copies them out (device to device, or straight to host memory); pool
+// buffers are reused by later requests, so finishing a request neither
+// allocates pinned memory nor waits on a free.
 //
 // Every request is a single-beam job run by the same engine as gmc_run_beam,
 // so its result is bit-identical to running it alone.
@@ -39,8 +42,16 @@ struct Request {
   bool done = false;
   int rc = GMC_OK;
   std::string err;
-  std::vector<double> dose, sigma;
+  int res = -1;                 // result-pool buffer holding dose then sigma (nvox each), until polled
+  std::vector<double> dose, sigma;   // the result in host memory instead (moved there when the server stops)
   gmc_run_stats stats{};
+};
+
+// A device buffer of the result pool: 2 x elems doubles.
+struct ResultBuf {
+  double* p = nullptr;
+  size_t elems = 0;
+  bool busy = false;
 };
 
 struct Slot {
@@ -53,9 +64,6 @@ struct Slot {
   int nr = 0;
   uint64_t rounds = 0;
   const PhantomObj* P = nullptr;
-  double* h_dose = nullptr;     // pinned result staging
-  double* h_sigma = nullptr;
-  size_t h_elems = 0;
   hipEvent_t ev_done = nullptr;
 };
 
@@ -70,6 +78,8 @@ struct Server {
   std::deque<std::shared_ptr<Request>> pending;
   std::map<uint64_t, std::shared_ptr<Request>> tickets;
   std::vector<std::unique_ptr<Slot>> slots;
+  std::vector<ResultBuf> results;   // guarded by mu (the caller's gmc_poll releases buffers)
+  hipStream_t copy_stream = nullptr;  // the server thread's copies of results to host memory
   bool stopping = false;
   bool running = false;
   uint64_t next_ticket = 1;
@@ -84,6 +94,102 @@ void release_refs(gmc_context* c, const Request& r) {
   if (--c->refs[r.tid] <= 0) c->refs.erase(r.tid);
 }
 
+size_t result_bytes(const Server* s) {   // caller holds s->mu
+  size_t b = 0;
+  for (const ResultBuf& rb : s->results) b += 2 * rb.elems * sizeof(double);
+  return b;
+}
+
+// Free the pool's idle buffers (hipFree waits for the device: only when the
+// budget needs the room, or when the server stops).
+void trim_results(Server* s) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  for (ResultBuf& rb : s->results)
+    if (!rb.busy && rb.p) {
+      (void)hipFree(rb.p);
+      rb.p = nullptr;
+      rb.elems = 0;
+    }
+}
+
+// A pool buffer of at least 2 x elems doubles for a finishing request: the
+// smallest idle one that is large enough, else a new one.
+int acquire_result(Server* s, Workspace* w, size_t elems, int* idx) {
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    int best = -1;
+    for (int i = 0; i < (int)s->results.size(); ++i) {
+      const ResultBuf& rb = s->results[i];
+      if (!rb.busy && rb.p && rb.elems >= elems && (best < 0 || rb.elems < s->results[best].elems)) best = i;
+    }
+    if (best >= 0) {
+      s->results[best].busy = true;
+      *idx = best;
+      return GMC_OK;
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, 2 * elems * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    trim_results(s);
+    WS_TRY(w, hipMalloc(&p, 2 * elems * sizeof(double)));
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  int slot = -1;
+  for (int i = 0; i < (int)s->results.size() && slot < 0; ++i)
+    if (!s->results[i].p) slot = i;
+  if (slot < 0) {
+    slot = (int)s->results.size();
+    s->results.emplace_back();
+  }
+  s->results[slot].p = static_cast<double*>(p);
+  s->results[slot].elems = elems;
+  s->results[slot].busy = true;
+  *idx = slot;
+  return GMC_OK;
+}
+
+void release_result(Server* s, Request& r) {   // caller holds s->mu
+  if (r.res >= 0) s->results[r.res].busy = false;
+  r.res = -1;
+}
+
+// Move the result of the oldest finished, unclaimed request from its pool
+// buffer to host memory and free the buffer; false if there is none.
+bool spill_oldest_result(Server* s) {
+  void* freed = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    Request* oldest = nullptr;
+    for (auto& kv : s->tickets)   // ordered by ticket, i.e. by submission
+      if (kv.second->done && kv.second->res >= 0) {
+        oldest = kv.second.get();
+        break;
+      }
+    if (!oldest) return false;
+    Request& r = *oldest;
+    ResultBuf& rb = s->results[r.res];
+    r.dose.resize(r.nvox);
+    r.sigma.resize(r.nvox);
+    const size_t bytes = r.nvox * sizeof(double);
+    hipError_t e = hipMemcpyAsync(r.dose.data(), rb.p, bytes, hipMemcpyDeviceToHost, s->copy_stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(r.sigma.data(), rb.p + r.nvox, bytes, hipMemcpyDeviceToHost, s->copy_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->copy_stream);
+    if (e != hipSuccess) {
+      r.rc = GMC_EDEVICE;
+      r.err = std::string("copy of a finished result to host memory: ") + hipGetErrorString(e);
+    }
+    freed = rb.p;
+    rb.p = nullptr;
+    rb.elems = 0;
+    rb.busy = false;
+    r.res = -1;
+  }
+  (void)hipFree(freed);
+  return true;
+}
+
 void complete(Server* s, Slot& sl, int rc, const std::string& err) {
   std::shared_ptr<Request> r = sl.req;
   if (rc != GMC_OK && sl.w.stream) (void)hipStreamSynchronize(sl.w.stream);   // nothing of it still running
@@ -95,23 +201,12 @@ void complete(Server* s, Slot& sl, int rc, const std::string& err) {
   release_refs(s->c, *r);
   {
     std::lock_guard<std::mutex> lk(s->mu);
+    if (rc != GMC_OK) release_result(s, *r);
     r->rc = rc;
     r->err = err;
     r->done = true;
   }
   s->cv_done.notify_all();
-}
-
-int ensure_pinned(Slot& sl, size_t n) {
-  if (sl.h_elems >= n) return GMC_OK;
-  if (sl.h_dose) (void)hipHostFree(sl.h_dose);
-  if (sl.h_sigma) (void)hipHostFree(sl.h_sigma);
-  sl.h_dose = sl.h_sigma = nullptr;
-  sl.h_elems = 0;
-  WS_TRY(&sl.w, hipHostMalloc(&sl.h_dose, n * sizeof(double), hipHostMallocDefault));
-  WS_TRY(&sl.w, hipHostMalloc(&sl.h_sigma, n * sizeof(double), hipHostMallocDefault));
-  sl.h_elems = n;
-  return GMC_OK;
 }
 
 // Enqueue the request's set-up, capture its rounds and launch the first
@@ -132,8 +227,6 @@ int start(Server* s, Slot& sl) {
   }
   const Tune tu = resolve_tuning(&tun);
   int rc = ws_ensure_tally(w, r.nvox * r.K);
-  if (rc == GMC_OK) rc = ws_ensure_out(w, r.nvox);
-  if (rc == GMC_OK) rc = ensure_pinned(sl, r.nvox);
   if (rc) return rc;
   MajObj maj;
   rc = get_majorants(c, r.pid, r.tid, *pp, *tp, &maj, &w->err);
@@ -155,17 +248,24 @@ int start(Server* s, Slot& sl) {
   return GMC_OK;
 }
 
-// The job is done: finalize, and copy dose, sigma and counters to pinned
-// host memory, all behind one event.
-int finish(Slot& sl) {
+// The job is done: finalize into a result-pool buffer and copy the counters
+// to pinned host memory, all behind one event.
+int finish(Server* s, Slot& sl) {
   Workspace* w = &sl.w;
-  const Request& r = *sl.req;
+  Request& r = *sl.req;
   std::vector<double> nk;
   add_batch_sizes(nk, r.src.first_history, r.n, r.K);
-  int rc = finalize(w, *sl.P, w->d_tally, 1u, 0u, r.K, nk, r.n, w->d_dose, w->d_sigma, true, false);
+  int idx = -1;
+  int rc = acquire_result(s, w, r.nvox, &idx);
   if (rc) return rc;
-  WS_TRY(w, hipMemcpyAsync(sl.h_dose, w->d_dose, r.nvox * sizeof(double), hipMemcpyDeviceToHost, w->stream));
-  WS_TRY(w, hipMemcpyAsync(sl.h_sigma, w->d_sigma, r.nvox * sizeof(double), hipMemcpyDeviceToHost, w->stream));
+  double* res = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    r.res = idx;
+    res = s->results[idx].p;
+  }
+  rc = finalize(w, *sl.P, w->d_tally, 1u, 0u, r.K, nk, r.n, res, res + r.nvox, true, false);
+  if (rc) return rc;
   WS_TRY(w, hipMemcpyAsync(w->h_ctr, w->d_ctr, (size_t)C_COUNT * kCtrSlots * sizeof(unsigned long long),
                            hipMemcpyDeviceToHost, w->stream));
   WS_TRY(w, hipEventRecord(w->ev1, w->stream));
@@ -195,7 +295,7 @@ bool progress(Server* s, Slot& sl) {
       sl.rounds += (uint64_t)sl.nr;
       if (rc == GMC_OK) rc = enqueue_control_copy(w);
     } else if (rc == GMC_OK) {
-      rc = finish(sl);
+      rc = finish(s, sl);
     }
     if (rc) complete(s, sl, rc, w->err);
     return true;
@@ -205,18 +305,17 @@ bool progress(Server* s, Slot& sl) {
   (void)hipEventElapsedTime(&dev_ms, w->ev0, w->ev1);
   const double t_total = std::chrono::duration<double>(Clock::now() - r.t_start).count();
   rc = stats_from_counters(w, w->h_ctr, &r.stats, r.n, sl.rounds, t_total, dev_ms * 1e-3);
-  if (rc == GMC_OK) {
-    r.dose.assign(sl.h_dose, sl.h_dose + r.nvox);
-    r.sigma.assign(sl.h_sigma, sl.h_sigma + r.nvox);
-  }
   complete(s, sl, rc, rc ? w->err : std::string());
   return true;
 }
 
-size_t held_bytes(const Server* s) {
+// Device memory the server holds: its slots' workspaces and the result pool
+// (finished requests not yet polled, and idle buffers kept for reuse).
+size_t held_bytes(Server* s) {
   size_t b = 0;
   for (const auto& sl : s->slots) b += ws_device_bytes(sl->w);
-  return b;
+  std::lock_guard<std::mutex> lk(s->mu);
+  return b + result_bytes(s);
 }
 
 // Start pending requests, in order, on free slots while their footprint
@@ -236,7 +335,13 @@ void admit(Server* s) {
     if (held - cur + std::max(cur, r->need) > s->budget) {
       for (auto& o : s->slots)
         if (!o->req) ws_trim(&o->w);
+      trim_results(s);
       held = held_bytes(s);
+      // results waiting to be polled give way to host memory, oldest first,
+      // so that unpolled results never stop the queue
+      while (held - ws_device_bytes(sl.w) + std::max(ws_device_bytes(sl.w), r->need) > s->budget &&
+             spill_oldest_result(s))
+        held = held_bytes(s);
       if (held - ws_device_bytes(sl.w) + std::max(ws_device_bytes(sl.w), r->need) > s->budget) return;
     }
     {
@@ -279,11 +384,14 @@ void loop(Server* s) {
   }
   for (auto& sl : s->slots) {
     if (sl->ev_done) (void)hipEventDestroy(sl->ev_done);
-    if (sl->h_dose) (void)hipHostFree(sl->h_dose);
-    if (sl->h_sigma) (void)hipHostFree(sl->h_sigma);
     if (sl->ready) ws_free(&sl->w);
   }
   s->slots.clear();
+  // finished requests not yet polled keep their results in host memory, so
+  // that the device buffers can go
+  while (spill_oldest_result(s)) {
+  }
+  trim_results(s);
 }
 
 }  // namespace
@@ -297,6 +405,9 @@ void server_destroy(gmc_context* c) {
   }
   s->cv.notify_all();
   if (s->th.joinable()) s->th.join();
+  for (ResultBuf& rb : s->results)
+    if (rb.p) (void)hipFree(rb.p);
+  if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
   delete s;
   c->server = nullptr;
 }
@@ -318,6 +429,8 @@ int gmc_server_start(gmc_context* c, const gmc_server_config* cfg) {
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return cfail(c, GMC_EDEVICE, "hipMemGetInfo failed");
   s->budget = cfg && cfg->hbm_budget_bytes > 0 ? (size_t)cfg->hbm_budget_bytes : free_b / 4 * 3;
+  if (hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) != hipSuccess)
+    return cfail(c, GMC_EDEVICE, "stream creation failed");
   // queues and staging of one slot at the default tuning
   Workspace probe;
   probe.device = c->device;
@@ -410,6 +523,7 @@ int gmc_poll(gmc_context* c, uint64_t ticket, int wait, int* done, double* dose,
   Server* s = c->server;
   if (!s) return cfail(c, GMC_ENOTFOUND, "no server");
   std::shared_ptr<Request> r;
+  const double* res_p = nullptr;
   {
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->tickets.find(ticket);
@@ -418,7 +532,8 @@ int gmc_poll(gmc_context* c, uint64_t ticket, int wait, int* done, double* dose,
     if (wait) s->cv_done.wait(lk, [&] { return r->done; });
     *done = r->done ? 1 : 0;
     if (!r->done) return GMC_OK;
-    s->tickets.erase(it);
+    s->tickets.erase(it);   // claimed: the server no longer moves its result
+    if (r->res >= 0) res_p = s->results[r->res].p;
   }
   if (stats) {
     stats->t_queue_s = std::chrono::duration<double>(r->t_start - r->t_submit).count();
@@ -428,7 +543,22 @@ int gmc_poll(gmc_context* c, uint64_t ticket, int wait, int* done, double* dose,
   }
   if (r->rc) return cfail(c, r->rc, r->err);
   const size_t bytes = r->nvox * sizeof(double);
-  if (out_ptr_kind == GMC_HOST) {
+  int rc = GMC_OK;
+  if (res_p) {
+    // device-resident result: one copy to the caller's buffer (device to
+    // device, or device to host), complete on return, then the buffer goes
+    // back to the pool
+    (void)hipSetDevice(c->device);
+    const hipMemcpyKind kind = out_ptr_kind == GMC_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    hipStream_t st = c->ws.stream;   // the context stream, as the blocking forms' copies
+    hipError_t e = hipSuccess;
+    if (dose) e = hipMemcpyAsync(dose, res_p, bytes, kind, st);
+    if (e == hipSuccess && sigma) e = hipMemcpyAsync(sigma, res_p + r->nvox, bytes, kind, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = cfail(c, GMC_EDEVICE, std::string("copy of the result: ") + hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(s->mu);
+    release_result(s, *r);
+  } else if (out_ptr_kind == GMC_HOST) {
     if (dose) std::memcpy(dose, r->dose.data(), bytes);
     if (sigma) std::memcpy(sigma, r->sigma.data(), bytes);
   } else {
@@ -438,7 +568,7 @@ int gmc_poll(gmc_context* c, uint64_t ticket, int wait, int* done, double* dose,
     if (sigma && hipMemcpy(sigma, r->sigma.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
       return cfail(c, GMC_EDEVICE, "copy of sigma to device memory failed");
   }
-  return GMC_OK;
+  return rc;
 }
 
 int gmc_server_status(gmc_context* c, gmc_server_status_t* st) {

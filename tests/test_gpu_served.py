@@ -100,6 +100,36 @@ def test_one_slot_budget_serialises(ctx, G, stream):
         ctx.server_stop()
 
 
+def test_results_wait_in_device_memory_and_move_to_host_at_stop(ctx, stream):
+    """Finished results stay in the server's device result pool until polled;
+    stopping the server moves the unpolled ones to host memory.  Either way
+    the polled dose and sigma equal the plain form's bit for bit, delivered to
+    host or to device memory."""
+    import time
+    pool, reqs, tid, pids = stream
+    sub = reqs[:6]
+    ctx.server_start(max_slots=2)
+    try:
+        tickets = [ctx.submit(pids[r.phantom], tid, r.source, r.n_hist, r.seed) for r in sub]
+        # the first two polled at once (device results), the rest after the stop
+        early = [ctx.poll(t, pool[r.phantom].shape, wait=True, out=o)
+                 for t, r, o in zip(tickets[:2], sub[:2], ("numpy", "torch"))]
+        t_end = time.time() + 120
+        while ctx.server_status()["finished_unpolled"] < len(sub) - 2 and time.time() < t_end:
+            time.sleep(0.01)
+        assert ctx.server_status()["finished_unpolled"] == len(sub) - 2
+    finally:
+        ctx.server_stop()
+    late = [ctx.poll(t, pool[r.phantom].shape, wait=True, out=o)
+            for t, r, o in zip(tickets[2:], sub[2:], ("numpy", "torch") * 2)]
+    for (done, d, s, st), r in zip(early + late, sub):
+        assert done and st["ledger_residual_lsb"] == 0
+        d = d.cpu().numpy() if hasattr(d, "cpu") else d
+        s = s.cpu().numpy() if hasattr(s, "cpu") else s
+        da, sa, _ = ctx.run_beam(pids[r.phantom], tid, r.source, r.n_hist, r.seed, shape=pool[r.phantom].shape)
+        assert np.array_equal(d, da) and np.array_equal(s, sa), r
+
+
 def test_bad_requests_and_device_output(ctx, G, stream):
     pool, reqs, tid, pids = stream
     ctx.server_start()
