@@ -372,9 +372,12 @@ def bench_beamlets(args, G, E, I):
             "batched_tuning": args.tuning if args.tuning is not None else "autotuned",
             "outputs": "device memory (no PCIe in the timed region)",
         },
-        "plain": {"value": acc_p.hist / el_p, "ms_per_step": el_p / args.steps * 1e3},
+        "plain": {"value": acc_p.hist / el_p, "ms_per_step": el_p / args.steps * 1e3,
+                  "roofline": roofline(acc_p, "beamlets")},
         "batched_over_plain": (acc_b.hist / el_b) / (acc_p.hist / el_p),
-        "roofline": roofline(both, "beamlets"),
+        # the launches that produce `value`: the batched leg's (the plain leg's
+        # 256 short jobs have a roofline of their own under "plain")
+        "roofline": roofline(acc_b, "beamlets"),
         "ledger_residual_lsb": both.resid,
     }
     ctx.close()
