@@ -315,7 +315,8 @@ int gmc_run_beams(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, const
 
 /* Autotuner of the batched form.  Picks the admission chunk, the pass size,
  * the events per visit, the workgroup size, the particles per wavefront,
- * the refill threshold and the rounds per status check by coordinate
+ * the refill threshold, the rounds per status check and the persistent
+ * round kernel against graph-replayed passes by coordinate
  * descent, starting with the admission chunk and the pass size together
  * (pass = 2 x chunk): each candidate runs the whole job when about 24 such
  * runs fit the budget, else a sample (the first histories of every beam, in

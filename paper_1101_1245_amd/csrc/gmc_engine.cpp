@@ -142,6 +142,7 @@ int ws_init(Workspace* w, int device, hipStream_t stream) {
   WS_TRY(w, hipHostMalloc(&w->h_ctl, sizeof(Control), hipHostMallocDefault));
   WS_TRY(w, hipMalloc(&w->d_ctr, C_COUNT * kCtrSlots * sizeof(unsigned long long)));
   WS_TRY(w, hipHostMalloc(&w->h_ctr, C_COUNT * kCtrSlots * sizeof(unsigned long long), hipHostMallocDefault));
+  WS_TRY(w, hipMalloc(&w->d_claim, 2 * kMaxClaimParts * sizeof(uint32_t)));
   WS_TRY(w, hipMalloc(&w->d_nk, kMaxBatches * sizeof(double)));
   WS_TRY(w, hipMalloc(&w->d_srel, (3 * kRelBlocks + 1) * sizeof(double)));
   WS_TRY(w, hipHostMalloc(&w->h_srel, sizeof(double), hipHostMallocDefault));
@@ -173,7 +174,7 @@ void ws_free(Workspace* w) {
   free_queue(w->sorted);
   w->cap = w->stg_cap = w->sorted_cap = 0;
   for (void* p : {(void*)w->d_ctl, (void*)w->d_ctr, (void*)w->d_beams, (void*)w->d_sort, (void*)w->d_tab,
-                  (void*)w->d_sources, (void*)w->d_start, (void*)w->d_beam_of, (void*)w->d_nk})
+                  (void*)w->d_sources, (void*)w->d_start, (void*)w->d_beam_of, (void*)w->d_nk, (void*)w->d_claim})
     if (p) (void)hipFree(p);
   for (void* p : {(void*)w->h_ctl, (void*)w->h_ctr, (void*)w->h_nk, (void*)w->h_srel})
     if (p) (void)hipHostFree(p);
@@ -190,6 +191,7 @@ void ws_free(Workspace* w) {
   w->d_srel = nullptr;
   w->h_srel = nullptr;
   w->d_nk = w->h_nk = nullptr;
+  w->d_claim = nullptr;
   w->beams_cap = 0;
   for (hipEvent_t e : {w->ev0, w->ev1, w->kev0, w->kev1, w->ev_ctl})
     if (e) (void)hipEventDestroy(e);
@@ -630,11 +632,12 @@ int enqueue_round(Engine& E, hipEvent_t t0, hipEvent_t t1, bool capturing) {
   }
   pa.plan = w->d_ctl->plan;
   pa.claims = w->d_ctl->claim;
-  pa.claim_ctr = &w->d_ctl->claim_ctr[0][0];
+  pa.claim_ctr = w->d_claim;
   pa.cap = w->cap;
   pa.cap_soft = w->cap_soft;
   pa.max_items = (uint32_t)E.tu.pass_items;
   pa.waves = E.round_waves;
+  pa.blocks = E.round_blocks;
   pa.chunk_log2 = lg;
   pa.sec = (uint32_t)E.tu.secondaries;
   pa.sched = w->d_ctl->sched;
@@ -656,7 +659,7 @@ int enqueue_round(Engine& E, hipEvent_t t0, hipEvent_t t1, bool capturing) {
   r.e.tail_lanes = E.tu.tail_e;
   r.g.tail_min = r.e.tail_min = kTailMinItems;
   r.claims = w->d_ctl->claim;
-  r.claim_ctr = &w->d_ctl->claim_ctr[0][0];
+  r.claim_ctr = w->d_claim;
   WS_TRY(w, record_event(w->stream, t0, capturing));
   const hipError_t e = launch_round(r, (int)E.round_blocks, E.round_block, w->stream);
   if (e != hipSuccess) return wfail(w, GMC_EDEVICE, std::string("round launch: ") + hipGetErrorString(e));
@@ -1343,6 +1346,8 @@ int autotune(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_so
       {&gmc_tuning::wave_items, {64, 128, 256}, nullptr},
       {&gmc_tuning::refill_lanes, {1, 4, 8, 16}, nullptr},
       {&gmc_tuning::rounds_per_check, {2, 4, 8}, nullptr},
+      // the persistent round kernel against graph-replayed passes
+      {&gmc_tuning::persistent, {1}, nullptr},
   };
   bool out_of_time = false;
   for (const Dim& d : dims) {

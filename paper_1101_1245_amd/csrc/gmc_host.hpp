@@ -70,7 +70,6 @@ struct Control {
   PassPlan plan[2];
   AdmitPlan adm[2];
   ClaimType claim[2];           // the round kernel's work queue per type
-  uint32_t claim_ctr[2][kClaimParts];
   bool done() const {
     return sched[0] == sched[2] && sched[1] == sched[3] && counts[0] == 0 && counts[1] == 0 && counts[2] == 0 &&
            counts[3] == 0;
@@ -107,6 +106,7 @@ struct Workspace {
   uint32_t* d_start = nullptr;   // [2][beams_cap + 1]
   uint32_t* d_beam_of = nullptr;   // [2][beams_cap]
   size_t beams_cap = 0;
+  uint32_t* d_claim = nullptr;  // [2][kMaxClaimParts] chunk counters of the round kernel's work queue
   double* d_nk = nullptr;
   double* d_srel = nullptr;     // [3 kRelBlocks + 1] work of the s reduction, s last
   double* h_srel = nullptr;     // pinned copy of s

@@ -133,12 +133,16 @@ struct PassPlan {
 };
 
 // The device work queue of the persistent round kernel, per particle type:
-// the round's m items split into kClaimParts contiguous partitions (chunk
-// counters of their own), and the most items one wavefront may claim.
-constexpr int kClaimParts = 8;
+// the round's m items split into `parts` contiguous partitions, partition p
+// holding items [m p / parts, m (p+1) / parts) and a chunk counter of its
+// own, and the most items one wavefront may claim.  Workgroup b claims from
+// partition b mod parts first, so a claim is normally an atomic that only
+// its own workgroup's wavefronts share.
+constexpr int kMaxClaimParts = 4096;
 struct ClaimType {
   uint32_t cap;
-  uint32_t start[kClaimParts + 1];
+  uint32_t m;
+  uint32_t parts;
 };
 
 struct PlanArgs {
@@ -201,7 +205,7 @@ struct PassArgs {
 struct RoundArgs {
   PassArgs g, e;
   const ClaimType* claims;      // [2] photon, electron
-  uint32_t* claim_ctr;          // [2][kClaimParts] chunk counters (cleared by the plan)
+  uint32_t* claim_ctr;          // [2][kMaxClaimParts] chunk counters (cleared by the plan)
 };
 
 // Sizes of a round: both types' plans as k_plan_pass would make them in
@@ -212,10 +216,11 @@ struct RoundPlanArgs {
   uint32_t* n_new[2];           // counts of the new accumulating buffers: set to the carry-overs
   PassPlan* plan;               // [2]
   ClaimType* claims;            // [2]
-  uint32_t* claim_ctr;          // [2][kClaimParts]
+  uint32_t* claim_ctr;          // [2][kMaxClaimParts]
   uint32_t cap, cap_soft;       // allocated and soft queue capacity
   uint32_t max_items;           // most particles of a type per round
   uint32_t waves;               // wavefronts of the round grid
+  uint32_t blocks;              // workgroups of the round grid
   uint32_t chunk_log2;          // items per claimed chunk: 2^chunk_log2
   uint32_t sec;                 // secondaries per visit
   const uint32_t* sched;        // admission cursors [2] and totals [2]

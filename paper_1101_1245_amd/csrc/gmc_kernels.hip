@@ -235,39 +235,72 @@ __device__ __forceinline__ WaveRange wave_range(const PassPlan& P, uint32_t wave
 
 // A wavefront's work in the persistent round kernel: chunks of 2^lg
 // consecutive work-queue items claimed one at a time from a device work
-// queue.  The m items of a type are split into kClaimParts contiguous
-// partitions, each with its own chunk counter, so claims spread over
-// kClaimParts addresses instead of one hot word; a wavefront claims from the
-// partition of its workgroup's slot first and moves on to the next one when
-// that is empty.  It never claims more than `cap` items in all (the bound its
-// staging segments were sized for); the caps add up to more than m, so every
-// item is claimed by some wavefront.  No wavefront waits for another: a claim
-// is one atomic addition, and an empty partition is skipped.  [next, end)
-// are queue indices of the current chunk's items not yet handed out.
+// queue.  The m items of a type are split into `parts` contiguous
+// partitions, each with its own chunk counter; a wavefront claims from its
+// workgroup's partition (block mod parts) first, so most claims are atomics
+// on a counter only that workgroup's wavefronts share.  When that partition
+// is used up the wavefront steals: its 64 lanes read 64 partitions' counters
+// at once (agent-scope loads; a counter only grows, so one that reads
+// exhausted is exhausted) and it claims from the first that still has a
+// chunk, moving on through all partitions before it gives up.  It never
+// claims more than `cap` items in all (the bound its staging segments were
+// sized for); the caps add up to more than m, so every item is claimed by
+// some wavefront.  No wavefront waits for another.  [next, end) are queue
+// indices of the current chunk's items not yet handed out.
 struct ClaimRange {
   uint32_t next, end;
   uint32_t taken, cap;        // items claimed so far, most it may claim
-  uint32_t part, left;        // partition claimed from, partitions not yet found empty
-  uint32_t lg;
-  const ClaimType* T;
-  uint32_t* ctr;              // [kClaimParts] chunk counters of this type
+  uint32_t cur;               // partition of the last successful claim
+  uint32_t m, parts, lg;
+  bool exhausted;             // every partition found used up (or the cap reached)
+  uint32_t* ctr;              // [parts] chunk counters of this type
 
+  __device__ __forceinline__ uint32_t lo(uint32_t p) const {
+    return (uint32_t)(((uint64_t)m * p) / parts);
+  }
+  __device__ __forceinline__ uint32_t chunks(uint32_t p) const {
+    return (lo(p + 1u) - lo(p) + (1u << lg) - 1u) >> lg;
+  }
+  // one atomic on partition p's counter (wave-uniform p): true and the
+  // chunk set when p still had one
+  __device__ __forceinline__ bool take(uint32_t p) {
+    uint32_t c = 0u;
+    if (lane_id() == 0u) c = atomicAdd(ctr + p, 1u);
+    c = __shfl(c, 0);
+    const uint32_t a = lo(p), b = lo(p + 1u);
+    const uint64_t first = (uint64_t)a + ((uint64_t)c << lg);
+    if (first >= b) return false;
+    next = (uint32_t)first;
+    end = (uint32_t)min<uint64_t>(first + (1u << lg), b);
+    taken += end - next;
+    cur = p;
+    return true;
+  }
   __device__ __forceinline__ void claim() {
-    while (left > 0u && taken + (1u << lg) <= cap) {
-      uint32_t c = 0u;
-      if (lane_id() == 0u) c = atomicAdd(ctr + part, 1u);
-      c = __shfl(c, 0);
-      const uint32_t lo = T->start[part], hi = T->start[part + 1];
-      const uint64_t first = (uint64_t)lo + ((uint64_t)c << lg);
-      if (first < hi) {
-        next = (uint32_t)first;
-        end = (uint32_t)min<uint64_t>(first + (1u << lg), hi);
-        taken += end - next;
-        return;
-      }
-      part = part + 1u == (uint32_t)kClaimParts ? 0u : part + 1u;
-      --left;
+    if (exhausted || taken + (1u << lg) > cap) {
+      exhausted = true;
+      return;
     }
+    if (take(cur)) return;
+    // steal: scan the partitions after the current one, 64 at a time
+    for (uint32_t base = 1u; base < parts; base += 64u) {
+      const uint32_t off = base + lane_id();
+      uint32_t p = cur + off;
+      if (p >= parts) p -= parts;
+      bool avail = false;
+      if (off < parts) {
+        const uint32_t c = __hip_atomic_load(ctr + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        avail = c < chunks(p);
+      }
+      unsigned long long mask = __ballot(avail);
+      while (mask) {
+        const int j = __ffsll((long long)mask) - 1;
+        const uint32_t pj = (uint32_t)__shfl((int)p, j);
+        if (take(pj)) return;
+        mask &= mask - 1ull;
+      }
+    }
+    exhausted = true;
   }
   // wave-uniform: claims the next chunk when the current one is used up
   __device__ __forceinline__ bool done() {
@@ -279,15 +312,16 @@ struct ClaimRange {
   __device__ __forceinline__ uint32_t item(uint32_t j) const { return j; }
 };
 
-__device__ __forceinline__ ClaimRange claim_range(const ClaimType& T, uint32_t* ctr, uint32_t lg, uint32_t slot) {
+__device__ __forceinline__ ClaimRange claim_range(const ClaimType& T, uint32_t* ctr, uint32_t lg, uint32_t block) {
   ClaimRange r;
   r.next = r.end = 0u;
   r.taken = 0u;
   r.cap = T.cap;
-  r.part = slot % (uint32_t)kClaimParts;
-  r.left = (uint32_t)kClaimParts;
+  r.m = T.m;
+  r.parts = T.parts;
+  r.cur = block % T.parts;
   r.lg = lg;
-  r.T = &T;
+  r.exhausted = T.m == 0u;
   r.ctr = ctr;
   return r;
 }
@@ -1079,7 +1113,7 @@ __global__ void __launch_bounds__(kRoundMaxBlock) k_round(RoundArgs r) {
   const PassPlan Pg = *r.g.plan, Pe = *r.e.plan;
   WaveSeg se{wave * Pe.seg_same, Pe.seg_same, 0u}, sg{wave * Pg.seg_same, Pg.seg_same, 0u};
   WaveTotals tot;
-  ClaimRange re = claim_range(r.claims[1], r.claim_ctr + kClaimParts, Pe.chunk_log2, blockIdx.x);
+  ClaimRange re = claim_range(r.claims[1], r.claim_ctr + kMaxClaimParts, Pe.chunk_log2, blockIdx.x);
   electron_loop(r.e, Pe.admitting, re, se, sg, te, maje, ms, lbeams, nvox, tot);
   ClaimRange rg = claim_range(r.claims[0], r.claim_ctr, Pg.chunk_log2, blockIdx.x);
   photon_loop(r.g, Pg.admitting, rg, sg, se, tg, majg, lbeams, nvox, tot);
@@ -1288,6 +1322,8 @@ __global__ void k_plan_pass(PlanArgs a) {
 // capacity; the claim caps (an even share of chunks plus one) and the
 // segments those caps need; the claim counters are cleared.
 __global__ void k_plan_round(RoundPlanArgs a) {
+  // every thread of the one workgroup clears claim counters; thread 0 plans
+  for (uint32_t i = threadIdx.x; i < 2u * (uint32_t)kMaxClaimParts; i += blockDim.x) a.claim_ctr[i] = 0u;
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const uint32_t ne = *a.n_work[1], ng = *a.n_work[0];
   const uint64_t s = a.sec;
@@ -1311,11 +1347,16 @@ __global__ void k_plan_round(RoundPlanArgs a) {
   for (int t = 0; t < 2; ++t) {
     const uint64_t chunks = ((uint64_t)ms[t] + ch - 1u) >> a.chunk_log2;
     caps[t] = (uint32_t)(((chunks + a.waves - 1u) / a.waves + 1u) << a.chunk_log2);
+    // one partition per workgroup, of at least two chunks each
+    uint64_t parts = chunks >> 1;
+    const uint64_t most = a.blocks < (uint32_t)kMaxClaimParts ? a.blocks : (uint32_t)kMaxClaimParts;
+    if (parts > most) parts = most;
+    if (parts < 1u) parts = 1u;
     ClaimType c;
     c.cap = caps[t];
-    for (int p = 0; p <= kClaimParts; ++p) c.start[p] = (uint32_t)((uint64_t)ms[t] * (uint64_t)p / kClaimParts);
+    c.m = ms[t];
+    c.parts = (uint32_t)parts;
     a.claims[t] = c;
-    for (int p = 0; p < kClaimParts; ++p) a.claim_ctr[t * kClaimParts + p] = 0u;
     *a.n_work[t] = 0u;
     *a.n_new[t] = ns[t] - ms[t];
   }
@@ -1470,7 +1511,7 @@ hipError_t launch_photon_pass(const PassArgs& a, int grid, int block, hipStream_
 }
 
 hipError_t launch_plan_round(const RoundPlanArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_plan_round, dim3(1), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_plan_round, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
