@@ -174,7 +174,8 @@ void ws_free(Workspace* w) {
   free_queue(w->sorted);
   w->cap = w->stg_cap = w->sorted_cap = 0;
   for (void* p : {(void*)w->d_ctl, (void*)w->d_ctr, (void*)w->d_beams, (void*)w->d_sort, (void*)w->d_tab,
-                  (void*)w->d_sources, (void*)w->d_start, (void*)w->d_beam_of, (void*)w->d_nk, (void*)w->d_claim})
+                  (void*)w->d_sources, (void*)w->d_start, (void*)w->d_beam_of, (void*)w->d_seg_h, (void*)w->d_nk,
+                  (void*)w->d_claim})
     if (p) (void)hipFree(p);
   for (void* p : {(void*)w->h_ctl, (void*)w->h_ctr, (void*)w->h_nk, (void*)w->h_srel})
     if (p) (void)hipHostFree(p);
@@ -183,7 +184,8 @@ void ws_free(Workspace* w) {
   w->d_ctr = w->h_ctr = nullptr;
   w->d_beams = nullptr;
   w->d_sources = nullptr;
-  w->d_start = w->d_beam_of = nullptr;
+  w->d_start = w->d_beam_of = w->d_seg_h = nullptr;
+  w->seg_cap = 0;
   w->d_sort = nullptr;
   w->d_tab = nullptr;
   w->tab_cap = 0;
@@ -206,7 +208,8 @@ void ws_free(Workspace* w) {
 size_t ws_device_bytes(const Workspace& w) {
   return sizeof(uint32_t) * ((size_t)Q_FIELDS * (4ull * w.cap + w.sorted_cap) + (size_t)kStgFields * 2ull * w.stg_cap) +
          w.tally_elems * sizeof(unsigned long long) + 2 * w.out_elems * sizeof(double) +
-         w.beams_cap * (sizeof(DevBeam) + sizeof(DevSource) + 4 * sizeof(uint32_t)) + w.tab_cap * sizeof(double);
+         w.beams_cap * (sizeof(DevBeam) + sizeof(DevSource)) + w.seg_cap * 6 * sizeof(uint32_t) +
+         w.tab_cap * sizeof(double);
 }
 
 int ws_ensure_tally(Workspace* w, size_t elems) {
@@ -233,17 +236,27 @@ int ws_ensure_out(Workspace* w, size_t elems) {
 
 int ws_ensure_beams(Workspace* w, size_t n) {
   if (w->beams_cap >= n) return GMC_OK;
-  for (void* p : {(void*)w->d_beams, (void*)w->d_sources, (void*)w->d_start, (void*)w->d_beam_of})
+  for (void* p : {(void*)w->d_beams, (void*)w->d_sources})
     if (p) (void)hipFree(p);
   w->d_beams = nullptr;
   w->d_sources = nullptr;
-  w->d_start = w->d_beam_of = nullptr;
   w->beams_cap = 0;
   WS_TRY(w, hipMalloc(&w->d_beams, n * sizeof(DevBeam)));
   WS_TRY(w, hipMalloc(&w->d_sources, n * sizeof(DevSource)));
+  w->beams_cap = n;
+  return GMC_OK;
+}
+
+int ws_ensure_segments(Workspace* w, size_t n) {
+  if (w->seg_cap >= n) return GMC_OK;
+  for (void* p : {(void*)w->d_start, (void*)w->d_beam_of, (void*)w->d_seg_h})
+    if (p) (void)hipFree(p);
+  w->d_start = w->d_beam_of = w->d_seg_h = nullptr;
+  w->seg_cap = 0;
   WS_TRY(w, hipMalloc(&w->d_start, 2 * (n + 1) * sizeof(uint32_t)));
   WS_TRY(w, hipMalloc(&w->d_beam_of, 2 * n * sizeof(uint32_t)));
-  w->beams_cap = n;
+  WS_TRY(w, hipMalloc(&w->d_seg_h, 2 * n * sizeof(uint32_t)));
+  w->seg_cap = n;
   return GMC_OK;
 }
 
@@ -501,9 +514,14 @@ void build_job(Job* J, Workspace* w, const PhantomObj& P, const TablesObj& T, co
   J->P = &P;
   J->T = &T;
   J->maj = maj;
-  for (int t = 0; t < 2; ++t) J->start[t].assign(1, 0u);
+  for (int t = 0; t < 2; ++t) {
+    J->start[t].assign(1, 0u);
+    J->beam_of[t].clear();
+    J->seg_h[t].clear();
+  }
   uint32_t off = 0;
   uint64_t per_type[2] = {0, 0};
+  std::vector<int> of_type[2];
   for (int b = 0; b < n_beams; ++b) {
     DevBeam db{};
     db.key0 = (uint32_t)seed;
@@ -522,10 +540,41 @@ void build_job(Job* J, Workspace* w, const PhantomObj& P, const TablesObj& T, co
     J->tab_off.push_back(J->tab.size());
     if (srcs[b].spectrum == GMC_TABULATED) tabulated_cdf(srcs[b], &J->tab);
     const int t = srcs[b].particle;
-    J->beam_of[t].push_back((uint32_t)b);
-    J->start[t].push_back(J->start[t].back() + (uint32_t)n_hist[b]);
+    of_type[t].push_back(b);
     per_type[t] += n_hist[b];
     off += (uint32_t)n_hist[b];
+  }
+  // Admission order.  A beam's histories admitted as one block would put
+  // nearly every particle in flight on that beam, and its own tally (one
+  // slice when per-beam doses are kept beside the combined ones) would take
+  // all their additions on the few voxels of its axis.  So each type's beams
+  // are cut into segments of at least kAdmitSegment histories, ordered by the
+  // fraction of its beam a segment's middle lies at: every beam is admitted
+  // in proportion and the particles in flight spread over all of them.  Only
+  // the order of admission changes; a history's number, stream and batch do
+  // not, so neither does any result.
+  for (int t = 0; t < 2; ++t) {
+    struct Piece {
+      double key;
+      uint32_t beam, h, n;
+    };
+    std::vector<Piece> pieces;
+    const uint64_t seg = of_type[t].size() <= 1
+                             ? std::numeric_limits<uint32_t>::max()
+                             : std::max<uint64_t>(kAdmitSegment, (per_type[t] + kMaxAdmitSegments - 1) / kMaxAdmitSegments);
+    for (int b : of_type[t]) {
+      const uint64_t n = n_hist[b];
+      for (uint64_t h = 0; h < n; h += seg) {
+        const uint64_t len = std::min<uint64_t>(seg, n - h);
+        pieces.push_back(Piece{((double)h + 0.5 * (double)len) / (double)n, (uint32_t)b, (uint32_t)h, (uint32_t)len});
+      }
+    }
+    std::stable_sort(pieces.begin(), pieces.end(), [](const Piece& x, const Piece& y) { return x.key < y.key; });
+    for (const Piece& p : pieces) {
+      J->beam_of[t].push_back(p.beam);
+      J->seg_h[t].push_back(p.h);
+      J->start[t].push_back(J->start[t].back() + p.n);
+    }
   }
   J->total[0] = (uint32_t)per_type[0];
   J->total[1] = (uint32_t)per_type[1];
@@ -752,6 +801,8 @@ int engine_setup(Workspace* w, Engine& E, const Job& J, const Tune& tu) {
   const size_t nb = J.beams.size();
   rc = ws_ensure_beams(w, nb);
   if (rc) return rc;
+  rc = ws_ensure_segments(w, std::max(J.beam_of[0].size(), J.beam_of[1].size()));
+  if (rc) return rc;
   WS_TRY(w, hipMemcpy(w->d_beams, J.beams.data(), nb * sizeof(DevBeam), hipMemcpyHostToDevice));
   std::vector<DevSource> srcs = J.sources;
   if (!J.tab.empty()) {
@@ -768,11 +819,14 @@ int engine_setup(Workspace* w, Engine& E, const Job& J, const Tune& tu) {
   }
   WS_TRY(w, hipMemcpy(w->d_sources, srcs.data(), nb * sizeof(DevSource), hipMemcpyHostToDevice));
   for (int t = 0; t < 2; ++t) {
-    WS_TRY(w, hipMemcpy(w->d_start + t * (w->beams_cap + 1), J.start[t].data(), J.start[t].size() * sizeof(uint32_t),
+    WS_TRY(w, hipMemcpy(w->d_start + t * (w->seg_cap + 1), J.start[t].data(), J.start[t].size() * sizeof(uint32_t),
                         hipMemcpyHostToDevice));
-    if (!J.beam_of[t].empty())
-      WS_TRY(w, hipMemcpy(w->d_beam_of + t * w->beams_cap, J.beam_of[t].data(),
+    if (!J.beam_of[t].empty()) {
+      WS_TRY(w, hipMemcpy(w->d_beam_of + t * w->seg_cap, J.beam_of[t].data(),
                           J.beam_of[t].size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+      WS_TRY(w, hipMemcpy(w->d_seg_h + t * w->seg_cap, J.seg_h[t].data(), J.seg_h[t].size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice));
+    }
   }
   Control ctl{};
   ctl.sched[2] = J.total[0];
@@ -802,8 +856,9 @@ int engine_setup(Workspace* w, Engine& E, const Job& J, const Tune& tu) {
     a.ph = dph;
     a.cut = cuts;
     a.plan = w->d_ctl->adm + t;
-    a.start = w->d_start + t * (w->beams_cap + 1);
-    a.beam_of = w->d_beam_of + t * w->beams_cap;
+    a.start = w->d_start + t * (w->seg_cap + 1);
+    a.beam_of = w->d_beam_of + t * w->seg_cap;
+    a.seg_h = w->d_seg_h + t * w->seg_cap;
     a.nb = (uint32_t)J.beam_of[t].size();
     a.beams = w->d_beams;
     a.sources = w->d_sources;

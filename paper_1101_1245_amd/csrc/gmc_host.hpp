@@ -60,6 +60,10 @@ constexpr uint64_t kTuneMinSample = 1ull << 25;   // 8 chunks of the largest can
 constexpr int kResumeLanes = 32;
 // Smallest share of a pass (particles per wavefront) whose tail is requeued.
 constexpr uint32_t kTailMinItems = 256u;
+// Admission segments of a job with several beams of a type: at least this
+// many histories each, at most kMaxAdmitSegments per type.
+constexpr uint64_t kAdmitSegment = 4096u;
+constexpr uint64_t kMaxAdmitSegments = 1u << 16;
 
 // Device control block of a workspace: queue counts [type][buffer],
 // admission cursor and histories per type, the last pass plans and
@@ -103,9 +107,11 @@ struct Workspace {
   DevSource* d_sources = nullptr;
   double* d_tab = nullptr;      // the job's tabulated spectra
   size_t tab_cap = 0;
-  uint32_t* d_start = nullptr;   // [2][beams_cap + 1]
-  uint32_t* d_beam_of = nullptr;   // [2][beams_cap]
+  uint32_t* d_start = nullptr;   // [2][seg_cap + 1] admission segments per type: first job-wide index
+  uint32_t* d_beam_of = nullptr;   // [2][seg_cap] beam of each segment
+  uint32_t* d_seg_h = nullptr;     // [2][seg_cap] index in its beam of the segment's first history
   size_t beams_cap = 0;
+  size_t seg_cap = 0;
   uint32_t* d_claim = nullptr;  // [2][kMaxClaimParts] chunk counters of the round kernel's work queue
   double* d_nk = nullptr;
   double* d_srel = nullptr;     // [3 kRelBlocks + 1] work of the s reduction, s last
@@ -142,6 +148,8 @@ size_t ws_device_bytes(const Workspace& w);
 int ws_ensure_tally(Workspace* w, size_t elems);
 int ws_ensure_out(Workspace* w, size_t elems);
 int ws_ensure_beams(Workspace* w, size_t n);
+// Admission segment tables of n segments per type.
+int ws_ensure_segments(Workspace* w, size_t n);
 
 // Engine knobs (gmc_tuning with defaults filled in).
 struct Tune {
@@ -183,7 +191,9 @@ struct Job {
   std::vector<DevSource> sources;
   std::vector<double> tab;            // tabulated spectra: per such beam, edges then normalised CDF
   std::vector<size_t> tab_off;        // per beam: offset in tab (tabulated beams only)
-  std::vector<uint32_t> start[2], beam_of[2];
+  // admission segments per type: segment j covers job-wide indices
+  // [start[j], start[j+1]), histories seg_h[j] ... of beam beam_of[j]
+  std::vector<uint32_t> start[2], beam_of[2], seg_h[2];
   uint32_t total[2] = {0, 0};
 };
 

@@ -248,9 +248,10 @@ struct AdmitArgs {
   DevCuts cut;
   DevQueue out;
   const AdmitPlan* plan;
-  const uint32_t* start;        // [nb + 1] first history of each beam of this type
-  const uint32_t* beam_of;      // [nb] beam index of each beam of this type
-  uint32_t nb;
+  const uint32_t* start;        // [nb + 1] first job-wide index of each admission segment of this type
+  const uint32_t* beam_of;      // [nb] beam of each segment
+  const uint32_t* seg_h;        // [nb] index in its beam of each segment's first history
+  uint32_t nb;                  // segments
   const DevBeam* beams;
   const DevSource* sources;     // indexed by beam
   unsigned long long* ctr;

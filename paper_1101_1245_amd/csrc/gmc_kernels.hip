@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(256) k_admit(AdmitArgs a) {
   const bool valid = i < pl.count;
   const uint32_t g = pl.cursor + i;
   uint32_t j = 0;
-  if (valid) {   // the beam owning history g: last j with start[j] <= g
+  if (valid) {   // the segment holding index g: last j with start[j] <= g
     uint32_t lo = 0, hi = a.nb;
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
@@ -124,7 +124,7 @@ __global__ void __launch_bounds__(256) k_admit(AdmitArgs a) {
   if (valid) {
     const DevSource src = a.sources[beam];
     particle = src.particle;
-    h = g - a.start[j] + src.h0;
+    h = g - a.start[j] + a.seg_h[j] + src.h0;
     p = sample_primary(src, a.beams[beam], h);
   }
   const bool in = valid && inside(a.ph, p.x, p.y, 0.0f);
