@@ -103,13 +103,17 @@ size_t result_bytes(const Server* s) {   // caller holds s->mu
 // Free the pool's idle buffers (hipFree waits for the device: only when the
 // budget needs the room, or when the server stops).
 void trim_results(Server* s) {
-  std::lock_guard<std::mutex> lk(s->mu);
-  for (ResultBuf& rb : s->results)
-    if (!rb.busy && rb.p) {
-      (void)hipFree(rb.p);
-      rb.p = nullptr;
-      rb.elems = 0;
-    }
+  std::vector<void*> idle;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (ResultBuf& rb : s->results)
+      if (!rb.busy && rb.p) {
+        idle.push_back(rb.p);
+        rb.p = nullptr;
+        rb.elems = 0;
+      }
+  }
+  for (void* p : idle) (void)hipFree(p);   // outside the lock: a poll need not wait for the device
 }
 
 // A pool buffer of at least 2 x elems doubles for a finishing request: the
