@@ -152,6 +152,8 @@ typedef struct {
                      (combined) dose; NaN when sigma was not requested */
   double t_round_s;            /* summed durations of the persistent round kernels */
   uint64_t n_round_launches;   /* (tuning persistent), bracketed like the passes */
+  uint64_t n_photon_interactions;   /* photon flights (of n_photon_events) that ended in a real
+                                       Compton, photoelectric or pair interaction */
 } gmc_run_stats;
 
 /* Optional tuning of the engine.  A field <= 0 selects its default; a NULL

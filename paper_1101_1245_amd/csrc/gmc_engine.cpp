@@ -1073,6 +1073,7 @@ int stats_from_counters(Workspace* w, const unsigned long long* slots, gmc_run_s
     stats->n_hist = n_hist;
     stats->n_photon_events = ctr[C_PH_EVENTS];
     stats->n_fictitious = ctr[C_FICT];
+    stats->n_photon_interactions = ctr[C_PH_REAL];
     stats->n_e_steps = ctr[C_E_STEPS];
     stats->n_hard = ctr[C_HARD];
     stats->n_secondaries = ctr[C_SEC];

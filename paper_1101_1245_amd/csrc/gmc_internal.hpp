@@ -118,7 +118,7 @@ struct DevSource {
 // sums the slots.  C_E_DEP is the deposited total summed by the finalize.
 enum CounterIndex {
   C_E_IN = 0, C_E_ESC, C_E_SINK, C_PH_EVENTS, C_FICT, C_VIOL, C_E_STEPS, C_HARD, C_SEC, C_OVERFLOW, C_E_DEP,
-  C_COUNT
+  C_PH_REAL, C_COUNT
 };
 constexpr int kCtrSlots = 256;
 

@@ -579,17 +579,20 @@ __device__ __forceinline__ void push_electrons(const Lane& L, const PassArgs& a,
 struct WaveTotals {
   unsigned long long esc = 0, sink = 0;
   uint32_t ev = 0, fict = 0, viol = 0, sec = 0, steps = 0, hard = 0;
+  uint32_t real = 0;   // photon flights that end in a real interaction
 };
 
 __device__ __forceinline__ void add_totals(const WaveTotals& t, unsigned long long* ctr) {
   const unsigned long long s_esc = wave_sum(t.esc), s_sink = wave_sum(t.sink);
   const unsigned long long s_ev = wave_sum(t.ev), s_fict = wave_sum(t.fict), s_viol = wave_sum(t.viol),
-                           s_sec = wave_sum(t.sec), s_steps = wave_sum(t.steps), s_hard = wave_sum(t.hard);
+                           s_sec = wave_sum(t.sec), s_steps = wave_sum(t.steps), s_hard = wave_sum(t.hard),
+                           s_real = wave_sum(t.real);
   if (lane_id() == 0) {
     if (s_esc) ctr_add(ctr, C_E_ESC, s_esc);
     if (s_sink) ctr_add(ctr, C_E_SINK, s_sink);
     if (s_ev) ctr_add(ctr, C_PH_EVENTS, s_ev);
     if (s_fict) ctr_add(ctr, C_FICT, s_fict);
+    if (s_real) ctr_add(ctr, C_PH_REAL, s_real);
     if (s_viol) ctr_add(ctr, C_VIOL, s_viol);
     if (s_sec) ctr_add(ctr, C_SEC, s_sec);
     if (s_steps) ctr_add(ctr, C_E_STEPS, s_steps);
@@ -630,6 +633,7 @@ __device__ void photon_loop(const PassArgs& a, uint32_t admitting, R& range, Wav
       int v0 = 0;
       kind = photon_flight(L, a, tab, majg, v0, tot.viol);
       ++tot.ev;
+      if (kind >= PH_COMPTON) ++tot.real;
       if (kind == PH_ESCAPE) {
         tot.esc += L.e;
         have = false;

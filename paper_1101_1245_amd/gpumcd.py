@@ -60,7 +60,7 @@ class gmc_run_stats(C.Structure):
                 ("ledger_residual_lsb", C.c_int64), ("t_photon_pass_s", C.c_double),
                 ("t_electron_pass_s", C.c_double), ("n_photon_launches", C.c_uint64),
                 ("n_electron_launches", C.c_uint64), ("s_rel", C.c_double), ("t_round_s", C.c_double),
-                ("n_round_launches", C.c_uint64)]
+                ("n_round_launches", C.c_uint64), ("n_photon_interactions", C.c_uint64)]
 
 
 class gmc_tuning(C.Structure):

@@ -20,11 +20,11 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-def _acc(t_ph, t_e, n_ph, n_e, events, steps, t_round=0.0, n_round=0):
+def _acc(t_ph, t_e, n_ph, n_e, events, steps, t_round=0.0, n_round=0, interactions=0):
     a = bench.Acc()
     a.add({"t_photon_pass_s": t_ph, "t_electron_pass_s": t_e, "n_photon_launches": n_ph, "n_electron_launches": n_e,
            "t_round_s": t_round, "n_round_launches": n_round, "n_e_steps": steps, "n_photon_events": events,
-           "ledger_residual_lsb": 0, "n_hist": 1})
+           "n_photon_interactions": interactions, "ledger_residual_lsb": 0, "n_hist": 1})
     return a
 
 
@@ -38,9 +38,11 @@ def test_roofline_of_the_dominant_kernel():
     assert r["frac"] == pytest.approx(r["achieved"] / r["peak"])
     assert r["traffic"] is None          # only the water workload carries the measured bytes
     assert r["k_photon_pass"]["achieved"] == pytest.approx(2e8 * bench.OPS_PER_PH_EVENT / 0.005 / 1e12)
-    # photon pass dominant
-    r = bench.roofline(_acc(0.030, 0.020, 10, 10, 2e8, 1e8), "x")
+    # photon pass dominant: flights plus real interactions
+    r = bench.roofline(_acc(0.030, 0.020, 10, 10, 2e8, 1e8, interactions=5e7), "x")
     assert r["kernel"] == "k_photon_pass"
+    assert r["achieved"] == pytest.approx((2e8 * bench.OPS_PER_PH_EVENT + 5e7 * bench.OPS_PER_PH_INTERACTION)
+                                          / 10 / 3e-3 / 1e12)
     # the persistent round kernel, when it holds most of the time, counts both types' work
     r = bench.roofline(_acc(0.001, 0.001, 1, 1, 2e8, 1e8, t_round=0.05, n_round=5), "x")
     assert r["kernel"] == "k_round"

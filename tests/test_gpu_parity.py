@@ -142,6 +142,12 @@ def test_first_collision_mode_matches_oracle(ctx, oracle, G):
     w.source = I.centred(w.phantom, I.Source(I.PHOTON, e=6.0, wx=2.0, wy=2.0))
     d, s, st = G.run_workload(ctx, w)
     assert st["ledger_residual_lsb"] == 0
+    # each 6 MeV photon either escapes (6 MeV to the escape ledger) or ends in
+    # exactly one real interaction
+    escaped = st["e_esc_mev"] / 6.0
+    assert escaped == pytest.approx(round(escaped), abs=1e-6)
+    assert st["n_photon_interactions"] + round(escaped) == w.n_hist
+    assert st["n_photon_interactions"] == st["n_photon_events"] - st["n_fictitious"] - round(escaped)
     res = oracle.run_parallel(w.materials, w.phantom, w.source, w.physics, w.seed, w.n_hist)
     do, so = oracle.dose(res, w.phantom)
     # depth profile of energy: binomial counts of first interactions
@@ -187,6 +193,7 @@ def test_small_photon_water_ledger_and_counters(small_photon):
     assert st["ledger_residual_lsb"] == 0
     assert st["e_in_mev"] == pytest.approx(res.stats["e_in"], rel=1e-6)
     assert st["n_majorant_violations"] == 0
+    assert 0 < st["n_photon_interactions"] <= st["n_photon_events"] - st["n_fictitious"]
     # event counts per history agree statistically with the oracle
     for k in ("n_photon_events", "n_e_steps", "n_secondaries"):
         a, b = st[k], res.stats[k]
