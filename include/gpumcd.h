@@ -205,9 +205,11 @@ typedef struct {
  *     electron pass and a photon pass: its wavefronts claim chunks of
  *     wave_items particles from a device work queue -- the round's
  *     electrons first, then its photons (the round's new primaries come last
- *     in each queue) -- from counters spread over eight partitions of each
- *     queue, each wavefront up to a cap (an even share plus one chunk) that
- *     bounds its staging, and no wavefront waits for another; every
+ *     in each queue) -- each workgroup from a partition of the queue with a
+ *     counter of its own, then from other partitions once its own is used up,
+ *     each wavefront up to a cap (an even share plus one chunk) that bounds
+ *     its staging, and no wavefront waits for another; workgroups of at most
+ *     512 threads (wg_size is clamped to 512 for it); every
  *     workgroup holds both table blocks in LDS, so jobs with more than four
  *     materials run the passes instead (default 0; energy_sort is ignored
  *     with it);
