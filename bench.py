@@ -637,7 +637,7 @@ def bench_atomics(args, G):
     1, 64 and 4096 words (the library's own microbenchmark kernel)."""
     ctx = G.Context(0)
     sizes = {}
-    for lg in (15, 18, 21, 23, 25, 27):
+    for lg in (15, 18, 21, 23, 25, 27, 29, 31):
         rate = max(ctx.atomic_rate(lg) for _ in range(max(args.steps, 1)))
         sizes["%.3g MB" % ((1 << lg) * 8 / 1e6)] = rate
         print("random atomics into %8.3g MB: %.3e /s" % ((1 << lg) * 8 / 1e6, rate), file=sys.stderr, flush=True)
@@ -660,7 +660,7 @@ def bench_atomics(args, G):
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "2^20 lanes x 64 atomic adds of 1 into uint64 arrays of 2^15..2^27 words at hashed "
+        "config": {"workload": "2^20 lanes x 64 atomic adds of 1 into uint64 arrays of 2^15..2^31 words at hashed "
                                "addresses, and into hot sets of 1 / 64 / 4096 words; best of --steps launches"},
         "random_by_array_size": sizes,
         "hot_set": hot,

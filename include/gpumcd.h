@@ -424,7 +424,7 @@ int gmc_first_events(gmc_context* ctx, int32_t phantom_id, int32_t tables_id, co
 
 /* Measure the device's 64-bit atomic-add rate, the second roof of the
  * tally path: 2^20 lanes each add 1 to 64 words of an array of
- * 2^log2_words uint64 words (10..27), at hashed addresses (hot = 0) or on
+ * 2^log2_words uint64 words (10..31, up to 16 GiB), at hashed addresses (hot = 0) or on
  * word t mod hot of the first hot words (hot a power of two, at most the
  * array's size), with the instruction the tallies use; timed with HIP events
  * after a warm-up launch.  *adds_per_s receives the additions per second.

@@ -342,7 +342,7 @@ int gmc_autotune(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gm
 int gmc_atomic_rate(gmc_context* c, int log2_words, int hot, double* adds_per_s) {
   if (!c) return GMC_EINVAL;
   if (!adds_per_s) return cfail(c, GMC_EINVAL, "output pointer is NULL");
-  if (log2_words < 10 || log2_words > 27) return cfail(c, GMC_EINVAL, "log2_words must be in [10, 27]");
+  if (log2_words < 10 || log2_words > 31) return cfail(c, GMC_EINVAL, "log2_words must be in [10, 31]");
   const uint64_t words = 1ull << log2_words;
   if (hot < 0 || (hot > 0 && ((hot & (hot - 1)) != 0 || (uint64_t)hot > words)))
     return cfail(c, GMC_EINVAL, "hot must be 0 or a power of two no larger than the array");

@@ -375,7 +375,7 @@ def test_atomic_rate_microbenchmark(ctx, G):
     spread = ctx.atomic_rate(20)
     one = ctx.atomic_rate(12, 1)
     assert spread > 1e9 and one > 0 and spread > 10 * one, (spread, one)
-    for bad in ((9, 0), (28, 0), (12, 3), (10, 2048), (12, -1)):
+    for bad in ((9, 0), (32, 0), (12, 3), (10, 2048), (12, -1)):
         with pytest.raises(G.GpumcdError) as e:
             ctx.atomic_rate(*bad)
         assert e.value.code == G.GMC_EINVAL
