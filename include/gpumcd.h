@@ -149,7 +149,8 @@ typedef struct {
   double t_photon_pass_s, t_electron_pass_s;
   uint64_t n_photon_launches, n_electron_launches;
   double s_rel;   /* Eq. 12: mean sigma/D over voxels with D > 0.2 D_max of the
-                     (combined) dose; NaN when sigma was not requested */
+                     (combined) dose; NaN when sigma was not requested or
+                     nothing was deposited */
   double t_round_s;            /* summed durations of the persistent round kernels */
   uint64_t n_round_launches;   /* (tuning persistent), bracketed like the passes */
   uint64_t n_photon_interactions;   /* photon flights (of n_photon_events) that ended in a real
