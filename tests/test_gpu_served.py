@@ -13,7 +13,10 @@ Bars:
 * served requests of the request stream's kind -- an ellipsoid phantom with
   four materials, triangular 2-10-18 MeV photon and electron beams --
   submitted together with others agree with the FP64 oracle: per-voxel
-  z-tests on the same and on independent streams, event counts.
+  z-tests on the same and on independent streams, event counts;
+* a request on the largest grid of the request stream (256^3 voxels) served
+  beside a small one equals the plain form bit for bit and agrees with the
+  oracle on the same histories.
 """
 import numpy as np
 import pytest
@@ -198,3 +201,51 @@ def test_served_triangular_requests_match_oracle(ctx, oracle, batched_run):
                       batches=(bg, oracle_batches(r2, ph, n)))
         print("served triangular, independent: z-test %s" % E.describe(zi))
         assert zi.passed, E.describe(zi)
+
+
+def test_largest_grid_request_matches_plain_and_oracle(ctx, oracle):
+    """A request on the request stream's largest grid, 256^3 voxels of
+    0.25 cm (16.8M voxels, 4.3 GB of batch tallies), served beside a small
+    one: bit-identical to the plain form, the ledger exact, and the dose in
+    agreement with the FP64 oracle on the same histories."""
+    big = I.ellipsoids(256, 0.25, seed=31)
+    small = I.ellipsoids(32, 0.5, seed=32)
+    phys = I.serving_physics()
+    src = I.centred(big, I.Source(I.PHOTON, I.TRIANGULAR, 10.0, e_lo=2.0, e_mode=10.0, e_hi=18.0, wx=10.0, wy=10.0,
+                                  beam_id=6))
+    src_small = I.centred(small, I.Source(I.ELECTRON, I.MONO, 8.0, wx=4.0, wy=4.0, beam_id=7))
+    n = 1_000_000
+    print("\n256^3 request, n=%d" % n, flush=True)
+    tid = ctx.load_tables(I.DEFAULT_MATERIALS, phys)
+    pid = ctx.load_phantom(big)
+    pid_s = ctx.load_phantom(small)
+    try:
+        ctx.server_start(max_slots=2)
+        try:
+            t_big = ctx.submit(pid, tid, src, n, 17)
+            t_small = ctx.submit(pid_s, tid, src_small, 50_000, 18)
+            done, d, s, st = ctx.poll(t_big, big.shape, wait=True)
+            done_s, d_s, s_s, _ = ctx.poll(t_small, small.shape, wait=True)
+        finally:
+            ctx.server_stop()
+        assert done and done_s
+        da, sa, _ = ctx.run_beam(pid, tid, src, n, 17)
+        ref, _, _ = ctx.run_beam(pid, tid, src, n, 117)        # voxel mask only
+        ds, ss, _ = ctx.run_beam(pid_s, tid, src_small, 50_000, 18)
+    finally:
+        ctx.release(pid)
+        ctx.release(pid_s)
+        ctx.release(tid)
+    assert np.array_equal(d, da) and np.array_equal(s, sa)
+    assert np.array_equal(d_s, ds) and np.array_equal(s_s, ss)
+    assert st["ledger_residual_lsb"] == 0 and st["n_majorant_violations"] == 0
+    res = oracle.run_parallel(I.DEFAULT_MATERIALS, big, src, phys, 17, n, batches=False)
+    assert st["e_in_mev"] == pytest.approx(res.stats["e_in"], rel=1e-6)
+    do, so = oracle.dose(res, big)
+    zt = E.z_test(d, s, do, so, ref_for_mask=ref, dof=phys.n_batches - 1, same_streams=True)
+    p = E.precision_error(d, do)
+    print("256^3 served request, same histories: z-test %s; summed dose %+.2e, voxel |diff| max %.2e of D_max"
+          % (E.describe(zt), p.sum_rel, p.max_abs))
+    assert zt.passed, E.describe(zt)
+    for k in ("n_e_steps", "n_photon_events", "n_secondaries"):
+        assert abs(st[k] - res.stats[k]) < 2e-3 * res.stats[k] + 10, (k, st[k], res.stats[k])
