@@ -10,7 +10,6 @@ import json
 import os
 
 import numpy as np
-import pytest
 from scipy import stats
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_kat.json")
