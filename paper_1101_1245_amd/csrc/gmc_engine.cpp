@@ -504,12 +504,13 @@ int get_majorants(gmc_context* c, int32_t pid, int32_t tid, const PhantomObj& p,
 
 // ---------------------------------------------------------------------- jobs
 size_t job_tally_elems(TallyMode mode, size_t nvox, uint32_t K, size_t n_beams) {
-  return mode == kCombined ? nvox * K : mode == kBeamBatched ? nvox * K * n_beams : nvox * (K + n_beams);
+  const size_t nvp = tally_vox(nvox);
+  return mode == kCombined ? nvp * K : mode == kBeamBatched ? nvp * K * n_beams : nvp * (K + n_beams);
 }
 
 void build_job(Job* J, Workspace* w, const PhantomObj& P, const TablesObj& T, const MajObj& maj,
                const gmc_source* srcs, const uint64_t* n_hist, int n_beams, uint64_t seed, TallyMode mode) {
-  const size_t nvox = P.nvox();
+  const size_t nvp = tally_vox(P.nvox());   // voxels of a tally target, padded to whole blocks
   const uint32_t K = (uint32_t)T.phys.n_batches;
   J->P = &P;
   J->T = &T;
@@ -530,9 +531,9 @@ void build_job(Job* J, Workspace* w, const PhantomObj& P, const TablesObj& T, co
     if (mode == kCombined) {
       db.a = DevTally{w->d_tally, K, off};
     } else if (mode == kBeamBatched) {
-      db.a = DevTally{w->d_tally + nvox * K * (size_t)b, K, 0u};
+      db.a = DevTally{w->d_tally + nvp * K * (size_t)b, K, 0u};
     } else {
-      db.a = DevTally{w->d_tally + nvox * ((size_t)K + (size_t)b), 1u, 0u};
+      db.a = DevTally{w->d_tally + nvp * ((size_t)K + (size_t)b), 1u, 0u};
       db.b = DevTally{w->d_tally, K, off};
     }
     J->beams.push_back(db);
@@ -850,6 +851,13 @@ int engine_setup(Workspace* w, Engine& E, const Job& J, const Tune& tu) {
   bool single = true;   // every beam's own tally is one slice
   for (const DevBeam& b : J.beams) single &= b.a.K == 1u;
   E.proto.agg_a = tu.aggregate > 0 || (tu.aggregate == 0 && single) ? 1 : 0;
+  // batches of the tally targets (their blocked layout's line count per
+  // voxel block): the same for every beam of a job
+  const uint32_t ka = J.beams.empty() ? 1u : J.beams[0].a.K, kb = J.beams.empty() ? 1u : J.beams[0].b.K;
+  for (const DevBeam& b : J.beams)
+    if (b.a.K != ka || b.b.K != kb) return wfail(w, GMC_EINTERNAL, "tally targets of one job differ in batches");
+  E.proto.ka = ka;
+  E.proto.kb = kb;
   for (int t = 0; t < 2; ++t) {
     AdmitArgs& a = E.adm[t];
     a = AdmitArgs{};
@@ -864,6 +872,8 @@ int engine_setup(Workspace* w, Engine& E, const Job& J, const Tune& tu) {
     a.sources = w->d_sources;
     a.ctr = w->d_ctr;
     a.nvox = (uint32_t)J.P->nvox();
+    a.ka = ka;
+    a.kb = kb;
   }
   E.round = uses_round(tu, n_mat);
   if (E.round) {
@@ -1022,7 +1032,7 @@ double dose_per_lsb(const PhantomObj& P) { return kLsbMeV * 1.602176634e-13 / (P
 
 int finalize(Workspace* w, const PhantomObj& P, const unsigned long long* tally, uint32_t nsum, size_t stride,
              uint32_t K, const std::vector<double>& nk, uint64_t n, double* d_dose, double* d_sigma, bool ledger,
-             bool sync) {
+             bool sync, bool blocked) {
   if (sync) {
     WS_TRY(w, hipMemcpyAsync(w->d_nk, nk.data(), K * sizeof(double), hipMemcpyHostToDevice, w->stream));
   } else {
@@ -1042,6 +1052,7 @@ int finalize(Workspace* w, const PhantomObj& P, const unsigned long long* tally,
   fa.dose = d_dose;
   fa.sigma = d_sigma;
   fa.ctr = ledger ? w->d_ctr : nullptr;
+  fa.blocked = blocked ? 1u : 0u;
   WS_TRY(w, launch_finalize(fa, w->stream));
   // the job's s (Eq. 12) with its combined result, read with the counters
   if (ledger) {
@@ -1189,7 +1200,7 @@ int run_job_ws(gmc_context* c, Workspace* w, int32_t phantom_id, int32_t tables_
   if (batched && (dose_per_beam || sigma_per_beam)) {
     size_t free_b = 0, total_b = 0;
     (void)hipMemGetInfo(&free_b, &total_b);
-    const double need = (double)NB * K * nvox * sizeof(unsigned long long);
+    const double need = (double)NB * K * tally_vox(nvox) * sizeof(unsigned long long);
     const double room = 0.5 * ((double)free_b + (double)w->tally_elems * sizeof(unsigned long long));
     mode = (n_min >= K && need <= room) ? kBeamBatched : kBeamPlusComb;
     if (sigma_per_beam && mode != kBeamBatched)
@@ -1232,7 +1243,7 @@ int run_job_ws(gmc_context* c, Workspace* w, int32_t phantom_id, int32_t tables_
   double* d_out = out_kind == GMC_DEVICE && dose ? dose : w->d_dose;
   double* s_out = sigma ? (out_kind == GMC_DEVICE ? sigma : w->d_sigma) : nullptr;
   rc = mode == kBeamBatched
-           ? finalize(w, P, w->d_tally, (uint32_t)NB, nvox * K, K, nk, n_total, d_out, s_out, true, true)
+           ? finalize(w, P, w->d_tally, (uint32_t)NB, tally_vox(nvox) * K, K, nk, n_total, d_out, s_out, true, true)
            : finalize(w, P, w->d_tally, 1u, 0u, K, nk, n_total, d_out, s_out, true, true);
   if (rc) return rc;
   if (out_kind == GMC_HOST) {
@@ -1240,9 +1251,21 @@ int run_job_ws(gmc_context* c, Workspace* w, int32_t phantom_id, int32_t tables_
     if (rc == GMC_OK && sigma) rc = copy_out(w, sigma, w->d_sigma, nvox);
     if (rc) return rc;
   }
-  if (tally_out)
-    WS_TRY(w, hipMemcpyAsync(tally_out, w->d_tally, nvox * K * sizeof(unsigned long long),
-                             tally_kind == GMC_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, w->stream));
+  if (tally_out) {
+    // the raw tally in the ABI's slice-major layout (staged on the device for a host buffer)
+    const size_t bytes = nvox * K * sizeof(unsigned long long);
+    unsigned long long* tmp = nullptr;
+    if (tally_kind == GMC_HOST && hipMalloc(&tmp, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return wfail(w, GMC_ENOMEM, "staging buffer for the raw tally");
+    }
+    unsigned long long* dst = tmp ? tmp : reinterpret_cast<unsigned long long*>(tally_out);
+    hipError_t e = launch_tally_to_slices(w->d_tally, dst, (uint32_t)nvox, K, w->stream);
+    if (e == hipSuccess && tmp) e = hipMemcpyAsync(tally_out, tmp, bytes, hipMemcpyDeviceToHost, w->stream);
+    if (e == hipSuccess && tmp) e = hipStreamSynchronize(w->stream);
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) return wfail(w, GMC_EDEVICE, std::string("raw tally copy: ") + hipGetErrorString(e));
+  }
   // per-beam results
   if (mode != kCombined) {
     for (int b = 0; b < n_beams; ++b) {
@@ -1254,7 +1277,7 @@ int run_job_ws(gmc_context* c, Workspace* w, int32_t phantom_id, int32_t tables_
       double* ds = want_s ? (out_kind == GMC_DEVICE ? want_s : w->d_sigma) : nullptr;
       const uint32_t kb = mode == kBeamBatched ? K : 1u;
       const unsigned long long* tb =
-          w->d_tally + (mode == kBeamBatched ? nvox * K * (size_t)b : nvox * ((size_t)K + (size_t)b));
+          w->d_tally + (mode == kBeamBatched ? tally_vox(nvox) * K * (size_t)b : tally_vox(nvox) * ((size_t)K + (size_t)b));
       std::vector<double> nkb;
       add_batch_sizes(nkb, srcs[b].first_history, n_hist[b], kb);
       rc = finalize(w, P, tb, 1u, 0u, kb, nkb, n_hist[b], dd, ds, false, true);

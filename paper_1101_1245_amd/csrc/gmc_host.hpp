@@ -259,9 +259,11 @@ double dose_per_lsb(const PhantomObj& P);
 // Dose and sigma of `nsum` tallies ([K][nvox] each, `stride` apart, added).
 // With sync false the batch sizes go through the pinned w->h_nk and the
 // call does not wait (one finalize in flight per workspace).
+// `blocked`: the tally is in the library's blocked layout (else slice-major,
+// as the C ABI's raw tallies are).
 int finalize(Workspace* w, const PhantomObj& P, const unsigned long long* tally, uint32_t nsum, size_t stride,
              uint32_t K, const std::vector<double>& nk, uint64_t n, double* d_dose, double* d_sigma, bool ledger,
-             bool sync);
+             bool sync, bool blocked = true);
 // Counters -> stats (from the pinned copy when `pinned`), ledger check.
 int stats_from_counters(Workspace* w, const unsigned long long* slots, gmc_run_stats* stats, uint64_t n_hist,
                         uint64_t rounds, double t_total_s, double t_device_s);

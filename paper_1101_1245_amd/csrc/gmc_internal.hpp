@@ -26,6 +26,16 @@ constexpr double kEmin = 1.0e-3;        // MeV
 constexpr double kEmax = 32.0;          // MeV (the fixed-point energy range)
 constexpr int kNms = 512;               // nodes of the multiple-scattering screening table
 constexpr int kMaxMat = 8;
+// Tally layout inside the library: voxels in blocks of kTallyBlock, each
+// batch's sums of a block on one 128-byte line, and the block's K lines
+// adjacent -- the sum of batch k in voxel v at
+// (v / kTallyBlock) kTallyBlock K + k kTallyBlock + v mod kTallyBlock, over
+// tally_vox(nvox) voxels (the last block padded).  Batches never share a
+// line, so the additions of a narrow beam's histories to its few voxels do
+// not contend for one, and a voxel's batches stay within a few kilobytes.
+// The raw tallies of the C ABI are slice-major ([K][nvox]) instead.
+constexpr uint32_t kTallyBlock = 16;
+inline size_t tally_vox(size_t nvox) { return (nvox + kTallyBlock - 1) / kTallyBlock * kTallyBlock; }
 constexpr int kMaxBatches = 1024;
 constexpr double kLsbMeV = 1.0 / 134217728.0;   // 2^-27 MeV per energy unit
 
@@ -84,6 +94,8 @@ struct DevQueue {
 // base + ((off + h) mod K) * nvox; base null: no target.  Interleaved batches
 // keep every run of consecutive histories spread over all K slices, so lanes
 // working on neighbouring histories rarely add to the same address.
+// A tally target: K batch sums per voxel in the blocked layout above, from
+// base.  History h goes to batch (off + h) mod K.
 struct DevTally {
   unsigned long long* base;
   uint32_t K, off;
@@ -193,6 +205,7 @@ struct PassArgs {
   int tail_lanes;            // requeue the lanes' particles once the share is done and at most this many remain
   uint32_t tail_min;         // ... for shares of at least this many particles
   int agg_a;                 // electron pass: tally-a additions of a loop iteration aggregated per address
+  uint32_t ka, kb;           // batches of the beams' tally targets a and b, the same for every beam
 };
 
 // The persistent round kernel: one launch per round transports the
@@ -256,6 +269,7 @@ struct AdmitArgs {
   const DevSource* sources;     // indexed by beam
   unsigned long long* ctr;
   uint32_t nvox;
+  uint32_t ka, kb;              // as in PassArgs
 };
 
 // Energy regrouping of a work queue before its pass (the grouping of
@@ -274,7 +288,7 @@ struct SortArgs {
 };
 
 struct FinalizeArgs {
-  const unsigned long long* tally;  // [nsum][K][nvox] (the nsum tallies are added)
+  const unsigned long long* tally;  // nsum tallies sum_stride apart (added), each blocked or [K][nvox]
   uint32_t nsum;
   size_t sum_stride;                // elements between successive tallies
   const uint2* vox;
@@ -284,6 +298,7 @@ struct FinalizeArgs {
   double* dose;
   double* sigma;                    // may be null
   unsigned long long* ctr;          // [C_COUNT][kCtrSlots], gets C_E_DEP (may be null)
+  uint32_t blocked;                 // 1: the library's blocked layout; 0: slice-major [K][nvox]
 };
 
 // Launchers (gmc_kernels.hip).
@@ -299,6 +314,9 @@ hipError_t launch_electron_pass(const PassArgs& a, int grid, int block, hipStrea
 hipError_t launch_admit_plan(const AdmitPlanArgs& a, hipStream_t s);
 hipError_t launch_admit(const AdmitArgs& a, uint32_t max_count, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
+// A blocked tally (nvox voxels, K batches) rewritten slice-major, [K][nvox].
+hipError_t launch_tally_to_slices(const unsigned long long* blocked, unsigned long long* slices, uint32_t nvox,
+                                  uint32_t K, hipStream_t s);
 hipError_t launch_rng_words(uint32_t key0, uint32_t key1, uint32_t hist, uint32_t plo, uint32_t phi, uint32_t n0,
                             int count, uint32_t* out, hipStream_t s);
 hipError_t launch_table_eval(const DevTables& t, int which, int mat, const float* e, int n, float* out,

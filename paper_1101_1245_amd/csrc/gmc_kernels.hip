@@ -16,6 +16,7 @@
 // Deposits are uint64 fixed-point atomics, so the dose is an exact integer
 // sum independent of thread order.  Cross-section and stopping-power tables
 // are staged in LDS by every workgroup.
+#include <algorithm>
 #include <mutex>
 
 #include "gmc_device.hpp"
@@ -63,11 +64,15 @@ __device__ __forceinline__ Primary sample_primary(const DevSource& a, const DevB
   return p;
 }
 
-// Batch slice of a tally target for history h.
-__device__ __forceinline__ unsigned long long* tally_slice(const DevTally& t, uint32_t h, uint32_t nvox) {
+// History h's batch of a tally target: the sum of that batch in voxel v is
+// at the returned pointer + vox_off(v, K) (the blocked layout).
+__device__ __forceinline__ unsigned long long* tally_slice(const DevTally& t, uint32_t h) {
   if (!t.base) return nullptr;
   const uint32_t k = (t.off + h) % t.K;
-  return t.base + (size_t)k * nvox;
+  return t.base + (size_t)k * kTallyBlock;
+}
+__device__ __forceinline__ size_t vox_off(uint32_t v, uint32_t K) {
+  return (size_t)(v / kTallyBlock) * kTallyBlock * K + (v % kTallyBlock);
 }
 
 // Tally addition through the global address space: the tally pointers come
@@ -135,10 +140,10 @@ __global__ void __launch_bounds__(256) k_admit(AdmitArgs a) {
     int ix, iy, iz;
     const int v = voxel(a.ph, p.x, p.y, 0.0f, ix, iy, iz);
     const DevBeam b = a.beams[beam];
-    unsigned long long* ta = tally_slice(b.a, h, a.nvox);
-    unsigned long long* tb = tally_slice(b.b, h, a.nvox);
-    if (ta && p.e) tally_add(ta + v, (unsigned long long)p.e);
-    if (tb && p.e) tally_add(tb + v, (unsigned long long)p.e);
+    unsigned long long* ta = tally_slice(b.a, h);
+    unsigned long long* tb = tally_slice(b.b, h);
+    if (ta && p.e) tally_add(ta + vox_off((uint32_t)v, a.ka), (unsigned long long)p.e);
+    if (tb && p.e) tally_add(tb + vox_off((uint32_t)v, a.kb), (unsigned long long)p.e);
   }
   if (valid) {
     const uint32_t slot = pl.base + i;
@@ -192,8 +197,8 @@ __device__ __forceinline__ void load_lane(Lane& L, const DevQueue& q, uint32_t i
   const DevBeam b = a.n_beams <= kLdsBeams ? read_beam((lds_beam*)lbeams + L.beam)
                                            : read_beam((global_beam*)a.beams + L.beam);
   L.s.k0 = b.key0; L.s.k1 = b.key1;
-  L.ta = tally_slice(b.a, L.s.hist, nvox);
-  L.tb = tally_slice(b.b, L.s.hist, nvox);
+  L.ta = tally_slice(b.a, L.s.hist);
+  L.tb = tally_slice(b.b, L.s.hist);
 }
 
 __device__ __forceinline__ void store_lane(const Lane& L, const DevQueue& q, uint32_t slot) {
@@ -356,10 +361,10 @@ __device__ __forceinline__ bool seg_ok(const WaveSeg& g, uint32_t slot, unsigned
   return false;
 }
 
-__device__ __forceinline__ void deposit(const Lane& L, int v, uint32_t e) {
+__device__ __forceinline__ void deposit(const Lane& L, const PassArgs& a, int v, uint32_t e) {
   if (!e) return;
-  tally_add(L.ta + v, (unsigned long long)e);
-  if (L.tb) tally_add(L.tb + v, (unsigned long long)e);
+  tally_add(L.ta + vox_off((uint32_t)v, a.ka), (unsigned long long)e);
+  if (L.tb) tally_add(L.tb + vox_off((uint32_t)v, a.kb), (unsigned long long)e);
 }
 
 // An electron usually takes several steps in one voxel (a boundary-limited
@@ -385,14 +390,14 @@ struct Deferred {
   uint32_t e = 0;
 };
 
-__device__ __forceinline__ void flush(const Lane& L, Pending& p, Deferred& d, bool agg) {
+__device__ __forceinline__ void flush(const Lane& L, const PassArgs& a, Pending& p, Deferred& d, bool agg) {
   if (p.e) {
     if (!agg) {
-      deposit(L, p.v, p.e);
+      deposit(L, a, p.v, p.e);
     } else {
-      if (L.tb) tally_add(L.tb + p.v, (unsigned long long)p.e);
+      if (L.tb) tally_add(L.tb + vox_off((uint32_t)p.v, a.kb), (unsigned long long)p.e);
       if (d.e) tally_add(d.addr, (unsigned long long)d.e);   // a second one in the same iteration
-      d.addr = L.ta + p.v;
+      d.addr = L.ta + vox_off((uint32_t)p.v, a.ka);
       d.e = p.e;
     }
   }
@@ -400,10 +405,11 @@ __device__ __forceinline__ void flush(const Lane& L, Pending& p, Deferred& d, bo
   p.v = -1;
 }
 
-__device__ __forceinline__ void deposit_later(const Lane& L, Pending& p, int v, uint32_t e, Deferred& d, bool agg) {
+__device__ __forceinline__ void deposit_later(const Lane& L, const PassArgs& a, Pending& p, int v, uint32_t e,
+                                              Deferred& d, bool agg) {
   if (!e) return;
   if (v != p.v) {
-    flush(L, p, d, agg);
+    flush(L, a, p, d, agg);
     p.v = v;
   }
   p.e += e;
@@ -520,7 +526,7 @@ __device__ __forceinline__ void absorb_photon(Lane& L, const PassArgs& a, int ki
       child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
       nchild = 1;
     } else {
-      deposit(L, v0, L.e);
+      deposit(L, a, v0, L.e);
     }
     return;
   }
@@ -540,7 +546,7 @@ __device__ __forceinline__ void absorb_photon(Lane& L, const PassArgs& a, int ki
     child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
     nchild = 1;
   } else {
-    deposit(L, v0, t1);
+    deposit(L, a, v0, t1);
   }
   if (t2 >= a.cut.ecut_lsb) {
     c1.e = t2;
@@ -548,7 +554,7 @@ __device__ __forceinline__ void absorb_photon(Lane& L, const PassArgs& a, int ki
     if (nchild == 0) c0 = c1;   // keep the pushed children contiguous
     ++nchild;
   } else {
-    deposit(L, v0, t2);
+    deposit(L, a, v0, t2);
   }
 }
 
@@ -640,7 +646,7 @@ __device__ void photon_loop(const PassArgs& a, uint32_t admitting, R& range, Wav
       } else if (kind == PH_FICT) {
         ++tot.fict;
       } else if (a.cut.mode == 1) {
-        deposit(L, v0, L.e);
+        deposit(L, a, v0, L.e);
         have = false;
       } else if (kind == PH_COMPTON) {
         // scattered photon plus recoil electron (momentum conservation)
@@ -661,12 +667,12 @@ __device__ void photon_loop(const PassArgs& a, uint32_t admitting, R& range, Wav
           child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
           nchild = 1;
         } else {
-          deposit(L, v0, te);
+          deposit(L, a, v0, te);
         }
         L.u = nu; L.v = nv; L.w = nw;
         L.e = e1;
         if (e1 < a.cut.pcut_lsb) {
-          deposit(L, v0, e1);
+          deposit(L, a, v0, e1);
           have = false;
         }
       } else {
@@ -782,7 +788,7 @@ __device__ __forceinline__ bool hard_event(Lane& L, const PassArgs& a, const flo
       child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
       ctype = 1;
     } else {
-      deposit(L, v1, wl);
+      deposit(L, a, v1, wl);
     }
     L.e = tp;
   } else if (r < sm + sb) {
@@ -798,12 +804,12 @@ __device__ __forceinline__ bool hard_event(Lane& L, const PassArgs& a, const flo
       child_path(L.s.plo, L.s.phi, L.s.n, 0u, c0.plo, c0.phi);
       ctype = 0;
     } else {
-      deposit(L, v1, kl);
+      deposit(L, a, v1, kl);
     }
     L.e -= kl;
   }
   if (L.e < a.cut.ecut_lsb) {
-    deposit(L, v1, L.e);
+    deposit(L, a, v1, L.e);
     return false;
   }
   return true;
@@ -912,7 +918,7 @@ __device__ void electron_loop(const PassArgs& a, uint32_t admitting, R& range, W
     }
     // a resumed electron that ended at its hard event, or is requeued, adds
     // the pending deposit it brought back (idle lanes hold none)
-    if (!have) flush(L, pend, dfr, a.agg_a);
+    if (!have) flush(L, a, pend, dfr, a.agg_a);
     if (have) {
       L.s.align();
       int ix, iy, iz, v0;
@@ -924,7 +930,7 @@ __device__ void electron_loop(const PassArgs& a, uint32_t admitting, R& range, W
         const float rho0 = __uint_as_float(vx.x);
         const int base0 = (int)vx.y * kNE;
         if (L.e < a.cut.ecut_lsb) {
-          deposit_later(L, pend, v0, L.e, dfr, a.agg_a);
+          deposit_later(L, a, pend, v0, L.e, dfr, a.agg_a);
           have = false;
         } else {
           ++tot.steps;
@@ -952,7 +958,7 @@ __device__ void electron_loop(const PassArgs& a, uint32_t admitting, R& range, W
           L.z = fmaf(s1, L.w, L.z);
           const uint32_t dl = to_lsb(de);
           if (dl >= L.e || L.e - dl < a.cut.ecut_lsb) {
-            deposit_later(L, pend, v0, L.e, dfr, a.agg_a);
+            deposit_later(L, a, pend, v0, L.e, dfr, a.agg_a);
             have = false;
           } else {
             const uint32_t e1 = L.e - dl;
@@ -965,7 +971,7 @@ __device__ void electron_loop(const PassArgs& a, uint32_t admitting, R& range, W
               const float g1 = xx < 1e-3f ? xx * (1.0f - 0.5f * xx * (1.0f - xx * (1.0f / 3.0f))) : 1.0f - fexp(-xx);
               rotate_om(L.u, L.v, L.w, wentzel_om(a.tab, ms, g1, ua), kTwoPi * uphi);
             }
-            deposit_later(L, pend, v0, dl, dfr, a.agg_a);
+            deposit_later(L, a, pend, v0, dl, dfr, a.agg_a);
             L.e = e1;
             const float s2 = (1.0f - zeta) * es;
             L.x = fmaf(s2, L.u, L.x);
@@ -992,7 +998,7 @@ __device__ void electron_loop(const PassArgs& a, uint32_t admitting, R& range, W
       // before the lane takes another particle; a parked electron keeps its
       // pending deposit (pencil beams concentrate deposits on few voxels,
       // where every extra atomic costs)
-      if (!have && !park) flush(L, pend, dfr, a.agg_a);
+      if (!have && !park) flush(L, a, pend, dfr, a.agg_a);
     }
     {
       // survivors to the bottom of the electron staging segment, parked electrons onto its stack
@@ -1011,7 +1017,7 @@ __device__ void electron_loop(const PassArgs& a, uint32_t admitting, R& range, W
           pend = Pending{};
         } else {
           ctr_add(a.ctr, C_OVERFLOW, 1ull);
-          flush(L, pend, dfr, a.agg_a);
+          flush(L, a, pend, dfr, a.agg_a);
         }
       }
       npark += (uint32_t)__popcll(pm);
@@ -1129,7 +1135,8 @@ __global__ void __launch_bounds__(kRoundMaxBlock) k_round(RoundArgs r) {
 // Batch k of voxel v, summed over the nsum tallies being finalized together.
 __device__ __forceinline__ unsigned long long batch_total(const FinalizeArgs& a, uint32_t k, uint32_t v) {
   unsigned long long t = 0;
-  for (uint32_t j = 0; j < a.nsum; ++j) t += a.tally[(size_t)j * a.sum_stride + (size_t)k * a.nvox + v];
+  const size_t e = a.blocked ? vox_off(v, a.K) + (size_t)k * kTallyBlock : (size_t)k * a.nvox + v;
+  for (uint32_t j = 0; j < a.nsum; ++j) t += a.tally[(size_t)j * a.sum_stride + e];
   return t;
 }
 
@@ -1533,6 +1540,26 @@ hipError_t launch_electron_pass(const PassArgs& a, int grid, int block, hipStrea
   const hipError_t e = lds_limits();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_electron_pass, dim3(grid), dim3(block), lds, s, a);
+  return hipGetLastError();
+}
+
+// Thread i writes slice-major element i (batch i / nvox, voxel i mod nvox):
+// coalesced stores, reads one line per 16 threads.
+__global__ void __launch_bounds__(256) k_tally_to_slices(const unsigned long long* in, unsigned long long* out,
+                                                         uint32_t nvox, uint32_t K) {
+  const size_t n = (size_t)nvox * K;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t k = (uint32_t)(i / nvox), v = (uint32_t)(i % nvox);
+    out[i] = in[vox_off(v, K) + (size_t)k * kTallyBlock];
+  }
+}
+
+hipError_t launch_tally_to_slices(const unsigned long long* blocked, unsigned long long* slices, uint32_t nvox,
+                                  uint32_t K, hipStream_t s) {
+  const size_t n = (size_t)nvox * K;
+  if (n == 0) return hipSuccess;
+  const int grid = (int)std::min<size_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_tally_to_slices, dim3(grid), dim3(256), 0, s, blocked, slices, nvox, K);
   return hipGetLastError();
 }
 

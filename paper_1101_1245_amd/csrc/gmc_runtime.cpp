@@ -239,7 +239,7 @@ int gmc_finalize_tally(gmc_context* c, int32_t phantom_id, int32_t tables_id, co
   add_batch_sizes(nk, h_begin, h_end - h_begin, K);
   double* dd = out_kind == GMC_DEVICE ? dose : w->d_dose;
   double* ds = sigma ? (out_kind == GMC_DEVICE ? sigma : w->d_sigma) : nullptr;
-  rc = finalize(w, *pp, d_tally, 1u, 0u, K, nk, h_end - h_begin, dd, ds, true, true);
+  rc = finalize(w, *pp, d_tally, 1u, 0u, K, nk, h_end - h_begin, dd, ds, true, true, false);
   if (rc) return cfail(c, rc, w->err);
   if (out_kind == GMC_HOST) {
     hipError_t e = hipMemcpy(dose, w->d_dose, nvox * sizeof(double), hipMemcpyDeviceToHost);
@@ -291,6 +291,7 @@ int gmc_finalize_tally_noalloc(gmc_context* c, int32_t phantom_id, int32_t table
   fa.dose = dose;
   fa.sigma = sigma;
   fa.ctr = nullptr;
+  fa.blocked = 0u;   // the ABI's slice-major raw tallies
   if (e == hipSuccess) e = launch_finalize(fa, w->stream);
   w->h_srel[0] = std::numeric_limits<double>::quiet_NaN();
   if (e == hipSuccess && sigma && s_rel) {
@@ -454,6 +455,7 @@ int gmc_first_events(gmc_context* c, int32_t phantom_id, int32_t tables_id, cons
   beam.a = DevTally{nullptr, 1u, 0u};
   beam.b = DevTally{nullptr, 1u, 0u};
   PassArgs a{};
+  a.ka = a.kb = 1u;
   a.ph = dev_phantom(*pp);
   a.tab = dev_tables(*tp, maj);
   a.cut = dev_cuts(*tp);

@@ -230,7 +230,7 @@ int start(Server* s, Slot& sl) {
     if (hit != c->tuned.end()) tun = hit->second;
   }
   const Tune tu = resolve_tuning(&tun);
-  int rc = ws_ensure_tally(w, r.nvox * r.K);
+  int rc = ws_ensure_tally(w, tally_vox(r.nvox) * r.K);
   if (rc) return rc;
   MajObj maj;
   rc = get_majorants(c, r.pid, r.tid, *pp, *tp, &maj, &w->err);
@@ -240,7 +240,7 @@ int start(Server* s, Slot& sl) {
   sl.P = pp;
   sl.rounds = 0;
   WS_TRY(w, hipEventRecord(w->ev0, w->stream));
-  WS_TRY(w, launch_fill_u64(w->d_tally, r.nvox * r.K, 0ull, w->stream));
+  WS_TRY(w, launch_fill_u64(w->d_tally, tally_vox(r.nvox) * r.K, 0ull, w->stream));
   rc = engine_setup(w, sl.E, J, tu);
   if (rc == GMC_OK) rc = engine_capture(sl.E, &sl.exec, &sl.nr);
   if (rc) return rc;
@@ -490,7 +490,7 @@ int gmc_submit(gmc_context* c, int32_t phantom_id, int32_t tables_id, const gmc_
     if ((double)n_hist * (e_max * 134217728.0 + 1.0) >= 9.2e18)
       return cfail(c, GMC_EOVERFLOW, "histories x energy would overflow the 64-bit tallies");
     r->nvox = P.nvox();
-    r->need = s->slot_fixed + r->nvox * r->K * sizeof(unsigned long long) + 2 * r->nvox * sizeof(double);
+    r->need = s->slot_fixed + tally_vox(r->nvox) * r->K * sizeof(unsigned long long) + 2 * r->nvox * sizeof(double);
     if (r->need > s->budget)
       return cfail(c, GMC_EBUSY, "the request's device footprint exceeds the server's memory budget");
     ++c->refs[phantom_id];
