@@ -871,7 +871,6 @@ int engine_setup(Workspace* w, Engine& E, const Job& J, const Tune& tu) {
     a.beams = w->d_beams;
     a.sources = w->d_sources;
     a.ctr = w->d_ctr;
-    a.nvox = (uint32_t)J.P->nvox();
     a.ka = ka;
     a.kb = kb;
   }

@@ -268,7 +268,6 @@ struct AdmitArgs {
   const DevBeam* beams;
   const DevSource* sources;     // indexed by beam
   unsigned long long* ctr;
-  uint32_t nvox;
   uint32_t ka, kb;              // as in PassArgs
 };
 

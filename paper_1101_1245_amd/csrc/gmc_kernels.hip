@@ -184,7 +184,7 @@ __device__ __forceinline__ DevBeam read_beam(P p) {
 }
 
 __device__ __forceinline__ void load_lane(Lane& L, const DevQueue& q, uint32_t i, const PassArgs& a,
-                                          const DevBeam* lbeams, uint32_t nvox) {
+                                          const DevBeam* lbeams) {
   L.x = __uint_as_float(qf(q, Q_X, i)); L.y = __uint_as_float(qf(q, Q_Y, i)); L.z = __uint_as_float(qf(q, Q_Z, i));
   L.u = __uint_as_float(qf(q, Q_U, i)); L.v = __uint_as_float(qf(q, Q_V, i)); L.w = __uint_as_float(qf(q, Q_W, i));
   L.e = qf(q, Q_E, i);
@@ -337,13 +337,13 @@ __device__ __forceinline__ ClaimRange claim_range(const ClaimType& T, uint32_t* 
 // Entries with zero energy (primaries settled by the source) are skipped.
 template <class R>
 __device__ __forceinline__ void refill(Lane& L, bool& have, int& events, int& pushes, R& r, const PassArgs& a,
-                                       const DevBeam* lbeams, uint32_t nvox) {
+                                       const DevBeam* lbeams) {
   const unsigned long long need = __ballot(!have);
   if (need == 0 || __popcll(need) < a.refill_lanes || r.done()) return;
   if (!have) {
     const uint32_t it = r.next + (uint32_t)__popcll(need & lanes_below());
     if (it < r.end) {
-      load_lane(L, a.work, r.item(it), a, lbeams, nvox);
+      load_lane(L, a.work, r.item(it), a, lbeams);
       have = L.e != 0;
       events = 0;
       pushes = 0;
@@ -610,15 +610,14 @@ __device__ __forceinline__ void add_totals(const WaveTotals& t, unsigned long lo
 // LDS at tab (per material) and majg (majorant), the beam table at lbeams.
 template <class R>
 __device__ void photon_loop(const PassArgs& a, uint32_t admitting, R& range, WaveSeg& gsame, WaveSeg& gother,
-                            const float4* tab, const float* majg, const DevBeam* lbeams, uint32_t nvox,
-                            WaveTotals& tot) {
+                            const float4* tab, const float* majg, const DevBeam* lbeams, WaveTotals& tot) {
   Lane L;
   bool have = false;
   int events = 0, pushes = 0;
   uint32_t npark = 0;   // parked absorptions on the stack, wave-uniform
 
   for (;;) {
-    refill(L, have, events, pushes, range, a, lbeams, nvox);
+    refill(L, have, events, pushes, range, a, lbeams);
     // a refill may bring only zero-energy entries: the wavefront goes on
     // until its range is done
     if (!__any(have)) {
@@ -717,7 +716,7 @@ __device__ void photon_loop(const PassArgs& a, uint32_t admitting, R& range, Wav
     Child c0, c1;
     if (k < npark) {
       const uint32_t slot = gsame.base + gsame.cap - 1u - k;
-      load_lane(L, a.stg_same, slot, a, lbeams, nvox);
+      load_lane(L, a.stg_same, slot, a, lbeams);
       L.s.resume();
       const int kind = (int)qf(a.stg_same, Q_AUX, slot);
       int ix, iy, iz;
@@ -740,13 +739,12 @@ __global__ void __launch_bounds__(1024) k_photon_pass(PassArgs a) {
     for (int i = threadIdx.x; i < a.n_beams; i += blockDim.x) lbeams[i] = a.beams[i];
   __syncthreads();
 
-  const uint32_t nvox = (uint32_t)(a.ph.nx * a.ph.ny * a.ph.nz);
   const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const PassPlan P = *a.plan;
   WaveRange range = wave_range(P, wave, (gridDim.x * blockDim.x) >> 6);
   WaveSeg gsame{wave * P.seg_same, P.seg_same, 0u}, gother{wave * P.seg_other, P.seg_other, 0u};
   WaveTotals tot;
-  photon_loop(a, P.admitting, range, gsame, gother, smem, majg, lbeams, nvox, tot);
+  photon_loop(a, P.admitting, range, gsame, gother, smem, majg, lbeams, tot);
   append_outputs(a, P, gsame, gother);
   add_totals(tot, a.ctr);
 }
@@ -841,7 +839,7 @@ __device__ __forceinline__ bool hard_event(Lane& L, const PassArgs& a, const flo
 template <class R>
 __device__ void electron_loop(const PassArgs& a, uint32_t admitting, R& range, WaveSeg& gsame, WaveSeg& gother,
                               const float4* tab, const float* maje, const float* ms, const DevBeam* lbeams,
-                              uint32_t nvox, WaveTotals& tot) {
+                              WaveTotals& tot) {
   Lane L;
   Pending pend;
   Deferred dfr;
@@ -851,7 +849,7 @@ __device__ void electron_loop(const PassArgs& a, uint32_t admitting, R& range, W
   const float emin = a.cut.emin;
 
   for (;;) {
-    refill(L, have, events, pushes, range, a, lbeams, nvox);
+    refill(L, have, events, pushes, range, a, lbeams);
     // range done: idle lanes take back parked electrons, newest first
     bool hd = false;
     float hsh = 0.0f;
@@ -864,7 +862,7 @@ __device__ void electron_loop(const PassArgs& a, uint32_t admitting, R& range, W
           const uint32_t r = (uint32_t)__popcll(need & lanes_below());
           if (r < take) {
             const uint32_t slot = gsame.base + gsame.cap - npark + r;
-            load_lane(L, a.stg_same, slot, a, lbeams, nvox);
+            load_lane(L, a.stg_same, slot, a, lbeams);
             L.s.resume();
             hsh = __uint_as_float(qf(a.stg_same, Q_AUX, slot));
             const uint32_t cnt = qf(a.stg_same, Q_AUX2, slot);
@@ -1041,13 +1039,12 @@ __global__ void __launch_bounds__(1024) k_electron_pass(PassArgs a) {
     for (int i = threadIdx.x; i < a.n_beams; i += blockDim.x) lbeams[i] = a.beams[i];
   __syncthreads();
 
-  const uint32_t nvox = (uint32_t)(a.ph.nx * a.ph.ny * a.ph.nz);
   const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const PassPlan P = *a.plan;
   WaveRange range = wave_range(P, wave, (gridDim.x * blockDim.x) >> 6);
   WaveSeg gsame{wave * P.seg_same, P.seg_same, 0u}, gother{wave * P.seg_other, P.seg_other, 0u};
   WaveTotals tot;
-  electron_loop(a, P.admitting, range, gsame, gother, smem, maje, ms, lbeams, nvox, tot);
+  electron_loop(a, P.admitting, range, gsame, gother, smem, maje, ms, lbeams, tot);
   append_outputs(a, P, gsame, gother);
   add_totals(tot, a.ctr);
 }
@@ -1118,15 +1115,14 @@ __global__ void __launch_bounds__(kRoundMaxBlock) k_round(RoundArgs r) {
     for (int i = threadIdx.x; i < r.e.n_beams; i += blockDim.x) lbeams[i] = r.e.beams[i];
   __syncthreads();
 
-  const uint32_t nvox = (uint32_t)(r.e.ph.nx * r.e.ph.ny * r.e.ph.nz);
   const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const PassPlan Pg = *r.g.plan, Pe = *r.e.plan;
   WaveSeg se{wave * Pe.seg_same, Pe.seg_same, 0u}, sg{wave * Pg.seg_same, Pg.seg_same, 0u};
   WaveTotals tot;
   ClaimRange re = claim_range(r.claims[1], r.claim_ctr + kMaxClaimParts, Pe.chunk_log2, blockIdx.x);
-  electron_loop(r.e, Pe.admitting, re, se, sg, te, maje, ms, lbeams, nvox, tot);
+  electron_loop(r.e, Pe.admitting, re, se, sg, te, maje, ms, lbeams, tot);
   ClaimRange rg = claim_range(r.claims[0], r.claim_ctr, Pg.chunk_log2, blockIdx.x);
-  photon_loop(r.g, Pg.admitting, rg, sg, se, tg, majg, lbeams, nvox, tot);
+  photon_loop(r.g, Pg.admitting, rg, sg, se, tg, majg, lbeams, tot);
   append_round(r, Pe, Pg, se, sg);
   add_totals(tot, r.e.ctr);
 }
