@@ -68,11 +68,16 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # HBM bytes per unit of algorithmic work (electron step / photon event) of the
 # pass kernels, from two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE)
 # over the timed legs of the water workload, each scaled by the same counter
-# on a 1 GiB device copy (fetched bytes x2.0, written x1.0).  Valid only for the kernel and engine sources they
-# were measured on (their digest); per launch they are multiplied by this
-# run's work per launch.
+# on a 1 GiB device copy (fetched bytes x2.0, written x1.0), and the tally
+# additions per electron step (TCP_TCC_ATOMIC_WITHOUT_RET_REQ over the same
+# legs).  Valid only for the kernel and engine sources they were measured on
+# (their digest); per launch they are multiplied by this run's work per
+# launch.
 TRAFFIC = {"sources_sha256": "ec1d9791c3f61b08bbd41556d9098d1f2cc5b7ae2973485cdc8755dd2a0defe7",
-           "k_electron_pass": 57.79}
+           "k_electron_pass": 57.79, "k_electron_pass_atomics": 0.614}
+# Words of the array the atomic roof is measured on: 2^23 uint64 (67 MB), the
+# size of the water job's 32-batch tally.
+ATOMIC_ROOF_LOG2_WORDS = 23
 MEASURED_SOURCES = ("paper_1101_1245_amd/csrc/gmc_kernels.hip",
                     "paper_1101_1245_amd/csrc/gmc_device.hpp",
                     "paper_1101_1245_amd/csrc/gmc_internal.hpp",
@@ -133,6 +138,7 @@ class Acc:
         self.interactions = 0
         self.resid = 0
         self.hist = 0
+        self.atomic_roof = None   # additions/s of the atomic microbenchmark, when measured
 
     def add(self, st):
         self.t[0] += st["t_photon_pass_s"]
@@ -160,7 +166,9 @@ class Acc:
 
 def roofline(acc, workload="water"):
     """Dominant pass kernel (most device time), its average launch duration and
-    algorithmic lane-ops per launch against the VALU lane-op peak."""
+    algorithmic lane-ops per launch against the VALU lane-op peak; for the
+    water workload also its measured HBM bytes and its tally additions
+    against the atomic rate measured in the same run."""
     ph_ops = acc.events * OPS_PER_PH_EVENT + acc.interactions * OPS_PER_PH_INTERACTION
     if acc.t[2] > max(acc.t[0], acc.t[1]):
         # persistent round kernels: both particle types in each launch
@@ -184,6 +192,15 @@ def roofline(acc, workload="water"):
         out["traffic_unit"] = "HBM bytes per launch (%.2f per unit of work x %.3g units)" % (per_unit, units)
         out["hbm_GBps"] = traffic / avg / 1e9
         out["hbm_frac"] = traffic / avg / 8.0e12
+    # the tally's second roof: additions per second against what random 64-bit
+    # atomics reach on an array the size of the tally, measured in the same run
+    adds = measured_traffic(name + "_atomics") if workload == "water" else None
+    if adds and acc.atomic_roof and avg > 0:
+        a = adds * units / avg
+        out["atomics"] = {"achieved": a, "peak": acc.atomic_roof, "unit": "additions/s", "frac": a / acc.atomic_roof,
+                          "per_unit": adds,
+                          "peak_from": "k_atomic_rate: 2^%d uint64 words at hashed addresses, best of 3 launches"
+                                       % ATOMIC_ROOF_LOG2_WORDS}
     # the other pass kernel against the same peak (in a job run by round
     # kernels the pass counts cover only the legs that ran passes)
     if name != "k_round":
@@ -318,6 +335,9 @@ def bench_water(args, G, E, I):
     }
     if alt is not None:
         out["alt_ecut_0p189"] = alt
+    # the atomic roof on an array the size of this job's tally (after the
+    # timed legs, outside them)
+    both.atomic_roof = max(ctx.atomic_rate(ATOMIC_ROOF_LOG2_WORDS) for _ in range(3))
     ctx.close()
     return out, both
 

@@ -50,6 +50,20 @@ def test_roofline_of_the_dominant_kernel():
                                           / 1e12)
 
 
+def test_atomic_roof_of_the_electron_pass(monkeypatch):
+    # 10 launches of 2 ms, 1e8 steps; 0.6 additions per step against 2e10 additions/s
+    stored = {"k_electron_pass": 50.0, "k_electron_pass_atomics": 0.6}
+    monkeypatch.setattr(bench, "measured_traffic", lambda k: stored.get(k))
+    acc = _acc(0.005, 0.020, 10, 10, 2e8, 1e8)
+    assert "atomics" not in bench.roofline(acc, "water")        # no roof measured in this run
+    acc.atomic_roof = 2e10
+    r = bench.roofline(acc, "water")
+    assert r["traffic"] == pytest.approx(50.0 * 1e7)
+    assert r["atomics"]["achieved"] == pytest.approx(0.6 * 1e7 / 2e-3)
+    assert r["atomics"]["frac"] == pytest.approx(0.6 * 1e7 / 2e-3 / 2e10)
+    assert "atomics" not in bench.roofline(acc, "beamlets")     # counted on the water workload only
+
+
 def test_traffic_is_dropped_when_the_sources_change(monkeypatch):
     monkeypatch.setitem(bench.TRAFFIC, "sources_sha256", "0" * 64)
     assert bench.measured_traffic("k_electron_pass") is None
