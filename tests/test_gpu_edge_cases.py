@@ -13,7 +13,9 @@ oracle, through the C ABI.
   the gap, and the doses on both sides agree with the oracle on the same
   streams (z-test) with event counts within 2e-3.
 * The smallest and ragged grids (one voxel; 7 x 5 x 3 voxels, fewer than one
-  finalize block) and the fewest histories allowed (n = n_batches), and
+  finalize block and not a whole number of the tally's 16-voxel blocks, whose
+  raw batch tallies finalize to the run's own dose and sigma) and the fewest
+  histories allowed (n = n_batches), and
   beams at the largest energy accepted (30 MeV): the ledger closes exactly
   and the doses agree with the oracle.
 """
@@ -145,10 +147,19 @@ def test_smallest_grids_and_fewest_histories(ctx, oracle, shape):
         n = 40_000
         d, s, st = ctx.run_beam(pid, tid, src, n, 9)
         ref, _, _ = ctx.run_beam(pid, tid, src, n, 10)
+        # the raw batch tallies of the same run (slice-major at the C ABI, whatever the
+        # voxel count) give the same dose and sigma through the finalize entry point
+        t, _ = ctx.run_beam_tally(pid, tid, src, n, 9)
+        dt, st_, _ = ctx.finalize_tally(pid, tid, t, 0, n)
     finally:
         release(ctx, pid, tid)
     assert d0.shape == ph.shape and np.all(np.isfinite(d0)) and np.all(np.isfinite(s0))
     assert st0["ledger_residual_lsb"] == 0 and st["ledger_residual_lsb"] == 0
+    assert t.shape == (K,) + ph.shape
+    assert np.array_equal(dt, d) and np.array_equal(st_, s)
+    # and hold exactly the energy the run deposited
+    e_total = float(t.sum()) * LSB
+    assert e_total == pytest.approx(st["e_dep_mev"], rel=1e-12)
     res = oracle.run((I.WATER,), ph, src, phys, seed=9, n_hist=n, batches=False)
     do, so = oracle.dose(res, ph)
     zt = E.z_test(d, s, do, so, ref_for_mask=ref, dof=K - 1, same_streams=True)
