@@ -18,7 +18,10 @@ Bars:
   histories, default tuning as timed by the benchmark): the integer ledger
   closes, no majorant is violated, and sampled beams are bit-identical to
   their plain-form runs; the smallest beam also passes the z-test against
-  the oracle.
+  the oracle;
+* at the benchmark's water size (5.25e6 electrons + 6.5e7 photons in one
+  batched job): per-beam results equal the plain runs, and each beam agrees
+  with an independent oracle run at the paper's counts.
 """
 import types
 
@@ -278,3 +281,46 @@ def test_beam_outside_the_phantom_ahead_of_another(ctx):
     finally:
         ctx.release(pid)
         ctx.release(tid)
+
+
+def test_water_beams_at_the_benchmark_size(ctx, oracle):
+    """The benchmark's job as it times it: the 15 MeV electron and photon
+    beams on 64^3 water at their 1% history counts (5.25e6 + 6.5e7) in one
+    batched job with per-beam doses and sigmas.  Each beam equals its plain
+    run bit for bit (through the raw batch tallies), the ledger closes, and
+    each beam's dose agrees with an independent FP64 oracle run at the
+    paper's counts (1e6 electrons, 4e6 photons): z-test with the mean bound
+    from both sides' batch spreads."""
+    from conftest import oracle_batches
+    we, wg = I.water_15mev(I.ELECTRON), I.water_15mev(I.PHOTON)
+    counts = [5_250_000, 65_000_000]
+    seed = 23
+    print("\nwater beams at the benchmark size: %d electrons + %d photons" % tuple(counts), flush=True)
+    tid = ctx.load_tables(we.materials, we.physics)
+    pid = ctx.load_phantom(we.phantom)
+    shape = we.phantom.shape
+    try:
+        pb, ps, d, s, st = ctx.run_beams(pid, tid, [we.source, wg.source], counts, seed, per_beam=True,
+                                         per_beam_sigma=True)
+        plain = []
+        for w, n in zip((we, wg), counts):
+            t, stt = ctx.run_beam_tally(pid, tid, w.source, n, seed)
+            dt, stg, _ = ctx.finalize_tally(pid, tid, t, 0, n)
+            bg = E.batch_doses(t.astype(np.float64) * E.LSB_MEV, we.phantom.rho, we.phantom.voxel, n)
+            ref, _, _ = ctx.run_beam(pid, tid, w.source, w.n_hist, seed + 100)   # voxel mask only
+            plain.append((dt, stg, stt, bg, ref))
+    finally:
+        ctx.release(pid)
+        ctx.release(tid)
+    assert st["ledger_residual_lsb"] == 0 and st["n_majorant_violations"] == 0
+    assert st["n_hist"] == sum(counts)
+    for b, (w, (dt, stg, stt, bg, ref)) in enumerate(zip((we, wg), plain)):
+        assert stt["ledger_residual_lsb"] == 0
+        assert np.array_equal(pb[b], dt) and np.array_equal(ps[b], stg), b
+        res = oracle.run_parallel(w.materials, w.phantom, w.source, w.physics, seed + 1, w.n_hist)
+        do, so = oracle.dose(res, w.phantom)
+        zi = E.z_test(dt, stg, do, so, ref_for_mask=ref, dof=w.physics.n_batches - 1,
+                      batches=(bg, oracle_batches(res, w.phantom, w.n_hist)))
+        print("%s, %d GPU histories against %d in the oracle: z-test %s" % (w.name, counts[b], w.n_hist,
+                                                                           E.describe(zi)))
+        assert zi.passed, E.describe(zi)
