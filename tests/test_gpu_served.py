@@ -16,7 +16,8 @@ Bars:
   z-tests on the same and on independent streams, event counts;
 * a request on the largest grid of the request stream (256^3 voxels) served
   beside a small one equals the plain form bit for bit and agrees with the
-  oracle on the same histories.
+  oracle on the same histories; the stream's largest request (1e8 histories
+  on 256^3 voxels) equals the plain form bit for bit with an exact ledger.
 """
 import numpy as np
 import pytest
@@ -249,3 +250,42 @@ def test_largest_grid_request_matches_plain_and_oracle(ctx, oracle):
     assert zt.passed, E.describe(zt)
     for k in ("n_e_steps", "n_photon_events", "n_secondaries"):
         assert abs(st[k] - res.stats[k]) < 2e-3 * res.stats[k] + 10, (k, st[k], res.stats[k])
+
+
+def test_largest_request_served_equals_plain(ctx):
+    """The request stream's largest request, 1e8 histories on a 256^3 grid,
+    served beside a small one: bit-identical to the plain form, the ledger
+    exact (the oracle cannot follow 1e8 histories; these properties hold at
+    any size)."""
+    big = I.ellipsoids(256, 0.25, seed=33)
+    phys = I.serving_physics()
+    src = I.centred(big, I.Source(I.PHOTON, I.MONO, 20.0, wx=10.0, wy=10.0, beam_id=8))
+    small = I.ellipsoids(32, 0.5, seed=34)
+    src_small = I.centred(small, I.Source(I.ELECTRON, I.TRIANGULAR, 10.0, e_lo=2.0, e_mode=10.0, e_hi=18.0, wx=3.0,
+                                          wy=3.0, beam_id=9))
+    n = 100_000_000
+    print("\n256^3 request, n=%d" % n, flush=True)
+    tid = ctx.load_tables(I.DEFAULT_MATERIALS, phys)
+    pid = ctx.load_phantom(big)
+    pid_s = ctx.load_phantom(small)
+    try:
+        ctx.server_start(max_slots=2)
+        try:
+            t_big = ctx.submit(pid, tid, src, n, 41)
+            t_small = ctx.submit(pid_s, tid, src_small, 100_000, 42)
+            done, d, s, st = ctx.poll(t_big, big.shape, wait=True)
+            done_s, d_s, s_s, st_s = ctx.poll(t_small, small.shape, wait=True)
+        finally:
+            ctx.server_stop()
+        da, sa, sta = ctx.run_beam(pid, tid, src, n, 41)
+        ds, ss, _ = ctx.run_beam(pid_s, tid, src_small, 100_000, 42)
+    finally:
+        ctx.release(pid)
+        ctx.release(pid_s)
+        ctx.release(tid)
+    assert done and done_s
+    assert st["ledger_residual_lsb"] == 0 and st["n_majorant_violations"] == 0 and st_s["ledger_residual_lsb"] == 0
+    assert st["n_hist"] == n and st["e_in_mev"] == pytest.approx(20.0 * n, rel=1e-6)
+    assert np.array_equal(d, da) and np.array_equal(s, sa)
+    assert np.array_equal(d_s, ds) and np.array_equal(s_s, ss)
+    assert st["s_rel"] == sta["s_rel"]
