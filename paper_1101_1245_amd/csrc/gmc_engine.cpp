@@ -175,8 +175,11 @@ void ws_free(Workspace* w) {
   w->cap = w->stg_cap = w->sorted_cap = 0;
   for (void* p : {(void*)w->d_ctl, (void*)w->d_ctr, (void*)w->d_beams, (void*)w->d_sort, (void*)w->d_tab,
                   (void*)w->d_sources, (void*)w->d_start, (void*)w->d_beam_of, (void*)w->d_seg_h, (void*)w->d_nk,
-                  (void*)w->d_claim})
+                  (void*)w->d_claim, (void*)w->d_fin, (void*)w->d_fin_nk})
     if (p) (void)hipFree(p);
+  w->d_fin = nullptr;
+  w->d_fin_nk = nullptr;
+  w->fin_cap = w->fin_nk_cap = 0;
   for (void* p : {(void*)w->h_ctl, (void*)w->h_ctr, (void*)w->h_nk, (void*)w->h_srel})
     if (p) (void)hipHostFree(p);
   w->d_ctl = nullptr;
@@ -244,6 +247,24 @@ int ws_ensure_beams(Workspace* w, size_t n) {
   WS_TRY(w, hipMalloc(&w->d_beams, n * sizeof(DevBeam)));
   WS_TRY(w, hipMalloc(&w->d_sources, n * sizeof(DevSource)));
   w->beams_cap = n;
+  return GMC_OK;
+}
+
+int ws_ensure_fin(Workspace* w, size_t n, size_t nk) {
+  if (w->fin_cap < n) {
+    if (w->d_fin) (void)hipFree(w->d_fin);
+    w->d_fin = nullptr;
+    w->fin_cap = 0;
+    WS_TRY(w, hipMalloc(&w->d_fin, n * sizeof(FinalizeArgs)));
+    w->fin_cap = n;
+  }
+  if (w->fin_nk_cap < nk) {
+    if (w->d_fin_nk) (void)hipFree(w->d_fin_nk);
+    w->d_fin_nk = nullptr;
+    w->fin_nk_cap = 0;
+    WS_TRY(w, hipMalloc(&w->d_fin_nk, nk * sizeof(double)));
+    w->fin_nk_cap = nk;
+  }
   return GMC_OK;
 }
 
@@ -1265,8 +1286,48 @@ int run_job_ws(gmc_context* c, Workspace* w, int32_t phantom_id, int32_t tables_
     if (tmp) (void)hipFree(tmp);
     if (e != hipSuccess) return wfail(w, GMC_EDEVICE, std::string("raw tally copy: ") + hipGetErrorString(e));
   }
-  // per-beam results
-  if (mode != kCombined) {
+  // per-beam results: into device memory all in one launch, into host memory
+  // one beam at a time through the scratch outputs
+  if (mode != kCombined && out_kind == GMC_DEVICE) {
+    const uint32_t kb = mode == kBeamBatched ? K : 1u;
+    std::vector<FinalizeArgs> list;
+    std::vector<double> nks;   // kb batch sizes per listed beam
+    for (int b = 0; b < n_beams; ++b) {
+      double* want_d = dose_per_beam ? dose_per_beam[b] : nullptr;
+      double* want_s = sigma_per_beam ? sigma_per_beam[b] : nullptr;
+      if (!want_d && !want_s) continue;
+      FinalizeArgs fa{};
+      fa.tally = w->d_tally +
+                 (mode == kBeamBatched ? tally_vox(nvox) * K * (size_t)b : tally_vox(nvox) * ((size_t)K + (size_t)b));
+      fa.nsum = 1u;
+      fa.sum_stride = 0u;
+      fa.vox = P.d_vox;
+      fa.nvox = (uint32_t)nvox;
+      fa.K = kb;
+      fa.n_total = (double)n_hist[b];
+      fa.conv = dose_per_lsb(P);
+      fa.dose = want_d;
+      fa.sigma = want_s;
+      fa.ctr = nullptr;
+      fa.blocked = 1u;
+      list.push_back(fa);
+      std::vector<double> nkb;
+      add_batch_sizes(nkb, srcs[b].first_history, n_hist[b], kb);
+      nks.insert(nks.end(), nkb.begin(), nkb.end());
+    }
+    if (!list.empty()) {
+      rc = ws_ensure_fin(w, list.size(), nks.size());
+      if (rc) return rc;
+      for (size_t i = 0; i < list.size(); ++i) list[i].nk = w->d_fin_nk + i * kb;
+      WS_TRY(w, hipMemcpyAsync(w->d_fin_nk, nks.data(), nks.size() * sizeof(double), hipMemcpyHostToDevice,
+                               w->stream));
+      WS_TRY(w, hipMemcpyAsync(w->d_fin, list.data(), list.size() * sizeof(FinalizeArgs), hipMemcpyHostToDevice,
+                               w->stream));
+      WS_TRY(w, launch_finalize_many(w->d_fin, (uint32_t)list.size(), (uint32_t)nvox, w->stream));
+      // the argument lists are host memory of this call: wait until the device has used them
+      WS_TRY(w, hipStreamSynchronize(w->stream));
+    }
+  } else if (mode != kCombined) {
     for (int b = 0; b < n_beams; ++b) {
       double* want_d = dose_per_beam ? dose_per_beam[b] : nullptr;
       double* want_s = sigma_per_beam ? sigma_per_beam[b] : nullptr;

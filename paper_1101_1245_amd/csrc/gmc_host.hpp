@@ -120,6 +120,9 @@ struct Workspace {
   double* d_dose = nullptr;
   double* d_sigma = nullptr;
   size_t out_elems = 0;
+  FinalizeArgs* d_fin = nullptr;   // per-beam finalize arguments of a batched job
+  double* d_fin_nk = nullptr;      // and their batch sizes
+  size_t fin_cap = 0, fin_nk_cap = 0;
   std::map<std::vector<int>, int> resident;    // (kernel, block, materials) -> resident workgroups
   hipEvent_t ev0 = nullptr, ev1 = nullptr;     // around a whole job
   hipEvent_t kev0 = nullptr, kev1 = nullptr;   // around a pass launch (plain form)
@@ -148,6 +151,7 @@ size_t ws_device_bytes(const Workspace& w);
 int ws_ensure_tally(Workspace* w, size_t elems);
 int ws_ensure_out(Workspace* w, size_t elems);
 int ws_ensure_beams(Workspace* w, size_t n);
+int ws_ensure_fin(Workspace* w, size_t n, size_t nk);
 // Admission segment tables of n segments per type.
 int ws_ensure_segments(Workspace* w, size_t n);
 

@@ -294,7 +294,7 @@ struct FinalizeArgs {
   const double* nk;                 // histories per batch
   uint32_t nvox, K;
   double n_total, conv;             // conv = LSB * J/MeV / (V * 1e-3 kg/g)
-  double* dose;
+  double* dose;                     // may be null in k_finalize_many (sigma only)
   double* sigma;                    // may be null
   unsigned long long* ctr;          // [C_COUNT][kCtrSlots], gets C_E_DEP (may be null)
   uint32_t blocked;                 // 1: the library's blocked layout; 0: slice-major [K][nvox]
@@ -313,6 +313,9 @@ hipError_t launch_electron_pass(const PassArgs& a, int grid, int block, hipStrea
 hipError_t launch_admit_plan(const AdmitPlanArgs& a, hipStream_t s);
 hipError_t launch_admit(const AdmitArgs& a, uint32_t max_count, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
+// n finalizes of one phantom (nvox voxels each), their arguments at d_list in
+// device memory (a null dose skips the dose).
+hipError_t launch_finalize_many(const FinalizeArgs* d_list, uint32_t n, uint32_t nvox, hipStream_t s);
 // A blocked tally (nvox voxels, K batches) rewritten slice-major, [K][nvox].
 hipError_t launch_tally_to_slices(const unsigned long long* blocked, unsigned long long* slices, uint32_t nvox,
                                   uint32_t K, hipStream_t s);

@@ -1140,15 +1140,14 @@ __device__ __forceinline__ unsigned long long batch_total(const FinalizeArgs& a,
 // D = sum_k T_k / N converted to Gy; sigma^2 = sum_k n_k^2 (m_k - m)^2 /
 // (N^2 (K-1)/K) with m_k the batch means.  Also sums the deposited energy for
 // the integer ledger.
-__global__ void __launch_bounds__(256) k_finalize(FinalizeArgs a) {
-  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void finalize_voxels(const FinalizeArgs& a, uint32_t v) {
   unsigned long long s1 = 0;
   if (v < a.nvox) {
     for (uint32_t k = 0; k < a.K; ++k) s1 += batch_total(a, k, v);
     const double rho = (double)__uint_as_float(a.vox[v].x);
     const double conv = rho > 0.0 ? a.conv / rho : 0.0;
     const double m = (double)s1 / a.n_total;
-    a.dose[v] = m * conv;
+    if (a.dose) a.dose[v] = m * conv;
     if (a.sigma) {
       double acc = 0.0;
       for (uint32_t k = 0; k < a.K; ++k) {
@@ -1163,6 +1162,17 @@ __global__ void __launch_bounds__(256) k_finalize(FinalizeArgs a) {
   }
   const unsigned long long t = wave_sum(s1);
   if (lane_id() == 0 && t && a.ctr) ctr_add(a.ctr, C_E_DEP, t);
+}
+
+__global__ void __launch_bounds__(256) k_finalize(FinalizeArgs a) {
+  finalize_voxels(a, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Many finalizes of one phantom in one launch (the beams of a batched job
+// with per-beam results): workgroup row y takes finalize y of the list, with
+// the same arithmetic as k_finalize.
+__global__ void __launch_bounds__(256) k_finalize_many(const FinalizeArgs* list) {
+  finalize_voxels(list[blockIdx.y], blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Eq. 12's s: block maxima of D, then per-block sums of sigma/D and counts
@@ -1556,6 +1566,14 @@ hipError_t launch_tally_to_slices(const unsigned long long* blocked, unsigned lo
   if (n == 0) return hipSuccess;
   const int grid = (int)std::min<size_t>((n + 255) / 256, 65536);
   hipLaunchKernelGGL(k_tally_to_slices, dim3(grid), dim3(256), 0, s, blocked, slices, nvox, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_many(const FinalizeArgs* d_list, uint32_t n, uint32_t nvox, hipStream_t s) {
+  for (uint32_t j0 = 0; j0 < n; j0 += 65535u) {   // rows of a grid
+    const uint32_t rows = std::min(n - j0, 65535u);
+    hipLaunchKernelGGL(k_finalize_many, dim3((nvox + 255) / 256, rows), dim3(256), 0, s, d_list + j0);
+  }
   return hipGetLastError();
 }
 
