@@ -1323,7 +1323,7 @@ int run_job_ws(gmc_context* c, Workspace* w, int32_t phantom_id, int32_t tables_
                                w->stream));
       WS_TRY(w, hipMemcpyAsync(w->d_fin, list.data(), list.size() * sizeof(FinalizeArgs), hipMemcpyHostToDevice,
                                w->stream));
-      WS_TRY(w, launch_finalize_many(w->d_fin, (uint32_t)list.size(), (uint32_t)nvox, w->stream));
+      WS_TRY(w, launch_finalize_many(w->d_fin, (uint32_t)list.size(), (uint32_t)nvox, kb, 1u, w->stream));
       // the argument lists are host memory of this call: wait until the device has used them
       WS_TRY(w, hipStreamSynchronize(w->stream));
     }

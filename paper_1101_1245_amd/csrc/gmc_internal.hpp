@@ -314,8 +314,9 @@ hipError_t launch_admit_plan(const AdmitPlanArgs& a, hipStream_t s);
 hipError_t launch_admit(const AdmitArgs& a, uint32_t max_count, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
 // n finalizes of one phantom (nvox voxels each), their arguments at d_list in
-// device memory (a null dose skips the dose).
-hipError_t launch_finalize_many(const FinalizeArgs* d_list, uint32_t n, uint32_t nvox, hipStream_t s);
+// device memory, all with the same K and nsum (a null dose skips the dose).
+hipError_t launch_finalize_many(const FinalizeArgs* d_list, uint32_t n, uint32_t nvox, uint32_t K, uint32_t nsum,
+                                hipStream_t s);
 // A blocked tally (nvox voxels, K batches) rewritten slice-major, [K][nvox].
 hipError_t launch_tally_to_slices(const unsigned long long* blocked, unsigned long long* slices, uint32_t nvox,
                                   uint32_t K, hipStream_t s);

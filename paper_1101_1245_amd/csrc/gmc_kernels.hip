@@ -1138,41 +1138,107 @@ __device__ __forceinline__ unsigned long long batch_total(const FinalizeArgs& a,
 
 // Dose per history and batch uncertainty in double precision (Sec. II.D):
 // D = sum_k T_k / N converted to Gy; sigma^2 = sum_k n_k^2 (m_k - m)^2 /
-// (N^2 (K-1)/K) with m_k the batch means.  Also sums the deposited energy for
-// the integer ledger.
-__device__ __forceinline__ void finalize_voxels(const FinalizeArgs& a, uint32_t v) {
+// (N^2 (K-1)/K) with m_k = T_k / n_k the batch means, each term formed as
+// (T_k - n_k m)^2 (the same quantity, without a division).  Both forms
+// below return the voxel's deposited energy for the integer ledger, and
+// give the same bits for the same batches.
+//
+// General form: any number of batches, nsum tallies added.
+__device__ __forceinline__ unsigned long long finalize_general(const FinalizeArgs& a, uint32_t v) {
   unsigned long long s1 = 0;
-  if (v < a.nvox) {
-    for (uint32_t k = 0; k < a.K; ++k) s1 += batch_total(a, k, v);
-    const double rho = (double)__uint_as_float(a.vox[v].x);
-    const double conv = rho > 0.0 ? a.conv / rho : 0.0;
-    const double m = (double)s1 / a.n_total;
-    if (a.dose) a.dose[v] = m * conv;
-    if (a.sigma) {
-      double acc = 0.0;
-      for (uint32_t k = 0; k < a.K; ++k) {
-        const double nk = a.nk[k];
-        if (!(nk > 0.0)) continue;   // a batch without histories adds nothing
-        const double d = (double)batch_total(a, k, v) / nk - m;
-        acc += nk * nk * d * d;
-      }
-      const double var = a.K > 1 ? acc / (a.n_total * a.n_total * (double)(a.K - 1) / (double)a.K) : 0.0;
-      a.sigma[v] = sqrt(var) * conv;
+  for (uint32_t k = 0; k < a.K; ++k) s1 += batch_total(a, k, v);
+  const double rho = (double)__uint_as_float(a.vox[v].x);
+  const double conv = rho > 0.0 ? a.conv / rho : 0.0;
+  const double m = (double)s1 / a.n_total;
+  if (a.dose) a.dose[v] = m * conv;
+  if (a.sigma) {
+    double acc = 0.0;
+    for (uint32_t k = 0; k < a.K; ++k) {
+      const double nk = a.nk[k];
+      if (!(nk > 0.0)) continue;   // a batch without histories adds nothing
+      const double d = (double)batch_total(a, k, v) - nk * m;
+      acc += d * d;
     }
+    const double var = a.K > 1 ? acc / (a.n_total * a.n_total * (double)(a.K - 1) / (double)a.K) : 0.0;
+    a.sigma[v] = sqrt(var) * conv;
   }
+  return s1;
+}
+
+// Register form, for one tally of at most KR batches: a lane issues every
+// batch load of its voxel before it uses any (K loads in flight, not one at
+// a time), then forms D and sigma from registers with the general form's
+// operations in the same order.  The batch sizes come from LDS (nk_lds:
+// kFinRegK entries, zero past K), and sigma's sum has no branch: a batch
+// without histories adds +0.0 to a sum of non-negative terms, which leaves
+// it as it was.
+constexpr uint32_t kFinRegK = 32;
+template <uint32_t KR>
+__device__ __forceinline__ unsigned long long finalize_reg(const FinalizeArgs& a, uint32_t v, const double* nk_lds) {
+  const size_t step = a.blocked ? kTallyBlock : a.nvox;
+  const unsigned long long* p = a.tally + (a.blocked ? vox_off(v, a.K) : v);
+  // batches past K (fewer than K of them) load batch K-1 again: in bounds,
+  // straight-line code with no wait between the loads; they count as zero
+  unsigned long long t[KR];
+#pragma unroll
+  for (uint32_t k = 0; k < KR; ++k) t[k] = p[(size_t)(k < a.K ? k : a.K - 1u) * step];
+  const double rho = (double)__uint_as_float(a.vox[v].x);
+  unsigned long long s1 = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < KR; ++k) s1 += k < a.K ? t[k] : 0ull;
+  const double conv = rho > 0.0 ? a.conv / rho : 0.0;
+  const double m = (double)s1 / a.n_total;
+  double sig = 0.0;
+  if (a.sigma) {
+    double acc = 0.0;
+#pragma unroll
+    for (uint32_t k = 0; k < KR; ++k) {
+      const double nk = nk_lds[k];
+      const double d = (double)t[k] - nk * m;
+      const double term = d * d;
+      acc += nk > 0.0 ? term : 0.0;
+    }
+    const double var = a.K > 1 ? acc / (a.n_total * a.n_total * (double)(a.K - 1) / (double)a.K) : 0.0;
+    sig = sqrt(var) * conv;
+  }
+  if (a.dose) a.dose[v] = m * conv;
+  if (a.sigma) a.sigma[v] = sig;
+  return s1;
+}
+
+// Every thread of the workgroup calls this (the LDS fill has a barrier).
+// KR: the register form's width, 0 for the general form; arguments it does
+// not fit (more batches than KR, or several tallies) take the general form.
+template <uint32_t KR>
+__device__ __forceinline__ void finalize_voxels(const FinalizeArgs& a, uint32_t v) {
+  __shared__ double nk_lds[kFinRegK];
+  const bool reg = KR > 0 && a.nsum == 1u && a.K >= 1u && a.K <= KR;
+  if (reg && a.sigma) {
+    if (threadIdx.x < kFinRegK) nk_lds[threadIdx.x] = threadIdx.x < a.K ? a.nk[threadIdx.x] : 0.0;
+    __syncthreads();
+  }
+  unsigned long long s1 = 0;
+  if (v < a.nvox) s1 = reg ? finalize_reg<(KR > 0 ? KR : 1u)>(a, v, nk_lds) : finalize_general(a, v);
   const unsigned long long t = wave_sum(s1);
   if (lane_id() == 0 && t && a.ctr) ctr_add(a.ctr, C_E_DEP, t);
 }
 
+// One instance per width, so that each has the registers of its own width
+// (a lane of the one-batch form holds two loads, not thirty-two, and the
+// occupancy that hides their latency).
+template <uint32_t KR>
 __global__ void __launch_bounds__(256) k_finalize(FinalizeArgs a) {
-  finalize_voxels(a, blockIdx.x * blockDim.x + threadIdx.x);
+  finalize_voxels<KR>(a, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Many finalizes of one phantom in one launch (the beams of a batched job
 // with per-beam results): workgroup row y takes finalize y of the list, with
-// the same arithmetic as k_finalize.
-__global__ void __launch_bounds__(256) k_finalize_many(const FinalizeArgs* list) {
-  finalize_voxels(list[blockIdx.y], blockIdx.x * blockDim.x + threadIdx.x);
+// the same arithmetic as k_finalize.  The row's arguments are copied before
+// any store or barrier, so that they are read once, as uniform scalar loads.
+template <uint32_t KR>
+__global__ void __launch_bounds__(256) k_finalize_many(const FinalizeArgs* __restrict__ list) {
+  const FinalizeArgs a = list[blockIdx.y];
+  finalize_voxels<KR>(a, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Eq. 12's s: block maxima of D, then per-block sums of sigma/D and counts
@@ -1569,17 +1635,44 @@ hipError_t launch_tally_to_slices(const unsigned long long* blocked, unsigned lo
   return hipGetLastError();
 }
 
-hipError_t launch_finalize_many(const FinalizeArgs* d_list, uint32_t n, uint32_t nvox, hipStream_t s) {
+// The narrowest register form that holds K batches of one tally, else 0
+// (the general form).
+static uint32_t finalize_width(uint32_t K, uint32_t nsum) {
+  if (nsum != 1u || K < 1u || K > kFinRegK) return 0u;
+  return K == 1u ? 1u : K <= 4u ? 4u : K <= 8u ? 8u : K <= 16u ? 16u : kFinRegK;
+}
+
+template <uint32_t KR>
+static void finalize_many_rows(const FinalizeArgs* d_list, uint32_t n, uint32_t nvox, hipStream_t s) {
   for (uint32_t j0 = 0; j0 < n; j0 += 65535u) {   // rows of a grid
     const uint32_t rows = std::min(n - j0, 65535u);
-    hipLaunchKernelGGL(k_finalize_many, dim3((nvox + 255) / 256, rows), dim3(256), 0, s, d_list + j0);
+    hipLaunchKernelGGL(k_finalize_many<KR>, dim3((nvox + 255) / 256, rows), dim3(256), 0, s, d_list + j0);
+  }
+}
+
+hipError_t launch_finalize_many(const FinalizeArgs* d_list, uint32_t n, uint32_t nvox, uint32_t K, uint32_t nsum,
+                                hipStream_t s) {
+  switch (finalize_width(K, nsum)) {
+    case 1u: finalize_many_rows<1u>(d_list, n, nvox, s); break;
+    case 4u: finalize_many_rows<4u>(d_list, n, nvox, s); break;
+    case 8u: finalize_many_rows<8u>(d_list, n, nvox, s); break;
+    case 16u: finalize_many_rows<16u>(d_list, n, nvox, s); break;
+    case kFinRegK: finalize_many_rows<kFinRegK>(d_list, n, nvox, s); break;
+    default: finalize_many_rows<0u>(d_list, n, nvox, s); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s) {
   const int grid = (int)((a.nvox + 255) / 256);
-  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(256), 0, s, a);
+  switch (finalize_width(a.K, a.nsum)) {
+    case 1u: hipLaunchKernelGGL(k_finalize<1u>, dim3(grid), dim3(256), 0, s, a); break;
+    case 4u: hipLaunchKernelGGL(k_finalize<4u>, dim3(grid), dim3(256), 0, s, a); break;
+    case 8u: hipLaunchKernelGGL(k_finalize<8u>, dim3(grid), dim3(256), 0, s, a); break;
+    case 16u: hipLaunchKernelGGL(k_finalize<16u>, dim3(grid), dim3(256), 0, s, a); break;
+    case kFinRegK: hipLaunchKernelGGL(k_finalize<kFinRegK>, dim3(grid), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_finalize<0u>, dim3(grid), dim3(256), 0, s, a); break;
+  }
   return hipGetLastError();
 }
 
