@@ -73,7 +73,7 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # legs).  Valid only for the kernel and engine sources they were measured on
 # (their digest); per launch they are multiplied by this run's work per
 # launch.
-TRAFFIC = {"sources_sha256": "9a06b4175cb6c6546e9d4a8fd87c84f2d736c3f5a4d82dcbe7745b0f68dc7782",
+TRAFFIC = {"sources_sha256": "5b3b60ed4269557a284f40a4c497f9aae69f898c97527f6374bab09d3456bf92",
            "k_electron_pass": 57.79, "k_electron_pass_atomics": 0.614}
 # Words of the array the atomic roof is measured on: 2^23 uint64 (67 MB), the
 # size of the water job's 32-batch tally.

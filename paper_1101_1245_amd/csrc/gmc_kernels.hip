@@ -1177,7 +1177,7 @@ template <uint32_t KR>
 __device__ __forceinline__ unsigned long long finalize_reg(const FinalizeArgs& a, uint32_t v, const double* nk_lds) {
   const size_t step = a.blocked ? kTallyBlock : a.nvox;
   const unsigned long long* p = a.tally + (a.blocked ? vox_off(v, a.K) : v);
-  // batches past K (fewer than K of them) load batch K-1 again: in bounds,
+  // batches past K (at most K of them) load batch K-1 again: in bounds,
   // straight-line code with no wait between the loads; they count as zero
   unsigned long long t[KR];
 #pragma unroll
