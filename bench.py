@@ -73,7 +73,7 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # legs).  Valid only for the kernel and engine sources they were measured on
 # (their digest); per launch they are multiplied by this run's work per
 # launch.
-TRAFFIC = {"sources_sha256": "5b3b60ed4269557a284f40a4c497f9aae69f898c97527f6374bab09d3456bf92",
+TRAFFIC = {"sources_sha256": "c71783d2b4d4446c51eece77bea5bccb8e66b3310010e8b2701854dd2c5123a5",
            "k_electron_pass": 57.79, "k_electron_pass_atomics": 0.614}
 # Words of the array the atomic roof is measured on: 2^23 uint64 (67 MB), the
 # size of the water job's 32-batch tally.

@@ -90,12 +90,11 @@ struct DevQueue {
   uint32_t cap;
 };
 
-// One tally target: history h of the beam deposits into the batch slice
-// base + ((off + h) mod K) * nvox; base null: no target.  Interleaved batches
-// keep every run of consecutive histories spread over all K slices, so lanes
-// working on neighbouring histories rarely add to the same address.
-// A tally target: K batch sums per voxel in the blocked layout above, from
-// base.  History h goes to batch (off + h) mod K.
+// One tally target: K batch sums per voxel in the blocked layout above, from
+// base (null: no target).  History h of the beam goes to batch (off + h) mod
+// K; interleaved batches keep every run of consecutive histories spread over
+// all K batches, so lanes working on neighbouring histories rarely add to the
+// same address.
 struct DevTally {
   unsigned long long* base;
   uint32_t K, off;

@@ -12,6 +12,11 @@ oracle, through the C ABI.
   events only, electrons stream through it; not one unit of energy lands in
   the gap, and the doses on both sides agree with the oracle on the same
   streams (z-test) with event counts within 2e-3.
+* The largest batch count accepted (n_batches = 1024): a run's 1024 batch
+  tallies fold (k mod 32) into exactly those of the same run with 32 batches
+  (history h in batch h mod K), the deposited energy is the same, the dose
+  of the 1024-batch finalize equals the 32-batch one bit for bit, and Eq. 12's
+  s of the two agree within 10%.
 * The smallest and ragged grids (one voxel; 7 x 5 x 3 voxels, fewer than one
   finalize block and not a whole number of the tally's 16-voxel blocks, whose
   raw batch tallies finalize to the run's own dose and sigma) and the fewest
@@ -187,3 +192,28 @@ def test_largest_energy(ctx, G, oracle, particle, n):
     zt = E.z_test(d, s, do, so, ref_for_mask=ref, dof=phys.n_batches - 1, same_streams=True)
     print("same streams: z-test %s" % E.describe(zt))
     assert zt.passed, E.describe(zt)
+
+
+def test_largest_batch_count_folds_into_fewer_batches(ctx):
+    ph = I.homogeneous((16, 10, 12), 0.5)
+    src = I.centred(ph, I.Source(I.PHOTON, e=6.0, wx=3.0, wy=3.0))
+    n = 150_000
+    print("\nn_batches 1024 vs 32, %s, n=%d" % (ph.shape, n), flush=True)
+    t_big = ctx.load_tables((I.WATER,), I.Physics(ecut=0.7, pcut=0.01, n_batches=1024))
+    t_small = ctx.load_tables((I.WATER,), I.Physics(ecut=0.7, pcut=0.01, n_batches=32))
+    pid = ctx.load_phantom(ph)
+    try:
+        a, sa = ctx.run_beam_tally(pid, t_big, src, n, 41)
+        b, sb = ctx.run_beam_tally(pid, t_small, src, n, 41)
+        da, _, ra = ctx.finalize_tally(pid, t_big, a, 0, n)
+        db, _, rb = ctx.finalize_tally(pid, t_small, b, 0, n)
+    finally:
+        release(ctx, pid, t_big, t_small)
+    assert a.shape == (1024,) + ph.shape and b.shape == (32,) + ph.shape
+    assert sa["ledger_residual_lsb"] == 0 and sb["ledger_residual_lsb"] == 0
+    assert sa["e_dep_mev"] == sb["e_dep_mev"]
+    # batch k = 32 j + k' of 1024 holds the histories h = k' (mod 32) with h = k (mod 1024)
+    assert np.array_equal(a.reshape((32, 32) + ph.shape).sum(axis=0), b)
+    assert np.array_equal(da, db)
+    print("s of Eq. 12: %.5f with 1024 batches, %.5f with 32" % (ra, rb))
+    assert abs(ra / rb - 1.0) < 0.1
