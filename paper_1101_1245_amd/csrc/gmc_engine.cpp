@@ -550,12 +550,12 @@ void build_job(Job* J, Workspace* w, const PhantomObj& P, const TablesObj& T, co
     db.key1 = (uint32_t)(seed >> 32) ^ srcs[b].beam_id;
     db.b = DevTally{nullptr, 1u, 0u};
     if (mode == kCombined) {
-      db.a = DevTally{w->d_tally, K, off};
+      db.a = DevTally{w->d_tally, K, off % K};
     } else if (mode == kBeamBatched) {
       db.a = DevTally{w->d_tally + nvp * K * (size_t)b, K, 0u};
     } else {
       db.a = DevTally{w->d_tally + nvp * ((size_t)K + (size_t)b), 1u, 0u};
-      db.b = DevTally{w->d_tally, K, off};
+      db.b = DevTally{w->d_tally, K, off % K};
     }
     J->beams.push_back(db);
     J->sources.push_back(dev_source(srcs[b]));
@@ -1197,8 +1197,9 @@ int run_job_ws(gmc_context* c, Workspace* w, int32_t phantom_id, int32_t tables_
     if (rc) return rc;
     if (n_hist[b] == 0) return wfail(w, GMC_EINVAL, "every beam needs at least one history");
     if (n_hist[b] >= (1ull << 32)) return wfail(w, GMC_EINVAL, "histories must be < 2^32");
-    // history numbers and their batch index (off + h, off < n_total) stay within 32 bits
-    if (srcs[b].first_history + n_hist[b] + n_total >= (1ull << 32))
+    // history numbers stay within 32 bits (their combined batch, (off + h) mod K, is
+    // formed from off mod K on the device)
+    if (srcs[b].first_history + n_hist[b] >= (1ull << 32))
       return wfail(w, GMC_EINVAL, "first_history + histories must stay below 2^32");
     n_total += n_hist[b];
     n_min = std::min<uint64_t>(n_min, n_hist[b]);

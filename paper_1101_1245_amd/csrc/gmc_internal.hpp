@@ -92,7 +92,7 @@ struct DevQueue {
 
 // One tally target: K batch sums per voxel in the blocked layout above, from
 // base (null: no target).  History h of the beam goes to batch (off + h) mod
-// K; interleaved batches keep every run of consecutive histories spread over
+// K, off < K (the host reduces it); interleaved batches keep every run of consecutive histories spread over
 // all K batches, so lanes working on neighbouring histories rarely add to the
 // same address.
 struct DevTally {

@@ -68,7 +68,8 @@ __device__ __forceinline__ Primary sample_primary(const DevSource& a, const DevB
 // at the returned pointer + vox_off(v, K) (the blocked layout).
 __device__ __forceinline__ unsigned long long* tally_slice(const DevTally& t, uint32_t h) {
   if (!t.base) return nullptr;
-  const uint32_t k = (t.off + h) % t.K;
+  uint32_t k = h % t.K + t.off;   // (off + h) mod K with off < K: no 32-bit overflow
+  if (k >= t.K) k -= t.K;
   return t.base + (size_t)k * kTallyBlock;
 }
 __device__ __forceinline__ size_t vox_off(uint32_t v, uint32_t K) {

@@ -17,6 +17,10 @@ oracle, through the C ABI.
   (history h in batch h mod K), the deposited energy is the same, the dose
   of the 1024-batch finalize equals the 32-batch one bit for bit, and Eq. 12's
   s of the two agree within 10%.
+* The largest history count one call accepts (2^32 - 1): the plain form
+  runs every history and closes the ledger; the batched form with the same
+  histories split over two beams (the second starting at history 2^31) gives
+  the same dose and sigma bit for bit; 2^32 histories are refused by both.
 * The smallest and ragged grids (one voxel; 7 x 5 x 3 voxels, fewer than one
   finalize block and not a whole number of the tally's 16-voxel blocks, whose
   raw batch tallies finalize to the run's own dose and sigma) and the fewest
@@ -24,6 +28,8 @@ oracle, through the C ABI.
   beams at the largest energy accepted (30 MeV): the ledger closes exactly
   and the doses agree with the oracle.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -217,3 +223,31 @@ def test_largest_batch_count_folds_into_fewer_batches(ctx):
     assert np.array_equal(da, db)
     print("s of Eq. 12: %.5f with 1024 batches, %.5f with 32" % (ra, rb))
     assert abs(ra / rb - 1.0) < 0.1
+
+
+def test_largest_history_count(ctx, G):
+    ph = I.homogeneous((32, 32, 32), 0.5)
+    phys = I.Physics(ecut=0.7, pcut=0.01)
+    src = I.centred(ph, I.Source(I.PHOTON, e=1.0, wx=4.0, wy=4.0))
+    second = dataclasses.replace(src, first_history=1 << 31)
+    n = (1 << 32) - 1
+    print("\n2^32 - 1 photons of 1 MeV on 32^3 water, plain and split over two beams", flush=True)
+    tid, pid = loaded(ctx, (I.WATER,), ph, phys)
+    try:
+        d, s, st = ctx.run_beam(pid, tid, src, n, 51)
+        _, _, db, sb, stb = ctx.run_beams(pid, tid, [src, second], [1 << 31, (1 << 31) - 1], 51, tuning={})
+        with pytest.raises(G.GpumcdError):
+            ctx.run_beam(pid, tid, src, 1 << 32, 51)
+        with pytest.raises(G.GpumcdError):
+            ctx.run_beams(pid, tid, [src, second], [1 << 31, 1 << 31], 51, tuning={})
+    finally:
+        release(ctx, pid, tid)
+    for stats in (st, stb):
+        assert stats["n_hist"] == n and stats["ledger_residual_lsb"] == 0
+        assert stats["e_in_mev"] == pytest.approx(float(n), rel=1e-12)
+        assert 0.0 < stats["s_rel"] < 0.01
+    print("s of Eq. 12: plain %.2e, batched %.2e; %.2f s and %.2f s on the device"
+          % (st["s_rel"], stb["s_rel"], st["t_device_s"], stb["t_device_s"]))
+    assert np.array_equal(db, d)
+    # the second beam's histories keep their batches (off + h = 2^32 + i and 2^31 + i agree mod 32)
+    assert np.array_equal(sb, s)
