@@ -73,8 +73,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # legs).  Valid only for the kernel and engine sources they were measured on
 # (their digest); per launch they are multiplied by this run's work per
 # launch.
-TRAFFIC = {"sources_sha256": "c71783d2b4d4446c51eece77bea5bccb8e66b3310010e8b2701854dd2c5123a5",
-           "k_electron_pass": 57.79, "k_electron_pass_atomics": 0.614}
+TRAFFIC = {"sources_sha256": "9e39638eb02b1fb17234828d06de818ee4dd27b87fb381394cb8ad690d9150e4",
+           "k_electron_pass": 57.98, "k_electron_pass_atomics": 0.614}
 # Words of the array the atomic roof is measured on: 2^23 uint64 (67 MB), the
 # size of the water job's 32-batch tally.
 ATOMIC_ROOF_LOG2_WORDS = 23
